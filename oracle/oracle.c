@@ -1,0 +1,305 @@
+/*
+ * CPU oracle for the pairwise dynamic programs of MuSAlS (arXiv 2601.15458).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: it is used by tests/, by the smoke check and by the
+ * benchmark's CPU-baseline leg.  It shares no code, header, table or helper
+ * with the device library; it reads the same seeded inputs and nothing else.
+ *
+ * Everything here is the plain, slow textbook form of each definition:
+ *   - Levenshtein distance: the Wagner-Fischer recurrence with two rolling
+ *     rows (Sec. 2 and Alg. 1 use Levenshtein as the distance f; Sec. 2.4
+ *     says exact Levenshtein, not an approximation).
+ *   - Needleman-Wunsch with unit costs (match 0, mismatch 1, gap 1) over the
+ *     full (m+1) x (n+1) score matrix, then a backward walk that at each cell
+ *     takes the first of diagonal / up / left that reproduces the cell's
+ *     value (Sec. 2.2 step 2 aligns the two centers and records the gap
+ *     positions; the tie order diag > up > left is this project's reading,
+ *     the paper names none).
+ *   - Alg. 1 (Partition) with the full geometric median (Sec. 2.1).
+ *   - The bottom-up merge of Sec. 2.2.
+ * Pairs are independent, so OpenMP spreads them over host threads; that is
+ * the only concession to speed.
+ *
+ * Symbols are uint8 codes; sequence k of a set is codes[off[k] .. off[k+1]).
+ * Alignment ops: 0 = M (a_i with b_j), 1 = D (a_i with a gap),
+ * 2 = I (a gap with b_j).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int64_t imin3(int64_t x, int64_t y, int64_t z) {
+    int64_t r = x < y ? x : y;
+    return r < z ? r : z;
+}
+
+/* Levenshtein distance by Wagner-Fischer:
+ *   D[i][0] = i, D[0][j] = j,
+ *   D[i][j] = min(D[i-1][j] + 1, D[i][j-1] + 1, D[i-1][j-1] + [a_i != b_j]).
+ * Only two rows are kept; the result is D[m][n]. */
+int64_t orc_lev(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n) {
+    int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    for (int64_t j = 0; j <= n; ++j) prev[j] = j;
+    for (int64_t i = 1; i <= m; ++i) {
+        cur[0] = i;
+        for (int64_t j = 1; j <= n; ++j) {
+            int64_t sub = prev[j - 1] + (a[i - 1] != b[j - 1] ? 1 : 0);
+            cur[j] = imin3(prev[j] + 1, cur[j - 1] + 1, sub);
+        }
+        int64_t *t = prev; prev = cur; cur = t;
+    }
+    int64_t d = prev[n];
+    free(prev);
+    free(cur);
+    return d;
+}
+
+/* out[p] = lev(A[ia[p]], B[ib[p]]) for every pair p. */
+void orc_lev_pairs(const uint8_t *ca, const int64_t *oa, const uint8_t *cb,
+                   const int64_t *ob, const int32_t *ia, const int32_t *ib,
+                   int64_t n_pairs, int64_t *out) {
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const uint8_t *a = ca + oa[ia[p]];
+        const uint8_t *b = cb + ob[ib[p]];
+        out[p] = orc_lev(a, oa[ia[p] + 1] - oa[ia[p]], b, ob[ib[p] + 1] - ob[ib[p]]);
+    }
+}
+
+/* Needleman-Wunsch, unit costs, full matrix, then the backward walk:
+ * at (i, j) take M if D[i-1][j-1] + [a_i != b_j] == D[i][j], else D (up)
+ * if D[i-1][j] + 1 == D[i][j], else I (left).  The op string is written in
+ * forward order to ops[0 .. *ops_len).  Returns D[m][n]. */
+int64_t orc_nw(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+               uint8_t *ops, int64_t *ops_len) {
+    const int64_t w = n + 1;
+    int32_t *D = (int32_t *)malloc(sizeof(int32_t) * (size_t)((m + 1) * w));
+    for (int64_t j = 0; j <= n; ++j) D[j] = (int32_t)j;
+    for (int64_t i = 1; i <= m; ++i) {
+        D[i * w] = (int32_t)i;
+        for (int64_t j = 1; j <= n; ++j) {
+            int64_t sub = D[(i - 1) * w + j - 1] + (a[i - 1] != b[j - 1] ? 1 : 0);
+            D[i * w + j] = (int32_t)imin3(D[(i - 1) * w + j] + 1, D[i * w + j - 1] + 1, sub);
+        }
+    }
+    int64_t score = D[m * w + n];
+    if (ops != NULL) {
+        int64_t i = m, j = n, k = 0;
+        while (i > 0 || j > 0) {
+            int32_t here = D[i * w + j];
+            if (i > 0 && j > 0 &&
+                D[(i - 1) * w + j - 1] + (a[i - 1] != b[j - 1] ? 1 : 0) == here) {
+                ops[k++] = 0; --i; --j;
+            } else if (i > 0 && D[(i - 1) * w + j] + 1 == here) {
+                ops[k++] = 1; --i;
+            } else {
+                ops[k++] = 2; --j;
+            }
+        }
+        for (int64_t x = 0, y = k - 1; x < y; ++x, --y) {
+            uint8_t t = ops[x]; ops[x] = ops[y]; ops[y] = t;
+        }
+        *ops_len = k;
+    }
+    free(D);
+    return score;
+}
+
+/* NW over pairs; ops for pair p go to ops[ops_off[p] ..], its length to
+ * ops_len[p] (ops may be NULL for scores only). */
+void orc_nw_pairs(const uint8_t *ca, const int64_t *oa, const uint8_t *cb,
+                  const int64_t *ob, const int32_t *ia, const int32_t *ib,
+                  int64_t n_pairs, int64_t *score, uint8_t *ops,
+                  const int64_t *ops_off, int64_t *ops_len) {
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const uint8_t *a = ca + oa[ia[p]];
+        const uint8_t *b = cb + ob[ib[p]];
+        int64_t m = oa[ia[p] + 1] - oa[ia[p]], n = ob[ib[p] + 1] - ob[ib[p]];
+        score[p] = orc_nw(a, m, b, n, ops ? ops + ops_off[p] : NULL,
+                          ops ? ops_len + p : NULL);
+    }
+}
+
+/* ------------------------------------------------------------------ Alg. 1
+ * Partition(C): if |C| > 1 then c = geometric median of C (the member with
+ * the least sum of distances to the members of C), l = argmax_x f(c, x),
+ * r = argmax_x f(l, x), L = {x : f(l,x) <= f(r,x)}, R = {x : f(r,x) < f(l,x)},
+ * recurse on L and R.  Readings fixed here: every argmin/argmax scans members
+ * in ascending index order and keeps the first optimum (lowest index); a
+ * cluster whose radius max_x f(c, x) is 0 (only copies of one sequence)
+ * becomes a leaf.
+ *
+ * Nodes are numbered breadth-first (children of node v are created when v is
+ * split, L before R).  Members of every node are a contiguous range of
+ * `perm`: a node's range is its L child's range followed by its R child's.
+ * Per node: parent, left, right (-1 if none), center, lpole, rpole (-1 for
+ * leaves), depth, mstart, mcount.  Returns the node count (<= 2n-1). */
+typedef struct {
+    int32_t parent, left, right, center, lpole, rpole, depth;
+    int64_t mstart, mcount;
+} orc_node;
+
+static int64_t dist_of(const uint8_t *codes, const int64_t *off, int32_t x, int32_t y) {
+    return orc_lev(codes + off[x], off[x + 1] - off[x], codes + off[y], off[y + 1] - off[y]);
+}
+
+int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
+                 int32_t *parent, int32_t *left, int32_t *right, int32_t *center,
+                 int32_t *lpole, int32_t *rpole, int32_t *depth,
+                 int64_t *mstart, int64_t *mcount, int32_t *perm) {
+    if (n <= 0) return 0;
+    /* members[v]: ascending member list of node v */
+    int32_t **members = (int32_t **)calloc((size_t)(2 * n), sizeof(int32_t *));
+    int64_t *msize = (int64_t *)calloc((size_t)(2 * n), sizeof(int64_t));
+    members[0] = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) members[0][i] = i;
+    msize[0] = n;
+    parent[0] = -1; depth[0] = 0;
+    int32_t n_nodes = 1;
+    for (int32_t v = 0; v < n_nodes; ++v) {
+        int64_t k = msize[v];
+        int32_t *C = members[v];
+        left[v] = right[v] = lpole[v] = rpole[v] = -1;
+        if (k == 1) { center[v] = C[0]; continue; }
+        /* geometric median over the whole cluster */
+        int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k * k));
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t x = 0; x < k; ++x) {
+            D[x * k + x] = 0;
+            for (int64_t y = x + 1; y < k; ++y) {
+                int64_t d = dist_of(codes, off, C[x], C[y]);
+                D[x * k + y] = d;
+                D[y * k + x] = d;
+            }
+        }
+        int64_t best = -1, best_sum = 0;
+        for (int64_t x = 0; x < k; ++x) {
+            int64_t s = 0;
+            for (int64_t y = 0; y < k; ++y) s += D[x * k + y];
+            if (best < 0 || s < best_sum) { best = x; best_sum = s; }
+        }
+        int64_t lp = 0;
+        for (int64_t x = 1; x < k; ++x) if (D[best * k + x] > D[best * k + lp]) lp = x;
+        center[v] = C[best];
+        if (D[best * k + lp] == 0) { free(D); continue; }   /* radius 0: leaf */
+        int64_t rp = 0;
+        for (int64_t x = 1; x < k; ++x) if (D[lp * k + x] > D[lp * k + rp]) rp = x;
+        lpole[v] = C[lp];
+        rpole[v] = C[rp];
+        int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        int64_t nl = 0, nr = 0;
+        for (int64_t x = 0; x < k; ++x) {
+            if (D[lp * k + x] <= D[rp * k + x]) L[nl++] = C[x];
+            else R[nr++] = C[x];
+        }
+        free(D);
+        int32_t a = n_nodes++, b = n_nodes++;
+        members[a] = L; msize[a] = nl;
+        members[b] = R; msize[b] = nr;
+        parent[a] = parent[b] = v;
+        depth[a] = depth[b] = depth[v] + 1;
+        left[v] = a; right[v] = b;
+    }
+    /* member ranges: a node's range is its children's ranges in order */
+    mstart[0] = 0;
+    for (int32_t v = 0; v < n_nodes; ++v) {
+        mcount[v] = msize[v];
+        if (left[v] >= 0) {
+            mstart[left[v]] = mstart[v];
+            mstart[right[v]] = mstart[v] + msize[left[v]];
+        } else {
+            for (int64_t x = 0; x < msize[v]; ++x) perm[mstart[v] + x] = members[v][x];
+        }
+    }
+    for (int32_t v = 0; v < n_nodes; ++v) free(members[v]);
+    free(members);
+    free(msize);
+    return n_nodes;
+}
+
+/* ------------------------------------------------------------------ merge
+ * Bottom-up merge of Sec. 2.2 over the tree from orc_tree.  A leaf's
+ * alignment is its sequence(s) (one row each, no gaps).  For an internal
+ * node with children L and R: take the aligned row of center(L) in L's
+ * alignment and the aligned row of center(R) in R's, align the two rows with
+ * the unit-cost NW above treating the gap symbol `sigma` as an ordinary
+ * symbol, then widen L's alignment with an all-gap column at every I op and
+ * R's alignment with an all-gap column at every D op, and stack L's rows over
+ * R's.  Rows of a node follow its `perm` range.  The final alignment is
+ * written with row i = input sequence i; returns its width (-1 on error). */
+int64_t orc_merge(const uint8_t *codes, const int64_t *off, int32_t n, int32_t sigma,
+                  int32_t n_nodes, const int32_t *left, const int32_t *right,
+                  const int32_t *center, const int64_t *mstart, const int64_t *mcount,
+                  const int32_t *perm, uint8_t *msa_out, int64_t msa_cap) {
+    uint8_t **aln = (uint8_t **)calloc((size_t)n_nodes, sizeof(uint8_t *));
+    int64_t *width = (int64_t *)calloc((size_t)n_nodes, sizeof(int64_t));
+    const uint8_t gap = (uint8_t)sigma;
+    for (int32_t v = n_nodes - 1; v >= 0; --v) {
+        int64_t rows = mcount[v];
+        if (left[v] < 0) {
+            int64_t W = 0;
+            for (int64_t r = 0; r < rows; ++r) {
+                int32_t s = perm[mstart[v] + r];
+                if (off[s + 1] - off[s] > W) W = off[s + 1] - off[s];
+            }
+            aln[v] = (uint8_t *)malloc((size_t)(rows * W + 1));
+            for (int64_t r = 0; r < rows; ++r) {
+                int32_t s = perm[mstart[v] + r];
+                int64_t len = off[s + 1] - off[s];
+                memcpy(aln[v] + r * W, codes + off[s], (size_t)len);
+                memset(aln[v] + r * W + len, gap, (size_t)(W - len));
+            }
+            width[v] = W;
+            continue;
+        }
+        int32_t L = left[v], R = right[v];
+        int64_t WL = width[L], WR = width[R];
+        int64_t rl = -1, rr = -1;
+        for (int64_t r = 0; r < mcount[L]; ++r) if (perm[mstart[L] + r] == center[L]) rl = r;
+        for (int64_t r = 0; r < mcount[R]; ++r) if (perm[mstart[R] + r] == center[R]) rr = r;
+        if (rl < 0 || rr < 0) return -1;
+        uint8_t *ops = (uint8_t *)malloc((size_t)(WL + WR + 1));
+        int64_t nops = 0;
+        orc_nw(aln[L] + rl * WL, WL, aln[R] + rr * WR, WR, ops, &nops);
+        uint8_t *out = (uint8_t *)malloc((size_t)(rows * nops + 1));
+        for (int64_t r = 0; r < mcount[L]; ++r) {
+            int64_t src = 0;
+            for (int64_t c = 0; c < nops; ++c)
+                out[r * nops + c] = (ops[c] == 2) ? gap : aln[L][r * WL + src++];
+        }
+        for (int64_t r = 0; r < mcount[R]; ++r) {
+            int64_t src = 0;
+            for (int64_t c = 0; c < nops; ++c)
+                out[(mcount[L] + r) * nops + c] = (ops[c] == 1) ? gap : aln[R][r * WR + src++];
+        }
+        free(ops);
+        free(aln[L]); aln[L] = NULL;
+        free(aln[R]); aln[R] = NULL;
+        aln[v] = out;
+        width[v] = nops;
+    }
+    int64_t W = width[0];
+    if ((int64_t)n * W > msa_cap) W = -1;
+    else
+        for (int64_t r = 0; r < n; ++r)
+            memcpy(msa_out + (int64_t)perm[r] * W, aln[0] + r * W, (size_t)W);
+    free(aln[0]);
+    free(aln);
+    free(width);
+    return W;
+}

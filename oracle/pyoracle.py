@@ -1,0 +1,141 @@
+"""ctypes face of the C oracle (test infrastructure only).
+
+Inputs are numpy arrays in the CSR form produced by the input generators:
+uint8 codes plus int64 offsets.  Nothing here imports the device library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB) or \
+                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        P = C.c_void_p
+        L.orc_lev.restype = C.c_int64
+        L.orc_lev.argtypes = [P, C.c_int64, P, C.c_int64]
+        L.orc_lev_pairs.restype = None
+        L.orc_lev_pairs.argtypes = [P, P, P, P, P, P, C.c_int64, P]
+        L.orc_nw.restype = C.c_int64
+        L.orc_nw.argtypes = [P, C.c_int64, P, C.c_int64, P, P]
+        L.orc_nw_pairs.restype = None
+        L.orc_nw_pairs.argtypes = [P, P, P, P, P, P, C.c_int64, P, P, P, P]
+        L.orc_tree.restype = C.c_int32
+        L.orc_tree.argtypes = [P, P, C.c_int32] + [P] * 10
+        L.orc_merge.restype = C.c_int64
+        L.orc_merge.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
+                                C.c_int64]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _u8(x):
+    if isinstance(x, (bytes, bytearray)):
+        return np.frombuffer(bytes(x), dtype=np.uint8).copy()
+    if isinstance(x, str):
+        return np.frombuffer(x.encode(), dtype=np.uint8).copy()
+    return np.ascontiguousarray(np.asarray(x, dtype=np.uint8))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def lev(a, b) -> int:
+    a, b = _u8(a), _u8(b)
+    return int(lib().orc_lev(_p(a), len(a), _p(b), len(b)))
+
+
+def lev_pairs(ca, oa, cb, ob, ia, ib) -> np.ndarray:
+    ca, cb = _u8(ca), _u8(cb)
+    oa = np.ascontiguousarray(oa, dtype=np.int64)
+    ob = np.ascontiguousarray(ob, dtype=np.int64)
+    ia = np.ascontiguousarray(ia, dtype=np.int32)
+    ib = np.ascontiguousarray(ib, dtype=np.int32)
+    out = np.zeros(len(ia), dtype=np.int64)
+    lib().orc_lev_pairs(_p(ca), _p(oa), _p(cb), _p(ob), _p(ia), _p(ib), len(ia), _p(out))
+    return out
+
+
+def nw(a, b):
+    """(score, ops) for one pair; ops uint8 with 0=M, 1=D, 2=I."""
+    a, b = _u8(a), _u8(b)
+    ops = np.zeros(len(a) + len(b) + 1, dtype=np.uint8)
+    n = np.zeros(1, dtype=np.int64)
+    s = lib().orc_nw(_p(a), len(a), _p(b), len(b), _p(ops), _p(n))
+    return int(s), ops[: int(n[0])].copy()
+
+
+def nw_pairs(ca, oa, cb, ob, ia, ib, with_ops=True):
+    """Scores (int64[P]) and, if asked, a list of op arrays."""
+    ca, cb = _u8(ca), _u8(cb)
+    oa = np.ascontiguousarray(oa, dtype=np.int64)
+    ob = np.ascontiguousarray(ob, dtype=np.int64)
+    ia = np.ascontiguousarray(ia, dtype=np.int32)
+    ib = np.ascontiguousarray(ib, dtype=np.int32)
+    P = len(ia)
+    score = np.zeros(P, dtype=np.int64)
+    if not with_ops:
+        lib().orc_nw_pairs(_p(ca), _p(oa), _p(cb), _p(ob), _p(ia), _p(ib), P, _p(score),
+                           None, None, None)
+        return score, None
+    cap = (oa[ia + 1] - oa[ia]) + (ob[ib + 1] - ob[ib])
+    ops_off = np.zeros(P + 1, dtype=np.int64)
+    np.cumsum(cap, out=ops_off[1:])
+    ops = np.zeros(max(int(ops_off[-1]), 1), dtype=np.uint8)
+    ops_len = np.zeros(P, dtype=np.int64)
+    lib().orc_nw_pairs(_p(ca), _p(oa), _p(cb), _p(ob), _p(ia), _p(ib), P, _p(score),
+                       _p(ops), _p(ops_off), _p(ops_len))
+    return score, [ops[ops_off[p]: ops_off[p] + ops_len[p]].copy() for p in range(P)]
+
+
+TREE_FIELDS = ("parent", "left", "right", "center", "lpole", "rpole", "depth",
+               "mstart", "mcount")
+
+
+def tree(codes, offsets):
+    """Alg. 1 with the full geometric median; dict of per-node arrays + perm."""
+    codes = _u8(codes)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(offsets) - 1
+    cap = max(2 * n - 1, 1)
+    arr = {f: np.zeros(cap, dtype=np.int64 if f in ("mstart", "mcount") else np.int32)
+           for f in TREE_FIELDS}
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    k = lib().orc_tree(_p(codes), _p(offsets), n, *[_p(arr[f]) for f in TREE_FIELDS],
+                       _p(perm))
+    out = {f: arr[f][:k].copy() for f in TREE_FIELDS}
+    out["perm"] = perm[:n].copy()
+    out["n_nodes"] = int(k)
+    return out
+
+
+def merge(codes, offsets, sigma, t):
+    """Final alignment (n x W uint8, gap = sigma) for the tree ``t``."""
+    codes = _u8(codes)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(offsets) - 1
+    cap = n * int(offsets[-1] + 1)
+    msa = np.zeros(max(cap, 1), dtype=np.uint8)
+    W = lib().orc_merge(_p(codes), _p(offsets), n, sigma, t["n_nodes"],
+                        _p(t["left"]), _p(t["right"]), _p(t["center"]),
+                        _p(t["mstart"]), _p(t["mcount"]), _p(t["perm"]), _p(msa), cap)
+    if W < 0:
+        raise RuntimeError("oracle merge failed")
+    return msa[: n * W].reshape(n, W).copy()

@@ -1,0 +1,181 @@
+"""Benchmark: all-pairs Levenshtein on 4096 DNA sequences (lengths 1000-1600).
+
+One step = one lev_allpairs call over the whole set (8,386,560 pairs): length
+binning, staging and the persistent bit-parallel kernel.  Prints one JSON
+line.  Inputs are resident on the GPU before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--nw]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("GCUPS & pairs/s (batched Levenshtein+NW, bit-exact); "
+          "surrogate vs exact tree-build speedup")
+# Roofline peak of the bit-parallel Levenshtein kernel: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3 T 32-bit VALU lane-ops/s, at 32 lane-ops per
+# 64-cell word step (two 32-bit ops per 64-bit logical op) = 78.6 T cells/s.
+LEV_PEAK_TCUPS = 256 * 4 * 16 * 2.4e9 * 64 / 32 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--nw", action="store_true", help="also time the 512-pair NW batch")
+    return ap.parse_args()
+
+
+def cpu_baseline(d, seconds):
+    """The oracle (plain Wagner-Fischer, OpenMP over pairs) on a seeded
+    sample of the same pairs, for about `seconds` of wall time."""
+    from oracle import pyoracle as orc
+    n = d["n"]
+    L = np.diff(d["offsets"])
+    rng = np.random.default_rng(2024)
+    done_cells = 0
+    done_pairs = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        ia = rng.integers(0, n, size=512)
+        ib = rng.integers(0, n, size=512)
+        keep = ia != ib
+        ia, ib = ia[keep], ib[keep]
+        orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], ia, ib)
+        done_cells += int((L[ia] * L[ib]).sum())
+        done_pairs += len(ia)
+    dt = time.perf_counter() - t0
+    return {"value": round(done_cells / dt / 1e9, 3), "unit": "GCUPS",
+            "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{done_pairs} seeded random pairs of the same 4096-sequence set "
+                      f"({done_cells:.3e} cells, {dt:.1f} s); pairs/s = "
+                      f"{done_pairs / dt:.1f}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
+              "of the pair triangle is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2601_15458_amd import msadp, synth
+
+    d = synth.allpairs()
+    n = d["n"]
+    L = np.diff(d["offsets"]).astype(np.int64)
+    tot = int(L.sum())
+    cells = (tot * tot - int((L * L).sum())) // 2
+    pairs = n * (n - 1) // 2
+    A = msadp.to_device(d["codes"], d["offsets"], d["sigma"])
+    ap = msadp.AllPairs(A)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ap(stream)
+    torch.cuda.synchronize()
+    ap.st.check("lev_allpairs")
+
+    # spot parity on a seeded sample (outside the timed region)
+    from oracle import pyoracle as orc
+    out = ap.out[:pairs].cpu().numpy().astype(np.int64)
+    rng = np.random.default_rng(5)
+    ia = rng.integers(0, n, size=300)
+    ib = rng.integers(0, n, size=300)
+    keep = ia != ib
+    ia, ib = ia[keep], ib[keep]
+    i, j = np.minimum(ia, ib), np.maximum(ia, ib)
+    want = orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], i, j)
+    parity = bool((out[i * n - i * (i + 1) // 2 + (j - i - 1)] == want).all())
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ap(stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    call_ms = [a.elapsed_time(b) for a, b in ev]
+    ms = float(np.mean(call_ms))
+    ap.st.check("lev_allpairs")
+    tcups = cells / (ms * 1e-3) / 1e12
+    res = {
+        "metric": METRIC,
+        "value": round(cells / (wall / args.steps) / 1e9, 1),
+        "unit": "GCUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "lev_allpairs: 4096 DNA seqs, lengths U{1000..1600}, "
+                               "seed 2, uint16 condensed output",
+                   "pairs": pairs, "cells": cells},
+        "pairs_per_s": round(pairs / (wall / args.steps), 1),
+        "parity_sample_ok": parity,
+        "roofline": {"bound": "alu", "achieved": round(tcups, 2),
+                     "peak": round(LEV_PEAK_TCUPS, 1), "unit": "Tcell/s",
+                     "frac": round(tcups / LEV_PEAK_TCUPS, 4), "traffic": None,
+                     "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3)},
+    }
+    if args.nw:
+        res["nw"] = bench_nw(msadp, synth, torch, args)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+def bench_nw(msadp, synth, torch, args):
+    import ctypes as C
+    d = synth.nw_long()
+    P = d["n_pairs"]
+    A = msadp.to_device(d["a_codes"], d["a_offsets"], 4)
+    B = msadp.to_device(d["b_codes"], d["b_offsets"], 4)
+    ia = np.arange(P)
+    r = msadp.nw_batch(A, B, ia, ia)
+    msadp.nw_traceback(A, B, r)
+    torch.cuda.synchronize()
+    la = np.diff(d["a_offsets"])
+    lb = np.diff(d["b_offsets"])
+    cells = int((la * lb).sum())
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fill, tb = [], []
+    for _ in range(max(args.steps, 3)):
+        e[0].record(stream)
+        r = msadp.nw_batch(A, B, ia, ia, check=False)
+        e[1].record(stream)
+        msadp.nw_traceback(A, B, r, check=False)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        fill.append(e[0].elapsed_time(e[1]))
+        tb.append(e[1].elapsed_time(e[2]))
+    f = float(np.median(fill))
+    t = float(np.median(tb))
+    tb_bytes = int(sum(msadp.lib().nw_tb_bytes(int(a), int(b)) for a, b in zip(la, lb)))
+    return {"workload": "nw_batch+nw_traceback: 512 DNA pairs, lengths U{5000..10000}, 10% "
+                        "divergence, unit costs, seed 4",
+            "cells": cells, "fill_ms": round(f, 3), "traceback_ms": round(t, 3),
+            "fill_gcups": round(cells / f / 1e6, 1),
+            "gcups_fill_plus_traceback": round(cells / (f + t) / 1e6, 1),
+            "pairs_per_s": round(P / ((f + t) * 1e-3), 1),
+            "tb_bytes": tb_bytes,
+            "fill_hbm_gbs": round(tb_bytes / f / 1e6, 1)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,136 @@
+/*
+ * msadp: batched Levenshtein and Needleman-Wunsch dynamic programs on
+ * MI355X (gfx950), for the guide-tree clustering and bottom-up alignment of
+ * MuSAlS (Light, Prior, Daniels, Ishaq; arXiv 2601.15458).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Sequences.  A sequence set is described by `msa_seqs`: symbol codes in
+ * CSR form.  Sequence k occupies symbols [offsets[k], offsets[k+1]).  With
+ * packed_2bit == 0 each symbol is one byte of `codes`; with packed_2bit == 1
+ * (only for sigma <= 4) symbol p sits in bits 2*(p%4) .. 2*(p%4)+1 of byte
+ * codes[p/4].  `codes` and `offsets` are DEVICE pointers; n, sigma, max_len
+ * and packed_2bit are host values.  max_len must bound every length; the
+ * library relies on it to size workspace and to pick kernels.
+ *
+ * Ownership.  The caller owns every buffer: inputs, outputs and workspace.
+ * The library never allocates device memory on these paths and never frees
+ * caller memory.  Workspace sizes come from the *_workspace_bytes queries.
+ * All calls are asynchronous on the caller's stream `s`; results are valid
+ * once the stream reaches them.
+ *
+ * Errors.  Functions return MSA_OK (0) or a negative code.  Errors detected
+ * on the host (null pointers, negative counts, sigma outside [2, 32],
+ * packed_2bit with sigma > 4, max_len outside [0, 65535], workspace too
+ * small) return before anything is launched and leave outputs untouched.
+ * MSA_EDEVICE reports a failed launch.  Errors only visible on the device
+ * (a code >= sigma, an index outside [0, n), a length above max_len or a
+ * negative length, an output capacity too small) are written to *d_status
+ * (a device int32 the caller zeroes; the first error wins) when d_status is
+ * non-null; the affected outputs are then unspecified.  n_pairs == 0 returns
+ * MSA_OK without launching.  No exception crosses this interface.
+ */
+#ifndef MSADP_H
+#define MSADP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MSA_OK = 0,
+    MSA_EINVAL = -1,   /* bad argument                                   */
+    MSA_ERANGE = -2,   /* a size outside what the entry point supports   */
+    MSA_ENOSPC = -3,   /* workspace or output capacity too small         */
+    MSA_EDEVICE = -4   /* a HIP launch or runtime call failed            */
+};
+
+/* Values written to *d_status by the device. */
+enum {
+    MSA_DS_OK = 0,
+    MSA_DS_SYMBOL = 1,     /* a symbol code >= sigma                      */
+    MSA_DS_INDEX = 2,      /* a sequence index outside [0, n)             */
+    MSA_DS_LENGTH = 3,     /* a length < 0 or > max_len                   */
+    MSA_DS_CAPACITY = 4    /* an output region smaller than required      */
+};
+
+typedef struct msa_seqs {
+    const uint8_t *codes;     /* device: symbol codes (see packed_2bit)   */
+    const int64_t *offsets;   /* device: n + 1 symbol offsets             */
+    int32_t n;                /* number of sequences                      */
+    int32_t sigma;            /* alphabet size, 2..32; codes 0..sigma-1   */
+    int32_t max_len;          /* upper bound on every length, <= 65535    */
+    int32_t packed_2bit;      /* 1: four 2-bit symbols per byte           */
+} msa_seqs;
+
+const char *msa_strerror(int code);
+int msa_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Levenshtein distance (the distance f of Alg. 1, Sec. 2.1; exact, not an
+ * approximation, Sec. 2): unit-cost edit distance with insertions,
+ * deletions and substitutions, D[m][n] of the Wagner-Fischer recurrence.
+ * Computed bit-parallel: one bit per DP row, 64 rows per machine word.   */
+
+/* Workspace for lev_batch over n_pairs pairs drawn from A and B. */
+size_t lev_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs);
+
+/* dist[p] = lev(A[ia[p]], B[ib[p]]) for p in [0, n_pairs).
+ * ia, ib: device int32[n_pairs]; dist: device uint16[n_pairs].
+ * Pairs are grouped by ia on the device so that every wavefront shares one
+ * pattern; any order of pairs is correct. */
+int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+              int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes,
+              int32_t *d_status, hipStream_t s);
+
+/* Workspace for lev_allpairs over the set A. */
+size_t lev_allpairs_workspace_bytes(const msa_seqs *A);
+
+/* All n(n-1)/2 distances of the set A (the root-level distance batch of
+ * Alg. 1).  condensed: device uint16[n(n-1)/2]; the pair i < j is stored at
+ * i*n - i*(i+1)/2 + (j - i - 1).  Sequences are binned by length on the
+ * device and all pairs run in one persistent launch, longest first. */
+int lev_allpairs(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws_bytes,
+                 int32_t *d_status, hipStream_t s);
+
+/* ------------------------------------------------------------------ */
+/* Needleman-Wunsch global alignment with unit costs (match 0, mismatch 1,
+ * gap 1), the pairwise aligner of the merge (Sec. 2.2, step 2: align the two
+ * centers and note where gaps were added).  The fill records, per DP cell,
+ * which predecessor the backward walk takes, in the order diagonal > up >
+ * left; nw_traceback follows those codes from (m, n) to (0, 0).           */
+
+/* Bytes of traceback codes for one pair with |a| = m, |b| = n (2 bits per
+ * cell plus a small layout overhead; 0 when m == 0 or n == 0). */
+size_t nw_tb_bytes(int32_t m, int32_t n);
+
+/* Workspace for nw_batch over n_pairs pairs drawn from A and B. */
+size_t nw_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs);
+
+/* Fill for each pair p: score[p] = D[m][n] (int32) and the traceback codes
+ * of pair p in tb[tb_offsets[p] .. tb_offsets[p+1]) (device int64[n_pairs+1],
+ * each region at least nw_tb_bytes(m, n) bytes and 8-byte aligned).  The
+ * code layout is private to nw_traceback.  score may be null. */
+int nw_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+             int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets,
+             void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
+/* Walk the codes written by nw_batch (same A, B, ia, ib, tb, tb_offsets).
+ * For pair p the alignment is written in forward order to
+ * ops[ops_offsets[p] ..] (device int64[n_pairs+1]; each region must hold
+ * m + n bytes), one byte per column: 0 = M (a_i with b_j), 1 = D (a_i with a
+ * gap), 2 = I (a gap with b_j); ops_len[p] receives the column count.
+ * Columns with op I are the gap positions added to a, op D those added to b. */
+int nw_traceback(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                 int64_t n_pairs, const uint8_t *tb, const int64_t *tb_offsets,
+                 uint8_t *ops, const int64_t *ops_offsets, int32_t *ops_len,
+                 int32_t *d_status, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSADP_H */

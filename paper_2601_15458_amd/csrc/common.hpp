@@ -1,0 +1,98 @@
+// Internal helpers shared by the msadp device library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "msadp.h"
+
+namespace msadp {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- bit ops
+// gfx950 has a three-input bitwise instruction (v_bitop3_b32) whose 8-bit
+// immediate is the truth table of f(S0, S1, S2) indexed by (S0 S1 S2) read
+// as a 3-bit number.  LUT(expr) builds that table by evaluating the
+// expression on the three canonical operand patterns 0xF0, 0xCC, 0xAA.
+#define MSADP_LUT(expr) \
+    ((uint8_t)([](uint32_t A, uint32_t B, uint32_t C) { return (expr); }(0xF0u, 0xCCu, 0xAAu)))
+
+template <uint8_t L>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, L);
+}
+
+// (hi:lo) >> 31, low word: (hi << 1) | (lo >> 31)
+__device__ __forceinline__ uint32_t shl1_carry(uint32_t hi, uint32_t lo) {
+    return __builtin_amdgcn_alignbit(hi, lo, 31);
+}
+
+__device__ __forceinline__ void set_status(int32_t *st, int32_t code) {
+    if (st != nullptr) atomicCAS(st, 0, code);
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// --------------------------------------------------------- staged sequences
+// Every entry point first copies its input sequences into this layout: one
+// row of `stride` bytes per sequence (one byte per symbol, zero padded), so
+// kernels read aligned words regardless of the caller's offsets or packing.
+struct Staged {
+    uint8_t *codes;     // n * stride bytes
+    int32_t *len;       // n lengths
+    int64_t stride;     // bytes per row, multiple of 16, >= max_len + 16
+    int32_t n;
+};
+
+inline int64_t staged_stride(int32_t max_len) { return ((int64_t)max_len + 16 + 15) / 16 * 16; }
+
+// ----------------------------------------------------------- host helpers
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct Carve {
+    uintptr_t base, cur, end;
+    explicit Carve(void *p, size_t bytes)
+        : base((uintptr_t)p), cur((uintptr_t)p), end((uintptr_t)p + bytes) {}
+    template <class T>
+    T *take(size_t count) {
+        cur = (cur + 255) / 256 * 256;
+        T *p = (T *)cur;
+        cur += count * sizeof(T);
+        return p;
+    }
+    size_t used() const { return (size_t)(cur - base) + 256; }
+    bool ok() const { return cur <= end; }
+};
+
+// Size-only twin of Carve for the workspace queries.
+struct Sizer {
+    size_t cur = 0;
+    template <class T>
+    void take(size_t count) {
+        cur = (cur + 255) / 256 * 256;
+        cur += count * sizeof(T);
+    }
+    size_t total() const { return cur + 256; }
+};
+
+int check_seqs(const msa_seqs *S);
+int launch_status();
+
+// staging (stage.hip)
+int stage_set(const msa_seqs *S, const int32_t *order, Staged out, int32_t *d_status,
+              hipStream_t s);
+int sort_by_length(const msa_seqs *S, int32_t *len_tmp, int32_t *hist, int32_t *order,
+                   int32_t *d_status, hipStream_t s);
+int fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+int fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
+int exclusive_scan_i64(int64_t *data, int64_t n, hipStream_t s);
+
+}  // namespace msadp

@@ -1,0 +1,382 @@
+// Needleman-Wunsch fill and traceback with unit costs (the pairwise aligner
+// of the merge, Sec. 2.2 step 2), bit-parallel.
+//
+// With match 0 / mismatch 1 / gap 1 the NW score matrix is the Levenshtein
+// matrix, so the fill runs the same bit-vector recurrence as lev.hip, here
+// one 32-row word per lane.  Per cell it also emits the backward-walk choice
+// (diagonal > up > left) as two bits derived from the bit vectors:
+//   M (diagonal) iff a_i == b_j or D[i][j] == D[i-1][j-1] + 1, i.e.
+//       M = Eq | ~D0 with D0 = Xh | Mv (diagonal delta zero);
+//   U (up)       iff not M and D[i][j] == D[i-1][j] + 1, i.e. the new Pv;
+//   else left.
+//
+// Fill layout.  A pair gets one workgroup; global lane g = 64*w + l holds
+// pattern word g (rows 32g+1 .. 32g+32).  Lanes run skewed: lane g handles
+// text column j one step after lane g-1 did, so the horizontal delta leaving
+// word g-1 and the text symbol of column j reach lane g by a one-lane
+// wavefront shift (DPP).  Between wavefronts the same packet goes through an
+// LDS ring; wavefront w runs kLag steps behind w-1 and all wavefronts meet at
+// a barrier every kRound steps, which orders every ring write before its read.
+// The equality mask of a word is rebuilt per column from the word's symbol
+// bit planes (no lookup table).  Codes are stored by anti-diagonal: the entry
+// of (column j, word g) is record (j + g) * W + g, so at every step one
+// wavefront writes 64 consecutive 8-byte records (M plane, U plane).
+#include "common.hpp"
+
+namespace msadp {
+
+constexpr int kRound = 32;     // steps between workgroup barriers
+constexpr int kLag = 96;       // step lag between consecutive wavefronts (>= 63 + kRound)
+constexpr int kRing = 256;     // ring entries per wavefront boundary (>= kLag - 63 + kRound)
+constexpr int kMaxFillWaves = 16;
+
+static_assert(kLag >= 63 + kRound, "ring handoff needs a barrier in between");
+static_assert(kRing >= kLag - 63 + kRound, "ring too small");
+
+__host__ __device__ inline int64_t tb_words(int32_t m) { return ((int64_t)m + 31) / 32; }
+
+__host__ __device__ inline int64_t tb_bytes(int32_t m, int32_t n) {
+    if (m <= 0 || n <= 0) return 0;
+    const int64_t W = tb_words(m);
+    return (n + W - 1) * W * 8;
+}
+
+struct NwLut {
+    static constexpr uint8_t NOTA_OR_B = MSADP_LUT(~A | B);          // Eq' = ~neq | hn
+    static constexpr uint8_t NOTA_OR_B2 = MSADP_LUT(~A | B);         // Xv = ~neq | Mv
+    static constexpr uint8_t XOR_OR = MSADP_LUT((A ^ B) | C);        // Xh
+    static constexpr uint8_t PH = MSADP_LUT(C | ~(A | B));           // Ph = Mv | ~(Xh | Pv)
+    static constexpr uint8_t PV = MSADP_LUT(A | ~(B | C));           // Pv = Mh | ~(Xv | Ph)
+    static constexpr uint8_t MCODE = MSADP_LUT(~(A & (B | C)));      // M = ~neq | ~(Xh | Mv)
+    static constexpr uint8_t ACC_XOR = MSADP_LUT(A | (B ^ C));       // neq |= plane ^ mask
+};
+
+struct FillArgs {
+    Staged A, B;
+    const int32_t *ia, *ib;
+    int32_t *score;
+    uint8_t *tb;
+    const int64_t *tb_off;
+    int32_t *st;
+    int32_t planes;   // bits per symbol code
+};
+
+// DPP control: shift the whole wavefront right by one lane.
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int P>
+__device__ void nw_fill_pair(const FillArgs &a, int64_t p, uint32_t *ring) {
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int32_t x = a.ia[p], y = a.ib[p];
+    if (x < 0 || x >= a.A.n || y < 0 || y >= a.B.n) {
+        if (threadIdx.x == 0) set_status(a.st, MSA_DS_INDEX);
+        return;
+    }
+    const int m = a.A.len[x], n = a.B.len[y];
+    if (m == 0 || n == 0) {
+        if (threadIdx.x == 0 && a.score) a.score[p] = m + n;
+        return;
+    }
+    const int64_t W = tb_words(m);
+    const int nw = (int)((W + 63) >> 6);
+    if (a.tb_off[p + 1] - a.tb_off[p] < tb_bytes(m, n)) {
+        if (threadIdx.x == 0) set_status(a.st, MSA_DS_CAPACITY);
+        return;
+    }
+    if (w >= nw) return;   // wavefronts past the last word leave at once
+    const int g = 64 * w + lane;
+    const bool word_ok = g < W;
+
+    // symbol bit planes of this lane's 32 pattern rows
+    uint32_t plane[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b) plane[b] = 0;
+    if (word_ok) {
+        const uint8_t *pat = a.A.codes + (int64_t)x * a.A.stride + 32 * g;
+        const uint4 q0 = ((const uint4 *)pat)[0], q1 = ((const uint4 *)pat)[1];
+        const uint32_t qs[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        const int rows = min(32, m - 32 * g);
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            const uint32_t c = (qs[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+            if (i < rows) {
+#pragma unroll
+                for (int b = 0; b < P; ++b) plane[b] |= ((c >> b) & 1u) << i;
+            }
+        }
+    }
+    const uint32_t bpos = (g == W - 1) ? (uint32_t)((m - 1) & 31) : 31u;
+    const uint8_t *text = a.B.codes + (int64_t)y * a.B.stride;
+    uint8_t *tbp = a.tb + a.tb_off[p];
+    uint32_t *ring_in = ring + (w - 1) * kRing;   // written by wavefront w-1
+    uint32_t *ring_out = ring + w * kRing;
+
+    uint32_t Pv = ~0u, Mv = 0u;
+    uint32_t acc = 0;          // lo 16 bits: count of +1, hi 16 bits: count of -1
+    uint32_t xout = 0;
+    const int total = n + 63 + kLag * (nw - 1);
+    const int rounds = (total + kRound - 1) / kRound;
+    const int shift = kLag * w + lane;       // column j = t - shift
+    // record index of (t): (j + g) * W + g with j + g = t - (kLag - 64) * w
+    const int64_t sbase = -(int64_t)(kLag - 64) * w;
+    for (int rnd = 0; rnd < rounds; ++rnd) {
+        const int t0 = rnd * kRound;
+        // feed[l] = packet entering lane 0 at step t0 + l (l < kRound)
+        // The barrier comes first: ring entries read here were written in an
+        // earlier round (at least kLag - 63 - kRound steps before).
+        __syncthreads();
+        uint32_t feed = 0;
+        {
+            const int jj = t0 + lane - kLag * w;   // column reaching lane 0 at step t0 + lane
+            if (lane < kRound && jj >= 0 && jj < n) {
+                if (w == 0) feed = ((uint32_t)text[jj] << 8) | 1u;
+                else feed = ring_in[jj & (kRing - 1)];
+            }
+        }
+        for (int s = 0; s < kRound; ++s) {
+            const int t = t0 + s;
+            const uint32_t sin = __builtin_amdgcn_readlane(feed, s);
+            const uint32_t xin = __builtin_amdgcn_update_dpp(sin, xout, kDppWaveShr1, 0xF, 0xF,
+                                                              false);
+            const uint32_t tc = (xin >> 8) & 0xFFu;
+            const uint32_t hp = xin & 1u, hn = (xin >> 1) & 1u;
+            // neq: bit i set iff pattern row i differs from tc
+            uint32_t neq = plane[0] ^ (uint32_t)(-(int32_t)(tc & 1u));
+#pragma unroll
+            for (int b = 1; b < P; ++b)
+                neq = bop3<NwLut::ACC_XOR>(neq, plane[b], (uint32_t)(-(int32_t)((tc >> b) & 1u)));
+            const uint32_t eqm = bop3<NwLut::NOTA_OR_B>(neq, hn, 0u);
+            const uint32_t xv = bop3<NwLut::NOTA_OR_B2>(neq, Mv, 0u);
+            const uint32_t sum = (eqm & Pv) + Pv;
+            const uint32_t xh = bop3<NwLut::XOR_OR>(sum, Pv, eqm);
+            const uint32_t ph = bop3<NwLut::PH>(xh, Pv, Mv);
+            const uint32_t mh = Pv & xh;
+            const uint32_t mcode = bop3<NwLut::MCODE>(neq, xh, Mv);
+            const uint32_t hpo = __builtin_amdgcn_ubfe(ph, bpos, 1);
+            const uint32_t hno = __builtin_amdgcn_ubfe(mh, bpos, 1);
+            xout = (xin & 0xFF00u) | hpo | (hno << 1);
+            const uint32_t Ph = (ph << 1) | hp, Mh = (mh << 1) | hn;
+            const int j = t - shift;
+            // a lane keeps its initial column state until its first column
+            const uint32_t pv_new = bop3<NwLut::PV>(Mh, xv, Ph);
+            const uint32_t mv_new = Ph & xv;
+            Pv = j >= 0 ? pv_new : Pv;
+            Mv = j >= 0 ? mv_new : Mv;
+            if (word_ok && j >= 0 && j < n) {
+                const int64_t rec = ((int64_t)t + sbase) * W + g;
+                ((uint2 *)tbp)[rec] = make_uint2(mcode, Pv);
+                acc += hpo + (hno << 16);
+                if (lane == 63 && w + 1 < nw) ring_out[j & (kRing - 1)] = xout;
+            }
+        }
+    }
+    if (g == W - 1 && a.score) a.score[p] = m + (int)(acc & 0xFFFFu) - (int)(acc >> 16);
+}
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_nw_fill(FillArgs a) {
+    __shared__ uint32_t ring[kMaxFillWaves * kRing];
+    nw_fill_pair<P>(a, blockIdx.x, ring);
+}
+
+// ------------------------------------------------------------ traceback
+struct TbArgs {
+    msa_seqs A, B;
+    const int32_t *ia, *ib;
+    const uint8_t *tb;
+    const int64_t *tb_off;
+    uint8_t *ops;
+    const int64_t *ops_off;
+    int32_t *ops_len;
+    int32_t *st;
+};
+
+// One wavefront per pair.  The walk is uniform across the wavefront; the
+// wavefront caches a tile of records: lane l holds records (s_hi - l,
+// g_hi - q) for q < 4.  Ops are emitted backwards, 64 per store, at the end
+// of the pair's region, then moved to its start.
+__global__ void __launch_bounds__(64) k_nw_traceback(TbArgs a) {
+    const int64_t p = blockIdx.x;
+    const int lane = lane_id();
+    const int32_t x = a.ia[p], y = a.ib[p];
+    if (x < 0 || x >= a.A.n || y < 0 || y >= a.B.n) {
+        if (lane == 0) set_status(a.st, MSA_DS_INDEX);
+        return;
+    }
+    const int64_t m = a.A.offsets[x + 1] - a.A.offsets[x];
+    const int64_t n = a.B.offsets[y + 1] - a.B.offsets[y];
+    if (m < 0 || n < 0 || m > a.A.max_len || n > a.B.max_len) {
+        if (lane == 0) set_status(a.st, MSA_DS_LENGTH);
+        return;
+    }
+    const int64_t cap = a.ops_off[p + 1] - a.ops_off[p];
+    if (cap < m + n || a.tb_off[p + 1] - a.tb_off[p] < tb_bytes((int32_t)m, (int32_t)n)) {
+        if (lane == 0) set_status(a.st, MSA_DS_CAPACITY);
+        return;
+    }
+    uint8_t *out = a.ops + a.ops_off[p];
+    const uint2 *rec = (const uint2 *)(a.tb + a.tb_off[p]);
+    const int64_t W = tb_words((int32_t)m);
+    int64_t i = m, j = n;
+    int64_t emitted = 0;
+    uint32_t obuf = 0;
+    int64_t s_hi = -1000000, g_hi = -1000000;
+    uint2 tile[4];
+    while (i > 0 || j > 0) {
+        uint32_t op;
+        if (i == 0) {
+            op = 2;
+        } else if (j == 0) {
+            op = 1;
+        } else {
+            const int64_t g = (i - 1) >> 5;
+            const int64_t sp = (j - 1) + g;
+            int64_t L = s_hi - sp, q = g_hi - g;
+            if (L < 0 || L >= 64 || q < 0 || q >= 4) {
+                s_hi = sp;
+                g_hi = g;
+                const int64_t sl = s_hi - lane;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int64_t gk = g_hi - k;
+                    // record (sl, gk) exists iff its column j' = sl - gk is in [0, n)
+                    const int64_t jc = sl - gk;
+                    tile[k] = (gk >= 0 && jc >= 0 && jc < n) ? rec[sl * W + gk] : make_uint2(0, 0);
+                }
+                L = 0;
+                q = 0;
+            }
+            uint32_t mw, uw;
+            switch ((int)q) {
+                case 0: mw = __builtin_amdgcn_readlane(tile[0].x, (int)L); uw = __builtin_amdgcn_readlane(tile[0].y, (int)L); break;
+                case 1: mw = __builtin_amdgcn_readlane(tile[1].x, (int)L); uw = __builtin_amdgcn_readlane(tile[1].y, (int)L); break;
+                case 2: mw = __builtin_amdgcn_readlane(tile[2].x, (int)L); uw = __builtin_amdgcn_readlane(tile[2].y, (int)L); break;
+                default: mw = __builtin_amdgcn_readlane(tile[3].x, (int)L); uw = __builtin_amdgcn_readlane(tile[3].y, (int)L); break;
+            }
+            const uint32_t bit = (uint32_t)((i - 1) & 31);
+            op = ((mw >> bit) & 1u) ? 0u : (((uw >> bit) & 1u) ? 1u : 2u);
+        }
+        if (op == 0) { --i; --j; }
+        else if (op == 1) { --i; }
+        else { --j; }
+        const int slot = (int)(emitted & 63);
+        if (lane == slot) obuf = op;
+        ++emitted;
+        if ((emitted & 63) == 0) {
+            out[cap - emitted + (63 - lane)] = (uint8_t)obuf;
+        }
+    }
+    const int rem = (int)(emitted & 63);
+    if (rem && lane < rem) out[cap - emitted + (rem - 1 - lane)] = (uint8_t)obuf;
+    // the alignment now sits in out[cap - emitted .. cap); move it to the front
+    // Chunks move from low to high addresses and the destination lies below
+    // the source, so no chunk overwrites bytes that are still to be read.
+    const int64_t src0 = cap - emitted;
+    if (src0 > 0) {
+        __threadfence();
+        for (int64_t c = 0; c < emitted; c += 64) {
+            const int64_t k = c + lane;
+            uint8_t v = 0;
+            if (k < emitted) v = out[src0 + k];
+            if (k < emitted) out[k] = v;
+        }
+    }
+    if (lane == 0) a.ops_len[p] = (int32_t)emitted;
+}
+
+static int bits_for(int sigma) {
+    int b = 1;
+    while ((1 << b) < sigma) ++b;
+    return b;
+}
+
+struct NwPlan {
+    int64_t strideA, strideB;
+};
+
+template <class Alloc>
+static void nw_layout(Alloc &al, const msa_seqs *A, const msa_seqs *B, const NwPlan &pl) {
+    al.template take<uint8_t>((size_t)A->n * pl.strideA);
+    al.template take<int32_t>((size_t)A->n + 1);
+    al.template take<uint8_t>((size_t)B->n * pl.strideB);
+    al.template take<int32_t>((size_t)B->n + 1);
+}
+
+static NwPlan plan_nw(const msa_seqs *A, const msa_seqs *B) {
+    NwPlan p;
+    // staged pattern rows are read 32 symbols past each word start
+    p.strideA = staged_stride(A->max_len) + 32;
+    p.strideB = staged_stride(B->max_len);
+    return p;
+}
+
+}  // namespace msadp
+
+using namespace msadp;
+
+extern "C" {
+
+size_t nw_tb_bytes(int32_t m, int32_t n) { return (size_t)tb_bytes(m, n); }
+
+size_t nw_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
+    if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
+    Sizer sz;
+    nw_layout(sz, A, B, plan_nw(A, B));
+    return sz.total();
+}
+
+int nw_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+             int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets, void *ws,
+             size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(A)) || (rc = check_seqs(B))) return rc;
+    if (n_pairs < 0) return MSA_EINVAL;
+    if (A->sigma != B->sigma) return MSA_EINVAL;
+    if (n_pairs == 0) return MSA_OK;
+    if (ia == nullptr || ib == nullptr || tb_offsets == nullptr || ws == nullptr) return MSA_EINVAL;
+    if (tb == nullptr && (A->max_len > 0 && B->max_len > 0)) return MSA_EINVAL;
+    if (n_pairs > 0x7fffffffLL) return MSA_ERANGE;
+    const int64_t W = tb_words(A->max_len);
+    if ((W + 63) / 64 > kMaxFillWaves) return MSA_ERANGE;   // patterns up to 32768 rows
+    const NwPlan pl = plan_nw(A, B);
+    Sizer sz;
+    nw_layout(sz, A, B, pl);
+    if (ws_bytes < sz.total()) return MSA_ENOSPC;
+    Carve cv(ws, ws_bytes);
+    Staged SA{cv.take<uint8_t>((size_t)A->n * pl.strideA), cv.take<int32_t>((size_t)A->n + 1),
+              pl.strideA, A->n};
+    Staged SB{cv.take<uint8_t>((size_t)B->n * pl.strideB), cv.take<int32_t>((size_t)B->n + 1),
+              pl.strideB, B->n};
+    if ((rc = stage_set(A, nullptr, SA, d_status, s))) return rc;
+    if ((rc = stage_set(B, nullptr, SB, d_status, s))) return rc;
+    const int waves = (int)std::max<int64_t>(1, (W + 63) / 64);
+    FillArgs fa{SA, SB, ia, ib, score, tb, tb_offsets, d_status, bits_for(A->sigma)};
+    dim3 grid((unsigned)n_pairs), block(64 * waves);
+    switch (fa.planes) {
+        case 1: hipLaunchKernelGGL(k_nw_fill<1>, grid, block, 0, s, fa); break;
+        case 2: hipLaunchKernelGGL(k_nw_fill<2>, grid, block, 0, s, fa); break;
+        case 3: hipLaunchKernelGGL(k_nw_fill<3>, grid, block, 0, s, fa); break;
+        case 4: hipLaunchKernelGGL(k_nw_fill<4>, grid, block, 0, s, fa); break;
+        default: hipLaunchKernelGGL(k_nw_fill<5>, grid, block, 0, s, fa); break;
+    }
+    return launch_status();
+}
+
+int nw_traceback(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                 int64_t n_pairs, const uint8_t *tb, const int64_t *tb_offsets, uint8_t *ops,
+                 const int64_t *ops_offsets, int32_t *ops_len, int32_t *d_status, hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(A)) || (rc = check_seqs(B))) return rc;
+    if (n_pairs < 0) return MSA_EINVAL;
+    if (n_pairs == 0) return MSA_OK;
+    if (ia == nullptr || ib == nullptr || tb_offsets == nullptr || ops == nullptr ||
+        ops_offsets == nullptr || ops_len == nullptr)
+        return MSA_EINVAL;
+    if (n_pairs > 0x7fffffffLL) return MSA_ERANGE;
+    TbArgs ta{*A, *B, ia, ib, tb, tb_offsets, ops, ops_offsets, ops_len, d_status};
+    hipLaunchKernelGGL(k_nw_traceback, dim3((unsigned)n_pairs), dim3(64), 0, s, ta);
+    return launch_status();
+}
+
+}  // extern "C"

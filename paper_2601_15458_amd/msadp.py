@@ -1,0 +1,261 @@
+"""Python face of libmsadp.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module allocates the
+caller-owned device buffers (torch tensors), fills the C structs and checks
+return codes.  There is no fallback: if the library or a GPU is missing the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsadp.so")
+
+MSA_OK, MSA_EINVAL, MSA_ERANGE, MSA_ENOSPC, MSA_EDEVICE = 0, -1, -2, -3, -4
+DS_NAMES = {0: "ok", 1: "symbol code >= sigma", 2: "sequence index out of range",
+            3: "length out of range", 4: "output capacity too small"}
+
+# Exported entry points and their C signatures (mirrors include/msadp.h).
+P = C.c_void_p
+
+
+class MsaSeqs(C.Structure):
+    _fields_ = [("codes", P), ("offsets", P), ("n", C.c_int32), ("sigma", C.c_int32),
+                ("max_len", C.c_int32), ("packed_2bit", C.c_int32)]
+
+
+SP = C.POINTER(MsaSeqs)
+SIGNATURES = {
+    "msa_strerror": (C.c_char_p, [C.c_int]),
+    "msa_version": (C.c_int, []),
+    "lev_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
+    "lev_batch": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, C.c_size_t, P, P]),
+    "lev_allpairs_workspace_bytes": (C.c_size_t, [SP]),
+    "lev_allpairs": (C.c_int, [SP, P, P, C.c_size_t, P, P]),
+    "nw_tb_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "nw_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
+    "nw_batch": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, C.c_size_t, P, P]),
+    "nw_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmsadp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MsaError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lib().msa_strerror(code).decode()} ({code})")
+
+
+def _check(rc: int, where: str):
+    if rc != MSA_OK:
+        raise MsaError(rc, where)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _device():
+    if not torch.cuda.is_available():
+        raise RuntimeError("msadp needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+@dataclass
+class Seqs:
+    """A sequence set resident on the GPU in CSR form (see include/msadp.h)."""
+    codes: torch.Tensor       # uint8 on the device
+    offsets: torch.Tensor     # int64 [n+1] on the device
+    lengths: np.ndarray       # host copy of the n lengths (for output sizing)
+    sigma: int
+    max_len: int
+    packed_2bit: bool = False
+
+    @property
+    def n(self) -> int:
+        return len(self.lengths)
+
+    def struct(self) -> MsaSeqs:
+        return MsaSeqs(self.codes.data_ptr() if self.codes.numel() else None,
+                       self.offsets.data_ptr(), self.n, self.sigma, self.max_len,
+                       int(self.packed_2bit))
+
+
+def to_device(codes, offsets, sigma, max_len=None, packed_2bit=False, device=None) -> Seqs:
+    """Copy a host CSR set to the GPU.  With packed_2bit, `codes` must already
+    hold four 2-bit symbols per byte (symbol p in bits 2*(p%4) of byte p//4)."""
+    dev = device or _device()
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    lengths = np.diff(offsets)
+    if max_len is None:
+        max_len = int(lengths.max()) if len(lengths) else 0
+    c = torch.from_numpy(np.ascontiguousarray(codes, dtype=np.uint8)).to(dev)
+    if c.numel() == 0:
+        c = torch.zeros(16, dtype=torch.uint8, device=dev)
+    o = torch.from_numpy(offsets).to(dev)
+    return Seqs(c, o, lengths, int(sigma), int(max_len), bool(packed_2bit))
+
+
+def pack_2bit_host(codes) -> np.ndarray:
+    """Host-side packing for building test inputs (four symbols per byte)."""
+    c = np.asarray(codes, dtype=np.uint8)
+    pad = (-len(c)) % 4
+    c = np.concatenate([c, np.zeros(pad, np.uint8)]).reshape(-1, 4)
+    return (c[:, 0] | (c[:, 1] << 2) | (c[:, 2] << 4) | (c[:, 3] << 6)).astype(np.uint8)
+
+
+def _i32(x, dev):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=dev, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32), device=dev)
+
+
+class Status:
+    """Device status word (first device-detected error wins)."""
+
+    def __init__(self, dev):
+        self.t = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def check(self, where):
+        v = int(self.t.item())
+        if v != 0:
+            raise RuntimeError(f"{where}: device reported {DS_NAMES.get(v, v)}")
+
+
+def lev_batch(A: Seqs, B: Seqs, ia, ib, out=None, stream=None, check=True):
+    """uint16 distances lev(A[ia[p]], B[ib[p]])."""
+    dev = A.codes.device
+    ia, ib = _i32(ia, dev), _i32(ib, dev)
+    n_pairs = ia.numel()
+    if out is None:
+        out = torch.empty(max(n_pairs, 1), dtype=torch.uint16, device=dev)
+    sa, sb = A.struct(), B.struct()
+    wsb = lib().lev_workspace_bytes(C.byref(sa), C.byref(sb), n_pairs)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = Status(dev)
+    rc = lib().lev_batch(C.byref(sa), C.byref(sb), _ptr(ia), _ptr(ib), n_pairs, _ptr(out),
+                         _ptr(ws), wsb, _ptr(st.t), _stream(stream))
+    _check(rc, "lev_batch")
+    if check:
+        st.check("lev_batch")
+    return out[:n_pairs]
+
+
+class AllPairs:
+    """Reusable all-pairs launcher: workspace sized once, output preallocated."""
+
+    def __init__(self, A: Seqs):
+        self.A = A
+        dev = A.codes.device
+        self.sa = A.struct()
+        n = A.n
+        self.out = torch.empty(max(n * (n - 1) // 2, 1), dtype=torch.uint16, device=dev)
+        self.wsb = lib().lev_allpairs_workspace_bytes(C.byref(self.sa))
+        self.ws = torch.empty(max(self.wsb, 1), dtype=torch.uint8, device=dev)
+        self.st = Status(dev)
+
+    def __call__(self, stream=None):
+        rc = lib().lev_allpairs(C.byref(self.sa), _ptr(self.out), _ptr(self.ws), self.wsb,
+                                _ptr(self.st.t), _stream(stream))
+        _check(rc, "lev_allpairs")
+        return self.out
+
+
+def lev_allpairs(A: Seqs, stream=None):
+    """Condensed uint16 distances of every pair i < j of A."""
+    ap = AllPairs(A)
+    out = ap(stream)
+    ap.st.check("lev_allpairs")
+    n = A.n
+    return out[: n * (n - 1) // 2]
+
+
+class NwResult:
+    def __init__(self, score, tb, tb_offsets, n_pairs):
+        self.score, self.tb, self.tb_offsets, self.n_pairs = score, tb, tb_offsets, n_pairs
+
+
+def nw_batch(A: Seqs, B: Seqs, ia, ib, stream=None, check=True) -> NwResult:
+    """Fill: int32 scores and the traceback codes of every pair."""
+    dev = A.codes.device
+    ia_h = np.ascontiguousarray(ia.cpu().numpy() if isinstance(ia, torch.Tensor) else ia,
+                                dtype=np.int32)
+    ib_h = np.ascontiguousarray(ib.cpu().numpy() if isinstance(ib, torch.Tensor) else ib,
+                                dtype=np.int32)
+    n_pairs = len(ia_h)
+    m = A.lengths[ia_h] if n_pairs else np.zeros(0, np.int64)
+    n = B.lengths[ib_h] if n_pairs else np.zeros(0, np.int64)
+    sizes = np.array([lib().nw_tb_bytes(int(a), int(b)) for a, b in zip(m, n)], dtype=np.int64)
+    sizes = (sizes + 255) // 256 * 256
+    tb_off = np.zeros(n_pairs + 1, dtype=np.int64)
+    np.cumsum(sizes, out=tb_off[1:])
+    tb = torch.empty(max(int(tb_off[-1]), 256), dtype=torch.uint8, device=dev)
+    tb_off_d = torch.from_numpy(tb_off).to(dev)
+    score = torch.empty(max(n_pairs, 1), dtype=torch.int32, device=dev)
+    ia_d, ib_d = _i32(ia_h, dev), _i32(ib_h, dev)
+    sa, sb = A.struct(), B.struct()
+    wsb = lib().nw_workspace_bytes(C.byref(sa), C.byref(sb), n_pairs)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = Status(dev)
+    rc = lib().nw_batch(C.byref(sa), C.byref(sb), _ptr(ia_d), _ptr(ib_d), n_pairs, _ptr(score),
+                        _ptr(tb), _ptr(tb_off_d), _ptr(ws), wsb, _ptr(st.t), _stream(stream))
+    _check(rc, "nw_batch")
+    if check:
+        st.check("nw_batch")
+    r = NwResult(score[:n_pairs], tb, tb_off_d, n_pairs)
+    r.ia, r.ib, r.m, r.n = ia_d, ib_d, m, n
+    return r
+
+
+def nw_traceback(A: Seqs, B: Seqs, r: NwResult, stream=None, check=True):
+    """Alignments (list of uint8 op arrays, 0=M 1=D 2=I) for a nw_batch result."""
+    dev = A.codes.device
+    caps = (r.m + r.n).astype(np.int64)
+    ops_off = np.zeros(r.n_pairs + 1, dtype=np.int64)
+    np.cumsum(caps, out=ops_off[1:])
+    ops = torch.empty(max(int(ops_off[-1]), 1), dtype=torch.uint8, device=dev)
+    ops_off_d = torch.from_numpy(ops_off).to(dev)
+    ops_len = torch.empty(max(r.n_pairs, 1), dtype=torch.int32, device=dev)
+    sa, sb = A.struct(), B.struct()
+    st = Status(dev)
+    rc = lib().nw_traceback(C.byref(sa), C.byref(sb), _ptr(r.ia), _ptr(r.ib), r.n_pairs,
+                            _ptr(r.tb), _ptr(r.tb_offsets), _ptr(ops), _ptr(ops_off_d),
+                            _ptr(ops_len), _ptr(st.t), _stream(stream))
+    _check(rc, "nw_traceback")
+    if check:
+        st.check("nw_traceback")
+    return ops, ops_off, ops_len[: r.n_pairs]
+
+
+def split_ops(ops, ops_off, ops_len):
+    """Host list of per-pair op arrays."""
+    o = ops.cpu().numpy()
+    L = ops_len.cpu().numpy()
+    return [o[ops_off[p]: ops_off[p] + L[p]].copy() for p in range(len(L))]

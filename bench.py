@@ -21,10 +21,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("GCUPS & pairs/s (batched Levenshtein+NW, bit-exact); "
           "surrogate vs exact tree-build speedup")
-# Roofline peak of the bit-parallel Levenshtein kernel: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz = 39.3 T 32-bit VALU lane-ops/s, at 32 lane-ops per
-# 64-cell word step (two 32-bit ops per 64-bit logical op) = 78.6 T cells/s.
-LEV_PEAK_TCUPS = 256 * 4 * 16 * 2.4e9 * 64 / 32 / 1e12
+# Roofline peak of the bit-parallel Levenshtein kernel.  Integer VALU: 256 CUs
+# x 4 SIMDs x 16 lanes x 2 instructions issued per cycle (gfx950 dual-issues
+# VALU; the same rate gives the 157.3 TFLOP/s fp32 vector figure) x 2.4 GHz
+# = 78.6 T 32-bit lane-ops/s.  The reference cost of the recurrence is 32
+# lane-ops per 64-cell word step (16 64-bit logical ops, two 32-bit halves
+# each), so the peak is 78.6e12 * 64 / 32 = 157.3 T cells/s.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2 * 2.4e9
+K_REF = 32
+LEV_PEAK_TCUPS = VALU_PEAK_LANE_OPS * 64 / K_REF / 1e12
 HBM_PEAK_GBS = 8000.0
 
 
@@ -36,7 +41,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--nw", action="store_true", help="also time the 512-pair NW batch")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of exactly 1 GiB, for scaling the HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) of the other kernels."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n}), flush=True)
 
 
 def cpu_baseline(d, seconds):
@@ -67,6 +87,9 @@ def cpu_baseline(d, seconds):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
               "of the pair triangle is described in DESIGN.md but not built", file=sys.stderr)
@@ -140,26 +163,28 @@ def main():
 
 
 def bench_nw(msadp, synth, torch, args):
-    import ctypes as C
+    """512 long DNA pairs: NW fill (traceback codes to HBM) then traceback."""
     d = synth.nw_long()
     P = d["n_pairs"]
     A = msadp.to_device(d["a_codes"], d["a_offsets"], 4)
     B = msadp.to_device(d["b_codes"], d["b_offsets"], 4)
     ia = np.arange(P)
-    r = msadp.nw_batch(A, B, ia, ia)
-    msadp.nw_traceback(A, B, r)
+    nb = msadp.NwBatch(A, B, ia, ia)
+    stream = torch.cuda.current_stream()
+    nb.fill(stream)
+    nb.traceback(stream)
     torch.cuda.synchronize()
+    nb.st.check("nw")
     la = np.diff(d["a_offsets"])
     lb = np.diff(d["b_offsets"])
     cells = int((la * lb).sum())
-    stream = torch.cuda.current_stream()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     fill, tb = [], []
     for _ in range(max(args.steps, 3)):
         e[0].record(stream)
-        r = msadp.nw_batch(A, B, ia, ia, check=False)
+        nb.fill(stream)
         e[1].record(stream)
-        msadp.nw_traceback(A, B, r, check=False)
+        nb.traceback(stream)
         e[2].record(stream)
         torch.cuda.synchronize()
         fill.append(e[0].elapsed_time(e[1]))
@@ -174,7 +199,8 @@ def bench_nw(msadp, synth, torch, args):
             "gcups_fill_plus_traceback": round(cells / (f + t) / 1e6, 1),
             "pairs_per_s": round(P / ((f + t) * 1e-3), 1),
             "tb_bytes": tb_bytes,
-            "fill_hbm_gbs": round(tb_bytes / f / 1e6, 1)}
+            "fill_hbm_gbs": round(tb_bytes / f / 1e6, 1),
+            "fill_hbm_frac": round(tb_bytes / f / 1e6 / HBM_PEAK_GBS, 4)}
 
 
 if __name__ == "__main__":

@@ -130,6 +130,37 @@ int nw_traceback(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const 
                  uint8_t *ops, const int64_t *ops_offsets, int32_t *ops_len,
                  int32_t *d_status, hipStream_t s);
 
+
+/* ------------------------------------------------------------------ */
+/* Guide tree by Alg. 1 (Partition, Sec. 2.1): recursive split of the set
+ * until every leaf holds one sequence.  Per cluster C: c = the member with
+ * the least sum of distances to all members (the full geometric median);
+ * l = argmax f(c, x); r = argmax f(l, x); L = {x : f(l,x) <= f(r,x)},
+ * R = {x : f(r,x) < f(l,x)}.  Readings where the paper is silent: every
+ * argmin/argmax keeps the lowest input index among equals; a cluster whose
+ * radius max f(c, x) is 0 (copies of one sequence) stays a leaf.
+ * Node ids are breadth-first (children of v are created when v splits, L
+ * before R).  Node arrays (device, capacity 2n - 1): parent, left, right
+ * (-1 if none), center, lpole, rpole (-1 for leaves), depth, mstart and
+ * mcount (the node's members are perm[mstart .. mstart + mcount); a node's
+ * range is its L child's range followed by its R child's).  perm (device,
+ * n) lists input indices. */
+typedef struct msa_tree {
+    int32_t *parent, *left, *right, *center, *lpole, *rpole, *depth;
+    int64_t *mstart, *mcount;
+    int32_t *perm;
+} msa_tree;
+
+size_t tree_workspace_bytes(const msa_seqs *S);
+
+/* Builds the tree of S into T; *n_nodes (host) receives the node count.
+ * Levels run on the device; the stream is synchronized once per level to
+ * read the number of splits.  use_graph != 0 records one level's launches
+ * into a HIP graph and replays it per level (needs a non-default stream).
+ * S->n must be below 2^24. */
+int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
+               void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

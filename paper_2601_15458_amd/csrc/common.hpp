@@ -84,6 +84,7 @@ struct Sizer {
 };
 
 int check_seqs(const msa_seqs *S);
+int device_cus();
 int launch_status();
 
 // staging (stage.hip)

@@ -1,0 +1,216 @@
+// Bit-parallel Levenshtein core shared by the all-pairs, pair-list and
+// tree-level kernels (see lev.hip for the method and the layout).
+#pragma once
+
+#include "common.hpp"
+
+namespace msadp {
+
+constexpr int kMaxWords = 32;  // 64-bit words per pass (2048 rows)
+constexpr int kSym = 32;       // symbol stride of the Peq table
+
+typedef const __attribute__((address_space(3))) uint64_t lds_u64;
+
+struct Lut {
+    static constexpr uint8_t XOR_OR = MSADP_LUT((A ^ B) | C);     // Xh
+    static constexpr uint8_t PH = MSADP_LUT(C | ~(A | B));        // Ph = Mv | ~(Xh | Pv)
+    static constexpr uint8_t PV = MSADP_LUT(A | ~(B | C));        // Pv = Mh | ~(Xv | Ph)
+};
+
+// Build this wavefront's Peq table for pattern words [w0, w0 + nw):
+// peq[k * kSym + c] has bit i set iff pattern[(w0 + k) * 64 + i] == c.
+__device__ __forceinline__ void build_peq(uint64_t *peq, const uint8_t *pat, int m, int w0,
+                                          int nw, int sigma) {
+    const int lane = lane_id();
+    for (int k = 0; k < nw; ++k) {
+        const int i = (w0 + k) * 64 + lane;
+        const int c = i < m ? (int)pat[i] : 255;
+        uint64_t mine = 0;
+        for (int s = 0; s < sigma; ++s) {
+            const uint64_t bal = __ballot(c == s);
+            if (lane == s) mine = bal;
+        }
+        if (lane < kSym) peq[k * kSym + lane] = mine;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One pass of W words over the lane's text.
+//   CIN: the horizontal deltas entering word 0 come from `hbuf` (2 bits per
+//        column: bit 2q = +1, bit 2q+1 = -1), else they are +1 (top row).
+//   cout: write the deltas leaving the last word to `hbuf` instead of adding
+//        them to the score.  `b` is the bit of the last row in word W-1.
+template <int W, bool CIN>
+__device__ __forceinline__ int lev_pass(lds_u64 *peq, const uint8_t *text, int n, int nmax,
+                                        int b, bool cout, uint32_t *hbuf) {
+    uint32_t pl[W], ph[W], ml[W], mh[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        pl[k] = ph[k] = ~0u;
+        ml[k] = mh[k] = 0u;
+    }
+    int score = 0;
+    const uint4 *tp = (const uint4 *)text;
+    uint4 cur = tp[0];
+    for (int j0 = 0; j0 < nmax; j0 += 16) {
+        uint4 nxt = cur;
+        if (j0 + 16 < nmax) nxt = tp[(j0 >> 4) + 1];
+        uint32_t cw = CIN ? hbuf[(j0 >> 4) * kWave] : 0x55555555u;
+        uint32_t ow = 0;
+        uint32_t c0 = cur.x, c1 = cur.y, c2 = cur.z, c3 = cur.w;
+        const int steps = min(16, nmax - j0);
+        for (int jj = 0; jj < steps; ++jj) {
+            const uint32_t t = c0 & 0xFFu;
+            c0 = __builtin_amdgcn_alignbyte(c1, c0, 1);
+            c1 = __builtin_amdgcn_alignbyte(c2, c1, 1);
+            c2 = __builtin_amdgcn_alignbyte(c3, c2, 1);
+            c3 >>= 8;
+            // carry into word 0, kept as "bit 31 of the previous word's hi half"
+            uint32_t cph = cw << 31;
+            uint32_t cmh = (cw & 2u) << 30;
+            cw >>= 2;
+            lds_u64 *pe = peq + t;   // this lane's symbol row of the table
+            uint32_t dp = 0, dn = 0;
+            // Eq of word k+2 is requested while word k computes; the
+            // scheduling barriers keep each word's temporaries short-lived.
+            uint64_t eq0 = pe[0], eq1 = W > 1 ? pe[kSym] : 0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const uint64_t e = (k & 1) ? eq1 : eq0;
+                if (k + 2 < W) {
+                    if (k & 1) eq1 = pe[(k + 2) * kSym];
+                    else eq0 = pe[(k + 2) * kSym];
+                }
+                const uint32_t el = (uint32_t)e, eh = (uint32_t)(e >> 32);
+                const uint32_t elm = el | (cmh >> 31);
+                const uint32_t xvl = el | ml[k], xvh = eh | mh[k];
+                // 64-bit (Eq' & Pv) + Pv as an add with carry on 32-bit halves
+                unsigned int cy, cy2;
+                const uint32_t sl = __builtin_addc(elm & pl[k], pl[k], 0u, &cy);
+                const uint32_t sh = __builtin_addc(eh & ph[k], ph[k], cy, &cy2);
+                const uint32_t xhl = bop3<Lut::XOR_OR>(sl, pl[k], elm);
+                const uint32_t xhh = bop3<Lut::XOR_OR>(sh, ph[k], eh);
+                const uint32_t phl = bop3<Lut::PH>(xhl, pl[k], ml[k]);
+                const uint32_t phh = bop3<Lut::PH>(xhh, ph[k], mh[k]);
+                const uint32_t mhl = pl[k] & xhl, mhh = ph[k] & xhh;
+                if (k == W - 1) {
+                    const uint64_t P = ((uint64_t)phh << 32) | phl;
+                    const uint64_t M = ((uint64_t)mhh << 32) | mhl;
+                    dp = (uint32_t)(P >> b) & 1u;
+                    dn = (uint32_t)(M >> b) & 1u;
+                }
+                const uint32_t Phl = shl1_carry(phl, cph), Phh = shl1_carry(phh, phl);
+                const uint32_t Mhl = shl1_carry(mhl, cmh), Mhh = shl1_carry(mhh, mhl);
+                cph = phh;
+                cmh = mhh;
+                pl[k] = bop3<Lut::PV>(Mhl, xvl, Phl);
+                ph[k] = bop3<Lut::PV>(Mhh, xvh, Phh);
+                ml[k] = Phl & xvl;
+                mh[k] = Phh & xvh;
+                // Tie the carries for word k+1 to word k's finished state so
+                // the compiler cannot run the carry chain ahead of the state
+                // updates (which would keep ~6 extra VGPRs per word alive).
+                asm volatile("" : "+v"(cph), "+v"(cmh), "+v"(pl[k]), "+v"(ph[k]), "+v"(ml[k]),
+                             "+v"(mh[k]));
+            }
+            if (cout) {
+                ow |= (dp | (dn << 1)) << (2 * jj);
+            } else {
+                const int d = (int)dp - (int)dn;
+                score += (j0 + jj < n) ? d : 0;
+            }
+        }
+        if (cout) hbuf[(j0 >> 4) * kWave] = ow;
+        cur = nxt;
+    }
+    return score;
+}
+
+template <int WMAX, int W = 1>
+__device__ __forceinline__ int dispatch_first(int w, lds_u64 *peq, const uint8_t *text, int n,
+                                              int nmax, int b, bool cout, uint32_t *hbuf) {
+    if constexpr (W > WMAX) {
+        return 0;
+    } else {
+        if (w == W) return lev_pass<W, false>(peq, text, n, nmax, b, cout, hbuf);
+        return dispatch_first<WMAX, W + 1>(w, peq, text, n, nmax, b, cout, hbuf);
+    }
+}
+
+// Distance between this wavefront's pattern (pat, m) and each lane's text
+// (text, n; lanes with valid == false still take part but their result is
+// ignored).  `hbuf` is this lane's carry buffer (used when m > 2048).
+template <int WMAX>
+__device__ __forceinline__ int lev_item(uint64_t *peq, const uint8_t *pat, int m, int sigma,
+                                        const uint8_t *text, int n, bool valid, uint32_t *hbuf) {
+    const int nmax = (int)uniform((uint32_t)wave_max(valid ? n : 0));
+    if (m == 0) return n;
+    if (nmax == 0) return m;
+    const int words = (m + 63) >> 6;
+    const int passes = (words + kMaxWords - 1) / kMaxWords;
+    const int w_first = words - (passes - 1) * kMaxWords;
+    const int b_last = (m - 1) & 63;
+    build_peq(peq, pat, m, 0, w_first, sigma);
+    lds_u64 *tbl = (lds_u64 *)peq;
+    int s = dispatch_first<WMAX>(w_first, tbl, text, n, nmax, passes == 1 ? b_last : 63,
+                                 passes > 1, hbuf);
+    if constexpr (WMAX == kMaxWords)
+    for (int p = 1; p < passes; ++p) {
+        const int w0 = w_first + (p - 1) * kMaxWords;
+        build_peq(peq, pat, m, w0, kMaxWords, sigma);
+        const bool last = (p == passes - 1);
+        s = lev_pass<kMaxWords, true>(tbl, text, n, nmax, last ? b_last : 63, !last, hbuf);
+    }
+    return m + s;
+}
+
+// Next work item of a persistent kernel.  Every lane executes the atomic
+// (lane 0 adds 1, the others 0) so the loop holds no lane-conditional
+// branch; the compiler may otherwise restructure a lane-0 branch around the
+// loop back edge and let the other lanes re-enter without lane 0.
+__device__ __forceinline__ uint32_t next_item(uint32_t *counter) {
+    const uint32_t lane0 = lane_id() == 0 ? 1u : 0u;
+    const uint32_t it = atomicAdd(counter, lane0);
+    return uniform(__builtin_amdgcn_readlane(it, 0));
+}
+
+__host__ __device__ inline int64_t items_upto(int64_t U) {
+    // sum_{u=1..U} ceil(u/64): work items of a triangle whose rows hold 1..U texts
+    const int64_t Q = U >> 6, s = U & 63;
+    return 32 * Q * (Q + 1) + s * (Q + 1);
+}
+
+// Smallest u >= 1 with items_upto(u) > g (u in [1, hi]).
+__device__ __forceinline__ int64_t triangle_row(int64_t g, int64_t hi) {
+    int64_t lo = 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (items_upto(mid) > g) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Pattern words per pass that a kernel variant is compiled for; a variant
+// holds 4 VGPRs of state per word, so small patterns get more wavefronts.
+inline int wmax_class(int32_t pat_max) {
+    const int w = (pat_max + 63) / 64;
+    if (w <= 4) return 4;
+    if (w <= 8) return 8;
+    if (w <= 16) return 16;
+    if (w <= 24) return 24;
+    return kMaxWords;
+}
+
+// Workgroups of one wavefront that fit on the device at once for `kernel`.
+template <class K>
+inline int persistent_grid(K kernel) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, 64, 0) != hipSuccess ||
+        blocks < 1)
+        blocks = 1;
+    return device_cus() * blocks;
+}
+
+}  // namespace msadp

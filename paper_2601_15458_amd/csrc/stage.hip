@@ -15,6 +15,18 @@ int launch_status() {
     return e == hipSuccess ? MSA_OK : MSA_EDEVICE;
 }
 
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 int check_seqs(const msa_seqs *S) {
     if (S == nullptr || S->offsets == nullptr) return MSA_EINVAL;
     if (S->n < 0) return MSA_EINVAL;

@@ -1,0 +1,550 @@
+// Alg. 1 (Partition, Sec. 2.1) on the GPU, one tree level at a time.
+//
+// All clusters of one depth are split together.  Per level:
+//   1. medoid: row sums S[x] = sum_y f(x, y) over every pair of every
+//      cluster (the triangle of each cluster, each distance added to both
+//      ends), then c = the member with the least sum;
+//   2. l = argmax_x f(c, x); 3. r = argmax_x f(l, x) (f(l, .) kept);
+//   4. f(r, .); 5. stable split: L = {x : f(l,x) <= f(r,x)}, R = the rest;
+//   6. children numbered breadth-first (L before R) after the level.
+// Ties: the least sum / the largest distance with the lowest input index
+// wins, encoded in 64-bit keys so that one min/max decides both.  A cluster
+// whose radius max_x f(c, x) is 0 (copies of one sequence) stays a leaf.
+//
+// Sequences are staged once in length order; a cluster's members stay in
+// that order through the stable splits, so the 64 texts of a wavefront have
+// nearly equal lengths.  The distance passes are the persistent bit-parallel
+// kernels of lev_core.hpp with per-level work lists derived on the device.
+// Every size a level needs lives in device memory, so the level's ~20
+// launches can be captured once into a HIP graph and replayed per level;
+// the host reads one 4-byte split count per level to know when to stop.
+#include "lev_core.hpp"
+
+namespace msadp {
+
+enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3 };
+
+struct TreeArgs {
+    Staged S;
+    const int32_t *order;    // rank -> input index
+    const int32_t *rank_of;  // input index -> rank
+    int32_t *perm;           // position -> rank (current level)
+    int32_t *perm_next;
+    int32_t *parent, *left, *right, *center, *lpole, *rpole, *depth;
+    int64_t *mstart, *mcount;
+    int32_t *desc;           // [0] level start, [1] level end, [2] splits of last level
+    int64_t *cnt;            // per cluster item count of the next pass (nq + 1)
+    int64_t *items;          // exclusive prefix of cnt (read by the pass)
+    uint64_t *key;           // per cluster min/max key
+    int32_t *pat;            // per cluster pattern rank of the current pass
+    int32_t *nleft;          // per cluster |L| (or -1 when it stays a leaf)
+    int64_t *split;          // per cluster 1 if split -> exclusive prefix
+    uint64_t *rowsum;        // per position
+    int32_t *dl, *dr;        // per position f(l, x), f(r, x)
+    uint32_t *counter;
+    uint32_t *hbuf;
+    int64_t hstride;
+    int32_t *st;             // device status
+    int32_t sigma;
+    int32_t n;
+};
+
+constexpr int kClusterGrid = 2048;
+
+__device__ __forceinline__ int32_t level_clusters(const int32_t *desc) { return desc[1] - desc[0]; }
+
+// largest q in [0, nq) with prefix[q] <= g
+__device__ __forceinline__ int32_t find_cluster(const int64_t *prefix, int32_t nq, int64_t g) {
+    int32_t lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint64_t w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Level start: reset per-node fields, member sums and the medoid work list.
+__global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int32_t v = lvl + q;
+        const int64_t ms = a.mstart[v], k = a.mcount[v];
+        if (threadIdx.x == 0) {
+            a.left[v] = a.right[v] = a.lpole[v] = a.rpole[v] = -1;
+            a.key[q] = ~0ull;
+            a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
+            a.nleft[q] = -1;
+            a.split[q] = 0;
+        }
+        for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.rowsum[ms + i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.cnt[nq] = 0;
+        a.split[nq] = 0;
+    }
+}
+
+// out[i] = sum of in[0 .. i) for i <= nq (one workgroup; in == out allowed).
+__global__ void __launch_bounds__(1024) k_scan_level(const int64_t *in, int64_t *out,
+                                                     const int32_t *desc) {
+    __shared__ int64_t part[1024];
+    const int64_t n = (int64_t)level_clusters(desc) + 1;
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t lo = t * chunk, hi = min(n, lo + chunk);
+    int64_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += in[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+}
+
+__global__ void k_zero_counter(uint32_t *c) { *c = 0; }
+
+// The distance passes of a level.
+template <int WMAX, int MODE>
+__global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
+    __shared__ uint64_t peq[kMaxWords * kSym];
+    const int lane = lane_id();
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    const int64_t total = a.items[nq];
+    // A level never holds more work than the triangle of all n sequences.
+    if (nq < 1 || nq > a.n || total < 0 || total > items_upto(a.n)) {
+        if (blockIdx.x == 0 && lane == 0) set_status(a.st, MSA_DS_CAPACITY);
+        return;
+    }
+    uint32_t *hb = a.hbuf ? a.hbuf + (int64_t)blockIdx.x * a.hstride * kWave + lane : nullptr;
+    for (;;) {
+        const uint32_t it = next_item(a.counter);
+        if ((int64_t)it >= total) break;
+        const int32_t q = find_cluster(a.items, nq, it);
+        const int64_t local = (int64_t)it - a.items[q];
+        const int32_t v = lvl + q;
+        const int64_t ms = a.mstart[v], k = a.mcount[v];
+        int64_t tpos, prow_pos = -1;
+        int32_t prow;
+        if (MODE == kMedoid) {
+            const int64_t u = triangle_row(local, k - 1);
+            const int64_t p = k - 1 - u;
+            const int64_t blk = local - items_upto(u - 1);
+            prow_pos = ms + p;
+            prow = a.perm[prow_pos];
+            tpos = ms + p + 1 + blk * 64 + lane;
+        } else {
+            prow = a.pat[q];
+            tpos = ms + local * 64 + lane;
+        }
+        const bool valid = tpos < ms + k;
+        const int32_t trow = a.perm[valid ? tpos : ms];
+        const int d = lev_item<WMAX>(peq, a.S.codes + (int64_t)prow * a.S.stride, a.S.len[prow],
+                                     a.sigma, a.S.codes + (int64_t)trow * a.S.stride,
+                                     a.S.len[trow], valid, hb);
+        // The epilogue has no lane-dependent branch (see next_item): lanes
+        // without a pair write to the spare slot n or add zero.
+        const int64_t slot = valid ? tpos : (int64_t)a.n;
+        if (MODE == kMedoid) {
+            atomicAdd((unsigned long long *)&a.rowsum[slot],
+                      (unsigned long long)(valid ? d : 0));
+            const uint64_t s = wave_sum_u64(valid ? (uint64_t)d : 0ull);
+            atomicAdd((unsigned long long *)&a.rowsum[prow_pos],
+                      (unsigned long long)(lane == 0 ? s : 0ull));
+        }
+        if (MODE == kPoleMax || MODE == kPoleMaxStore) {
+            const uint64_t key =
+                valid ? (((uint64_t)d << 32) | (0xFFFFFFFFu - (uint32_t)a.order[trow])) : 0ull;
+            const uint64_t m = wave_max_u64(key);
+            atomicMax((unsigned long long *)&a.key[q], (unsigned long long)m);
+        }
+        if (MODE == kPoleMaxStore) a.dl[slot] = d;
+        if (MODE == kPoleStore) a.dr[slot] = d;
+    }
+}
+
+// c = member with the least row sum (lowest input index on ties).
+__global__ void __launch_bounds__(256) k_pick_center(TreeArgs a) {
+    __shared__ uint64_t red[256];
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int32_t v = lvl + q;
+        const int64_t ms = a.mstart[v], k = a.mcount[v];
+        uint64_t best = ~0ull;
+        for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+            const int32_t orig = a.order[a.perm[ms + i]];
+            const uint64_t key = (a.rowsum[ms + i] << 24) | (uint64_t)orig;
+            best = key < best ? key : best;
+        }
+        red[threadIdx.x] = best;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if (threadIdx.x < o) {
+                const uint64_t w = red[threadIdx.x + o];
+                if (w < red[threadIdx.x]) red[threadIdx.x] = w;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int32_t c = (int32_t)(red[0] & 0xFFFFFFull);
+            a.center[v] = c;
+            a.pat[q] = a.rank_of[c];
+            a.key[q] = 0;
+            a.cnt[q] = k >= 2 ? (k + 63) / 64 : 0;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
+}
+
+// After a pole pass: decode the argmax into the next pattern.  `which` 0:
+// l (a zero radius turns the cluster into a leaf), 1: r.
+__global__ void k_pick_pole(TreeArgs a, int which) {
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const int32_t v = lvl + q;
+        const int64_t k = a.mcount[v];
+        if (a.items[q + 1] == a.items[q]) {     // no work in the last pass: a leaf
+            a.cnt[q] = 0;
+            continue;
+        }
+        const uint64_t key = a.key[q];
+        const int32_t far = (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+        const uint32_t dmax = (uint32_t)(key >> 32);
+        a.key[q] = 0;
+        if (which == 0 && dmax == 0) {
+            a.cnt[q] = 0;
+            continue;
+        }
+        if (which == 0) a.lpole[v] = far; else a.rpole[v] = far;
+        a.pat[q] = a.rank_of[far];
+        a.cnt[q] = (k + 63) / 64;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
+}
+
+// Stable split of every cluster that has both poles: L = f(l,x) <= f(r,x).
+__global__ void __launch_bounds__(256) k_split(TreeArgs a) {
+    __shared__ int32_t sc[256];
+    __shared__ int32_t base_l, base_r;
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int32_t v = lvl + q;
+        if (a.rpole[v] < 0) continue;   // uniform per block
+        const int64_t ms = a.mstart[v], k = a.mcount[v];
+        int32_t cnt = 0;
+        for (int64_t i = threadIdx.x; i < k; i += blockDim.x) cnt += a.dl[ms + i] <= a.dr[ms + i];
+        sc[threadIdx.x] = cnt;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if (threadIdx.x < o) sc[threadIdx.x] += sc[threadIdx.x + o];
+            __syncthreads();
+        }
+        const int32_t nl = sc[0];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            base_l = 0;
+            base_r = nl;
+        }
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < k; c0 += blockDim.x) {
+            const int64_t i = c0 + threadIdx.x;
+            const int f = (i < k && a.dl[ms + i] <= a.dr[ms + i]) ? 1 : 0;
+            sc[threadIdx.x] = f;
+            __syncthreads();
+            for (int o = 1; o < 256; o <<= 1) {   // inclusive scan of the chunk's flags
+                const int32_t t = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+                __syncthreads();
+                sc[threadIdx.x] += t;
+                __syncthreads();
+            }
+            const int32_t incl = sc[threadIdx.x];
+            const int32_t chunk_l = sc[255];
+            if (i < k) {
+                const int32_t before_l = incl - f;
+                const int64_t dst = f ? ms + base_l + before_l
+                                      : ms + base_r + (threadIdx.x - before_l);
+                a.perm_next[dst] = a.perm[ms + i];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                base_l += chunk_l;
+                base_r += (int32_t)min<int64_t>(blockDim.x, k - c0) - chunk_l;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            a.nleft[q] = nl;
+            a.split[q] = 1;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_make_children(TreeArgs a) {
+    const int32_t lvl = a.desc[0], end = a.desc[1], nq = level_clusters(a.desc);
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        if (a.nleft[q] < 0) continue;
+        const int32_t v = lvl + q;
+        const int32_t c0 = end + 2 * (int32_t)a.split[q], c1 = c0 + 1;
+        const int64_t ms = a.mstart[v], k = a.mcount[v], nl = a.nleft[q];
+        a.left[v] = c0;
+        a.right[v] = c1;
+        a.parent[c0] = a.parent[c1] = v;
+        a.depth[c0] = a.depth[c1] = a.depth[v] + 1;
+        a.mstart[c0] = ms;
+        a.mcount[c0] = nl;
+        a.mstart[c1] = ms + nl;
+        a.mcount[c1] = k - nl;
+    }
+}
+
+__global__ void k_next_level(TreeArgs a) {
+    const int32_t nq = level_clusters(a.desc);
+    const int32_t s = (int32_t)a.split[nq];
+    a.desc[2] = s;
+    a.desc[0] = a.desc[1];
+    a.desc[1] = a.desc[1] + 2 * s;
+}
+
+__global__ void k_tree_root(TreeArgs a) {
+    a.parent[0] = -1;
+    a.depth[0] = 0;
+    a.mstart[0] = 0;
+    a.mcount[0] = a.n;
+    a.desc[0] = 0;
+    a.desc[1] = 1;
+    a.desc[2] = 0;
+}
+
+__global__ void k_rank_of(const int32_t *order, int32_t n, int32_t *rank_of, int32_t *perm) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    rank_of[order[r]] = r;
+    perm[r] = r;
+}
+
+__global__ void k_perm_out(const int32_t *order, const int32_t *perm, int32_t n, int32_t *out) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) out[r] = order[perm[r]];
+}
+
+template <int WMAX>
+static void launch_passes(const TreeArgs &a, int grid, hipStream_t s) {
+    const dim3 cg(kClusterGrid), cb(256), tb(64), lg(grid);
+    hipLaunchKernelGGL(k_level_init, cg, cb, 0, s, a);
+    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+    hipLaunchKernelGGL((k_tree_lev<WMAX, kMedoid>), lg, tb, 0, s, a);
+    hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
+    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+    hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMax>), lg, tb, 0, s, a);
+    hipLaunchKernelGGL(k_pick_pole, dim3(256), dim3(256), 0, s, a, 0);
+    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+    hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMaxStore>), lg, tb, 0, s, a);
+    hipLaunchKernelGGL(k_pick_pole, dim3(256), dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+    hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleStore>), lg, tb, 0, s, a);
+    hipMemcpyAsync(a.perm_next, a.perm, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
+    hipLaunchKernelGGL(k_split, cg, cb, 0, s, a);
+    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.split, a.split, a.desc);
+    hipLaunchKernelGGL(k_make_children, dim3(256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_next_level, dim3(1), dim3(1), 0, s, a);
+    hipMemcpyAsync(a.perm, a.perm_next, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
+}
+
+static void level_pass(const TreeArgs &a, int wclass, int grid, hipStream_t s) {
+    switch (wclass) {
+        case 4: launch_passes<4>(a, grid, s); break;
+        case 8: launch_passes<8>(a, grid, s); break;
+        case 16: launch_passes<16>(a, grid, s); break;
+        case 24: launch_passes<24>(a, grid, s); break;
+        default: launch_passes<32>(a, grid, s); break;
+    }
+}
+
+static int tree_grid(int wclass) {
+    static int cache[33];
+    int &g = cache[wclass];
+    if (g == 0) {
+        switch (wclass) {
+            case 4: g = persistent_grid(k_tree_lev<4, kMedoid>); break;
+            case 8: g = persistent_grid(k_tree_lev<8, kMedoid>); break;
+            case 16: g = persistent_grid(k_tree_lev<16, kMedoid>); break;
+            case 24: g = persistent_grid(k_tree_lev<24, kMedoid>); break;
+            default: g = persistent_grid(k_tree_lev<32, kMedoid>); break;
+        }
+    }
+    return g;
+}
+
+struct TreePlan {
+    int64_t stride, hstride;
+    int wclass, grid;
+};
+
+static TreePlan plan_tree(const msa_seqs *S) {
+    TreePlan p;
+    p.stride = staged_stride(S->max_len);
+    p.wclass = wmax_class(S->max_len);
+    p.grid = tree_grid(p.wclass);
+    p.hstride = S->max_len > kMaxWords * 64 ? ((int64_t)S->max_len + 15) / 16 : 0;
+    return p;
+}
+
+template <class Alloc>
+static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
+    const size_t n = (size_t)S->n;
+    al.template take<uint8_t>(n * p.stride);
+    al.template take<int32_t>(n + 1);           // staged lengths
+    al.template take<int32_t>(n);               // order
+    al.template take<int32_t>(n);               // rank_of
+    al.template take<int32_t>((size_t)S->max_len + 1);
+    al.template take<int32_t>(n);               // perm
+    al.template take<int32_t>(n);               // perm_next
+    al.template take<int32_t>(4);               // desc
+    al.template take<int64_t>(n + 1);           // cnt
+    al.template take<int64_t>(n + 1);           // items
+    al.template take<uint64_t>(n + 1);          // key
+    al.template take<int32_t>(n + 1);           // pat
+    al.template take<int32_t>(n + 1);           // nleft
+    al.template take<int64_t>(n + 1);           // split
+    al.template take<uint64_t>(n + 1);          // rowsum (+ spare slot)
+    al.template take<int32_t>(n + 1);           // dl
+    al.template take<int32_t>(n + 1);           // dr
+    al.template take<uint32_t>(1);              // counter
+    if (p.hstride) al.template take<uint32_t>((size_t)p.grid * kWave * p.hstride);
+}
+
+}  // namespace msadp
+
+using namespace msadp;
+
+extern "C" {
+
+size_t tree_workspace_bytes(const msa_seqs *S) {
+    if (check_seqs(S)) return 0;
+    Sizer sz;
+    tree_layout(sz, S, plan_tree(S));
+    return sz.total();
+}
+
+int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
+               void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(S))) return rc;
+    if (T == nullptr || n_nodes == nullptr) return MSA_EINVAL;
+    *n_nodes = 0;
+    if (S->n == 0) return MSA_OK;
+    if (S->n >= (1 << 24)) return MSA_ERANGE;
+    if (!T->parent || !T->left || !T->right || !T->center || !T->lpole || !T->rpole ||
+        !T->depth || !T->mstart || !T->mcount || !T->perm || ws == nullptr)
+        return MSA_EINVAL;
+    const TreePlan p = plan_tree(S);
+    Sizer sz;
+    tree_layout(sz, S, p);
+    if (ws_bytes < sz.total()) return MSA_ENOSPC;
+    const size_t n = (size_t)S->n;
+    Carve cv(ws, ws_bytes);
+    TreeArgs a{};
+    a.S = Staged{cv.take<uint8_t>(n * p.stride), cv.take<int32_t>(n + 1), p.stride, S->n};
+    int32_t *order = cv.take<int32_t>(n);
+    int32_t *rank_of = cv.take<int32_t>(n);
+    int32_t *hist = cv.take<int32_t>((size_t)S->max_len + 1);
+    a.order = order;
+    a.rank_of = rank_of;
+    a.perm = cv.take<int32_t>(n);
+    a.perm_next = cv.take<int32_t>(n);
+    a.parent = T->parent; a.left = T->left; a.right = T->right; a.center = T->center;
+    a.lpole = T->lpole; a.rpole = T->rpole; a.depth = T->depth;
+    a.mstart = T->mstart; a.mcount = T->mcount;
+    a.desc = cv.take<int32_t>(4);
+    a.cnt = cv.take<int64_t>(n + 1);
+    a.items = cv.take<int64_t>(n + 1);
+    a.key = cv.take<uint64_t>(n + 1);
+    a.pat = cv.take<int32_t>(n + 1);
+    a.nleft = cv.take<int32_t>(n + 1);
+    a.split = cv.take<int64_t>(n + 1);
+    a.rowsum = cv.take<uint64_t>(n + 1);
+    a.dl = cv.take<int32_t>(n + 1);
+    a.dr = cv.take<int32_t>(n + 1);
+    a.counter = cv.take<uint32_t>(1);
+    a.hbuf = p.hstride ? cv.take<uint32_t>((size_t)p.grid * kWave * p.hstride) : nullptr;
+    a.hstride = p.hstride;
+    a.sigma = S->sigma;
+    a.n = S->n;
+    a.st = d_status;
+
+    if ((rc = sort_by_length(S, a.S.len, hist, order, d_status, s))) return rc;
+    if ((rc = stage_set(S, order, a.S, d_status, s))) return rc;
+    hipLaunchKernelGGL(k_rank_of, dim3((S->n + 255) / 256), dim3(256), 0, s, order, S->n, rank_of,
+                       a.perm);
+    hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, a);
+    if ((rc = launch_status())) return rc;
+
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (use_graph) {
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return MSA_EDEVICE;
+        level_pass(a, p.wclass, p.grid, s);
+        if (hipStreamEndCapture(s, &graph) != hipSuccess) return MSA_EDEVICE;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(graph);
+            return MSA_EDEVICE;
+        }
+    }
+    int32_t total = 1;
+    int32_t host_desc[3] = {0, 1, 0};
+    rc = MSA_OK;
+    for (int level = 0; level < S->n; ++level) {
+        if (use_graph) {
+            if (hipGraphLaunch(exec, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
+        } else {
+            level_pass(a, p.wclass, p.grid, s);
+        }
+        if ((rc = launch_status())) break;
+        if (hipMemcpyAsync(host_desc, a.desc, sizeof(host_desc), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = MSA_EDEVICE;
+            break;
+        }
+        if (host_desc[2] == 0) break;
+        total += 2 * host_desc[2];
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_perm_out, dim3((S->n + 255) / 256), dim3(256), 0, s, order, a.perm, S->n,
+                       T->perm);
+    if ((rc = launch_status())) return rc;
+    *n_nodes = total;
+    return MSA_OK;
+}
+
+}  // extern "C"

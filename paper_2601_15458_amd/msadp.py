@@ -31,6 +31,15 @@ class MsaSeqs(C.Structure):
 
 
 SP = C.POINTER(MsaSeqs)
+
+
+class MsaTree(C.Structure):
+    _fields_ = [(f, P) for f in ("parent", "left", "right", "center", "lpole", "rpole",
+                                 "depth", "mstart", "mcount", "perm")]
+
+
+TREE_FIELDS = ("parent", "left", "right", "center", "lpole", "rpole", "depth", "mstart",
+               "mcount")
 SIGNATURES = {
     "msa_strerror": (C.c_char_p, [C.c_int]),
     "msa_version": (C.c_int, []),
@@ -42,6 +51,8 @@ SIGNATURES = {
     "nw_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
     "nw_batch": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, C.c_size_t, P, P]),
     "nw_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
+    "tree_workspace_bytes": (C.c_size_t, [SP]),
+    "tree_build": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
 }
 
 _lib = None
@@ -202,6 +213,41 @@ class NwResult:
         self.score, self.tb, self.tb_offsets, self.n_pairs = score, tb, tb_offsets, n_pairs
 
 
+class NwBatch:
+    """Reusable NW launcher: buffers sized once for fixed (A, B, ia, ib)."""
+
+    def __init__(self, A: Seqs, B: Seqs, ia, ib):
+        self.A, self.B = A, B
+        self.r = nw_batch(A, B, ia, ib)
+        r = self.r
+        dev = A.codes.device
+        self.sa, self.sb = A.struct(), B.struct()
+        self.wsb = lib().nw_workspace_bytes(C.byref(self.sa), C.byref(self.sb), r.n_pairs)
+        self.ws = torch.empty(max(self.wsb, 1), dtype=torch.uint8, device=dev)
+        caps = (r.m + r.n).astype(np.int64)
+        self.ops_off = np.zeros(r.n_pairs + 1, dtype=np.int64)
+        np.cumsum(caps, out=self.ops_off[1:])
+        self.ops = torch.empty(max(int(self.ops_off[-1]), 1), dtype=torch.uint8, device=dev)
+        self.ops_off_d = torch.from_numpy(self.ops_off).to(dev)
+        self.ops_len = torch.empty(max(r.n_pairs, 1), dtype=torch.int32, device=dev)
+        self.st = Status(dev)
+
+    def fill(self, stream=None):
+        r = self.r
+        rc = lib().nw_batch(C.byref(self.sa), C.byref(self.sb), _ptr(r.ia), _ptr(r.ib),
+                            r.n_pairs, _ptr(r.score), _ptr(r.tb), _ptr(r.tb_offsets),
+                            _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
+        _check(rc, "nw_batch")
+
+    def traceback(self, stream=None):
+        r = self.r
+        rc = lib().nw_traceback(C.byref(self.sa), C.byref(self.sb), _ptr(r.ia), _ptr(r.ib),
+                                r.n_pairs, _ptr(r.tb), _ptr(r.tb_offsets), _ptr(self.ops),
+                                _ptr(self.ops_off_d), _ptr(self.ops_len), _ptr(self.st.t),
+                                _stream(stream))
+        _check(rc, "nw_traceback")
+
+
 def nw_batch(A: Seqs, B: Seqs, ia, ib, stream=None, check=True) -> NwResult:
     """Fill: int32 scores and the traceback codes of every pair."""
     dev = A.codes.device
@@ -259,3 +305,69 @@ def split_ops(ops, ops_off, ops_len):
     o = ops.cpu().numpy()
     L = ops_len.cpu().numpy()
     return [o[ops_off[p]: ops_off[p] + L[p]].copy() for p in range(len(L))]
+
+
+class Tree:
+    """Device arrays of a guide tree (capacity 2n - 1 nodes)."""
+
+    def __init__(self, n, dev):
+        cap = max(2 * n - 1, 1)
+        self.t = {f: torch.full((cap,), -1, dtype=torch.int64 if f in ("mstart", "mcount")
+                                else torch.int32, device=dev) for f in TREE_FIELDS}
+        self.t["perm"] = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+        self.n_nodes = 0
+        self.n = n
+
+    def struct(self):
+        return MsaTree(*[self.t[f].data_ptr() for f in TREE_FIELDS + ("perm",)])
+
+    def host(self):
+        k = self.n_nodes
+        out = {f: self.t[f][:k].cpu().numpy() for f in TREE_FIELDS}
+        out["perm"] = self.t["perm"][: self.n].cpu().numpy()
+        out["n_nodes"] = k
+        return out
+
+
+class TreeBuilder:
+    """Reusable Alg. 1 builder for one sequence set."""
+
+    def __init__(self, S: Seqs, use_graph=False):
+        self.S = S
+        dev = S.codes.device
+        self.ss = S.struct()
+        self.tree = Tree(S.n, dev)
+        self.ts = self.tree.struct()
+        self.wsb = lib().tree_workspace_bytes(C.byref(self.ss))
+        self.ws = torch.empty(max(self.wsb, 1), dtype=torch.uint8, device=dev)
+        self.st = Status(dev)
+        self.use_graph = bool(use_graph)
+
+    def __call__(self, stream=None):
+        nn = C.c_int32(0)
+        rc = lib().tree_build(C.byref(self.ss), C.byref(self.ts), C.byref(nn),
+                              int(self.use_graph), _ptr(self.ws), self.wsb, _ptr(self.st.t),
+                              _stream(stream))
+        _check(rc, "tree_build")
+        self.tree.n_nodes = nn.value
+        return self.tree
+
+
+def tree_build(S: Seqs, use_graph=False, stream=None):
+    """Alg. 1 guide tree of S; returns host numpy arrays like the oracle's."""
+    if use_graph and stream is None:
+        stream = torch.cuda.Stream()
+    tb = TreeBuilder(S, use_graph)
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        t = tb(stream)
+    torch.cuda.synchronize()
+    tb.st.check("tree_build")
+    return t.host()
+
+
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False

@@ -161,6 +161,24 @@ size_t tree_workspace_bytes(const msa_seqs *S);
 int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
                void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
+/* ------------------------------------------------------------------ */
+/* Bottom-up merge (Sec. 2.2) over a tree from tree_build (T, n_nodes as
+ * returned).  A leaf's alignment is its sequence.  For an internal node the
+ * aligned rows of its children's centers (each child's Alg. 1 medoid) are
+ * aligned by nw_batch/nw_traceback with the gap as an ordinary symbol (code
+ * S->sigma, so S->sigma <= 31), then the L child's rows get an all-gap column
+ * at every I op, the R child's rows one at every D op, and the rows are
+ * joined, L's first.  Output: msa (device, S->n rows of msa_pitch bytes,
+ * row i = sequence i, gap = S->sigma, columns >= *width undefined); *width
+ * (host) = the final width.  width_cap bounds every node's width (<= 32768)
+ * and tb_cap the traceback bytes of one tree level; exceeding either returns
+ * MSA_ENOSPC.  The stream is synchronized once per tree level. */
+size_t msa_merge_workspace_bytes(const msa_seqs *S, int32_t n_nodes, int32_t width_cap,
+                                 size_t tb_cap);
+int msa_merge(const msa_seqs *S, const msa_tree *T, int32_t n_nodes, int32_t width_cap,
+              size_t tb_cap, uint8_t *msa, int64_t msa_pitch, int32_t *width, void *ws,
+              size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,9 @@ SIGNATURES = {
     "nw_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
     "tree_workspace_bytes": (C.c_size_t, [SP]),
     "tree_build": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
+    "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
+    "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
+                            C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
 }
 
 _lib = None
@@ -371,3 +374,41 @@ class _nullctx:
 
     def __exit__(self, *a):
         return False
+
+
+def msa_merge(S: Seqs, tree: Tree, width_cap=None, tb_cap=1 << 30, stream=None):
+    """Final alignment (host uint8 array n x W, gap code = sigma) of S along
+    a tree built on the device.  width_cap grows until the alignment fits."""
+    dev = S.codes.device
+    cap = width_cap or min(32768, max(64, 2 * S.max_len))
+    ss, ts = S.struct(), tree.struct()
+    while True:
+        pitch = (cap + 15) // 16 * 16
+        out = torch.empty(max(S.n * pitch, 1), dtype=torch.uint8, device=dev)
+        wsb = lib().msa_merge_workspace_bytes(C.byref(ss), tree.n_nodes, cap, tb_cap)
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+        st = Status(dev)
+        w = C.c_int32(0)
+        rc = lib().msa_merge(C.byref(ss), C.byref(ts), tree.n_nodes, cap, tb_cap, _ptr(out),
+                             pitch, C.byref(w), _ptr(ws), wsb, _ptr(st.t), _stream(stream))
+        if rc == MSA_ENOSPC and width_cap is None and cap < 32768:
+            cap = min(32768, cap * 2)
+            continue
+        _check(rc, "msa_merge")
+        torch.cuda.synchronize()
+        st.check("msa_merge")
+        W = w.value
+        return out[: S.n * pitch].view(S.n, pitch)[:, :W].cpu().numpy()
+
+
+def align(S: Seqs, use_graph=False, stream=None):
+    """Guide tree (Alg. 1) then the bottom-up merge: (tree dict, alignment)."""
+    tb = TreeBuilder(S, use_graph)
+    if use_graph and stream is None:
+        stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        tree = tb(stream)
+        torch.cuda.synchronize()
+        tb.st.check("tree_build")
+        msa = msa_merge(S, tree, stream=stream)
+    return tree.host(), msa

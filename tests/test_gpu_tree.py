@@ -75,3 +75,35 @@ def test_duplicates_leaf():
     seqs = [np.array([0, 1, 2, 3], np.uint8)] * 3 + [np.array([3, 3], np.uint8)]
     codes, off = synth.to_csr(seqs)
     _compare(codes, off, 4)
+
+
+def _check_msa(codes, off, sigma, use_graph=False):
+    M = _msadp()
+    n = len(off) - 1
+    print(f"[merge] n={n} sigma={sigma}: device tree + merge", flush=True)
+    S = M.to_device(codes, off, sigma)
+    tree, msa = M.align(S, use_graph=use_graph)
+    print(f"[merge] device done, width {msa.shape[1]}; oracle", flush=True)
+    want_tree = orc.tree(codes, off)
+    want = orc.merge(codes, off, sigma, want_tree)
+    assert msa.shape == want.shape, (msa.shape, want.shape)
+    bad = np.argwhere(msa != want)
+    assert len(bad) == 0, bad[:5]
+
+
+def test_tiny_workload_alignment_byte_equal():
+    d = synth.tiny()
+    _check_msa(d["codes"], d["offsets"], d["sigma"])
+
+
+def test_hand_worked_alignment():
+    seqs = [np.array(["ACGT".index(c) for c in s], dtype=np.uint8) for s in ["AC", "ACG", "G"]]
+    codes, off = synth.to_csr(seqs)
+    _check_msa(codes, off, 4)
+
+
+def test_protein_subset_alignment():
+    d = synth.protein_tree()
+    rng = np.random.default_rng(34)
+    sub = synth.subset(d, rng.choice(d["n"], size=150, replace=False))
+    _check_msa(sub["codes"], sub["offsets"], 20, use_graph=True)

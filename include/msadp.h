@@ -179,6 +179,49 @@ int msa_merge(const msa_seqs *S, const msa_tree *T, int32_t n_nodes, int32_t wid
               size_t tb_cap, uint8_t *msa, int64_t msa_pitch, int32_t *width, void *ws,
               size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
+/* ------------------------------------------------------------------ */
+/* Learned surrogate of f (not part of the paper; used to prune the exact
+ * medoid work of Alg. 1).  A 1D-CNN embedder with a fixed shape: one-hot
+ * input over 8 channels (sigma <= 8), 4 conv layers of width 128 and kernel
+ * 5 with zero padding, ReLU after layers 1-3, mean over the sequence ->
+ * 128-d embedding; trained so that ||e_a - e_b|| approximates
+ * lev(a, b) / ((|a| + |b|) / 2) (mean squared error over pairs, Adam).
+ * BF16 weights/activations, FP32 accumulation on the matrix cores, FP32
+ * master weights and Adam state, all in one device blob of
+ * cnn_param_bytes() bytes owned by the caller. */
+size_t cnn_param_bytes(void);
+
+/* Load weights from host: per layer l, W[k][cin_l][128] (cin_0 = 8, the
+ * one-hot channels beyond sigma zero; cin_l = 128 after) concatenated over
+ * layers, and b[l][128].  Resets the Adam state.  Synchronous. */
+int cnn_set_params(void *params, const float *w_host, const float *b_host, hipStream_t s);
+
+/* Copy master weights and the last step's gradients back to host (any of
+ * the four pointers may be null).  Synchronizes the stream. */
+int cnn_get_params(const void *params, float *w_host, float *b_host, float *gw_host,
+                   float *gb_host, hipStream_t s);
+
+/* Workspace of a batch of n_idx sequences of total length total_len
+ * (n_pairs = 0 for inference). */
+size_t cnn_workspace_bytes(const msa_seqs *S, int32_t n_idx, int64_t total_len, int32_t n_pairs);
+
+/* Embeddings of the sequences S[idx[i]] (idx: device int32[n_idx];
+ * total_len = their summed length, checked on the device): emb (device
+ * float[n_idx][128]). */
+int cnn_embed(const void *params, const msa_seqs *S, const int32_t *idx, int32_t n_idx,
+              int64_t total_len, float *emb, void *ws, size_t ws_bytes, int32_t *d_status,
+              hipStream_t s);
+
+/* One training step on the pairs (idx[pa[p]], idx[pb[p]]) with exact
+ * distances dist[p] (device uint16, e.g. from lev_batch): forward, loss,
+ * backward, and an Adam update with learning rate lr at step `step` (>= 1);
+ * lr == 0 computes gradients only.  *loss (device float) receives the mean
+ * squared error before the update. */
+int cnn_train_step(void *params, const msa_seqs *S, const int32_t *idx, int32_t n_idx,
+                   int64_t total_len, const int32_t *pa, const int32_t *pb,
+                   const uint16_t *dist, int32_t n_pairs, float lr, int32_t step, float *loss,
+                   void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

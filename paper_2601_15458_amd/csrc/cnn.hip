@@ -1,0 +1,669 @@
+// Learned surrogate of the Levenshtein distance: a 1D-CNN sequence embedder
+// (4 conv layers of width 128, kernel 5, ReLU between, masked mean pool),
+// trained so that the Euclidean distance of two embeddings approximates
+// lev(a, b) / mean length.  BF16 weights and activations, FP32 accumulation
+// on the matrix cores (v_mfma_f32_16x16x32_bf16), FP32 master weights and
+// Adam state.
+//
+// Layout.  A batch's sequences are laid end to end as rows (one row per
+// position, channels contiguous), each sequence framed by 2 zero rows on
+// either side; kLead zero rows precede the first sequence and at least
+// kLead + 127 follow the last.  A convolution output row r then reads the
+// contiguous span X[(r - 2) * Cin .. (r - 2) * Cin + K * Cin), which makes
+// every layer an implicit GEMM with rows x (K * Cin) times (K * Cin) x 128:
+//   forward:        Z_l  = span(H_{l-1}) . W_l          (+ bias, ReLU, mask)
+//   input gradient: dH   = span(dZ_l) . flip(W_l)^T     (x ReLU'(H), mask)
+//   weight gradient dW_l = span(H_{l-1})^T . dZ_l       (reduction over rows)
+// Padding rows are written as zeros by every epilogue, so the spans of the
+// next layer see each sequence's zero padding.
+#include <vector>
+
+#include "common.hpp"
+
+namespace msadp {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef uint16_t bf16_t;   // storage type
+
+constexpr int kW = 128;      // channels
+constexpr int kKer = 5;      // kernel width
+constexpr int kLayers = 4;
+constexpr int kIn = 8;       // one-hot channels (sigma <= 8)
+constexpr int kLead = 8;     // zero rows before the first sequence
+constexpr int kTile = 128;   // rows per GEMM workgroup
+
+__host__ __device__ constexpr int cin_of(int l) { return l == 0 ? kIn : kW; }
+__host__ __device__ constexpr int kd_of(int l) { return kKer * cin_of(l); }              // 40 / 640
+__host__ __device__ constexpr int kdp_of(int l) { return (kd_of(l) + 31) / 32 * 32; }   // 64 / 640
+
+// ------------------------------------------------------------ parameters
+// One device blob; offsets in floats (bf16 copies use the same byte offsets).
+struct ParamLayout {
+    size_t w[kLayers], b[kLayers];              // fp32 master [128][kdp], [128]
+    size_t mw[kLayers], mb[kLayers], vw[kLayers], vb[kLayers];
+    size_t gw[kLayers], gb[kLayers];            // fp32 gradients
+    size_t wt[kLayers];                         // bf16 forward [128][kdp] (byte offsets)
+    size_t wbt[kLayers];                        // bf16 input-gradient [cin][640]
+    size_t bytes;
+};
+
+static ParamLayout param_layout() {
+    ParamLayout p{};
+    size_t off = 0;   // bytes
+    auto take = [&](size_t bytes) {
+        off = (off + 255) / 256 * 256;
+        size_t o = off;
+        off += bytes;
+        return o;
+    };
+    for (int l = 0; l < kLayers; ++l) {
+        const size_t nw = (size_t)kW * kdp_of(l);
+        p.w[l] = take(4 * nw);
+        p.b[l] = take(4 * kW);
+        p.mw[l] = take(4 * nw);
+        p.mb[l] = take(4 * kW);
+        p.vw[l] = take(4 * nw);
+        p.vb[l] = take(4 * kW);
+        p.gw[l] = take(4 * nw);
+        p.gb[l] = take(4 * kW);
+        p.wt[l] = take(2 * nw);
+        p.wbt[l] = take(2 * (size_t)cin_of(l) * kKer * kW);
+    }
+    p.bytes = take(0) + 256;
+    return p;
+}
+
+template <class T>
+__host__ __device__ inline T *at(void *base, size_t off) { return (T *)((uint8_t *)base + off); }
+
+__device__ inline bf16_t to_bf16(float f) {
+    // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+__device__ inline float from_bf16(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Forward weights Wt[co][k*cin + ci] and input-gradient weights
+// Wbt[ci][k'*128 + co] = W[K-1-k'][ci][co] from the fp32 master.
+__global__ void k_pack_weights(void *P, ParamLayout pl) {
+    for (int l = 0; l < kLayers; ++l) {
+        const int kdp = kdp_of(l), cin = cin_of(l);
+        const float *w = at<float>(P, pl.w[l]);
+        bf16_t *wt = at<bf16_t>(P, pl.wt[l]);
+        bf16_t *wbt = at<bf16_t>(P, pl.wbt[l]);
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kW * kdp;
+             i += gridDim.x * blockDim.x) {
+            wt[i] = to_bf16(w[i]);
+            const int co = i / kdp, kk = i % kdp;
+            if (kk < kd_of(l)) {
+                const int k = kk / cin, ci = kk % cin;
+                wbt[(size_t)ci * kKer * kW + (kKer - 1 - k) * kW + co] = to_bf16(w[i]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ batch layout
+struct Batch {
+    const uint8_t *codes;    // staged rows of the sequence set
+    const int32_t *len;
+    int64_t stride;
+    const int32_t *idx;      // sequences of the batch
+    int32_t nb;
+    int64_t rows;            // data + framing rows (excludes lead/tail)
+    int64_t *roff;           // [nb + 1] first row of each sequence's frame
+    int32_t *rowseq;         // [rows] batch index of a data row, -1 for framing
+};
+
+__global__ void k_frame_lengths(Batch b, int32_t *st) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= b.nb; i += gridDim.x * blockDim.x)
+        b.roff[i] = i < b.nb ? (int64_t)b.len[b.idx[i]] + 4 : 0;
+}
+
+__global__ void k_frame_rows(Batch b, int32_t *st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && b.roff[b.nb] != b.rows)
+        set_status(st, MSA_DS_CAPACITY);
+    for (int i = blockIdx.x; i < b.nb; i += gridDim.x) {
+        const int64_t r0 = b.roff[i];
+        const int32_t L = b.len[b.idx[i]];
+        if (r0 + L + 4 > b.rows) continue;
+        for (int64_t t = threadIdx.x; t < L + 4; t += blockDim.x)
+            b.rowseq[r0 + t] = (t >= 2 && t < L + 2) ? i : -1;
+    }
+}
+
+// One-hot input rows (8 channels, bf16).
+__global__ void k_onehot(Batch b, bf16_t *H0) {
+    for (int i = blockIdx.x; i < b.nb; i += gridDim.x) {
+        const int64_t r0 = b.roff[i];
+        const int32_t s = b.idx[i], L = b.len[s];
+        const uint8_t *x = b.codes + (int64_t)s * b.stride;
+        for (int64_t t = threadIdx.x; t < (int64_t)(L + 4) * kIn; t += blockDim.x) {
+            const int64_t row = t / kIn, c = t % kIn;
+            const bool data = row >= 2 && row < L + 2;
+            const float v = (data && x[row - 2] == c) ? 1.0f : 0.0f;
+            H0[(kLead + r0 + row) * kIn + c] = to_bf16(v);
+        }
+    }
+}
+
+// ------------------------------------------------------------ conv GEMM
+enum { kEpiRelu = 0, kEpiLinearF32 = 1, kEpiGradRelu = 2 };
+
+struct ConvArgs {
+    const bf16_t *X;         // input rows (lead included), cin channels
+    const bf16_t *Wt;        // [128][kdp]
+    const float *bias;
+    const int32_t *rowseq;
+    int64_t rows;
+    void *out;               // output rows (lead included), 128 channels
+    const bf16_t *relu_ref;  // rows whose sign gates the input gradient
+};
+
+// Workgroup = 4 wavefronts = 128 output rows x 128 channels; wavefront w
+// owns rows [32w, 32w + 32): 2 x 8 tiles of 16 x 16, K in steps of 32.
+template <int CIN, int KDP, int EPI>
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * kTile + 32 * w;
+    f32x4 acc[2][8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    const int kq = 8 * (lane >> 4);   // this lane's first K element of a step
+    const int li = lane & 15;
+    const bf16_t *arow[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        arow[i] = a.X + (kLead + row0 + 16 * i + li - 2) * CIN + kq;
+    const bf16_t *brow = a.Wt + (size_t)li * KDP + kq;
+    for (int k0 = 0; k0 < KDP; k0 += 32) {
+        bf16x8 af[2], bfr[8];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = *(const bf16x8 *)(arow[i] + k0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bfr[j] = *(const bf16x8 *)(brow + (size_t)16 * j * KDP + k0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    // lane holds rows 4*(lane/16) + r of each 16 x 16 tile, column lane % 16
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = row0 + 16 * i + 4 * (lane >> 4) + r;
+            if (row >= a.rows) continue;
+            const bool data = a.rowseq[row] >= 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int col = 16 * j + li;
+                const float v = acc[i][j][r];
+                const int64_t o = (kLead + row) * kW + col;
+                if (EPI == kEpiRelu) {
+                    const float z = v + a.bias[col];
+                    ((bf16_t *)a.out)[o] = to_bf16(data && z > 0.0f ? z : 0.0f);
+                } else if (EPI == kEpiLinearF32) {
+                    ((float *)a.out)[o] = data ? v + a.bias[col] : 0.0f;
+                } else {
+                    const bool on = data && from_bf16(a.relu_ref[o]) > 0.0f;
+                    ((bf16_t *)a.out)[o] = to_bf16(on ? v : 0.0f);
+                }
+            }
+        }
+    }
+}
+
+// Weight gradient: gW[co][kk] += sum over rows r of dZ[r][co] * span(H)[r][kk].
+// Workgroup = 128 co x 128 kk columns over a chunk of rows, staged in LDS in
+// steps of 32 rows; each wavefront owns 32 co.
+constexpr int kWgChunk = 8192;
+
+template <int CIN, int KDP>
+__global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_t *dZ,
+                                                    int64_t rows, float *gW) {
+    constexpr int kDzPitch = kW + 2;
+    constexpr int kXElems = 32 * CIN + KDP;
+    __shared__ bf16_t sdz[32 * kDzPitch];
+    __shared__ bf16_t sx[kXElems];
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int li = lane & 15, kq = 8 * (lane >> 4);
+    const int kk0 = blockIdx.y * 128;
+    const int64_t r_begin = (int64_t)blockIdx.x * kWgChunk;
+    const int64_t r_end = min(rows, r_begin + kWgChunk);
+    f32x4 acc[2][8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += 32) {
+        __syncthreads();
+        // dZ rows [r0, r0 + 32) (rows past the end read as zero)
+        for (int e = threadIdx.x; e < 32 * kW; e += blockDim.x) {
+            const int rr = e / kW, c = e % kW;
+            sdz[rr * kDzPitch + c] = (r0 + rr < r_end) ? dZ[(kLead + r0 + rr) * kW + c] : (bf16_t)0;
+        }
+        // H span base (r0 - 2) * CIN, 32 * CIN + KDP elements
+        const bf16_t *hb = H + (kLead + r0 - 2) * CIN;
+        for (int e = threadIdx.x; e < kXElems; e += blockDim.x) sx[e] = hb[e];
+        __syncthreads();
+        bf16x8 af[2], bfr[8];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int co = 32 * w + 16 * i + li;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) af[i][j] = __builtin_bit_cast(__bf16, sdz[(kq + j) * kDzPitch + co]);
+        }
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const int kk = kk0 + 16 * n + li;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                bfr[n][j] = kk < KDP ? __builtin_bit_cast(__bf16, sx[(kq + j) * CIN + kk]) : (__bf16)0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int n = 0; n < 8; ++n)
+                acc[i][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[n], acc[i][n], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const int kk = kk0 + 16 * n + li;
+            if (kk >= KDP) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = 32 * w + 16 * i + 4 * (lane >> 4) + r;
+                atomicAdd(&gW[(size_t)co * KDP + kk], acc[i][n][r]);
+            }
+        }
+}
+
+// Bias gradient: gb[c] += sum of dZ[r][c] over a chunk of rows.
+__global__ void __launch_bounds__(128) k_bias_grad(const bf16_t *dZ, int64_t rows, float *gb) {
+    const int c = threadIdx.x;
+    const int64_t r_begin = (int64_t)blockIdx.x * kWgChunk;
+    const int64_t r_end = min(rows, r_begin + kWgChunk);
+    float s = 0.0f;
+    for (int64_t r = r_begin; r < r_end; ++r) s += from_bf16(dZ[(kLead + r) * kW + c]);
+    atomicAdd(&gb[c], s);
+}
+
+// ------------------------------------------------------------ pool, loss
+__global__ void __launch_bounds__(128) k_pool(Batch b, const float *Z4, float *E) {
+    const int c = threadIdx.x;
+    for (int i = blockIdx.x; i < b.nb; i += gridDim.x) {
+        const int64_t r0 = b.roff[i] + 2;
+        const int32_t L = b.len[b.idx[i]];
+        float s = 0.0f;
+        for (int t = 0; t < L; ++t) s += Z4[(kLead + r0 + t) * kW + c];
+        E[(int64_t)i * kW + c] = L > 0 ? s / (float)L : 0.0f;
+    }
+}
+
+// One wavefront per pair: pred = ||E[a] - E[b]||; loss += (pred - y)^2 / P;
+// dE[a] += g, dE[b] -= g with g = 2 (pred - y) / P * (E[a] - E[b]) / pred.
+__global__ void __launch_bounds__(64) k_pair_loss(const float *E, const int32_t *pa,
+                                                 const int32_t *pb, const float *label,
+                                                 int32_t P, float *dE, float *loss) {
+    const int lane = lane_id();
+    const int p = blockIdx.x;
+    const int a = pa[p], bq = pb[p];
+    const float d0 = E[(int64_t)a * kW + lane] - E[(int64_t)bq * kW + lane];
+    const float d1 = E[(int64_t)a * kW + lane + 64] - E[(int64_t)bq * kW + lane + 64];
+    float ss = d0 * d0 + d1 * d1;
+    for (int o = 32; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, kWave);
+    const float pred = sqrtf(ss);
+    const float r = pred - label[p];
+    const float scale = pred > 0.0f ? 2.0f * r / ((float)P * pred) : 0.0f;
+    atomicAdd(&dE[(int64_t)a * kW + lane], scale * d0);
+    atomicAdd(&dE[(int64_t)a * kW + lane + 64], scale * d1);
+    atomicAdd(&dE[(int64_t)bq * kW + lane], -scale * d0);
+    atomicAdd(&dE[(int64_t)bq * kW + lane + 64], -scale * d1);
+    if (lane == 0) atomicAdd(loss, r * r / (float)P);
+}
+
+// Regression target of a pair: lev(a, b) / ((|a| + |b|) / 2).
+__global__ void k_labels(Batch b, const int32_t *pa, const int32_t *pb, const uint16_t *dist,
+                         int32_t P, float *label) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const float la = (float)b.len[b.idx[pa[p]]], lb = (float)b.len[b.idx[pb[p]]];
+        label[p] = la + lb > 0.0f ? (float)dist[p] / (0.5f * (la + lb)) : 0.0f;
+    }
+}
+
+// Mean-pool backward: dZ4[r][c] = dE[seq][c] / L on data rows, 0 elsewhere.
+__global__ void __launch_bounds__(128) k_pool_bwd(Batch b, const float *dE, bf16_t *dZ4) {
+    const int c = threadIdx.x;
+    for (int64_t r = blockIdx.x; r < b.rows; r += gridDim.x) {
+        const int32_t i = b.rowseq[r];
+        float v = 0.0f;
+        if (i >= 0) v = dE[(int64_t)i * kW + c] / (float)b.len[b.idx[i]];
+        dZ4[(kLead + r) * kW + c] = to_bf16(v);
+    }
+}
+
+// Adam (Kingma & Ba) on one flat array.
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void k_zero_f32(float *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+// ------------------------------------------------------------ host side
+struct CnnWork {
+    Batch b;
+    bf16_t *h[kLayers];      // H0 (8 ch), H1..H3 (128 ch)
+    float *z4;               // last layer output (fp32)
+    bf16_t *dz;              // gradient rows (two buffers)
+    bf16_t *dz2;
+    float *E, *dE, *loss, *label;
+    int64_t alloc_rows;
+};
+
+// Tail: the last tile's overhang plus the longest span (8 rows) past it.
+constexpr int kTail = 64;
+static int64_t alloc_rows_for(int64_t rows) {
+    return kLead + (rows + kTile - 1) / kTile * kTile + kTail;
+}
+
+template <class Alloc>
+static void cnn_layout(Alloc &al, int32_t nb, int64_t rows, const msa_seqs *S, bool train,
+                       int32_t n_pairs) {
+    const int64_t ar = alloc_rows_for(rows);
+    al.template take<uint8_t>((size_t)S->n * staged_stride(S->max_len));
+    al.template take<int32_t>((size_t)S->n + 1);
+    al.template take<int64_t>((size_t)nb + 1);
+    al.template take<int32_t>((size_t)rows + 1);
+    al.template take<bf16_t>((size_t)ar * kIn);
+    for (int l = 1; l < kLayers; ++l) al.template take<bf16_t>((size_t)ar * kW);
+    al.template take<float>((size_t)ar * kW);
+    al.template take<float>((size_t)nb * kW);
+    if (train) {
+        al.template take<bf16_t>((size_t)ar * kW);
+        al.template take<bf16_t>((size_t)ar * kW);
+        al.template take<float>((size_t)nb * kW);
+        al.template take<float>(1);
+        al.template take<float>((size_t)n_pairs);
+    }
+}
+
+static int zero(void *p, size_t bytes, hipStream_t s) {
+    return fill_i32((int32_t *)p, (int64_t)(bytes / 4), 0, s);
+}
+
+// Zero the lead rows and every row from `rows` to the end of the buffer.
+static int zero_frame(void *p, size_t row_bytes, int64_t alloc_rows, int64_t rows, hipStream_t s) {
+    int rc;
+    if ((rc = zero(p, row_bytes * kLead, s))) return rc;
+    return zero((uint8_t *)p + row_bytes * (kLead + rows), row_bytes * (alloc_rows - kLead - rows), s);
+}
+
+static int cnn_forward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t s) {
+    const Batch &b = w.b;
+    const unsigned tiles = (unsigned)((b.rows + kTile - 1) / kTile);
+    int rc;
+    // the GEMMs write every row in [0, rows); only the lead and tail rows,
+    // which spans read but no epilogue writes, need zeros
+    if ((rc = zero_frame(w.h[0], kIn * 2, w.alloc_rows, b.rows, s))) return rc;
+    for (int l = 1; l < kLayers; ++l)
+        if ((rc = zero_frame(w.h[l], kW * 2, w.alloc_rows, b.rows, s))) return rc;
+    hipLaunchKernelGGL(k_onehot, dim3((unsigned)std::min(b.nb, 65535)), dim3(256), 0, s, b, w.h[0]);
+    ConvArgs c{};
+    c.rowseq = b.rowseq;
+    c.rows = b.rows;
+    for (int l = 0; l < kLayers; ++l) {
+        c.X = w.h[l];
+        c.Wt = at<bf16_t>(P, pl.wt[l]);
+        c.bias = at<float>(P, pl.b[l]);
+        if (l == 0) {
+            c.out = w.h[1];
+            hipLaunchKernelGGL((k_conv<kIn, kdp_of(0), kEpiRelu>), dim3(tiles), dim3(256), 0, s, c);
+        } else if (l < kLayers - 1) {
+            c.out = w.h[l + 1];
+            hipLaunchKernelGGL((k_conv<kW, kdp_of(1), kEpiRelu>), dim3(tiles), dim3(256), 0, s, c);
+        } else {
+            c.out = w.z4;
+            hipLaunchKernelGGL((k_conv<kW, kdp_of(1), kEpiLinearF32>), dim3(tiles), dim3(256), 0, s, c);
+        }
+    }
+    hipLaunchKernelGGL(k_pool, dim3((unsigned)std::min(b.nb, 65535)), dim3(128), 0, s, b, w.z4, w.E);
+    return launch_status();
+}
+
+static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t s) {
+    const Batch &b = w.b;
+    const unsigned tiles = (unsigned)((b.rows + kTile - 1) / kTile);
+    const unsigned chunks = (unsigned)((b.rows + kWgChunk - 1) / kWgChunk);
+    int rc;
+    if ((rc = zero_frame(w.dz, kW * 2, w.alloc_rows, b.rows, s))) return rc;
+    if ((rc = zero_frame(w.dz2, kW * 2, w.alloc_rows, b.rows, s))) return rc;
+    hipLaunchKernelGGL(k_pool_bwd, dim3((unsigned)std::min<int64_t>(b.rows, 65535)), dim3(128), 0, s,
+                       b, w.dE, w.dz);
+    bf16_t *dz = w.dz, *dzn = w.dz2;
+    for (int l = kLayers - 1; l >= 0; --l) {
+        float *gw = at<float>(P, pl.gw[l]);
+        float *gb = at<float>(P, pl.gb[l]);
+        if (l == 0)
+            hipLaunchKernelGGL((k_conv_wgrad<kIn, kdp_of(0)>), dim3(chunks, 1), dim3(256), 0, s,
+                               w.h[0], dz, b.rows, gw);
+        else
+            hipLaunchKernelGGL((k_conv_wgrad<kW, kdp_of(1)>), dim3(chunks, kKer), dim3(256), 0, s,
+                               w.h[l], dz, b.rows, gw);
+        hipLaunchKernelGGL(k_bias_grad, dim3(chunks), dim3(128), 0, s, dz, b.rows, gb);
+        if (l > 0) {
+            ConvArgs c{};
+            c.X = dz;
+            c.Wt = at<bf16_t>(P, pl.wbt[l]);
+            c.rowseq = b.rowseq;
+            c.rows = b.rows;
+            c.out = dzn;
+            c.relu_ref = w.h[l];
+            hipLaunchKernelGGL((k_conv<kW, kKer * kW, kEpiGradRelu>), dim3(tiles), dim3(256), 0, s, c);
+            std::swap(dz, dzn);
+        }
+    }
+    return launch_status();
+}
+
+static int setup(const msa_seqs *S, const int32_t *idx, int32_t nb, int64_t total_len, bool train,
+                 int32_t n_pairs, void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s,
+                 CnnWork &w) {
+    int rc;
+    const int64_t rows = total_len + 4 * (int64_t)nb;
+    Sizer sz;
+    cnn_layout(sz, nb, rows, S, train, n_pairs);
+    if (ws_bytes < sz.total()) return MSA_ENOSPC;
+    Carve cv(ws, ws_bytes);
+    Staged st{cv.take<uint8_t>((size_t)S->n * staged_stride(S->max_len)),
+              cv.take<int32_t>((size_t)S->n + 1), staged_stride(S->max_len), S->n};
+    w.b.codes = st.codes;
+    w.b.len = st.len;
+    w.b.stride = st.stride;
+    w.b.idx = idx;
+    w.b.nb = nb;
+    w.b.rows = rows;
+    w.b.roff = cv.take<int64_t>((size_t)nb + 1);
+    w.b.rowseq = cv.take<int32_t>((size_t)rows + 1);
+    w.alloc_rows = alloc_rows_for(rows);
+    w.h[0] = cv.take<bf16_t>((size_t)w.alloc_rows * kIn);
+    for (int l = 1; l < kLayers; ++l) w.h[l] = cv.take<bf16_t>((size_t)w.alloc_rows * kW);
+    w.z4 = cv.take<float>((size_t)w.alloc_rows * kW);
+    w.E = cv.take<float>((size_t)nb * kW);
+    if (train) {
+        w.dz = cv.take<bf16_t>((size_t)w.alloc_rows * kW);
+        w.dz2 = cv.take<bf16_t>((size_t)w.alloc_rows * kW);
+        w.dE = cv.take<float>((size_t)nb * kW);
+        w.loss = cv.take<float>(1);
+        w.label = cv.take<float>((size_t)n_pairs);
+    }
+    if ((rc = stage_set(S, nullptr, st, d_status, s))) return rc;
+    hipLaunchKernelGGL(k_frame_lengths, dim3((nb + 256) / 256), dim3(256), 0, s, w.b, d_status);
+    if ((rc = exclusive_scan_i64(w.b.roff, (int64_t)nb + 1, s))) return rc;
+    hipLaunchKernelGGL(k_frame_rows, dim3((unsigned)std::min(nb, 65535)), dim3(256), 0, s, w.b,
+                       d_status);
+    return launch_status();
+}
+
+static int check_cnn_args(const msa_seqs *S, const int32_t *idx, int32_t nb, int64_t total_len) {
+    int rc;
+    if ((rc = check_seqs(S))) return rc;
+    if (S->sigma > kIn) return MSA_ERANGE;
+    if (idx == nullptr || nb < 1 || total_len < 0) return MSA_EINVAL;
+    return MSA_OK;
+}
+
+}  // namespace msadp
+
+using namespace msadp;
+
+extern "C" {
+
+size_t cnn_param_bytes(void) { return param_layout().bytes; }
+
+int cnn_set_params(void *P, const float *w_host, const float *b_host, hipStream_t s) {
+    if (P == nullptr || w_host == nullptr || b_host == nullptr) return MSA_EINVAL;
+    const ParamLayout pl = param_layout();
+    if (zero(P, pl.bytes / 4 * 4, s)) return MSA_EDEVICE;
+    // host layout: per layer W[k][ci][co] then b[co]; device master [co][k*cin + ci]
+    size_t wo = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const int cin = cin_of(l), kdp = kdp_of(l);
+        const int cin_host = l == 0 ? 0 : kW;   // layer 0 host cin = sigma, padded below
+        (void)cin_host;
+        std::vector<float> m((size_t)kW * kdp, 0.0f);
+        for (int k = 0; k < kKer; ++k)
+            for (int ci = 0; ci < cin; ++ci)
+                for (int co = 0; co < kW; ++co)
+                    m[(size_t)co * kdp + k * cin + ci] = w_host[wo + ((size_t)k * cin + ci) * kW + co];
+        wo += (size_t)kKer * cin * kW;
+        if (hipMemcpy(at<float>(P, pl.w[l]), m.data(), 4 * m.size(), hipMemcpyHostToDevice) ||
+            hipMemcpy(at<float>(P, pl.b[l]), b_host + (size_t)l * kW, 4 * kW, hipMemcpyHostToDevice))
+            return MSA_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_pack_weights, dim3(256), dim3(256), 0, s, P, pl);
+    return launch_status();
+}
+
+int cnn_get_params(const void *Pc, float *w_host, float *b_host, float *gw_host, float *gb_host,
+                   hipStream_t s) {
+    if (Pc == nullptr) return MSA_EINVAL;
+    void *P = (void *)Pc;
+    const ParamLayout pl = param_layout();
+    if (hipStreamSynchronize(s)) return MSA_EDEVICE;
+    size_t wo = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const int cin = cin_of(l), kdp = kdp_of(l);
+        std::vector<float> m((size_t)kW * kdp), g((size_t)kW * kdp);
+        if (hipMemcpy(m.data(), at<float>(P, pl.w[l]), 4 * m.size(), hipMemcpyDeviceToHost) ||
+            hipMemcpy(g.data(), at<float>(P, pl.gw[l]), 4 * g.size(), hipMemcpyDeviceToHost))
+            return MSA_EDEVICE;
+        for (int k = 0; k < kKer; ++k)
+            for (int ci = 0; ci < cin; ++ci)
+                for (int co = 0; co < kW; ++co) {
+                    const size_t h = wo + ((size_t)k * cin + ci) * kW + co;
+                    if (w_host) w_host[h] = m[(size_t)co * kdp + k * cin + ci];
+                    if (gw_host) gw_host[h] = g[(size_t)co * kdp + k * cin + ci];
+                }
+        wo += (size_t)kKer * cin * kW;
+        if ((b_host && hipMemcpy(b_host + (size_t)l * kW, at<float>(P, pl.b[l]), 4 * kW,
+                                 hipMemcpyDeviceToHost)) ||
+            (gb_host && hipMemcpy(gb_host + (size_t)l * kW, at<float>(P, pl.gb[l]), 4 * kW,
+                                  hipMemcpyDeviceToHost)))
+            return MSA_EDEVICE;
+    }
+    return MSA_OK;
+}
+
+size_t cnn_workspace_bytes(const msa_seqs *S, int32_t n_idx, int64_t total_len,
+                           int32_t n_pairs) {
+    if (check_cnn_args(S, (const int32_t *)16, n_idx, total_len) || n_pairs < 0) return 0;
+    Sizer sz;
+    cnn_layout(sz, n_idx, total_len + 4 * (int64_t)n_idx, S, n_pairs > 0, n_pairs);
+    return sz.total();
+}
+
+int cnn_embed(const void *P, const msa_seqs *S, const int32_t *idx, int32_t n_idx,
+              int64_t total_len, float *emb, void *ws, size_t ws_bytes, int32_t *d_status,
+              hipStream_t s) {
+    int rc;
+    if ((rc = check_cnn_args(S, idx, n_idx, total_len))) return rc;
+    if (P == nullptr || emb == nullptr || ws == nullptr) return MSA_EINVAL;
+    const ParamLayout pl = param_layout();
+    CnnWork w{};
+    if ((rc = setup(S, idx, n_idx, total_len, false, 0, ws, ws_bytes, d_status, s, w))) return rc;
+    if ((rc = cnn_forward((void *)P, pl, w, s))) return rc;
+    if (hipMemcpyAsync(emb, w.E, 4 * (size_t)n_idx * kW, hipMemcpyDeviceToDevice, s))
+        return MSA_EDEVICE;
+    return MSA_OK;
+}
+
+int cnn_train_step(void *P, const msa_seqs *S, const int32_t *idx, int32_t n_idx,
+                   int64_t total_len, const int32_t *pa, const int32_t *pb, const uint16_t *dist,
+                   int32_t n_pairs, float lr, int32_t step, float *loss, void *ws,
+                   size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    int rc;
+    if ((rc = check_cnn_args(S, idx, n_idx, total_len))) return rc;
+    if (P == nullptr || pa == nullptr || pb == nullptr || dist == nullptr || n_pairs < 1 ||
+        ws == nullptr || step < 1)
+        return MSA_EINVAL;
+    const ParamLayout pl = param_layout();
+    CnnWork w{};
+    if ((rc = setup(S, idx, n_idx, total_len, true, n_pairs, ws, ws_bytes, d_status, s, w)))
+        return rc;
+    hipLaunchKernelGGL(k_labels, dim3((n_pairs + 255) / 256), dim3(256), 0, s, w.b, pa, pb, dist,
+                       n_pairs, w.label);
+    if ((rc = cnn_forward(P, pl, w, s))) return rc;
+    hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, s, w.dE, (int64_t)n_idx * kW);
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, w.loss, (int64_t)1);
+    for (int l = 0; l < kLayers; ++l) {
+        hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, s, at<float>(P, pl.gw[l]),
+                           (int64_t)kW * kdp_of(l));
+        hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(128), 0, s, at<float>(P, pl.gb[l]),
+                           (int64_t)kW);
+    }
+    hipLaunchKernelGGL(k_pair_loss, dim3(n_pairs), dim3(64), 0, s, w.E, pa, pb, w.label, n_pairs,
+                       w.dE, w.loss);
+    if ((rc = cnn_backward(P, pl, w, s))) return rc;
+    if (lr > 0.0f) {
+        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+        const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+        for (int l = 0; l < kLayers; ++l) {
+            hipLaunchKernelGGL(k_adam, dim3(256), dim3(256), 0, s, at<float>(P, pl.w[l]),
+                               at<float>(P, pl.gw[l]), at<float>(P, pl.mw[l]),
+                               at<float>(P, pl.vw[l]), (int64_t)kW * kdp_of(l), lr, b1, b2, eps,
+                               c1, c2);
+            hipLaunchKernelGGL(k_adam, dim3(1), dim3(128), 0, s, at<float>(P, pl.b[l]),
+                               at<float>(P, pl.gb[l]), at<float>(P, pl.mb[l]),
+                               at<float>(P, pl.vb[l]), (int64_t)kW, lr, b1, b2, eps, c1, c2);
+        }
+        hipLaunchKernelGGL(k_pack_weights, dim3(256), dim3(256), 0, s, P, pl);
+    }
+    if (loss && hipMemcpyAsync(loss, w.loss, 4, hipMemcpyDeviceToDevice, s)) return MSA_EDEVICE;
+    return launch_status();
+}
+
+}  // extern "C"

@@ -369,12 +369,12 @@ static void launch_passes(const TreeArgs &a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
     hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleStore>), lg, tb, 0, s, a);
-    hipMemcpyAsync(a.perm_next, a.perm, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(a.perm_next, a.perm, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
     hipLaunchKernelGGL(k_split, cg, cb, 0, s, a);
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.split, a.split, a.desc);
     hipLaunchKernelGGL(k_make_children, dim3(256), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_next_level, dim3(1), dim3(1), 0, s, a);
-    hipMemcpyAsync(a.perm, a.perm_next, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(a.perm, a.perm_next, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
 }
 
 static void level_pass(const TreeArgs &a, int wclass, int grid, hipStream_t s) {
@@ -514,7 +514,7 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
         level_pass(a, p.wclass, p.grid, s);
         if (hipStreamEndCapture(s, &graph) != hipSuccess) return MSA_EDEVICE;
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            hipGraphDestroy(graph);
+            (void)hipGraphDestroy(graph);
             return MSA_EDEVICE;
         }
     }
@@ -537,8 +537,8 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
         if (host_desc[2] == 0) break;
         total += 2 * host_desc[2];
     }
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (rc) return rc;
     hipLaunchKernelGGL(k_perm_out, dim3((S->n + 255) / 256), dim3(256), 0, s, order, a.perm, S->n,
                        T->perm);

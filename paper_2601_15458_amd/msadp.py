@@ -56,6 +56,13 @@ SIGNATURES = {
     "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
     "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
                             C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
+    "cnn_param_bytes": (C.c_size_t, []),
+    "cnn_set_params": (C.c_int, [P, P, P, P]),
+    "cnn_get_params": (C.c_int, [P, P, P, P, P, P]),
+    "cnn_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int64, C.c_int32]),
+    "cnn_embed": (C.c_int, [P, SP, P, C.c_int32, C.c_int64, P, P, C.c_size_t, P, P]),
+    "cnn_train_step": (C.c_int, [P, SP, P, C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_float,
+                                 C.c_int32, P, P, C.c_size_t, P, P]),
 }
 
 _lib = None
@@ -412,3 +419,100 @@ def align(S: Seqs, use_graph=False, stream=None):
         tb.st.check("tree_build")
         msa = msa_merge(S, tree, stream=stream)
     return tree.host(), msa
+
+
+# ---------------------------------------------------------------- embedder
+CNN_LAYERS, CNN_WIDTH, CNN_K, CNN_IN = 4, 128, 5, 8
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Embedder:
+    """Device parameters of the CNN surrogate (see include/msadp.h)."""
+
+    def __init__(self, dev=None):
+        dev = dev or _device()
+        self.dev = dev
+        self.params = torch.zeros(lib().cnn_param_bytes(), dtype=torch.uint8, device=dev)
+        self.step = 0
+
+    def set_params(self, params):
+        """params: list of (W[K][cin][128], b[128]) float arrays; layer 0 may
+        have cin = sigma (< 8): the extra one-hot channels get zero weights."""
+        ws, bs = [], []
+        for l, (W, b) in enumerate(params):
+            W = np.asarray(W, dtype=np.float32)
+            if l == 0 and W.shape[1] < CNN_IN:
+                W = np.concatenate([W, np.zeros((W.shape[0], CNN_IN - W.shape[1], W.shape[2]),
+                                                np.float32)], axis=1)
+            ws.append(W.ravel())
+            bs.append(np.asarray(b, dtype=np.float32).ravel())
+        w = np.ascontiguousarray(np.concatenate(ws))
+        b = np.ascontiguousarray(np.concatenate(bs))
+        _check(lib().cnn_set_params(_ptr(self.params), _np_ptr(w), _np_ptr(b),
+                                    _stream(None)), "cnn_set_params")
+        torch.cuda.synchronize()
+        self.step = 0
+
+    def get(self):
+        """(params, grads) as lists of (W[K][cin][128], b[128]) float32."""
+        sizes = [CNN_K * (CNN_IN if l == 0 else CNN_WIDTH) * CNN_WIDTH for l in range(CNN_LAYERS)]
+        w = np.zeros(sum(sizes), np.float32)
+        gw = np.zeros(sum(sizes), np.float32)
+        b = np.zeros(CNN_LAYERS * CNN_WIDTH, np.float32)
+        gb = np.zeros(CNN_LAYERS * CNN_WIDTH, np.float32)
+        torch.cuda.synchronize()
+        _check(lib().cnn_get_params(_ptr(self.params), _np_ptr(w), _np_ptr(b), _np_ptr(gw),
+                                    _np_ptr(gb), _stream(None)), "cnn_get_params")
+        out_p, out_g, o = [], [], 0
+        for l, n in enumerate(sizes):
+            cin = CNN_IN if l == 0 else CNN_WIDTH
+            shape = (CNN_K, cin, CNN_WIDTH)
+            out_p.append((w[o:o + n].reshape(shape), b[l * CNN_WIDTH:(l + 1) * CNN_WIDTH]))
+            out_g.append((gw[o:o + n].reshape(shape), gb[l * CNN_WIDTH:(l + 1) * CNN_WIDTH]))
+            o += n
+        return out_p, out_g
+
+    def embed(self, S: Seqs, idx=None, chunk=16384, stream=None):
+        """float32 embeddings [len(idx), 128] (device tensor)."""
+        idx = np.arange(S.n, dtype=np.int32) if idx is None else np.asarray(idx, np.int32)
+        out = torch.empty((len(idx), CNN_WIDTH), dtype=torch.float32, device=self.dev)
+        ss = S.struct()
+        st = Status(self.dev)
+        for a in range(0, len(idx), chunk):
+            sub = idx[a:a + chunk]
+            tl = int(S.lengths[sub].sum())
+            wsb = lib().cnn_workspace_bytes(C.byref(ss), len(sub), tl, 0)
+            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=self.dev)
+            d_idx = torch.from_numpy(sub).to(self.dev)
+            rc = lib().cnn_embed(_ptr(self.params), C.byref(ss), _ptr(d_idx), len(sub), tl,
+                                 _ptr(out[a:a + len(sub)]), _ptr(ws), wsb, _ptr(st.t),
+                                 _stream(stream))
+            _check(rc, "cnn_embed")
+        st.check("cnn_embed")
+        return out
+
+    def train_step(self, S: Seqs, idx, pa, pb, dist, lr=1e-3, stream=None):
+        """One Adam step; returns the batch loss before the update."""
+        idx = np.asarray(idx, np.int32)
+        tl = int(S.lengths[idx].sum())
+        ss = S.struct()
+        wsb = lib().cnn_workspace_bytes(C.byref(ss), len(idx), tl, len(pa))
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=self.dev)
+        d_idx = torch.from_numpy(idx).to(self.dev)
+        d_pa = _i32(pa, self.dev)
+        d_pb = _i32(pb, self.dev)
+        d_dist = dist if isinstance(dist, torch.Tensor) else \
+            torch.from_numpy(np.asarray(dist, np.uint16)).to(self.dev)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.dev)
+        st = Status(self.dev)
+        self.step += 1
+        rc = lib().cnn_train_step(_ptr(self.params), C.byref(ss), _ptr(d_idx), len(idx), tl,
+                                  _ptr(d_pa), _ptr(d_pb), _ptr(d_dist), len(pa), float(lr),
+                                  self.step, _ptr(loss), _ptr(ws), wsb, _ptr(st.t),
+                                  _stream(stream))
+        _check(rc, "cnn_train_step")
+        st.check("cnn_train_step")
+        return float(loss.item())

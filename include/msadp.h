@@ -161,6 +161,21 @@ size_t tree_workspace_bytes(const msa_seqs *S);
 int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
                void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
+/* The same tree build with the medoid step (Alg. 1, the geometric median
+ * of each cluster) pruned by a surrogate; not a method of the paper, which
+ * only allows the median to be taken over a subset to save time.  emb
+ * (device float[n][128], row i = embedding of input i, e.g. from cnn_embed)
+ * ranks every member by its summed Euclidean embedding distance to the
+ * cluster; the topk best (lowest input index on ties, 1 <= topk <= 32) get
+ * exact Levenshtein row sums over the whole cluster and c is the one with
+ * the least (lowest input index on ties).  Poles, split and every other
+ * step stay exact, so a cluster of at most topk members gets the same c
+ * as tree_build.  Same outputs, workspace and errors as tree_build;
+ * EINVAL when emb is null or topk is out of range. */
+int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, const msa_tree *T,
+                      int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
+                      int32_t *d_status, hipStream_t s);
+
 /* ------------------------------------------------------------------ */
 /* Bottom-up merge (Sec. 2.2) over a tree from tree_build (T, n_nodes as
  * returned).  A leaf's alignment is its sequence.  For an internal node the

@@ -16,7 +16,9 @@
  *     value (Sec. 2.2 step 2 aligns the two centers and records the gap
  *     positions; the tie order diag > up > left is this project's reading,
  *     the paper names none).
- *   - Alg. 1 (Partition) with the full geometric median (Sec. 2.1).
+ *   - Alg. 1 (Partition) with the full geometric median (Sec. 2.1), and
+ *     the same with the median taken over candidates that a learned
+ *     embedding ranks first (a surrogate of this project, not the paper's).
  *   - The bottom-up merge of Sec. 2.2.
  * Pairs are independent, so OpenMP spreads them over host threads; that is
  * the only concession to speed.
@@ -28,6 +30,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -157,10 +160,42 @@ static int64_t dist_of(const uint8_t *codes, const int64_t *off, int32_t x, int3
     return orc_lev(codes + off[x], off[x + 1] - off[x], codes + off[y], off[y + 1] - off[y]);
 }
 
-int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
-                 int32_t *parent, int32_t *left, int32_t *right, int32_t *center,
-                 int32_t *lpole, int32_t *rpole, int32_t *depth,
-                 int64_t *mstart, int64_t *mcount, int32_t *perm) {
+/* Surrogate distance of two embeddings (128 floats each), in the exact
+ * float32 steps the pruned medoid uses: squares of the coordinate
+ * differences added one coordinate after another (each difference, square
+ * and sum rounded to float, no fused multiply-add), the square root, then
+ * the value in units of 2^-24 rounded to the nearest integer (ties to even).
+ * Rounding decides the candidate ranking, so both sides take the same
+ * float32 steps; the integer row sums are then exact. */
+static uint64_t emb_dist_q(const float *ex, const float *ey) {
+    float acc = 0.0f;
+    for (int c = 0; c < 128; ++c) {
+        const float d = ex[c] - ey[c];
+        const float sq = d * d;
+        acc = acc + sq;
+    }
+    return (uint64_t)rintf(sqrtf(acc) * 16777216.0f);
+}
+
+/* f(C[x], C[y]) for every y of the cluster. */
+static int64_t *dist_row(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
+                         int64_t x) {
+    int64_t *row = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t y = 0; y < k; ++y) row[y] = dist_of(codes, off, C[x], C[y]);
+    return row;
+}
+
+/* Alg. 1 (Partition).  emb == NULL: c is the full geometric median of the
+ * cluster (Sec. 2.1).  Otherwise c is the surrogate-pruned median: every
+ * member x gets the estimate E(x) = sum over the cluster of emb_dist_q,
+ * the topk members with the least (E, input index) are the candidates,
+ * and c is the candidate with the least exact sum of f over the cluster
+ * (lowest input index on ties).  l, r and the split are the same in both. */
+static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
+                         int32_t topk, int32_t *parent, int32_t *left, int32_t *right,
+                         int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
+                         int64_t *mstart, int64_t *mcount, int32_t *perm) {
     if (n <= 0) return 0;
     /* members[v]: ascending member list of node v */
     int32_t **members = (int32_t **)calloc((size_t)(2 * n), sizeof(int32_t *));
@@ -175,39 +210,78 @@ int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
         int32_t *C = members[v];
         left[v] = right[v] = lpole[v] = rpole[v] = -1;
         if (k == 1) { center[v] = C[0]; continue; }
-        /* geometric median over the whole cluster */
-        int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k * k));
-        #pragma omp parallel for schedule(dynamic, 1)
-        for (int64_t x = 0; x < k; ++x) {
-            D[x * k + x] = 0;
-            for (int64_t y = x + 1; y < k; ++y) {
-                int64_t d = dist_of(codes, off, C[x], C[y]);
-                D[x * k + y] = d;
-                D[y * k + x] = d;
+        int64_t best = -1;
+        int64_t *rowc;
+        if (emb == NULL) {
+            /* geometric median over the whole cluster */
+            int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k * k));
+            #pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t x = 0; x < k; ++x) {
+                D[x * k + x] = 0;
+                for (int64_t y = x + 1; y < k; ++y) {
+                    int64_t d = dist_of(codes, off, C[x], C[y]);
+                    D[x * k + y] = d;
+                    D[y * k + x] = d;
+                }
             }
-        }
-        int64_t best = -1, best_sum = 0;
-        for (int64_t x = 0; x < k; ++x) {
-            int64_t s = 0;
-            for (int64_t y = 0; y < k; ++y) s += D[x * k + y];
-            if (best < 0 || s < best_sum) { best = x; best_sum = s; }
+            int64_t best_sum = 0;
+            for (int64_t x = 0; x < k; ++x) {
+                int64_t s = 0;
+                for (int64_t y = 0; y < k; ++y) s += D[x * k + y];
+                if (best < 0 || s < best_sum) { best = x; best_sum = s; }
+            }
+            rowc = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+            memcpy(rowc, D + best * k, sizeof(int64_t) * (size_t)k);
+            free(D);
+        } else {
+            uint64_t *E = (uint64_t *)calloc((size_t)k, sizeof(uint64_t));
+            #pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t x = 0; x < k; ++x)
+                for (int64_t y = 0; y < k; ++y)
+                    E[x] += emb_dist_q(emb + (int64_t)C[x] * 128, emb + (int64_t)C[y] * 128);
+            char *taken = (char *)calloc((size_t)k, 1);
+            int64_t best_sum = 0;
+            const int64_t nc = k < topk ? k : topk;
+            for (int64_t j = 0; j < nc; ++j) {
+                int64_t cand = -1;   /* least (E, index) not yet taken */
+                for (int64_t x = 0; x < k; ++x)
+                    if (!taken[x] && (cand < 0 || E[x] < E[cand])) cand = x;
+                if (cand < 0) break;
+                taken[cand] = 1;
+                int64_t *row = dist_row(codes, off, C, k, cand);
+                int64_t s = 0;
+                for (int64_t y = 0; y < k; ++y) s += row[y];
+                free(row);
+                if (best < 0 || s < best_sum || (s == best_sum && cand < best)) {
+                    best = cand;
+                    best_sum = s;
+                }
+            }
+            free(taken);
+            free(E);
+            rowc = dist_row(codes, off, C, k, best);
         }
         int64_t lp = 0;
-        for (int64_t x = 1; x < k; ++x) if (D[best * k + x] > D[best * k + lp]) lp = x;
+        for (int64_t x = 1; x < k; ++x) if (rowc[x] > rowc[lp]) lp = x;
         center[v] = C[best];
-        if (D[best * k + lp] == 0) { free(D); continue; }   /* radius 0: leaf */
+        const int64_t radius = rowc[lp];
+        free(rowc);
+        if (radius == 0) continue;   /* radius 0: leaf */
+        int64_t *rowl = dist_row(codes, off, C, k, lp);
         int64_t rp = 0;
-        for (int64_t x = 1; x < k; ++x) if (D[lp * k + x] > D[lp * k + rp]) rp = x;
+        for (int64_t x = 1; x < k; ++x) if (rowl[x] > rowl[rp]) rp = x;
+        int64_t *rowr = dist_row(codes, off, C, k, rp);
         lpole[v] = C[lp];
         rpole[v] = C[rp];
         int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
         int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
         int64_t nl = 0, nr = 0;
         for (int64_t x = 0; x < k; ++x) {
-            if (D[lp * k + x] <= D[rp * k + x]) L[nl++] = C[x];
+            if (rowl[x] <= rowr[x]) L[nl++] = C[x];
             else R[nr++] = C[x];
         }
-        free(D);
+        free(rowl);
+        free(rowr);
         int32_t a = n_nodes++, b = n_nodes++;
         members[a] = L; msize[a] = nl;
         members[b] = R; msize[b] = nr;
@@ -230,6 +304,36 @@ int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
     free(members);
     free(msize);
     return n_nodes;
+}
+
+int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
+                 int32_t *parent, int32_t *left, int32_t *right, int32_t *center,
+                 int32_t *lpole, int32_t *rpole, int32_t *depth,
+                 int64_t *mstart, int64_t *mcount, int32_t *perm) {
+    return tree_impl(codes, off, n, NULL, 0, parent, left, right, center, lpole, rpole, depth,
+                     mstart, mcount, perm);
+}
+
+/* The same with the surrogate-pruned median (emb: float[n][128]). */
+int32_t orc_tree_pruned(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
+                        int32_t topk, int32_t *parent, int32_t *left, int32_t *right,
+                        int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
+                        int64_t *mstart, int64_t *mcount, int32_t *perm) {
+    if (emb == NULL || topk < 1) return -1;
+    return tree_impl(codes, off, n, emb, topk, parent, left, right, center, lpole, rpole, depth,
+                     mstart, mcount, perm);
+}
+
+/* Surrogate row sums E(x) of emb_dist_q over an explicit member list
+ * (for tests of the ranking step). */
+void orc_emb_rowsums(const float *emb, const int32_t *members, int64_t k, uint64_t *E) {
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t x = 0; x < k; ++x) {
+        uint64_t s = 0;
+        for (int64_t y = 0; y < k; ++y)
+            s += emb_dist_q(emb + (int64_t)members[x] * 128, emb + (int64_t)members[y] * 128);
+        E[x] = s;
+    }
 }
 
 /* ------------------------------------------------------------------ merge

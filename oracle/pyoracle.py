@@ -33,6 +33,10 @@ def lib():
         L.orc_nw_pairs.argtypes = [P, P, P, P, P, P, C.c_int64, P, P, P, P]
         L.orc_tree.restype = C.c_int32
         L.orc_tree.argtypes = [P, P, C.c_int32] + [P] * 10
+        L.orc_tree_pruned.restype = C.c_int32
+        L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_int32] + [P] * 10
+        L.orc_emb_rowsums.restype = None
+        L.orc_emb_rowsums.argtypes = [P, P, C.c_int64, P]
         L.orc_merge.restype = C.c_int64
         L.orc_merge.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
                                 C.c_int64]
@@ -124,6 +128,36 @@ def tree(codes, offsets):
     out["perm"] = perm[:n].copy()
     out["n_nodes"] = int(k)
     return out
+
+
+def tree_pruned(codes, offsets, emb, topk=16):
+    """Alg. 1 with the surrogate-pruned median (emb: float32 [n, 128])."""
+    codes = _u8(codes)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(offsets) - 1
+    emb = np.ascontiguousarray(emb, dtype=np.float32)
+    assert emb.shape == (n, 128)
+    cap = max(2 * n - 1, 1)
+    arr = {f: np.zeros(cap, dtype=np.int64 if f in ("mstart", "mcount") else np.int32)
+           for f in TREE_FIELDS}
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    k = lib().orc_tree_pruned(_p(codes), _p(offsets), n, _p(emb), int(topk),
+                              *[_p(arr[f]) for f in TREE_FIELDS], _p(perm))
+    if k < 0:
+        raise ValueError("bad arguments")
+    out = {f: arr[f][:k].copy() for f in TREE_FIELDS}
+    out["perm"] = perm[:n].copy()
+    out["n_nodes"] = int(k)
+    return out
+
+
+def emb_rowsums(emb, members):
+    """Surrogate row sums E(x) over the member list (uint64 units of 2^-24)."""
+    emb = np.ascontiguousarray(emb, dtype=np.float32)
+    members = np.ascontiguousarray(members, dtype=np.int32)
+    E = np.zeros(len(members), dtype=np.uint64)
+    lib().orc_emb_rowsums(_p(emb), _p(members), len(members), _p(E))
+    return E
 
 
 def merge(codes, offsets, sigma, t):

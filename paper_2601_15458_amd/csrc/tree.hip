@@ -22,7 +22,12 @@
 
 namespace msadp {
 
-enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3 };
+enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 4 };
+
+// Surrogate-pruned medoid: at most this many candidates per cluster get
+// exact row sums.
+constexpr int kMaxCand = 32;
+constexpr float kEmbScale = 16777216.0f;   // fixed point of embedding distances (2^24)
 
 struct TreeArgs {
     Staged S;
@@ -47,6 +52,12 @@ struct TreeArgs {
     int32_t *st;             // device status
     int32_t sigma;
     int32_t n;
+    // surrogate-pruned medoid (emb == nullptr: exact medoid)
+    const float *emb;        // [n][128] by input index
+    int32_t topk;
+    int32_t *cand;           // [nq][kMaxCand] candidate ranks
+    int32_t *ncand;          // [nq]
+    uint64_t *candsum;       // [nq][kMaxCand] exact row sums of the candidates
 };
 
 constexpr int kClusterGrid = 2048;
@@ -89,6 +100,7 @@ __global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
             a.nleft[q] = -1;
             a.split[q] = 0;
         }
+        if (a.emb != nullptr && threadIdx.x < kMaxCand) a.candsum[(int64_t)q * kMaxCand + threadIdx.x] = 0;
         for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.rowsum[ms + i] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -147,6 +159,7 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
         const int64_t ms = a.mstart[v], k = a.mcount[v];
         int64_t tpos, prow_pos = -1;
         int32_t prow;
+        int64_t cslot = 0;
         if (MODE == kMedoid) {
             const int64_t u = triangle_row(local, k - 1);
             const int64_t p = k - 1 - u;
@@ -154,6 +167,12 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
             prow_pos = ms + p;
             prow = a.perm[prow_pos];
             tpos = ms + p + 1 + blk * 64 + lane;
+        } else if (MODE == kCandSum) {
+            const int64_t nblk = (k + 63) / 64;
+            const int64_t j = local / nblk, blk = local % nblk;
+            cslot = (int64_t)q * kMaxCand + j;
+            prow = a.cand[cslot];
+            tpos = ms + blk * 64 + lane;
         } else {
             prow = a.pat[q];
             tpos = ms + local * 64 + lane;
@@ -178,6 +197,11 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
                 valid ? (((uint64_t)d << 32) | (0xFFFFFFFFu - (uint32_t)a.order[trow])) : 0ull;
             const uint64_t m = wave_max_u64(key);
             atomicMax((unsigned long long *)&a.key[q], (unsigned long long)m);
+        }
+        if (MODE == kCandSum) {
+            const uint64_t s = wave_sum_u64(valid ? (uint64_t)d : 0ull);
+            atomicAdd((unsigned long long *)&a.candsum[cslot],
+                      (unsigned long long)(lane == 0 ? s : 0ull));
         }
         if (MODE == kPoleMaxStore) a.dl[slot] = d;
         if (MODE == kPoleStore) a.dr[slot] = d;
@@ -350,14 +374,154 @@ __global__ void k_perm_out(const int32_t *order, const int32_t *perm, int32_t n,
     if (r < n) out[r] = order[perm[r]];
 }
 
+// Surrogate distance of two embeddings in units of 2^-24: the squared
+// coordinate differences are added one coordinate after another with every
+// step rounded to float (no fused multiply-add), then the square root is
+// scaled and rounded to the nearest integer.  Fixing these float steps
+// makes the candidate ranking reproducible; the row sums are exact integers.
+__device__ __forceinline__ uint64_t emb_dist_q(const float4 *x, const float4 *y) {
+#pragma clang fp contract(off)
+    float acc = 0.0f;
+#pragma unroll 8
+    for (int c = 0; c < 32; ++c) {
+        const float4 a = x[c], b = y[c];
+        const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+        acc = acc + d0 * d0;
+        acc = acc + d1 * d1;
+        acc = acc + d2 * d2;
+        acc = acc + d3 * d3;
+    }
+    return (uint64_t)rintf(sqrtf(acc) * kEmbScale);
+}
+
+// Estimated medoid row sums from the embeddings: over every pair of every
+// cluster (the same triangle as the exact medoid pass) add
+// ||e_x - e_y|| in fixed point to both ends.
+__global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
+    const int lane = lane_id();
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    const int64_t total = a.items[nq];
+    if (nq < 1 || nq > a.n || total < 0 || total > items_upto(a.n)) {
+        if (blockIdx.x == 0 && lane == 0) set_status(a.st, MSA_DS_CAPACITY);
+        return;
+    }
+    for (;;) {
+        const uint32_t it = next_item(a.counter);
+        if ((int64_t)it >= total) break;
+        const int32_t q = find_cluster(a.items, nq, it);
+        const int64_t local = (int64_t)it - a.items[q];
+        const int32_t v = lvl + q;
+        const int64_t ms = a.mstart[v], k = a.mcount[v];
+        const int64_t u = triangle_row(local, k - 1);
+        const int64_t p = k - 1 - u;
+        const int64_t blk = local - items_upto(u - 1);
+        const int64_t ppos = ms + p;
+        const int64_t tpos = ms + p + 1 + blk * 64 + lane;
+        const bool valid = tpos < ms + k;
+        const float4 *ep = (const float4 *)(a.emb + (int64_t)a.order[a.perm[ppos]] * 128);
+        const float4 *et = (const float4 *)(a.emb + (int64_t)a.order[a.perm[valid ? tpos : ms]] * 128);
+        const uint64_t qd = valid ? emb_dist_q(ep, et) : 0ull;
+        const int64_t slot = valid ? tpos : (int64_t)a.n;
+        atomicAdd((unsigned long long *)&a.rowsum[slot], (unsigned long long)qd);
+        const uint64_t s = wave_sum_u64(qd);
+        atomicAdd((unsigned long long *)&a.rowsum[ppos], (unsigned long long)(lane == 0 ? s : 0ull));
+    }
+}
+
+__device__ __forceinline__ bool key_less(uint64_t s0, uint32_t i0, uint64_t s1, uint32_t i1) {
+    return s0 < s1 || (s0 == s1 && i0 < i1);
+}
+
+// The topk members with the least estimated row sum (lowest input index on
+// ties), one workgroup per cluster: topk rounds of a block-wide minimum
+// over the members above the last pick.
+__global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
+    __shared__ uint64_t rs[256];
+    __shared__ uint32_t ri[256];
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int32_t v = lvl + q;
+        const int64_t ms = a.mstart[v], k = a.mcount[v];
+        const int32_t nc = (int32_t)min<int64_t>(k, a.topk);
+        uint64_t last_s = 0;
+        uint32_t last_i = 0;
+        bool have_last = false;
+        for (int32_t j = 0; j < nc; ++j) {
+            uint64_t bs = ~0ull;
+            uint32_t bi = ~0u;
+            int64_t bpos = -1;
+            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+                const uint64_t sv = a.rowsum[ms + i];
+                const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
+                if (have_last && !key_less(last_s, last_i, sv, oi)) continue;
+                if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; bpos = ms + i; }
+            }
+            rs[threadIdx.x] = bs;
+            ri[threadIdx.x] = bi;
+            __syncthreads();
+            for (int o = 128; o >= 1; o >>= 1) {
+                if (threadIdx.x < o && key_less(rs[threadIdx.x + o], ri[threadIdx.x + o],
+                                                rs[threadIdx.x], ri[threadIdx.x])) {
+                    rs[threadIdx.x] = rs[threadIdx.x + o];
+                    ri[threadIdx.x] = ri[threadIdx.x + o];
+                }
+                __syncthreads();
+            }
+            last_s = rs[0];
+            last_i = ri[0];
+            have_last = true;
+            if (threadIdx.x == 0) a.cand[(int64_t)q * kMaxCand + j] = a.rank_of[last_i];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            a.ncand[q] = nc;
+            a.cnt[q] = k >= 2 ? (int64_t)nc * ((k + 63) / 64) : 0;
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
+}
+
+// c = the candidate with the least exact row sum (lowest input index on ties).
+__global__ void k_pick_center_cand(TreeArgs a) {
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const int32_t v = lvl + q;
+        const int64_t k = a.mcount[v];
+        const int32_t nc = a.ncand[q];
+        uint64_t bs = ~0ull;
+        uint32_t bi = ~0u;
+        for (int32_t j = 0; j < nc; ++j) {
+            const uint64_t sv = a.candsum[(int64_t)q * kMaxCand + j];
+            const uint32_t oi = (uint32_t)a.order[a.cand[(int64_t)q * kMaxCand + j]];
+            if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; }
+        }
+        if (k == 1) bi = (uint32_t)a.order[a.perm[a.mstart[v]]];
+        a.center[v] = (int32_t)bi;
+        a.pat[q] = a.rank_of[bi];
+        a.key[q] = 0;
+        a.cnt[q] = k >= 2 ? (k + 63) / 64 : 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
+}
+
 template <int WMAX>
-static void launch_passes(const TreeArgs &a, int grid, hipStream_t s) {
+static void launch_passes(const TreeArgs &a, int grid, int egrid, hipStream_t s) {
     const dim3 cg(kClusterGrid), cb(256), tb(64), lg(grid);
     hipLaunchKernelGGL(k_level_init, cg, cb, 0, s, a);
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-    hipLaunchKernelGGL((k_tree_lev<WMAX, kMedoid>), lg, tb, 0, s, a);
-    hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
+    if (a.emb == nullptr) {
+        hipLaunchKernelGGL((k_tree_lev<WMAX, kMedoid>), lg, tb, 0, s, a);
+        hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_emb_rowsum, dim3(egrid), tb, 0, s, a);
+        hipLaunchKernelGGL(k_topk, cg, cb, 0, s, a);
+        hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+        hipLaunchKernelGGL((k_tree_lev<WMAX, kCandSum>), lg, tb, 0, s, a);
+        hipLaunchKernelGGL(k_pick_center_cand, dim3(256), dim3(256), 0, s, a);
+    }
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
     hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMax>), lg, tb, 0, s, a);
@@ -377,14 +541,20 @@ static void launch_passes(const TreeArgs &a, int grid, hipStream_t s) {
     (void)hipMemcpyAsync(a.perm, a.perm_next, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
 }
 
-static void level_pass(const TreeArgs &a, int wclass, int grid, hipStream_t s) {
+static void level_pass(const TreeArgs &a, int wclass, int grid, int egrid, hipStream_t s) {
     switch (wclass) {
-        case 4: launch_passes<4>(a, grid, s); break;
-        case 8: launch_passes<8>(a, grid, s); break;
-        case 16: launch_passes<16>(a, grid, s); break;
-        case 24: launch_passes<24>(a, grid, s); break;
-        default: launch_passes<32>(a, grid, s); break;
+        case 4: launch_passes<4>(a, grid, egrid, s); break;
+        case 8: launch_passes<8>(a, grid, egrid, s); break;
+        case 16: launch_passes<16>(a, grid, egrid, s); break;
+        case 24: launch_passes<24>(a, grid, egrid, s); break;
+        default: launch_passes<32>(a, grid, egrid, s); break;
     }
+}
+
+static int emb_grid() {
+    static int g = 0;
+    if (g == 0) g = persistent_grid(k_emb_rowsum);
+    return g;
 }
 
 static int tree_grid(int wclass) {
@@ -438,6 +608,9 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<int32_t>(n + 1);           // dr
     al.template take<uint32_t>(1);              // counter
     if (p.hstride) al.template take<uint32_t>((size_t)p.grid * kWave * p.hstride);
+    al.template take<int32_t>(n * kMaxCand);    // candidates
+    al.template take<int32_t>(n);               // candidate counts
+    al.template take<uint64_t>(n * kMaxCand);   // candidate sums
 }
 
 }  // namespace msadp
@@ -453,8 +626,9 @@ size_t tree_workspace_bytes(const msa_seqs *S) {
     return sz.total();
 }
 
-int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
-               void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, const msa_tree *T,
+                      int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
+                      int32_t *d_status, hipStream_t s) {
     int rc;
     if ((rc = check_seqs(S))) return rc;
     if (T == nullptr || n_nodes == nullptr) return MSA_EINVAL;
@@ -495,6 +669,11 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
     a.counter = cv.take<uint32_t>(1);
     a.hbuf = p.hstride ? cv.take<uint32_t>((size_t)p.grid * kWave * p.hstride) : nullptr;
     a.hstride = p.hstride;
+    a.cand = cv.take<int32_t>(n * kMaxCand);
+    a.ncand = cv.take<int32_t>(n);
+    a.candsum = cv.take<uint64_t>(n * kMaxCand);
+    a.emb = emb;
+    a.topk = topk;
     a.sigma = S->sigma;
     a.n = S->n;
     a.st = d_status;
@@ -511,7 +690,7 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
     if (use_graph) {
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return MSA_EDEVICE;
-        level_pass(a, p.wclass, p.grid, s);
+        level_pass(a, p.wclass, p.grid, emb_grid(), s);
         if (hipStreamEndCapture(s, &graph) != hipSuccess) return MSA_EDEVICE;
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGraphDestroy(graph);
@@ -525,7 +704,7 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
         if (use_graph) {
             if (hipGraphLaunch(exec, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
         } else {
-            level_pass(a, p.wclass, p.grid, s);
+            level_pass(a, p.wclass, p.grid, emb_grid(), s);
         }
         if ((rc = launch_status())) break;
         if (hipMemcpyAsync(host_desc, a.desc, sizeof(host_desc), hipMemcpyDeviceToHost, s) !=
@@ -545,6 +724,18 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
     if ((rc = launch_status())) return rc;
     *n_nodes = total;
     return MSA_OK;
+}
+
+int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
+               void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    return build_impl(S, nullptr, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
+}
+
+int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, const msa_tree *T,
+                      int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
+                      int32_t *d_status, hipStream_t s) {
+    if (emb == nullptr || topk < 1 || topk > kMaxCand) return MSA_EINVAL;
+    return build_impl(S, emb, topk, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
 }
 
 }  // extern "C"

@@ -53,6 +53,8 @@ SIGNATURES = {
     "nw_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
     "tree_workspace_bytes": (C.c_size_t, [SP]),
     "tree_build": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
+    "tree_build_pruned": (C.c_int, [SP, P, C.c_int32, P, C.POINTER(C.c_int32), C.c_int32, P,
+                                    C.c_size_t, P, P]),
     "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
     "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
                             C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
@@ -340,10 +342,18 @@ class Tree:
 
 
 class TreeBuilder:
-    """Reusable Alg. 1 builder for one sequence set."""
+    """Reusable Alg. 1 builder for one sequence set.  With emb (device
+    float32 [n, 128]) the medoid is pruned to the topk members closest in
+    embedding space (tree_build_pruned)."""
 
-    def __init__(self, S: Seqs, use_graph=False):
+    def __init__(self, S: Seqs, use_graph=False, emb=None, topk=16):
         self.S = S
+        if emb is not None:
+            if (emb.dtype != torch.float32 or emb.device != S.codes.device
+                    or tuple(emb.shape) != (S.n, 128) or not emb.is_contiguous()):
+                raise ValueError("emb must be a contiguous float32 [n, 128] tensor on the device")
+        self.emb = emb
+        self.topk = int(topk)
         dev = S.codes.device
         self.ss = S.struct()
         self.tree = Tree(S.n, dev)
@@ -355,19 +365,26 @@ class TreeBuilder:
 
     def __call__(self, stream=None):
         nn = C.c_int32(0)
-        rc = lib().tree_build(C.byref(self.ss), C.byref(self.ts), C.byref(nn),
-                              int(self.use_graph), _ptr(self.ws), self.wsb, _ptr(self.st.t),
-                              _stream(stream))
-        _check(rc, "tree_build")
+        if self.emb is None:
+            rc = lib().tree_build(C.byref(self.ss), C.byref(self.ts), C.byref(nn),
+                                  int(self.use_graph), _ptr(self.ws), self.wsb, _ptr(self.st.t),
+                                  _stream(stream))
+            _check(rc, "tree_build")
+        else:
+            rc = lib().tree_build_pruned(C.byref(self.ss), _ptr(self.emb), self.topk,
+                                         C.byref(self.ts), C.byref(nn), int(self.use_graph),
+                                         _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
+            _check(rc, "tree_build_pruned")
         self.tree.n_nodes = nn.value
         return self.tree
 
 
-def tree_build(S: Seqs, use_graph=False, stream=None):
-    """Alg. 1 guide tree of S; returns host numpy arrays like the oracle's."""
+def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16):
+    """Alg. 1 guide tree of S; returns host numpy arrays like the oracle's.
+    emb/topk select the surrogate-pruned medoid (see TreeBuilder)."""
     if use_graph and stream is None:
         stream = torch.cuda.Stream()
-    tb = TreeBuilder(S, use_graph)
+    tb = TreeBuilder(S, use_graph, emb, topk)
     with torch.cuda.stream(stream) if stream is not None else _nullctx():
         t = tb(stream)
     torch.cuda.synchronize()

@@ -1,0 +1,127 @@
+"""Surrogate-pruned Alg. 1 on the GPU against the CPU oracle (node arrays equal).
+
+The candidate ranking takes fixed float32 steps on both sides, so the
+pruned tree is reproduced exactly, not approximately."""
+import numpy as np
+import pytest
+
+from oracle import pyoracle as orc
+from paper_2601_15458_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _msadp():
+    from paper_2601_15458_amd import msadp
+    return msadp
+
+
+def _emb(seed, n, scale=0.1):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, 128)) * scale).astype(np.float32)
+
+
+def _equal_trees(got, want):
+    assert got["n_nodes"] == want["n_nodes"]
+    for f in orc.TREE_FIELDS:
+        g = got[f].astype(np.int64)
+        w = want[f].astype(np.int64)
+        bad = np.flatnonzero(g != w)
+        assert len(bad) == 0, (f, bad[:5], g[bad[:5]], w[bad[:5]])
+    gp, wp = got["perm"].copy(), want["perm"].copy()
+    for v in range(want["n_nodes"]):
+        if want["left"][v] < 0 and want["mcount"][v] > 1:
+            a, k = want["mstart"][v], want["mcount"][v]
+            gp[a:a + k].sort()
+            wp[a:a + k].sort()
+    assert np.array_equal(gp, wp)
+
+
+def _compare(codes, off, sigma, emb, topk, use_graph=False):
+    import torch
+    M = _msadp()
+    n = len(off) - 1
+    print(f"[pruned] n={n} sigma={sigma} topk={topk} graph={use_graph}: device", flush=True)
+    S = M.to_device(codes, off, sigma)
+    e = torch.from_numpy(emb).to(S.codes.device)
+    got = M.tree_build(S, use_graph=use_graph, emb=e, topk=topk)
+    print(f"[pruned] device done ({got['n_nodes']} nodes); oracle", flush=True)
+    want = orc.tree_pruned(codes, off, emb, topk=topk)
+    _equal_trees(got, want)
+    return got
+
+
+@pytest.mark.parametrize("topk", [1, 4, 16])
+def test_tiny_workload(topk):
+    d = synth.tiny()
+    _compare(d["codes"], d["offsets"], d["sigma"], _emb(20 + topk, d["n"]), topk)
+
+
+def test_tiny_workload_graph_replay():
+    d = synth.tiny()
+    _compare(d["codes"], d["offsets"], d["sigma"], _emb(30, d["n"]), 8, use_graph=True)
+
+
+def test_protein_subset():
+    d = synth.protein_tree()
+    rng = np.random.default_rng(35)
+    sub = synth.subset(d, rng.choice(d["n"], size=300, replace=False))
+    _compare(sub["codes"], sub["offsets"], 20, _emb(31, 300, scale=0.5), 16, use_graph=True)
+
+
+def test_ragged_single_and_duplicates():
+    codes, off = synth.random_set(42, 150, 1, 90, 4)
+    _compare(codes, off, 4, _emb(32, 150), 2)
+    codes, off = synth.to_csr([np.array([1, 2, 3], np.uint8)])
+    assert _compare(codes, off, 4, _emb(33, 1), 16)["n_nodes"] == 1
+    seqs = [np.array([0, 1, 2, 3], np.uint8)] * 3 + [np.array([3, 3], np.uint8)]
+    codes, off = synth.to_csr(seqs)
+    _compare(codes, off, 4, _emb(34, 4), 1)
+
+
+def test_equal_estimates_and_ties():
+    """All-equal embeddings (every estimate 0): lowest indices are the candidates."""
+    codes, off = synth.random_set(43, 80, 10, 60, 4)
+    _compare(codes, off, 4, np.zeros((80, 128), np.float32), 3)
+
+
+def test_full_candidates_equal_exact_device_tree():
+    """n <= topk: every cluster's candidates are all its members, so the
+    pruned build is the exact one."""
+    import torch
+    M = _msadp()
+    d = synth.tiny()
+    sub = synth.subset(d, np.arange(32))
+    S = M.to_device(sub["codes"], sub["offsets"], 4)
+    exact = M.tree_build(S)
+    pruned = M.tree_build(S, emb=torch.from_numpy(_emb(36, 32)).to(S.codes.device), topk=32)
+    _equal_trees(pruned, exact)
+
+
+def test_device_embeddings_pipeline():
+    """Embeddings from the device CNN feed the pruned build; the oracle gets
+    the same embeddings."""
+    from oracle import cnn_ref as ref
+    M = _msadp()
+    d = synth.tiny()
+    S = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    E = M.Embedder()
+    E.set_params(ref.init_params(5, sigma=4, width=128, layers=4))
+    e = E.embed(S)
+    got = M.tree_build(S, emb=e, topk=4)
+    want = orc.tree_pruned(d["codes"], d["offsets"], e.cpu().numpy(), topk=4)
+    _equal_trees(got, want)
+
+
+def test_bad_arguments():
+    import torch
+    M = _msadp()
+    d = synth.tiny()
+    S = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    e = torch.zeros((d["n"], 128), dtype=torch.float32, device=S.codes.device)
+    for k in (0, 33):
+        with pytest.raises(M.MsaError) as ex:
+            M.tree_build(S, emb=e, topk=k)
+        assert ex.value.code == M.MSA_EINVAL
+    with pytest.raises(ValueError):
+        M.tree_build(S, emb=e[:10], topk=4)

@@ -1,0 +1,143 @@
+"""Pins of the CPU oracle's surrogate-pruned Alg. 1 (no GPU).
+
+The pruned median replaces the full geometric median of a cluster by the
+best of `topk` candidates that an embedding ranks first; everything else
+(poles, split, numbering) is Alg. 1 as in the exact oracle."""
+import numpy as np
+import pytest
+
+from oracle import pyoracle as orc
+from paper_2601_15458_amd import synth
+
+from test_oracle_tree import check_partition
+
+TWO24 = float(1 << 24)
+
+
+def _emb(seed, n, scale=0.1):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, 128)) * scale).astype(np.float32)
+
+
+def test_emb_distance_closed_form():
+    e = np.zeros((2, 128), dtype=np.float32)
+    e[1, 0], e[1, 1] = 3.0, 4.0                    # |(3, 4)| = 5 exactly
+    E = orc.emb_rowsums(e, np.array([0, 1], dtype=np.int32))
+    assert E.tolist() == [5 * (1 << 24), 5 * (1 << 24)]
+    # a single member: the sum holds only d(x, x) = 0
+    assert orc.emb_rowsums(e, np.array([1], dtype=np.int32)).tolist() == [0]
+
+
+def test_emb_distance_within_float32_bound():
+    """|E - 2^24 ||x - y||| stays within the float32 error of 128 squares
+    added in sequence, a square root and the final rounding."""
+    e = _emb(7, 64, scale=1.0)
+    for i in range(1, 64):
+        E = orc.emb_rowsums(e, np.array([0, i], dtype=np.int32))
+        d = np.linalg.norm(e[0].astype(np.float64) - e[i].astype(np.float64))
+        assert abs(float(E[0]) - TWO24 * d) <= TWO24 * d * 140 * 2.0 ** -24 + 1.0
+
+
+def test_emb_distance_float32_steps():
+    """The oracle takes separately rounded float32 steps (no fused
+    multiply-add): the same steps spelled out with numpy float32 scalars."""
+    e = _emb(8, 20, scale=0.7)
+    f = np.float32
+    for i in range(1, 20):
+        acc = f(0.0)
+        for c in range(128):
+            d = f(e[0, c] - e[i, c])
+            acc = f(acc + f(d * d))
+        want = int(np.rint(f(np.sqrt(acc)) * f(TWO24)))
+        got = orc.emb_rowsums(e, np.array([0, i], dtype=np.int32))
+        assert int(got[0]) == want
+
+
+def test_row_sums_are_sums_of_pairs():
+    e = _emb(9, 12)
+    mem = np.array([3, 0, 7, 11, 5], dtype=np.int32)
+    E = orc.emb_rowsums(e, mem)
+    for x in range(len(mem)):
+        s = sum(int(orc.emb_rowsums(e, mem[[x, y]])[0]) for y in range(len(mem)) if y != x)
+        assert int(E[x]) == s
+
+
+def test_topk_covering_cluster_is_exact_median():
+    """With every member a candidate the pruned median is the full one."""
+    d = synth.tiny()
+    t0 = orc.tree(d["codes"], d["offsets"])
+    t1 = orc.tree_pruned(d["codes"], d["offsets"], _emb(10, 64), topk=64)
+    for f in orc.TREE_FIELDS + ("perm",):
+        assert (t0[f] == t1[f]).all(), f
+
+
+def _members(t, v):
+    return np.sort(t["perm"][t["mstart"][v]: t["mstart"][v] + t["mcount"][v]])
+
+
+def test_center_follows_the_ranking():
+    """topk = 1: the root center is the member the embedding puts in the
+    middle (origin among points on a sphere), not the exact medoid."""
+    codes, off = synth.random_set(33, 30, 20, 60, 4)
+    e = _emb(11, 30, scale=1.0)
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    e[17] = 0.0
+    t = orc.tree_pruned(codes, off, e, topk=1)
+    assert t["center"][0] == 17
+    exact = orc.tree(codes, off)
+    assert exact["center"][0] != 17                 # the pin would be vacuous otherwise
+
+
+def test_equal_estimates_take_lowest_indices():
+    """All estimates equal: the candidates are the topk lowest indices and
+    c is the one of them with the least exact row sum (lowest on ties)."""
+    codes, off = synth.random_set(34, 25, 10, 40, 4)
+    seqs = synth.from_csr(codes, off)
+    t = orc.tree_pruned(codes, off, np.zeros((25, 128), np.float32), topk=3)
+    sums = [sum(orc.lev(seqs[x], seqs[y]) for y in range(25)) for x in range(3)]
+    assert t["center"][0] == int(np.argmin(sums))
+
+
+def check_pruned(seqs, emb, topk, t):
+    """Alg. 1 with the median taken over the embedding's candidates: c is
+    among the members the float64 estimate ranks near the top, beats every
+    member it ranks clearly inside the top topk, and the rest is exact."""
+    n = len(seqs)
+    assert t["n_nodes"] == 2 * n - 1
+    assert sorted(t["perm"].tolist()) == list(range(n))
+    for v in range(t["n_nodes"]):
+        C = _members(t, v)
+        if t["left"][v] < 0:
+            assert len(C) == 1 and t["center"][v] == C[0]
+            continue
+        D = np.array([[orc.lev(seqs[x], seqs[y]) for y in C] for x in C])
+        E = np.linalg.norm(emb[C][:, None, :].astype(np.float64) -
+                           emb[C][None, :, :].astype(np.float64), axis=2).sum(1)
+        rank = np.argsort(E, kind="stable")
+        c = int(np.where(C == t["center"][v])[0][0])
+        pos = int(np.where(rank == c)[0][0])
+        assert pos < topk + 2
+        sure = rank[: max(topk - 2, 0)]
+        assert all(D[c].sum() <= D[s].sum() for s in sure)
+        l = int(np.argmax(D[c]))
+        r = int(np.argmax(D[l]))
+        assert t["lpole"][v] == C[l] and t["rpole"][v] == C[r]
+        a, b = t["left"][v], t["right"][v]
+        assert _members(t, a).tolist() == C[D[l] <= D[r]].tolist()
+        assert _members(t, b).tolist() == C[D[r] < D[l]].tolist()
+
+
+@pytest.mark.parametrize("topk", [1, 4, 16])
+def test_pruned_partition_random_dna(topk):
+    codes, off = synth.random_set(35, 48, 20, 70, 4)
+    seqs = synth.from_csr(codes, off)
+    emb = _emb(12, 48)
+    check_pruned(seqs, emb, topk, orc.tree_pruned(codes, off, emb, topk=topk))
+
+
+def test_pruned_exact_checker_agrees_on_full_topk():
+    """The exact partition checker accepts a pruned tree whose candidates
+    cover every cluster."""
+    codes, off = synth.random_set(36, 20, 5, 30, 20)
+    seqs = synth.from_csr(codes, off)
+    check_partition(seqs, orc.tree_pruned(codes, off, _emb(13, 20), topk=20))

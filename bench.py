@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--nw", action="store_true", help="also time the 512-pair NW batch")
+    ap.add_argument("--pruned", action="store_true",
+                    help="also train the embedder and time the surrogate-pruned tree build "
+                         "against the exact one (100,000 DNA sequences)")
+    ap.add_argument("--epochs", type=int, default=2, help="embedder epochs over 2M pairs")
+    ap.add_argument("--topk", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -157,6 +162,8 @@ def main():
     }
     if args.nw:
         res["nw"] = bench_nw(msadp, synth, torch, args)
+    if args.pruned:
+        res["pruned"] = bench_pruned(msadp, synth, torch, args)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
     print(json.dumps(res), flush=True)
@@ -201,6 +208,79 @@ def bench_nw(msadp, synth, torch, args):
             "tb_bytes": tb_bytes,
             "fill_hbm_gbs": round(tb_bytes / f / 1e6, 1),
             "fill_hbm_frac": round(tb_bytes / f / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_pruned(msadp, synth, torch, args):
+    """Learned pruning on 100,000 DNA sequences of 1,000 families: train the
+    embedder on 2M exact pairs, then the exact and the pruned tree build,
+    teacher-forced agreement of (c, l, r) and the control rankers."""
+    from paper_2601_15458_amd import learned
+    d = synth.learned()
+    S = msadp.to_device(d["codes"], d["offsets"], d["sigma"])
+    _log(f"learned workload: {d['n']} seqs")
+    ia, ib = learned.sample_pairs(d["family"], 2_000_000, seed=11)
+    ha, hb = learned.sample_pairs(d["family"], 20_000, seed=12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dist = learned.lev_labels(S, ia, ib)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    hdist = learned.lev_labels(S, ha, hb)
+    _log(f"labels {t_label:.2f} s; training {args.epochs} epochs")
+    E, losses, t_train = learned.train(S, ia, ib, dist, epochs=args.epochs, seed=13, log=_log)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    emb = E.embed(S)
+    torch.cuda.synchronize()
+    t_embed = time.perf_counter() - t0
+    mae, rel = learned.pair_error(emb, S, ha, hb, hdist)
+    _log(f"trained in {t_train:.1f} s, held-out MAE {mae:.2f} edits ({rel:.4f} rel); "
+         "exact build")
+    exact_b = msadp.TreeBuilder(S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    exact = exact_b().host()
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t0
+    exact_b.st.check("tree_build")
+    _log(f"exact build {t_exact:.2f} s ({exact['n_nodes']} nodes); pruned builds")
+    out = {"workload": "tree build: 100,000 DNA seqs (1,000 families x 100, mutate d=0.30, "
+                       "lengths 100-500, seed 5)",
+           "topk": args.topk, "train_pairs": len(ia), "epochs": args.epochs,
+           "label_s": round(t_label, 3), "train_s": round(t_train, 2),
+           "train_loss_first_last": [round(float(losses[:50].mean()), 5),
+                                     round(float(losses[-50:].mean()), 5)],
+           "embed_s": round(t_embed, 3), "heldout_mae_edits": round(mae, 3),
+           "heldout_rel_err": round(rel, 4), "exact_build_s": round(t_exact, 3),
+           "exact_nodes": int(exact["n_nodes"])}
+    rankers = {"cnn": emb, "length": learned.control_embeddings(S, "length"),
+               "random": learned.control_embeddings(S, "random", seed=14)}
+    for name, e in rankers.items():
+        b = msadp.TreeBuilder(S, emb=e, topk=args.topk)
+        b()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(1, min(args.steps, 3))):
+            t0 = time.perf_counter()
+            t = b()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        b.st.check("tree_build_pruned")
+        t = t.host()
+        clr = msadp.tree_eval_centers(S, exact, emb=e, topk=args.topk)
+        agree = learned.agreement(exact, clr, min_size=args.topk + 1)
+        rep = learned.reproduced_clusters(exact, t)
+        tp = float(np.median(times))
+        out[name] = {"build_s": round(tp, 4), "speedup": round(t_exact / tp, 2),
+                     "agreement": agree, "reproduced_clusters": round(rep, 4),
+                     "nodes": int(t["n_nodes"])}
+        _log(f"{name}: build {tp:.3f} s, speedup {t_exact / tp:.1f}x, agreement {agree}, "
+             f"reproduced {rep:.4f}")
+    return out
 
 
 if __name__ == "__main__":

@@ -163,10 +163,10 @@ static int64_t dist_of(const uint8_t *codes, const int64_t *off, int32_t x, int3
 /* Surrogate distance of two embeddings (128 floats each), in the exact
  * float32 steps the pruned medoid uses: squares of the coordinate
  * differences added one coordinate after another (each difference, square
- * and sum rounded to float, no fused multiply-add), the square root, then
- * the value in units of 2^-24 rounded to the nearest integer (ties to even).
- * Rounding decides the candidate ranking, so both sides take the same
- * float32 steps; the integer row sums are then exact. */
+ * and sum rounded to float, no fused multiply-add), the square root capped
+ * at 2^15, then the value in units of 2^-16 rounded to the nearest integer
+ * (ties to even).  Rounding decides the candidate ranking, so both sides
+ * take the same float32 steps; the integer sums are then exact. */
 static uint64_t emb_dist_q(const float *ex, const float *ey) {
     float acc = 0.0f;
     for (int c = 0; c < 128; ++c) {
@@ -174,7 +174,15 @@ static uint64_t emb_dist_q(const float *ex, const float *ey) {
         const float sq = d * d;
         acc = acc + sq;
     }
-    return (uint64_t)rintf(sqrtf(acc) * 16777216.0f);
+    return (uint64_t)rintf(fminf(sqrtf(acc), 32768.0f) * 65536.0f);
+}
+
+/* The estimate of f(x, y) behind the ranking, in units of 2^-17: the
+ * embedder predicts f divided by the pair's mean length, so the distance
+ * is scaled by |x| + |y|. */
+static uint64_t emb_estimate(const int64_t *off, const float *emb, int32_t x, int32_t y) {
+    const uint64_t len = (uint64_t)((off[x + 1] - off[x]) + (off[y + 1] - off[y]));
+    return emb_dist_q(emb + (int64_t)x * 128, emb + (int64_t)y * 128) * len;
 }
 
 /* f(C[x], C[y]) for every y of the cluster. */
@@ -186,12 +194,86 @@ static int64_t *dist_row(const uint8_t *codes, const int64_t *off, const int32_t
     return row;
 }
 
-/* Alg. 1 (Partition).  emb == NULL: c is the full geometric median of the
- * cluster (Sec. 2.1).  Otherwise c is the surrogate-pruned median: every
- * member x gets the estimate E(x) = sum over the cluster of emb_dist_q,
- * the topk members with the least (E, input index) are the candidates,
- * and c is the candidate with the least exact sum of f over the cluster
- * (lowest input index on ties).  l, r and the split are the same in both. */
+/* The choice Alg. 1 makes for one cluster C (ascending input indices, k
+ * members): out[0] = c, out[1] = l = argmax f(c, x), out[2] = r = argmax
+ * f(l, x) (lowest index on ties; l = r = -1 when k = 1 or the radius
+ * f(c, l) is 0).  emb == NULL: c is the full geometric median of C
+ * (Sec. 2.1).  Otherwise c is the surrogate-pruned median: every member x
+ * gets the estimate E(x) = sum over C of emb_estimate, the topk members with
+ * the least (E, input index) are the candidates, and c is the candidate
+ * with the least exact sum of f over C (lowest input index on ties). */
+void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
+                const float *emb, int32_t topk, int32_t out[3]) {
+    out[1] = out[2] = -1;
+    if (k == 1) { out[0] = C[0]; return; }
+    int64_t best = -1;
+    int64_t *rowc;
+    if (emb == NULL) {
+        /* geometric median over the whole cluster */
+        int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k * k));
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t x = 0; x < k; ++x) {
+            D[x * k + x] = 0;
+            for (int64_t y = x + 1; y < k; ++y) {
+                int64_t d = dist_of(codes, off, C[x], C[y]);
+                D[x * k + y] = d;
+                D[y * k + x] = d;
+            }
+        }
+        int64_t best_sum = 0;
+        for (int64_t x = 0; x < k; ++x) {
+            int64_t s = 0;
+            for (int64_t y = 0; y < k; ++y) s += D[x * k + y];
+            if (best < 0 || s < best_sum) { best = x; best_sum = s; }
+        }
+        rowc = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+        memcpy(rowc, D + best * k, sizeof(int64_t) * (size_t)k);
+        free(D);
+    } else {
+        uint64_t *E = (uint64_t *)calloc((size_t)k, sizeof(uint64_t));
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t x = 0; x < k; ++x)
+            for (int64_t y = 0; y < k; ++y)
+                E[x] += emb_estimate(off, emb, C[x], C[y]);
+        char *taken = (char *)calloc((size_t)k, 1);
+        int64_t best_sum = 0;
+        const int64_t nc = k < topk ? k : topk;
+        for (int64_t j = 0; j < nc; ++j) {
+            int64_t cand = -1;   /* least (E, index) not yet taken */
+            for (int64_t x = 0; x < k; ++x)
+                if (!taken[x] && (cand < 0 || E[x] < E[cand])) cand = x;
+            if (cand < 0) break;
+            taken[cand] = 1;
+            int64_t *row = dist_row(codes, off, C, k, cand);
+            int64_t s = 0;
+            for (int64_t y = 0; y < k; ++y) s += row[y];
+            free(row);
+            if (best < 0 || s < best_sum || (s == best_sum && cand < best)) {
+                best = cand;
+                best_sum = s;
+            }
+        }
+        free(taken);
+        free(E);
+        rowc = dist_row(codes, off, C, k, best);
+    }
+    out[0] = C[best];
+    int64_t lp = 0;
+    for (int64_t x = 1; x < k; ++x) if (rowc[x] > rowc[lp]) lp = x;
+    const int64_t radius = rowc[lp];
+    free(rowc);
+    if (radius == 0) return;   /* radius 0: the cluster stays a leaf */
+    int64_t *rowl = dist_row(codes, off, C, k, lp);
+    int64_t rp = 0;
+    for (int64_t x = 1; x < k; ++x) if (rowl[x] > rowl[rp]) rp = x;
+    free(rowl);
+    out[1] = C[lp];
+    out[2] = C[rp];
+}
+
+/* Alg. 1 (Partition) with the choice of orc_select, then the split
+ * L = {x : f(l, x) <= f(r, x)}, R = the rest, both in ascending order, and
+ * breadth-first node numbering (L before R). */
 static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
                          int32_t topk, int32_t *parent, int32_t *left, int32_t *right,
                          int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
@@ -208,71 +290,20 @@ static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, co
     for (int32_t v = 0; v < n_nodes; ++v) {
         int64_t k = msize[v];
         int32_t *C = members[v];
-        left[v] = right[v] = lpole[v] = rpole[v] = -1;
-        if (k == 1) { center[v] = C[0]; continue; }
-        int64_t best = -1;
-        int64_t *rowc;
-        if (emb == NULL) {
-            /* geometric median over the whole cluster */
-            int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k * k));
-            #pragma omp parallel for schedule(dynamic, 1)
-            for (int64_t x = 0; x < k; ++x) {
-                D[x * k + x] = 0;
-                for (int64_t y = x + 1; y < k; ++y) {
-                    int64_t d = dist_of(codes, off, C[x], C[y]);
-                    D[x * k + y] = d;
-                    D[y * k + x] = d;
-                }
-            }
-            int64_t best_sum = 0;
-            for (int64_t x = 0; x < k; ++x) {
-                int64_t s = 0;
-                for (int64_t y = 0; y < k; ++y) s += D[x * k + y];
-                if (best < 0 || s < best_sum) { best = x; best_sum = s; }
-            }
-            rowc = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
-            memcpy(rowc, D + best * k, sizeof(int64_t) * (size_t)k);
-            free(D);
-        } else {
-            uint64_t *E = (uint64_t *)calloc((size_t)k, sizeof(uint64_t));
-            #pragma omp parallel for schedule(dynamic, 1)
-            for (int64_t x = 0; x < k; ++x)
-                for (int64_t y = 0; y < k; ++y)
-                    E[x] += emb_dist_q(emb + (int64_t)C[x] * 128, emb + (int64_t)C[y] * 128);
-            char *taken = (char *)calloc((size_t)k, 1);
-            int64_t best_sum = 0;
-            const int64_t nc = k < topk ? k : topk;
-            for (int64_t j = 0; j < nc; ++j) {
-                int64_t cand = -1;   /* least (E, index) not yet taken */
-                for (int64_t x = 0; x < k; ++x)
-                    if (!taken[x] && (cand < 0 || E[x] < E[cand])) cand = x;
-                if (cand < 0) break;
-                taken[cand] = 1;
-                int64_t *row = dist_row(codes, off, C, k, cand);
-                int64_t s = 0;
-                for (int64_t y = 0; y < k; ++y) s += row[y];
-                free(row);
-                if (best < 0 || s < best_sum || (s == best_sum && cand < best)) {
-                    best = cand;
-                    best_sum = s;
-                }
-            }
-            free(taken);
-            free(E);
-            rowc = dist_row(codes, off, C, k, best);
+        left[v] = right[v] = -1;
+        int32_t clr[3];
+        orc_select(codes, off, C, k, emb, topk, clr);
+        center[v] = clr[0];
+        lpole[v] = clr[1];
+        rpole[v] = clr[2];
+        if (clr[1] < 0) continue;
+        int64_t lp = 0, rp = 0;
+        for (int64_t x = 0; x < k; ++x) {
+            if (C[x] == clr[1]) lp = x;
+            if (C[x] == clr[2]) rp = x;
         }
-        int64_t lp = 0;
-        for (int64_t x = 1; x < k; ++x) if (rowc[x] > rowc[lp]) lp = x;
-        center[v] = C[best];
-        const int64_t radius = rowc[lp];
-        free(rowc);
-        if (radius == 0) continue;   /* radius 0: leaf */
         int64_t *rowl = dist_row(codes, off, C, k, lp);
-        int64_t rp = 0;
-        for (int64_t x = 1; x < k; ++x) if (rowl[x] > rowl[rp]) rp = x;
         int64_t *rowr = dist_row(codes, off, C, k, rp);
-        lpole[v] = C[lp];
-        rpole[v] = C[rp];
         int32_t *L = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
         int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
         int64_t nl = 0, nr = 0;
@@ -324,14 +355,14 @@ int32_t orc_tree_pruned(const uint8_t *codes, const int64_t *off, int32_t n, con
                      mstart, mcount, perm);
 }
 
-/* Surrogate row sums E(x) of emb_dist_q over an explicit member list
+/* Surrogate row sums E(x) of emb_estimate over an explicit member list
  * (for tests of the ranking step). */
-void orc_emb_rowsums(const float *emb, const int32_t *members, int64_t k, uint64_t *E) {
+void orc_emb_rowsums(const int64_t *off, const float *emb, const int32_t *members, int64_t k,
+                     uint64_t *E) {
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t x = 0; x < k; ++x) {
         uint64_t s = 0;
-        for (int64_t y = 0; y < k; ++y)
-            s += emb_dist_q(emb + (int64_t)members[x] * 128, emb + (int64_t)members[y] * 128);
+        for (int64_t y = 0; y < k; ++y) s += emb_estimate(off, emb, members[x], members[y]);
         E[x] = s;
     }
 }

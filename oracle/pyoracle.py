@@ -35,8 +35,10 @@ def lib():
         L.orc_tree.argtypes = [P, P, C.c_int32] + [P] * 10
         L.orc_tree_pruned.restype = C.c_int32
         L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_int32] + [P] * 10
+        L.orc_select.restype = None
+        L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_int32, P]
         L.orc_emb_rowsums.restype = None
-        L.orc_emb_rowsums.argtypes = [P, P, C.c_int64, P]
+        L.orc_emb_rowsums.argtypes = [P, P, P, C.c_int64, P]
         L.orc_merge.restype = C.c_int64
         L.orc_merge.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
                                 C.c_int64]
@@ -151,12 +153,27 @@ def tree_pruned(codes, offsets, emb, topk=16):
     return out
 
 
-def emb_rowsums(emb, members):
-    """Surrogate row sums E(x) over the member list (uint64 units of 2^-24)."""
+def select(codes, offsets, members, emb=None, topk=16):
+    """(c, l, r) that Alg. 1 picks for the cluster `members` (input indices);
+    emb=None: full geometric median, else the surrogate-pruned one."""
+    codes = _u8(codes)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    mem = np.ascontiguousarray(np.sort(np.asarray(members)), dtype=np.int32)
+    e = None if emb is None else np.ascontiguousarray(emb, dtype=np.float32)
+    out = np.zeros(3, dtype=np.int32)
+    lib().orc_select(_p(codes), _p(offsets), _p(mem), len(mem), None if e is None else _p(e),
+                     int(topk), _p(out))
+    return tuple(int(x) for x in out)
+
+
+def emb_rowsums(offsets, emb, members):
+    """Surrogate row sums E(x) over the member list: the summed embedding
+    distance times the pair's summed length, in units of 2^-16."""
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     emb = np.ascontiguousarray(emb, dtype=np.float32)
     members = np.ascontiguousarray(members, dtype=np.int32)
     E = np.zeros(len(members), dtype=np.uint64)
-    lib().orc_emb_rowsums(_p(emb), _p(members), len(members), _p(E))
+    lib().orc_emb_rowsums(_p(offsets), _p(emb), _p(members), len(members), _p(E))
     return E
 
 

@@ -27,7 +27,8 @@ enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 
 // Surrogate-pruned medoid: at most this many candidates per cluster get
 // exact row sums.
 constexpr int kMaxCand = 32;
-constexpr float kEmbScale = 16777216.0f;   // fixed point of embedding distances (2^24)
+constexpr float kEmbScale = 65536.0f;   // fixed point of embedding distances (2^16)
+constexpr float kEmbCap = 32768.0f;     // embedding distances saturate here
 
 struct TreeArgs {
     Staged S;
@@ -374,11 +375,29 @@ __global__ void k_perm_out(const int32_t *order, const int32_t *perm, int32_t n,
     if (r < n) out[r] = order[perm[r]];
 }
 
-// Surrogate distance of two embeddings in units of 2^-24: the squared
+// Members of a given tree: perm (input indices) to ranks; out-of-range
+// entries are reported and read as rank 0.
+__global__ void k_perm_in(const int32_t *perm_in, const int32_t *rank_of, int32_t n,
+                          int32_t *perm, int32_t *st) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t x = perm_in[i];
+    const bool ok = x >= 0 && x < n;
+    if (!ok) set_status(st, MSA_DS_INDEX);
+    perm[i] = rank_of[ok ? x : 0];
+}
+
+__global__ void k_set_desc(int32_t *desc, int32_t lo, int32_t hi) {
+    desc[0] = lo;
+    desc[1] = hi;
+    desc[2] = 0;
+}
+
+// Surrogate distance of two embeddings in units of 2^-16: the squared
 // coordinate differences are added one coordinate after another with every
-// step rounded to float (no fused multiply-add), then the square root is
-// scaled and rounded to the nearest integer.  Fixing these float steps
-// makes the candidate ranking reproducible; the row sums are exact integers.
+// step rounded to float (no fused multiply-add), the square root is capped
+// at 2^15, scaled and rounded to the nearest integer.  Fixing these float
+// steps makes the candidate ranking reproducible; the sums are integers.
 __device__ __forceinline__ uint64_t emb_dist_q(const float4 *x, const float4 *y) {
 #pragma clang fp contract(off)
     float acc = 0.0f;
@@ -391,12 +410,14 @@ __device__ __forceinline__ uint64_t emb_dist_q(const float4 *x, const float4 *y)
         acc = acc + d2 * d2;
         acc = acc + d3 * d3;
     }
-    return (uint64_t)rintf(sqrtf(acc) * kEmbScale);
+    return (uint64_t)rintf(fminf(sqrtf(acc), kEmbCap) * kEmbScale);
 }
 
-// Estimated medoid row sums from the embeddings: over every pair of every
-// cluster (the same triangle as the exact medoid pass) add
-// ||e_x - e_y|| in fixed point to both ends.
+// Estimated medoid row sums from the embeddings.  The embedder is trained
+// so that ||e_x - e_y|| predicts f(x, y) divided by the pair's mean length,
+// so the estimate of f(x, y) is ||e_x - e_y|| (|x| + |y|) / 2; over every
+// pair of every cluster (the same triangle as the exact medoid pass)
+// emb_dist_q(x, y) * (|x| + |y|) is added to both ends.
 __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
     const int lane = lane_id();
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
@@ -418,9 +439,11 @@ __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
         const int64_t ppos = ms + p;
         const int64_t tpos = ms + p + 1 + blk * 64 + lane;
         const bool valid = tpos < ms + k;
-        const float4 *ep = (const float4 *)(a.emb + (int64_t)a.order[a.perm[ppos]] * 128);
-        const float4 *et = (const float4 *)(a.emb + (int64_t)a.order[a.perm[valid ? tpos : ms]] * 128);
-        const uint64_t qd = valid ? emb_dist_q(ep, et) : 0ull;
+        const int32_t prank = a.perm[ppos], trank = a.perm[valid ? tpos : ms];
+        const float4 *ep = (const float4 *)(a.emb + (int64_t)a.order[prank] * 128);
+        const float4 *et = (const float4 *)(a.emb + (int64_t)a.order[trank] * 128);
+        const uint64_t qd =
+            valid ? emb_dist_q(ep, et) * (uint64_t)(a.S.len[prank] + a.S.len[trank]) : 0ull;
         const int64_t slot = valid ? tpos : (int64_t)a.n;
         atomicAdd((unsigned long long *)&a.rowsum[slot], (unsigned long long)qd);
         const uint64_t s = wave_sum_u64(qd);
@@ -505,8 +528,9 @@ __global__ void k_pick_center_cand(TreeArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
 }
 
+// The choice of c, l and r for every cluster of the level.
 template <int WMAX>
-static void launch_passes(const TreeArgs &a, int grid, int egrid, hipStream_t s) {
+static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s) {
     const dim3 cg(kClusterGrid), cb(256), tb(64), lg(grid);
     hipLaunchKernelGGL(k_level_init, cg, cb, 0, s, a);
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
@@ -530,6 +554,13 @@ static void launch_passes(const TreeArgs &a, int grid, int egrid, hipStream_t s)
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
     hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMaxStore>), lg, tb, 0, s, a);
     hipLaunchKernelGGL(k_pick_pole, dim3(256), dim3(256), 0, s, a, 1);
+}
+
+// One level of Alg. 1: c, l, r, then f(r, x), the split and the children.
+template <int WMAX>
+static void launch_passes(const TreeArgs &a, int grid, int egrid, hipStream_t s) {
+    const dim3 cg(kClusterGrid), cb(256), tb(64), lg(grid);
+    launch_select<WMAX>(a, grid, egrid, s);
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
     hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleStore>), lg, tb, 0, s, a);
@@ -548,6 +579,16 @@ static void level_pass(const TreeArgs &a, int wclass, int grid, int egrid, hipSt
         case 16: launch_passes<16>(a, grid, egrid, s); break;
         case 24: launch_passes<24>(a, grid, egrid, s); break;
         default: launch_passes<32>(a, grid, egrid, s); break;
+    }
+}
+
+static void level_select(const TreeArgs &a, int wclass, int grid, int egrid, hipStream_t s) {
+    switch (wclass) {
+        case 4: launch_select<4>(a, grid, egrid, s); break;
+        case 8: launch_select<8>(a, grid, egrid, s); break;
+        case 16: launch_select<16>(a, grid, egrid, s); break;
+        case 24: launch_select<24>(a, grid, egrid, s); break;
+        default: launch_select<32>(a, grid, egrid, s); break;
     }
 }
 
@@ -611,6 +652,8 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<int32_t>(n * kMaxCand);    // candidates
     al.template take<int32_t>(n);               // candidate counts
     al.template take<uint64_t>(n * kMaxCand);   // candidate sums
+    al.template take<int32_t>(2 * n);           // child ids of an evaluated tree
+    al.template take<int32_t>(2 * n);
 }
 
 }  // namespace msadp
@@ -672,6 +715,10 @@ static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, const m
     a.cand = cv.take<int32_t>(n * kMaxCand);
     a.ncand = cv.take<int32_t>(n);
     a.candsum = cv.take<uint64_t>(n * kMaxCand);
+    int32_t *eval_left = cv.take<int32_t>(2 * n);
+    int32_t *eval_right = cv.take<int32_t>(2 * n);
+    (void)eval_left;
+    (void)eval_right;
     a.emb = emb;
     a.topk = topk;
     a.sigma = S->sigma;
@@ -736,6 +783,115 @@ int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, const m
                       int32_t *d_status, hipStream_t s) {
     if (emb == nullptr || topk < 1 || topk > kMaxCand) return MSA_EINVAL;
     return build_impl(S, emb, topk, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
+}
+
+int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, const msa_tree *T,
+                      int32_t n_nodes, int32_t *center, int32_t *lpole, int32_t *rpole,
+                      void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(S))) return rc;
+    if (T == nullptr || center == nullptr || lpole == nullptr || rpole == nullptr ||
+        T->mstart == nullptr || T->mcount == nullptr || T->depth == nullptr ||
+        T->perm == nullptr || ws == nullptr || n_nodes < 0)
+        return MSA_EINVAL;
+    if (emb != nullptr && (topk < 1 || topk > kMaxCand)) return MSA_EINVAL;
+    if (S->n == 0 || n_nodes == 0) return n_nodes == 0 ? MSA_OK : MSA_EINVAL;
+    if (S->n >= (1 << 24)) return MSA_ERANGE;
+    if (n_nodes > 2 * S->n - 1) return MSA_EINVAL;
+    const TreePlan p = plan_tree(S);
+    Sizer sz;
+    tree_layout(sz, S, p);
+    if (ws_bytes < sz.total()) return MSA_ENOSPC;
+    // The node table is read back to find the levels and to check that the
+    // clusters of one depth are disjoint ranges of perm.
+    const size_t nn = (size_t)n_nodes;
+    int32_t *h_depth = (int32_t *)malloc(nn * sizeof(int32_t));
+    int64_t *h_ms = (int64_t *)malloc(nn * sizeof(int64_t));
+    int64_t *h_mc = (int64_t *)malloc(nn * sizeof(int64_t));
+    if (!h_depth || !h_ms || !h_mc) {
+        free(h_depth); free(h_ms); free(h_mc);
+        return MSA_EDEVICE;
+    }
+    rc = MSA_OK;
+    if (hipMemcpyAsync(h_depth, T->depth, nn * sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(h_ms, T->mstart, nn * sizeof(int64_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(h_mc, T->mcount, nn * sizeof(int64_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        rc = MSA_EDEVICE;
+    if (rc == MSA_OK && (h_depth[0] != 0 || h_ms[0] != 0 || h_mc[0] != S->n)) rc = MSA_EINVAL;
+    for (size_t v = 0; rc == MSA_OK && v < nn; ++v) {
+        if (h_mc[v] < 1 || h_ms[v] < 0 || h_ms[v] + h_mc[v] > S->n) rc = MSA_EINVAL;
+        if (v > 0 && (h_depth[v] < h_depth[v - 1] || h_depth[v] > h_depth[v - 1] + 1))
+            rc = MSA_EINVAL;
+        // same depth: ranges in increasing, non-overlapping order
+        if (v > 0 && h_depth[v] == h_depth[v - 1] && h_ms[v] < h_ms[v - 1] + h_mc[v - 1])
+            rc = MSA_EINVAL;
+    }
+    if (rc) {
+        free(h_depth); free(h_ms); free(h_mc);
+        return rc;
+    }
+    const size_t n = (size_t)S->n;
+    Carve cv(ws, ws_bytes);
+    TreeArgs a{};
+    a.S = Staged{cv.take<uint8_t>(n * p.stride), cv.take<int32_t>(n + 1), p.stride, S->n};
+    int32_t *order = cv.take<int32_t>(n);
+    int32_t *rank_of = cv.take<int32_t>(n);
+    int32_t *hist = cv.take<int32_t>((size_t)S->max_len + 1);
+    a.order = order;
+    a.rank_of = rank_of;
+    a.perm = cv.take<int32_t>(n);
+    a.perm_next = cv.take<int32_t>(n);
+    a.desc = cv.take<int32_t>(4);
+    a.cnt = cv.take<int64_t>(n + 1);
+    a.items = cv.take<int64_t>(n + 1);
+    a.key = cv.take<uint64_t>(n + 1);
+    a.pat = cv.take<int32_t>(n + 1);
+    a.nleft = cv.take<int32_t>(n + 1);
+    a.split = cv.take<int64_t>(n + 1);
+    a.rowsum = cv.take<uint64_t>(n + 1);
+    a.dl = cv.take<int32_t>(n + 1);
+    a.dr = cv.take<int32_t>(n + 1);
+    a.counter = cv.take<uint32_t>(1);
+    a.hbuf = p.hstride ? cv.take<uint32_t>((size_t)p.grid * kWave * p.hstride) : nullptr;
+    a.hstride = p.hstride;
+    a.cand = cv.take<int32_t>(n * kMaxCand);
+    a.ncand = cv.take<int32_t>(n);
+    a.candsum = cv.take<uint64_t>(n * kMaxCand);
+    a.left = cv.take<int32_t>(2 * n);
+    a.right = cv.take<int32_t>(2 * n);
+    a.center = center;
+    a.lpole = lpole;
+    a.rpole = rpole;
+    a.mstart = T->mstart;
+    a.mcount = T->mcount;
+    a.emb = emb;
+    a.topk = topk;
+    a.sigma = S->sigma;
+    a.n = S->n;
+    a.st = d_status;
+
+    if ((rc = sort_by_length(S, a.S.len, hist, order, d_status, s)) == MSA_OK &&
+        (rc = stage_set(S, order, a.S, d_status, s)) == MSA_OK) {
+        hipLaunchKernelGGL(k_rank_of, dim3((S->n + 255) / 256), dim3(256), 0, s, order, S->n,
+                           rank_of, a.perm_next);
+        hipLaunchKernelGGL(k_perm_in, dim3((S->n + 255) / 256), dim3(256), 0, s, T->perm,
+                           rank_of, S->n, a.perm, d_status);
+        rc = launch_status();
+    }
+    for (size_t lo = 0; rc == MSA_OK && lo < nn;) {
+        size_t hi = lo + 1;
+        while (hi < nn && h_depth[hi] == h_depth[lo]) ++hi;
+        hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, a.desc, (int32_t)lo, (int32_t)hi);
+        level_select(a, p.wclass, p.grid, emb_grid(), s);
+        rc = launch_status();
+        lo = hi;
+    }
+    free(h_depth); free(h_ms); free(h_mc);
+    return rc;
 }
 
 }  // extern "C"

@@ -55,6 +55,8 @@ SIGNATURES = {
     "tree_build": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
     "tree_build_pruned": (C.c_int, [SP, P, C.c_int32, P, C.POINTER(C.c_int32), C.c_int32, P,
                                     C.c_size_t, P, P]),
+    "tree_eval_centers": (C.c_int, [SP, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_size_t,
+                                    P, P]),
     "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
     "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
                             C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
@@ -333,6 +335,18 @@ class Tree:
     def struct(self):
         return MsaTree(*[self.t[f].data_ptr() for f in TREE_FIELDS + ("perm",)])
 
+    @classmethod
+    def from_host(cls, h, dev):
+        """Device copy of a host tree dict (as returned by tree_build)."""
+        n = len(h["perm"])
+        t = cls(n, dev)
+        k = int(h["n_nodes"])
+        for f in TREE_FIELDS:
+            t.t[f][:k] = torch.as_tensor(np.asarray(h[f][:k]), dtype=t.t[f].dtype).to(dev)
+        t.t["perm"][:n] = torch.as_tensor(np.asarray(h["perm"]), dtype=torch.int32).to(dev)
+        t.n_nodes = k
+        return t
+
     def host(self):
         k = self.n_nodes
         out = {f: self.t[f][:k].cpu().numpy() for f in TREE_FIELDS}
@@ -390,6 +404,31 @@ def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16):
     torch.cuda.synchronize()
     tb.st.check("tree_build")
     return t.host()
+
+
+def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, stream=None):
+    """(center, lpole, rpole) host arrays that the build picks for each node
+    of `tree` (a device Tree) when that node's members are given: the full
+    median (emb None) or the pruned one."""
+    dev = S.codes.device
+    if isinstance(tree, dict):
+        tree = Tree.from_host(tree, dev)
+    if emb is not None and (emb.dtype != torch.float32 or tuple(emb.shape) != (S.n, 128)
+                            or not emb.is_contiguous() or emb.device != dev):
+        raise ValueError("emb must be a contiguous float32 [n, 128] tensor on the device")
+    nn = tree.n_nodes
+    out = [torch.full((max(nn, 1),), -1, dtype=torch.int32, device=dev) for _ in range(3)]
+    ss, ts = S.struct(), tree.struct()
+    wsb = lib().tree_workspace_bytes(C.byref(ss))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = Status(dev)
+    rc = lib().tree_eval_centers(C.byref(ss), _ptr(emb), int(topk), C.byref(ts), nn,
+                                 *[_ptr(o) for o in out], _ptr(ws), wsb, _ptr(st.t),
+                                 _stream(stream))
+    _check(rc, "tree_eval_centers")
+    torch.cuda.synchronize()
+    st.check("tree_eval_centers")
+    return tuple(o[:nn].cpu().numpy() for o in out)
 
 
 class _nullctx:

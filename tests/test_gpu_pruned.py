@@ -125,3 +125,48 @@ def test_bad_arguments():
         assert ex.value.code == M.MSA_EINVAL
     with pytest.raises(ValueError):
         M.tree_build(S, emb=e[:10], topk=4)
+
+
+def test_teacher_forced_exact_reproduces_tree():
+    """Evaluating the full median on the clusters of the exact tree gives
+    back that tree's own (c, l, r)."""
+    M = _msadp()
+    d = synth.protein_tree()
+    rng = np.random.default_rng(37)
+    sub = synth.subset(d, rng.choice(d["n"], size=300, replace=False))
+    S = M.to_device(sub["codes"], sub["offsets"], 20)
+    t = M.tree_build(S)
+    c, l, r = M.tree_eval_centers(S, t)
+    assert np.array_equal(c, t["center"]) and np.array_equal(l, t["lpole"])
+    assert np.array_equal(r, t["rpole"])
+
+
+def test_teacher_forced_pruned_matches_oracle():
+    """The pruned choice on every cluster of the exact tree, against the
+    oracle's choice for the same member set."""
+    import torch
+    M = _msadp()
+    d = synth.tiny()
+    S = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    t = M.tree_build(S)
+    emb = _emb(38, d["n"])
+    for topk in (1, 5):
+        c, l, r = M.tree_eval_centers(S, t, emb=torch.from_numpy(emb).to(S.codes.device),
+                                      topk=topk)
+        for v in range(t["n_nodes"]):
+            C = t["perm"][t["mstart"][v]: t["mstart"][v] + t["mcount"][v]]
+            want = orc.select(d["codes"], d["offsets"], C, emb, topk)
+            assert (int(c[v]), int(l[v]), int(r[v])) == want, (topk, v)
+
+
+def test_teacher_forced_rejects_bad_tree():
+    M = _msadp()
+    d = synth.tiny()
+    S = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    t = M.tree_build(S)
+    bad = dict(t)
+    bad["mcount"] = t["mcount"].copy()
+    bad["mcount"][1] += 1                     # overlaps its sibling
+    with pytest.raises(M.MsaError) as ex:
+        M.tree_eval_centers(S, bad)
+    assert ex.value.code == M.MSA_EINVAL

@@ -11,7 +11,7 @@ from paper_2601_15458_amd import synth
 
 from test_oracle_tree import check_partition
 
-TWO24 = float(1 << 24)
+TWO16 = float(1 << 16)
 
 
 def _emb(seed, n, scale=0.1):
@@ -19,46 +19,59 @@ def _emb(seed, n, scale=0.1):
     return (rng.standard_normal((n, 128)) * scale).astype(np.float32)
 
 
+def _off(lengths):
+    return np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+
+
 def test_emb_distance_closed_form():
     e = np.zeros((2, 128), dtype=np.float32)
     e[1, 0], e[1, 1] = 3.0, 4.0                    # |(3, 4)| = 5 exactly
-    E = orc.emb_rowsums(e, np.array([0, 1], dtype=np.int32))
-    assert E.tolist() == [5 * (1 << 24), 5 * (1 << 24)]
+    off = _off([7, 10])                            # |x| + |y| = 17
+    E = orc.emb_rowsums(off, e, np.array([0, 1], dtype=np.int32))
+    assert E.tolist() == [5 * 17 * (1 << 16)] * 2
     # a single member: the sum holds only d(x, x) = 0
-    assert orc.emb_rowsums(e, np.array([1], dtype=np.int32)).tolist() == [0]
+    assert orc.emb_rowsums(off, e, np.array([1], dtype=np.int32)).tolist() == [0]
+    # distances saturate at 2^15
+    e[1, 0] = 1e6
+    E = orc.emb_rowsums(off, e, np.array([0, 1], dtype=np.int32))
+    assert E.tolist() == [17 * (1 << 31)] * 2
 
 
 def test_emb_distance_within_float32_bound():
-    """|E - 2^24 ||x - y||| stays within the float32 error of 128 squares
-    added in sequence, a square root and the final rounding."""
+    """|E - 2^16 (|x| + |y|) ||e_x - e_y||| stays within the float32 error of
+    128 squares added in sequence, a square root and the final rounding."""
     e = _emb(7, 64, scale=1.0)
+    off = _off(np.arange(64) + 1)
     for i in range(1, 64):
-        E = orc.emb_rowsums(e, np.array([0, i], dtype=np.int32))
+        E = orc.emb_rowsums(off, e, np.array([0, i], dtype=np.int32))
         d = np.linalg.norm(e[0].astype(np.float64) - e[i].astype(np.float64))
-        assert abs(float(E[0]) - TWO24 * d) <= TWO24 * d * 140 * 2.0 ** -24 + 1.0
+        L = 1 + (i + 1)
+        assert abs(float(E[0]) - TWO16 * L * d) <= L * (TWO16 * d * 140 * 2.0 ** -24 + 0.5)
 
 
 def test_emb_distance_float32_steps():
     """The oracle takes separately rounded float32 steps (no fused
     multiply-add): the same steps spelled out with numpy float32 scalars."""
     e = _emb(8, 20, scale=0.7)
+    off = _off(np.ones(20, dtype=np.int64))
     f = np.float32
     for i in range(1, 20):
         acc = f(0.0)
         for c in range(128):
             d = f(e[0, c] - e[i, c])
             acc = f(acc + f(d * d))
-        want = int(np.rint(f(np.sqrt(acc)) * f(TWO24)))
-        got = orc.emb_rowsums(e, np.array([0, i], dtype=np.int32))
+        want = 2 * int(np.rint(f(np.sqrt(acc)) * f(TWO16)))
+        got = orc.emb_rowsums(off, e, np.array([0, i], dtype=np.int32))
         assert int(got[0]) == want
 
 
 def test_row_sums_are_sums_of_pairs():
     e = _emb(9, 12)
+    off = _off(np.arange(12) * 3 + 2)
     mem = np.array([3, 0, 7, 11, 5], dtype=np.int32)
-    E = orc.emb_rowsums(e, mem)
+    E = orc.emb_rowsums(off, e, mem)
     for x in range(len(mem)):
-        s = sum(int(orc.emb_rowsums(e, mem[[x, y]])[0]) for y in range(len(mem)) if y != x)
+        s = sum(int(orc.emb_rowsums(off, e, mem[[x, y]])[0]) for y in range(len(mem)) if y != x)
         assert int(E[x]) == s
 
 
@@ -111,8 +124,10 @@ def check_pruned(seqs, emb, topk, t):
             assert len(C) == 1 and t["center"][v] == C[0]
             continue
         D = np.array([[orc.lev(seqs[x], seqs[y]) for y in C] for x in C])
-        E = np.linalg.norm(emb[C][:, None, :].astype(np.float64) -
-                           emb[C][None, :, :].astype(np.float64), axis=2).sum(1)
+        lens = np.array([len(seqs[x]) for x in C], dtype=np.float64)
+        E = (np.linalg.norm(emb[C][:, None, :].astype(np.float64) -
+                            emb[C][None, :, :].astype(np.float64), axis=2) *
+             (lens[:, None] + lens[None, :])).sum(1)
         rank = np.argsort(E, kind="stable")
         c = int(np.where(C == t["center"][v])[0][0])
         pos = int(np.where(rank == c)[0][0])
@@ -141,3 +156,26 @@ def test_pruned_exact_checker_agrees_on_full_topk():
     codes, off = synth.random_set(36, 20, 5, 30, 20)
     seqs = synth.from_csr(codes, off)
     check_partition(seqs, orc.tree_pruned(codes, off, _emb(13, 20), topk=20))
+
+
+def test_select_reproduces_tree_choices():
+    """orc_select on a node's member set gives the node's (c, l, r) in the
+    tree built from it, exact and pruned."""
+    codes, off = synth.random_set(37, 40, 10, 50, 4)
+    emb = _emb(14, 40)
+    for e, t in ((None, orc.tree(codes, off)), (emb, orc.tree_pruned(codes, off, emb, 4))):
+        for v in range(t["n_nodes"]):
+            C = _members(t, v)
+            want = (int(t["center"][v]), int(t["lpole"][v]), int(t["rpole"][v]))
+            assert orc.select(codes, off, C, e, 4) == want
+
+
+def test_select_brute_force_median():
+    codes, off = synth.random_set(38, 12, 3, 12, 3)
+    seqs = synth.from_csr(codes, off)
+    C = np.array([1, 4, 5, 8, 11])
+    D = np.array([[orc.lev(seqs[x], seqs[y]) for y in C] for x in C])
+    c = int(np.argmin(D.sum(1)))
+    l = int(np.argmax(D[c]))
+    r = int(np.argmax(D[l]))
+    assert orc.select(codes, off, C) == (C[c], C[l], C[r])

@@ -46,6 +46,8 @@ def parse():
                          "against the exact one (100,000 DNA sequences)")
     ap.add_argument("--epochs", type=int, default=2, help="embedder epochs over 2M pairs")
     ap.add_argument("--topk", type=int, default=16)
+    ap.add_argument("--exact-below", type=int, default=256,
+                    help="hybrid point: clusters of at most this many members keep the full median")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -250,7 +252,7 @@ def bench_pruned(msadp, synth, torch, args):
     _log(f"exact build {t_exact:.2f} s ({exact['n_nodes']} nodes); pruned builds")
     out = {"workload": "tree build: 100,000 DNA seqs (1,000 families x 100, mutate d=0.30, "
                        "lengths 100-500, seed 5)",
-           "topk": args.topk, "train_pairs": len(ia), "epochs": args.epochs,
+           "train_pairs": len(ia), "epochs": args.epochs,
            "label_s": round(t_label, 3), "train_s": round(t_train, 2),
            "train_loss_first_last": [round(float(losses[:50].mean()), 5),
                                      round(float(losses[-50:].mean()), 5)],
@@ -259,8 +261,16 @@ def bench_pruned(msadp, synth, torch, args):
            "exact_nodes": int(exact["n_nodes"])}
     rankers = {"cnn": emb, "length": learned.control_embeddings(S, "length"),
                "random": learned.control_embeddings(S, "random", seed=14)}
-    for name, e in rankers.items():
-        b = msadp.TreeBuilder(S, emb=e, topk=args.topk)
+    # (ranker, topk, exact_below): pure top-k pruning of every cluster, and
+    # the hybrid that keeps the full median for clusters it finds cheap
+    points = [("cnn", args.topk, 0), ("length", args.topk, 0), ("random", args.topk, 0),
+              ("cnn", args.topk, args.exact_below), ("length", args.topk, args.exact_below),
+              ("random", args.topk, args.exact_below),
+              ("cnn", args.topk, 8 * args.exact_below), ("random", args.topk, 8 * args.exact_below)]
+    out["points"] = []
+    for name, topk, eb in points:
+        e = rankers[name]
+        b = msadp.TreeBuilder(S, emb=e, topk=topk, exact_below=eb)
         b()
         torch.cuda.synchronize()
         times = []
@@ -271,15 +281,20 @@ def bench_pruned(msadp, synth, torch, args):
             times.append(time.perf_counter() - t0)
         b.st.check("tree_build_pruned")
         t = t.host()
-        clr = msadp.tree_eval_centers(S, exact, emb=e, topk=args.topk)
-        agree = learned.agreement(exact, clr, min_size=args.topk + 1)
+        clr = msadp.tree_eval_centers(S, exact, emb=e, topk=topk, exact_below=eb)
+        agree = learned.agreement(exact, clr, min_size=17, pruned_above=max(topk, eb))
         rep = learned.reproduced_clusters(exact, t)
+        nd, ex_mean, ex_max = learned.rowsum_excess(S, exact, clr, max(topk, eb))
         tp = float(np.median(times))
-        out[name] = {"build_s": round(tp, 4), "speedup": round(t_exact / tp, 2),
-                     "agreement": agree, "reproduced_clusters": round(rep, 4),
-                     "nodes": int(t["n_nodes"])}
-        _log(f"{name}: build {tp:.3f} s, speedup {t_exact / tp:.1f}x, agreement {agree}, "
-             f"reproduced {rep:.4f}")
+        out["points"].append({"ranker": name, "topk": topk, "exact_below": eb,
+                              "build_s": round(tp, 4), "speedup": round(t_exact / tp, 2),
+                              "agreement": agree, "reproduced_clusters": round(rep, 4),
+                              "center_differs": nd, "rowsum_excess_mean": round(ex_mean, 6),
+                              "rowsum_excess_max": round(ex_max, 6),
+                              "nodes": int(t["n_nodes"])})
+        _log(f"{name} topk={topk} exact_below={eb}: build {tp:.3f} s, speedup "
+             f"{t_exact / tp:.1f}x, agreement {agree}, reproduced {rep:.4f}, "
+             f"excess over {nd} differing centers mean {ex_mean:.2e} max {ex_max:.2e}")
     return out
 
 

@@ -198,12 +198,14 @@ static int64_t *dist_row(const uint8_t *codes, const int64_t *off, const int32_t
  * members): out[0] = c, out[1] = l = argmax f(c, x), out[2] = r = argmax
  * f(l, x) (lowest index on ties; l = r = -1 when k = 1 or the radius
  * f(c, l) is 0).  emb == NULL: c is the full geometric median of C
- * (Sec. 2.1).  Otherwise c is the surrogate-pruned median: every member x
- * gets the estimate E(x) = sum over C of emb_estimate, the topk members with
- * the least (E, input index) are the candidates, and c is the candidate
- * with the least exact sum of f over C (lowest input index on ties). */
+ * (Sec. 2.1).  Otherwise c is the surrogate-pruned median: if C has more
+ * than exact_below members, every member x gets the estimate E(x) = sum
+ * over C of emb_estimate and the topk members with the least
+ * (E, input index) are the candidates, else every member is one; c is the
+ * candidate with the least exact sum of f over C (lowest input index on
+ * ties). */
 void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
-                const float *emb, int32_t topk, int32_t out[3]) {
+                const float *emb, int32_t topk, int32_t exact_below, int32_t out[3]) {
     out[1] = out[2] = -1;
     if (k == 1) { out[0] = C[0]; return; }
     int64_t best = -1;
@@ -237,7 +239,7 @@ void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int6
                 E[x] += emb_estimate(off, emb, C[x], C[y]);
         char *taken = (char *)calloc((size_t)k, 1);
         int64_t best_sum = 0;
-        const int64_t nc = k < topk ? k : topk;
+        const int64_t nc = k <= exact_below ? k : (k < topk ? k : topk);
         for (int64_t j = 0; j < nc; ++j) {
             int64_t cand = -1;   /* least (E, index) not yet taken */
             for (int64_t x = 0; x < k; ++x)
@@ -275,7 +277,7 @@ void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int6
  * L = {x : f(l, x) <= f(r, x)}, R = the rest, both in ascending order, and
  * breadth-first node numbering (L before R). */
 static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
-                         int32_t topk, int32_t *parent, int32_t *left, int32_t *right,
+                         int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left, int32_t *right,
                          int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
                          int64_t *mstart, int64_t *mcount, int32_t *perm) {
     if (n <= 0) return 0;
@@ -292,7 +294,7 @@ static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, co
         int32_t *C = members[v];
         left[v] = right[v] = -1;
         int32_t clr[3];
-        orc_select(codes, off, C, k, emb, topk, clr);
+        orc_select(codes, off, C, k, emb, topk, exact_below, clr);
         center[v] = clr[0];
         lpole[v] = clr[1];
         rpole[v] = clr[2];
@@ -341,17 +343,18 @@ int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
                  int32_t *parent, int32_t *left, int32_t *right, int32_t *center,
                  int32_t *lpole, int32_t *rpole, int32_t *depth,
                  int64_t *mstart, int64_t *mcount, int32_t *perm) {
-    return tree_impl(codes, off, n, NULL, 0, parent, left, right, center, lpole, rpole, depth,
+    return tree_impl(codes, off, n, NULL, 0, 0, parent, left, right, center, lpole, rpole, depth,
                      mstart, mcount, perm);
 }
 
 /* The same with the surrogate-pruned median (emb: float[n][128]). */
 int32_t orc_tree_pruned(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
-                        int32_t topk, int32_t *parent, int32_t *left, int32_t *right,
+                        int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left, int32_t *right,
                         int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
                         int64_t *mstart, int64_t *mcount, int32_t *perm) {
-    if (emb == NULL || topk < 1) return -1;
-    return tree_impl(codes, off, n, emb, topk, parent, left, right, center, lpole, rpole, depth,
+    if (emb == NULL || topk < 1 || exact_below < 0) return -1;
+    return tree_impl(codes, off, n, emb, topk, exact_below, parent, left, right, center, lpole,
+                     rpole, depth,
                      mstart, mcount, perm);
 }
 

@@ -34,9 +34,9 @@ def lib():
         L.orc_tree.restype = C.c_int32
         L.orc_tree.argtypes = [P, P, C.c_int32] + [P] * 10
         L.orc_tree_pruned.restype = C.c_int32
-        L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_int32] + [P] * 10
+        L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_int32, C.c_int32] + [P] * 10
         L.orc_select.restype = None
-        L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_int32, P]
+        L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_int32, C.c_int32, P]
         L.orc_emb_rowsums.restype = None
         L.orc_emb_rowsums.argtypes = [P, P, P, C.c_int64, P]
         L.orc_merge.restype = C.c_int64
@@ -132,8 +132,9 @@ def tree(codes, offsets):
     return out
 
 
-def tree_pruned(codes, offsets, emb, topk=16):
-    """Alg. 1 with the surrogate-pruned median (emb: float32 [n, 128])."""
+def tree_pruned(codes, offsets, emb, topk=16, exact_below=0):
+    """Alg. 1 with the surrogate-pruned median (emb: float32 [n, 128]);
+    clusters of at most exact_below members keep the full median."""
     codes = _u8(codes)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     n = len(offsets) - 1
@@ -143,7 +144,7 @@ def tree_pruned(codes, offsets, emb, topk=16):
     arr = {f: np.zeros(cap, dtype=np.int64 if f in ("mstart", "mcount") else np.int32)
            for f in TREE_FIELDS}
     perm = np.zeros(max(n, 1), dtype=np.int32)
-    k = lib().orc_tree_pruned(_p(codes), _p(offsets), n, _p(emb), int(topk),
+    k = lib().orc_tree_pruned(_p(codes), _p(offsets), n, _p(emb), int(topk), int(exact_below),
                               *[_p(arr[f]) for f in TREE_FIELDS], _p(perm))
     if k < 0:
         raise ValueError("bad arguments")
@@ -153,7 +154,7 @@ def tree_pruned(codes, offsets, emb, topk=16):
     return out
 
 
-def select(codes, offsets, members, emb=None, topk=16):
+def select(codes, offsets, members, emb=None, topk=16, exact_below=0):
     """(c, l, r) that Alg. 1 picks for the cluster `members` (input indices);
     emb=None: full geometric median, else the surrogate-pruned one."""
     codes = _u8(codes)
@@ -162,7 +163,7 @@ def select(codes, offsets, members, emb=None, topk=16):
     e = None if emb is None else np.ascontiguousarray(emb, dtype=np.float32)
     out = np.zeros(3, dtype=np.int32)
     lib().orc_select(_p(codes), _p(offsets), _p(mem), len(mem), None if e is None else _p(e),
-                     int(topk), _p(out))
+                     int(topk), int(exact_below), _p(out))
     return tuple(int(x) for x in out)
 
 

@@ -24,9 +24,13 @@ namespace msadp {
 
 enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 4 };
 
-// Surrogate-pruned medoid: at most this many candidates per cluster get
-// exact row sums.
-constexpr int kMaxCand = 32;
+// Surrogate-pruned medoid: clusters above exact_below members get exact row
+// sums for their topk best-ranked members only.  The surrogate distance of two embeddings is the square
+// root of their squared coordinate differences added in coordinate order,
+// each step rounded to float (no fused multiply-add), capped at kEmbCap,
+// scaled by kEmbScale and rounded to the nearest integer: fixed float steps
+// make the candidate ranking reproducible, and the sums are integers.
+constexpr int kMaxTopk = 1024;
 constexpr float kEmbScale = 65536.0f;   // fixed point of embedding distances (2^16)
 constexpr float kEmbCap = 32768.0f;     // embedding distances saturate here
 
@@ -56,9 +60,11 @@ struct TreeArgs {
     // surrogate-pruned medoid (emb == nullptr: exact medoid)
     const float *emb;        // [n][128] by input index
     int32_t topk;
-    int32_t *cand;           // [nq][kMaxCand] candidate ranks
-    int32_t *ncand;          // [nq]
-    uint64_t *candsum;       // [nq][kMaxCand] exact row sums of the candidates
+    int32_t exact_below;     // clusters of at most this many members: all are candidates
+    int64_t *ncand;          // per cluster candidate count (nq + 1)
+    int64_t *coff;           // exclusive prefix of ncand: the cluster's first candidate
+    int32_t *cand;           // [n] candidate ranks, cluster by cluster
+    uint64_t *candsum;       // [n] exact row sums of the candidates
 };
 
 constexpr int kClusterGrid = 2048;
@@ -88,6 +94,17 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
+// Tiles of 64 x 64 members (I <= J) over the upper triangle of a cluster of
+// k members, row by row: tile_rows_before(I, nb) tiles precede row I.
+__host__ __device__ inline int64_t tile_rows_before(int64_t I, int64_t nb) {
+    return I * nb - I * (I - 1) / 2;
+}
+
+__host__ __device__ inline int64_t emb_tiles(int64_t k) {
+    const int64_t nb = (k + 63) / 64;
+    return k >= 2 ? nb * (nb + 1) / 2 : 0;
+}
+
 // Level start: reset per-node fields, member sums and the medoid work list.
 __global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
@@ -97,16 +114,22 @@ __global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
         if (threadIdx.x == 0) {
             a.left[v] = a.right[v] = a.lpole[v] = a.rpole[v] = -1;
             a.key[q] = ~0ull;
-            a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
+            if (a.emb != nullptr) {
+                const bool pruned = k > a.exact_below;
+                a.cnt[q] = pruned ? emb_tiles(k) : 0;
+                a.ncand[q] = pruned ? min<int64_t>(k, a.topk) : k;
+            } else {
+                a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
+            }
             a.nleft[q] = -1;
             a.split[q] = 0;
         }
-        if (a.emb != nullptr && threadIdx.x < kMaxCand) a.candsum[(int64_t)q * kMaxCand + threadIdx.x] = 0;
         for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.rowsum[ms + i] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.cnt[nq] = 0;
         a.split[nq] = 0;
+        if (a.emb != nullptr) a.ncand[nq] = 0;
     }
 }
 
@@ -171,7 +194,7 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
         } else if (MODE == kCandSum) {
             const int64_t nblk = (k + 63) / 64;
             const int64_t j = local / nblk, blk = local % nblk;
-            cslot = (int64_t)q * kMaxCand + j;
+            cslot = a.coff[q] + j;
             prow = a.cand[cslot];
             tpos = ms + blk * 64 + lane;
         } else {
@@ -393,36 +416,44 @@ __global__ void k_set_desc(int32_t *desc, int32_t lo, int32_t hi) {
     desc[2] = 0;
 }
 
-// Surrogate distance of two embeddings in units of 2^-16: the squared
-// coordinate differences are added one coordinate after another with every
-// step rounded to float (no fused multiply-add), the square root is capped
-// at 2^15, scaled and rounded to the nearest integer.  Fixing these float
-// steps makes the candidate ranking reproducible; the sums are integers.
-__device__ __forceinline__ uint64_t emb_dist_q(const float4 *x, const float4 *y) {
+// Read-only global memory seen through the scalar unit: a load from a
+// uniform address in this address space is a scalar (SMEM) load, so the
+// row of block J that every lane needs costs no vector-memory issue slots.
+typedef const __attribute__((address_space(4))) float const_f32;
+
+// Squared differences of one quarter (32 coordinates) of two embeddings,
+// added to acc coordinate by coordinate in float32 (no fused multiply-add).
+__device__ __forceinline__ float emb_quarter(float acc, const float4 *x, const_f32 *y) {
 #pragma clang fp contract(off)
-    float acc = 0.0f;
-#pragma unroll 8
-    for (int c = 0; c < 32; ++c) {
-        const float4 a = x[c], b = y[c];
-        const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float d0 = x[c].x - y[4 * c], d1 = x[c].y - y[4 * c + 1];
+        const float d2 = x[c].z - y[4 * c + 2], d3 = x[c].w - y[4 * c + 3];
         acc = acc + d0 * d0;
         acc = acc + d1 * d1;
         acc = acc + d2 * d2;
         acc = acc + d3 * d3;
     }
-    return (uint64_t)rintf(fminf(sqrtf(acc), kEmbCap) * kEmbScale);
+    return acc;
 }
 
 // Estimated medoid row sums from the embeddings.  The embedder is trained
 // so that ||e_x - e_y|| predicts f(x, y) divided by the pair's mean length,
-// so the estimate of f(x, y) is ||e_x - e_y|| (|x| + |y|) / 2; over every
-// pair of every cluster (the same triangle as the exact medoid pass)
-// emb_dist_q(x, y) * (|x| + |y|) is added to both ends.
+// so the estimate of f(x, y) is ||e_x - e_y|| (|x| + |y|) / 2; every pair of
+// a cluster adds the surrogate distance times (|x| + |y|) to the row sums of
+// both.  One work item is a 64 x 64 tile (I, J) of the cluster's upper block
+// triangle: lane i keeps the embedding of member 64 I + i in registers and
+// walks the 64 members of block J, whose rows every lane needs whole and
+// reads by scalar loads.
+// Lanes sum their row; for I < J the column sums are reduced across the
+// wave.  A diagonal tile visits every ordered pair of its block and adds row
+// sums only.
 __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
     const int lane = lane_id();
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     const int64_t total = a.items[nq];
-    if (nq < 1 || nq > a.n || total < 0 || total > items_upto(a.n)) {
+    // Clusters of a level are disjoint, so their tiles number at most n(n+1)/2.
+    if (nq < 1 || nq > a.n || total < 0 || total > (int64_t)a.n * (a.n + 1) / 2) {
         if (blockIdx.x == 0 && lane == 0) set_status(a.st, MSA_DS_CAPACITY);
         return;
     }
@@ -433,21 +464,50 @@ __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
         const int64_t local = (int64_t)it - a.items[q];
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
-        const int64_t u = triangle_row(local, k - 1);
-        const int64_t p = k - 1 - u;
-        const int64_t blk = local - items_upto(u - 1);
-        const int64_t ppos = ms + p;
-        const int64_t tpos = ms + p + 1 + blk * 64 + lane;
-        const bool valid = tpos < ms + k;
-        const int32_t prank = a.perm[ppos], trank = a.perm[valid ? tpos : ms];
-        const float4 *ep = (const float4 *)(a.emb + (int64_t)a.order[prank] * 128);
-        const float4 *et = (const float4 *)(a.emb + (int64_t)a.order[trank] * 128);
-        const uint64_t qd =
-            valid ? emb_dist_q(ep, et) * (uint64_t)(a.S.len[prank] + a.S.len[trank]) : 0ull;
-        const int64_t slot = valid ? tpos : (int64_t)a.n;
-        atomicAdd((unsigned long long *)&a.rowsum[slot], (unsigned long long)qd);
-        const uint64_t s = wave_sum_u64(qd);
-        atomicAdd((unsigned long long *)&a.rowsum[ppos], (unsigned long long)(lane == 0 ? s : 0ull));
+        const int64_t nb = (k + 63) / 64;
+        int64_t lo = 0, hi = nb - 1;            // row I of the tile
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (tile_rows_before(mid, nb) <= local) lo = mid; else hi = mid - 1;
+        }
+        const int64_t I = lo, J = I + (local - tile_rows_before(I, nb));
+        // this lane's member of block I (x) and of block J (y)
+        const int64_t xi = I * 64 + lane, yi = J * 64 + lane;
+        const bool xv = xi < k, yl = yi < k;
+        const int32_t xr = a.perm[ms + (xv ? xi : 0)];
+        const int32_t yr = a.perm[ms + (yl ? yi : 0)];
+        const uint32_t yrow = (uint32_t)a.order[yr];
+        const uint32_t ylen = (uint32_t)a.S.len[yr] | (yl ? 0u : 0x80000000u);
+        const float4 *xp = (const float4 *)(a.emb + (int64_t)a.order[xr] * 128);
+        float4 x[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) x[c] = xp[c];
+        const uint64_t lx = (uint64_t)a.S.len[xr];
+        const_f32 *embs = (const_f32 *)a.emb;
+        uint64_t rs = 0, cs = 0;
+        for (int j = 0; j < 64; ++j) {
+            const uint32_t lj = __builtin_amdgcn_readlane(ylen, j);
+            const_f32 *row = embs + (int64_t)__builtin_amdgcn_readlane(yrow, j) * 128;
+            float acc = 0.0f;
+            acc = emb_quarter(acc, x + 0, row + 0);
+            acc = emb_quarter(acc, x + 8, row + 32);
+            acc = emb_quarter(acc, x + 16, row + 64);
+            acc = emb_quarter(acc, x + 24, row + 96);
+            const uint64_t qd = (uint64_t)rintf(fminf(sqrtf(acc), kEmbCap) * kEmbScale);
+            // lj's top bit marks a missing member of block J
+            const uint64_t w = (xv && !(lj >> 31)) ? lx + (uint64_t)lj : 0ull;
+            const uint64_t e = qd * w;
+            rs += e;
+            if (I != J) {                        // uniform per item
+                const uint64_t col = wave_sum_u64(e);
+                cs = lane == j ? col : cs;
+            }
+        }
+        atomicAdd((unsigned long long *)&a.rowsum[xv ? ms + xi : (int64_t)a.n],
+                  (unsigned long long)(xv ? rs : 0ull));
+        if (I != J)
+            atomicAdd((unsigned long long *)&a.rowsum[yl ? ms + yi : (int64_t)a.n],
+                      (unsigned long long)(yl ? cs : 0ull));
     }
 }
 
@@ -455,9 +515,11 @@ __device__ __forceinline__ bool key_less(uint64_t s0, uint32_t i0, uint64_t s1, 
     return s0 < s1 || (s0 == s1 && i0 < i1);
 }
 
-// The topk members with the least estimated row sum (lowest input index on
-// ties), one workgroup per cluster: topk rounds of a block-wide minimum
-// over the members above the last pick.
+// Candidates of each cluster, from its first candidate slot on: every member
+// of a cluster of at most exact_below members; otherwise the topk members
+// with the least estimated row sum (lowest input index on ties), by topk
+// rounds of a block-wide minimum over the members above the last pick.
+// Clears the candidates' sums and sets the work of the candidate-sum pass.
 __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
     __shared__ uint64_t rs[256];
     __shared__ uint32_t ri[256];
@@ -465,41 +527,42 @@ __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
-        const int32_t nc = (int32_t)min<int64_t>(k, a.topk);
-        uint64_t last_s = 0;
-        uint32_t last_i = 0;
-        bool have_last = false;
-        for (int32_t j = 0; j < nc; ++j) {
-            uint64_t bs = ~0ull;
-            uint32_t bi = ~0u;
-            int64_t bpos = -1;
-            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
-                const uint64_t sv = a.rowsum[ms + i];
-                const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
-                if (have_last && !key_less(last_s, last_i, sv, oi)) continue;
-                if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; bpos = ms + i; }
-            }
-            rs[threadIdx.x] = bs;
-            ri[threadIdx.x] = bi;
-            __syncthreads();
-            for (int o = 128; o >= 1; o >>= 1) {
-                if (threadIdx.x < o && key_less(rs[threadIdx.x + o], ri[threadIdx.x + o],
-                                                rs[threadIdx.x], ri[threadIdx.x])) {
-                    rs[threadIdx.x] = rs[threadIdx.x + o];
-                    ri[threadIdx.x] = ri[threadIdx.x + o];
+        const int64_t nc = a.ncand[q], base = a.coff[q];
+        for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) a.candsum[base + j] = 0;
+        if (k <= a.exact_below) {
+            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.cand[base + i] = a.perm[ms + i];
+        } else {
+            uint64_t last_s = 0;
+            uint32_t last_i = 0;
+            bool have_last = false;
+            for (int64_t j = 0; j < nc; ++j) {
+                uint64_t bs = ~0ull;
+                uint32_t bi = ~0u;
+                for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+                    const uint64_t sv = a.rowsum[ms + i];
+                    const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
+                    if (have_last && !key_less(last_s, last_i, sv, oi)) continue;
+                    if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; }
                 }
+                rs[threadIdx.x] = bs;
+                ri[threadIdx.x] = bi;
+                __syncthreads();
+                for (int o = 128; o >= 1; o >>= 1) {
+                    if (threadIdx.x < o && key_less(rs[threadIdx.x + o], ri[threadIdx.x + o],
+                                                    rs[threadIdx.x], ri[threadIdx.x])) {
+                        rs[threadIdx.x] = rs[threadIdx.x + o];
+                        ri[threadIdx.x] = ri[threadIdx.x + o];
+                    }
+                    __syncthreads();
+                }
+                last_s = rs[0];
+                last_i = ri[0];
+                have_last = true;
+                if (threadIdx.x == 0) a.cand[base + j] = a.rank_of[last_i];
                 __syncthreads();
             }
-            last_s = rs[0];
-            last_i = ri[0];
-            have_last = true;
-            if (threadIdx.x == 0) a.cand[(int64_t)q * kMaxCand + j] = a.rank_of[last_i];
-            __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            a.ncand[q] = nc;
-            a.cnt[q] = k >= 2 ? (int64_t)nc * ((k + 63) / 64) : 0;
-        }
+        if (threadIdx.x == 0) a.cnt[q] = k >= 2 ? nc * ((k + 63) / 64) : 0;
         __syncthreads();
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
@@ -511,12 +574,12 @@ __global__ void k_pick_center_cand(TreeArgs a) {
     for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const int32_t v = lvl + q;
         const int64_t k = a.mcount[v];
-        const int32_t nc = a.ncand[q];
+        const int64_t nc = a.ncand[q], base = a.coff[q];
         uint64_t bs = ~0ull;
         uint32_t bi = ~0u;
-        for (int32_t j = 0; j < nc; ++j) {
-            const uint64_t sv = a.candsum[(int64_t)q * kMaxCand + j];
-            const uint32_t oi = (uint32_t)a.order[a.cand[(int64_t)q * kMaxCand + j]];
+        for (int64_t j = 0; j < nc; ++j) {
+            const uint64_t sv = a.candsum[base + j];
+            const uint32_t oi = (uint32_t)a.order[a.cand[base + j]];
             if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; }
         }
         if (k == 1) bi = (uint32_t)a.order[a.perm[a.mstart[v]]];
@@ -540,6 +603,7 @@ static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s)
         hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
     } else {
         hipLaunchKernelGGL(k_emb_rowsum, dim3(egrid), tb, 0, s, a);
+        hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.ncand, a.coff, a.desc);
         hipLaunchKernelGGL(k_topk, cg, cb, 0, s, a);
         hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
@@ -649,9 +713,10 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<int32_t>(n + 1);           // dr
     al.template take<uint32_t>(1);              // counter
     if (p.hstride) al.template take<uint32_t>((size_t)p.grid * kWave * p.hstride);
-    al.template take<int32_t>(n * kMaxCand);    // candidates
-    al.template take<int32_t>(n);               // candidate counts
-    al.template take<uint64_t>(n * kMaxCand);   // candidate sums
+    al.template take<int64_t>(n + 1);           // candidate counts
+    al.template take<int64_t>(n + 1);           // candidate offsets
+    al.template take<int32_t>(n);               // candidates
+    al.template take<uint64_t>(n);              // candidate sums
     al.template take<int32_t>(2 * n);           // child ids of an evaluated tree
     al.template take<int32_t>(2 * n);
 }
@@ -669,7 +734,8 @@ size_t tree_workspace_bytes(const msa_seqs *S) {
     return sz.total();
 }
 
-static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, const msa_tree *T,
+static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
+                      const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
                       int32_t *d_status, hipStream_t s) {
     int rc;
@@ -712,15 +778,17 @@ static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, const m
     a.counter = cv.take<uint32_t>(1);
     a.hbuf = p.hstride ? cv.take<uint32_t>((size_t)p.grid * kWave * p.hstride) : nullptr;
     a.hstride = p.hstride;
-    a.cand = cv.take<int32_t>(n * kMaxCand);
-    a.ncand = cv.take<int32_t>(n);
-    a.candsum = cv.take<uint64_t>(n * kMaxCand);
+    a.ncand = cv.take<int64_t>(n + 1);
+    a.coff = cv.take<int64_t>(n + 1);
+    a.cand = cv.take<int32_t>(n);
+    a.candsum = cv.take<uint64_t>(n);
     int32_t *eval_left = cv.take<int32_t>(2 * n);
     int32_t *eval_right = cv.take<int32_t>(2 * n);
     (void)eval_left;
     (void)eval_right;
     a.emb = emb;
     a.topk = topk;
+    a.exact_below = exact_below;
     a.sigma = S->sigma;
     a.n = S->n;
     a.st = d_status;
@@ -775,17 +843,19 @@ static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, const m
 
 int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
                void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
-    return build_impl(S, nullptr, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
+    return build_impl(S, nullptr, 0, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
 }
 
-int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, const msa_tree *T,
-                      int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
-                      int32_t *d_status, hipStream_t s) {
-    if (emb == nullptr || topk < 1 || topk > kMaxCand) return MSA_EINVAL;
-    return build_impl(S, emb, topk, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
+int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
+                      const msa_tree *T, int32_t *n_nodes, int32_t use_graph, void *ws,
+                      size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    if (emb == nullptr || topk < 1 || topk > kMaxTopk || exact_below < 0) return MSA_EINVAL;
+    return build_impl(S, emb, topk, exact_below, T, n_nodes, use_graph, ws, ws_bytes, d_status,
+                      s);
 }
 
-int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, const msa_tree *T,
+int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
+                      const msa_tree *T,
                       int32_t n_nodes, int32_t *center, int32_t *lpole, int32_t *rpole,
                       void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
     int rc;
@@ -794,7 +864,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, const m
         T->mstart == nullptr || T->mcount == nullptr || T->depth == nullptr ||
         T->perm == nullptr || ws == nullptr || n_nodes < 0)
         return MSA_EINVAL;
-    if (emb != nullptr && (topk < 1 || topk > kMaxCand)) return MSA_EINVAL;
+    if (emb != nullptr && (topk < 1 || topk > kMaxTopk || exact_below < 0)) return MSA_EINVAL;
     if (S->n == 0 || n_nodes == 0) return n_nodes == 0 ? MSA_OK : MSA_EINVAL;
     if (S->n >= (1 << 24)) return MSA_ERANGE;
     if (n_nodes > 2 * S->n - 1) return MSA_EINVAL;
@@ -858,9 +928,10 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, const m
     a.counter = cv.take<uint32_t>(1);
     a.hbuf = p.hstride ? cv.take<uint32_t>((size_t)p.grid * kWave * p.hstride) : nullptr;
     a.hstride = p.hstride;
-    a.cand = cv.take<int32_t>(n * kMaxCand);
-    a.ncand = cv.take<int32_t>(n);
-    a.candsum = cv.take<uint64_t>(n * kMaxCand);
+    a.ncand = cv.take<int64_t>(n + 1);
+    a.coff = cv.take<int64_t>(n + 1);
+    a.cand = cv.take<int32_t>(n);
+    a.candsum = cv.take<uint64_t>(n);
     a.left = cv.take<int32_t>(2 * n);
     a.right = cv.take<int32_t>(2 * n);
     a.center = center;
@@ -870,6 +941,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, const m
     a.mcount = T->mcount;
     a.emb = emb;
     a.topk = topk;
+    a.exact_below = exact_below;
     a.sigma = S->sigma;
     a.n = S->n;
     a.st = d_status;

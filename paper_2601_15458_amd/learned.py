@@ -119,35 +119,66 @@ def control_embeddings(S, kind: str, seed: int = 0):
     return torch.from_numpy(e).to(S.codes.device)
 
 
-def agreement(tree, clr, min_size: int = 17):
+def agreement(tree, clr, min_size: int = 17, pruned_above: int = 16):
     """Teacher-forced agreement of a choice (center, lpole, rpole per node of
-    the exact tree) with the tree's own: fractions over the internal nodes
-    with at least min_size members, and over all internal nodes."""
+    the exact tree) with the tree's own, as fractions of internal nodes:
+    over those with at least min_size members ("clr", "c", "poles"), over
+    all ("clr_all"), and over those above pruned_above members, the only
+    ones whose choice was pruned ("clr_pruned")."""
     c, l, r = clr
     internal = tree["left"] >= 0
     big = internal & (tree["mcount"] >= min_size)
+    pruned = internal & (tree["mcount"] > pruned_above)
     same_clr = (c == tree["center"]) & (l == tree["lpole"]) & (r == tree["rpole"])
     same_c = c == tree["center"]
     same_lr = (l == tree["lpole"]) & (r == tree["rpole"])
 
     def frac(mask, sel):
-        return float(mask[sel].mean()) if sel.any() else 1.0
+        return round(float(mask[sel].mean()), 4) if sel.any() else 1.0
 
     return {"clusters": int(big.sum()), "clr": frac(same_clr, big), "c": frac(same_c, big),
             "poles": frac(same_lr, big), "clr_all": frac(same_clr, internal),
-            "internal": int(internal.sum())}
+            "internal": int(internal.sum()), "pruned_clusters": int(pruned.sum()),
+            "clr_pruned": frac(same_clr, pruned)}
 
 
 def reproduced_clusters(exact, other, seed: int = 0):
-    """Fraction of the exact tree's clusters (member sets) that the other
-    tree also holds, by 64-bit set hashes over each node's perm range."""
+    """Fraction of the exact tree's internal clusters (member sets of two or
+    more) that the other tree also holds, by 64-bit set hashes over each
+    node's perm range."""
     n = len(exact["perm"])
     h = np.random.default_rng(seed).integers(0, 2 ** 63, size=n, dtype=np.uint64)
 
     def keys(t):
         pre = np.concatenate([[np.uint64(0)], np.cumsum(h[t["perm"]], dtype=np.uint64)])
         s = pre[t["mstart"] + t["mcount"]] - pre[t["mstart"]]
-        return set(zip(s.tolist(), t["mcount"].tolist()))
+        big = t["mcount"] >= 2
+        return set(zip(s[big].tolist(), t["mcount"][big].tolist()))
 
     ke, ko = keys(exact), keys(other)
     return len(ke & ko) / max(len(ke), 1)
+
+
+def rowsum_excess(S, exact, clr, pruned_above: int):
+    """How far a pruned center is from the full median where they differ:
+    (sum f(c', x) - sum f(c, x)) / sum f(c, x) over the members x of each
+    internal cluster above pruned_above members, exact sums by lev_batch.
+    Returns (number of clusters that differ, mean and max relative excess)."""
+    c2 = clr[0]
+    sel = np.flatnonzero((exact["left"] >= 0) & (exact["mcount"] > pruned_above) &
+                         (c2 != exact["center"]))
+    if len(sel) == 0:
+        return 0, 0.0, 0.0
+    ia, ib, seg = [], [], []
+    for j, v in enumerate(sel):
+        mem = exact["perm"][exact["mstart"][v]: exact["mstart"][v] + exact["mcount"][v]]
+        for t, c in enumerate((exact["center"][v], c2[v])):
+            ia.append(np.full(len(mem), c, np.int32))
+            ib.append(mem.astype(np.int32))
+            seg.append(np.full(len(mem), 2 * j + t, np.int64))
+    ia, ib = np.concatenate(ia), np.concatenate(ib)
+    seg = np.concatenate(seg)
+    d = M.lev_batch(S, S, ia, ib).to(torch.int64).cpu().numpy()
+    sums = np.bincount(seg, weights=d, minlength=2 * len(sel)).reshape(len(sel), 2)
+    rel = (sums[:, 1] - sums[:, 0]) / np.maximum(sums[:, 0], 1)
+    return int(len(sel)), float(rel.mean()), float(rel.max())

@@ -53,10 +53,10 @@ SIGNATURES = {
     "nw_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
     "tree_workspace_bytes": (C.c_size_t, [SP]),
     "tree_build": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
-    "tree_build_pruned": (C.c_int, [SP, P, C.c_int32, P, C.POINTER(C.c_int32), C.c_int32, P,
+    "tree_build_pruned": (C.c_int, [SP, P, C.c_int32, C.c_int32, P, C.POINTER(C.c_int32),
+                                    C.c_int32, P, C.c_size_t, P, P]),
+    "tree_eval_centers": (C.c_int, [SP, P, C.c_int32, C.c_int32, P, C.c_int32, P, P, P, P,
                                     C.c_size_t, P, P]),
-    "tree_eval_centers": (C.c_int, [SP, P, C.c_int32, P, C.c_int32, P, P, P, P, C.c_size_t,
-                                    P, P]),
     "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
     "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
                             C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
@@ -360,7 +360,7 @@ class TreeBuilder:
     float32 [n, 128]) the medoid is pruned to the topk members closest in
     embedding space (tree_build_pruned)."""
 
-    def __init__(self, S: Seqs, use_graph=False, emb=None, topk=16):
+    def __init__(self, S: Seqs, use_graph=False, emb=None, topk=16, exact_below=0):
         self.S = S
         if emb is not None:
             if (emb.dtype != torch.float32 or emb.device != S.codes.device
@@ -368,6 +368,7 @@ class TreeBuilder:
                 raise ValueError("emb must be a contiguous float32 [n, 128] tensor on the device")
         self.emb = emb
         self.topk = int(topk)
+        self.exact_below = int(exact_below)
         dev = S.codes.device
         self.ss = S.struct()
         self.tree = Tree(S.n, dev)
@@ -386,19 +387,20 @@ class TreeBuilder:
             _check(rc, "tree_build")
         else:
             rc = lib().tree_build_pruned(C.byref(self.ss), _ptr(self.emb), self.topk,
-                                         C.byref(self.ts), C.byref(nn), int(self.use_graph),
+                                         self.exact_below, C.byref(self.ts), C.byref(nn),
+                                         int(self.use_graph),
                                          _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
             _check(rc, "tree_build_pruned")
         self.tree.n_nodes = nn.value
         return self.tree
 
 
-def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16):
+def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16, exact_below=0):
     """Alg. 1 guide tree of S; returns host numpy arrays like the oracle's.
-    emb/topk select the surrogate-pruned medoid (see TreeBuilder)."""
+    emb/topk/exact_below select the surrogate-pruned medoid (see TreeBuilder)."""
     if use_graph and stream is None:
         stream = torch.cuda.Stream()
-    tb = TreeBuilder(S, use_graph, emb, topk)
+    tb = TreeBuilder(S, use_graph, emb, topk, exact_below)
     with torch.cuda.stream(stream) if stream is not None else _nullctx():
         t = tb(stream)
     torch.cuda.synchronize()
@@ -406,7 +408,7 @@ def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16):
     return t.host()
 
 
-def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, stream=None):
+def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, exact_below=0, stream=None):
     """(center, lpole, rpole) host arrays that the build picks for each node
     of `tree` (a device Tree) when that node's members are given: the full
     median (emb None) or the pruned one."""
@@ -422,7 +424,8 @@ def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, stream=None):
     wsb = lib().tree_workspace_bytes(C.byref(ss))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
     st = Status(dev)
-    rc = lib().tree_eval_centers(C.byref(ss), _ptr(emb), int(topk), C.byref(ts), nn,
+    rc = lib().tree_eval_centers(C.byref(ss), _ptr(emb), int(topk), int(exact_below),
+                                 C.byref(ts), nn,
                                  *[_ptr(o) for o in out], _ptr(ws), wsb, _ptr(st.t),
                                  _stream(stream))
     _check(rc, "tree_eval_centers")

@@ -37,16 +37,17 @@ def _equal_trees(got, want):
     assert np.array_equal(gp, wp)
 
 
-def _compare(codes, off, sigma, emb, topk, use_graph=False):
+def _compare(codes, off, sigma, emb, topk, use_graph=False, exact_below=0):
     import torch
     M = _msadp()
     n = len(off) - 1
-    print(f"[pruned] n={n} sigma={sigma} topk={topk} graph={use_graph}: device", flush=True)
+    print(f"[pruned] n={n} sigma={sigma} topk={topk} exact_below={exact_below} "
+          f"graph={use_graph}: device", flush=True)
     S = M.to_device(codes, off, sigma)
     e = torch.from_numpy(emb).to(S.codes.device)
-    got = M.tree_build(S, use_graph=use_graph, emb=e, topk=topk)
+    got = M.tree_build(S, use_graph=use_graph, emb=e, topk=topk, exact_below=exact_below)
     print(f"[pruned] device done ({got['n_nodes']} nodes); oracle", flush=True)
-    want = orc.tree_pruned(codes, off, emb, topk=topk)
+    want = orc.tree_pruned(codes, off, emb, topk=topk, exact_below=exact_below)
     _equal_trees(got, want)
     return got
 
@@ -55,6 +56,13 @@ def _compare(codes, off, sigma, emb, topk, use_graph=False):
 def test_tiny_workload(topk):
     d = synth.tiny()
     _compare(d["codes"], d["offsets"], d["sigma"], _emb(20 + topk, d["n"]), topk)
+
+
+@pytest.mark.parametrize("topk,exact_below", [(2, 12), (40, 0), (3, 70)])
+def test_exact_below_and_large_topk(topk, exact_below):
+    d = synth.tiny()
+    _compare(d["codes"], d["offsets"], d["sigma"], _emb(40 + topk, d["n"]), topk,
+             exact_below=exact_below)
 
 
 def test_tiny_workload_graph_replay():
@@ -119,9 +127,9 @@ def test_bad_arguments():
     d = synth.tiny()
     S = M.to_device(d["codes"], d["offsets"], d["sigma"])
     e = torch.zeros((d["n"], 128), dtype=torch.float32, device=S.codes.device)
-    for k in (0, 33):
+    for k, eb in ((0, 0), (1025, 0), (4, -1)):
         with pytest.raises(M.MsaError) as ex:
-            M.tree_build(S, emb=e, topk=k)
+            M.tree_build(S, emb=e, topk=k, exact_below=eb)
         assert ex.value.code == M.MSA_EINVAL
     with pytest.raises(ValueError):
         M.tree_build(S, emb=e[:10], topk=4)
@@ -150,13 +158,13 @@ def test_teacher_forced_pruned_matches_oracle():
     S = M.to_device(d["codes"], d["offsets"], d["sigma"])
     t = M.tree_build(S)
     emb = _emb(38, d["n"])
-    for topk in (1, 5):
+    for topk, eb in ((1, 0), (5, 0), (2, 10)):
         c, l, r = M.tree_eval_centers(S, t, emb=torch.from_numpy(emb).to(S.codes.device),
-                                      topk=topk)
+                                      topk=topk, exact_below=eb)
         for v in range(t["n_nodes"]):
             C = t["perm"][t["mstart"][v]: t["mstart"][v] + t["mcount"][v]]
-            want = orc.select(d["codes"], d["offsets"], C, emb, topk)
-            assert (int(c[v]), int(l[v]), int(r[v])) == want, (topk, v)
+            want = orc.select(d["codes"], d["offsets"], C, emb, topk, eb)
+            assert (int(c[v]), int(l[v]), int(r[v])) == want, (topk, eb, v)
 
 
 def test_teacher_forced_rejects_bad_tree():

@@ -179,3 +179,24 @@ def test_select_brute_force_median():
     l = int(np.argmax(D[c]))
     r = int(np.argmax(D[l]))
     assert orc.select(codes, off, C) == (C[c], C[l], C[r])
+
+
+def test_exact_below_covering_set_is_exact():
+    """exact_below >= n: every cluster keeps the full median."""
+    codes, off = synth.random_set(39, 40, 10, 50, 4)
+    t0 = orc.tree(codes, off)
+    t1 = orc.tree_pruned(codes, off, _emb(15, 40), topk=1, exact_below=40)
+    for f in orc.TREE_FIELDS + ("perm",):
+        assert (t0[f] == t1[f]).all(), f
+
+
+def test_exact_below_splits_by_size():
+    """Clusters of at most exact_below members take the exact choice, larger
+    ones the ranked one."""
+    codes, off = synth.random_set(40, 50, 10, 50, 4)
+    emb = _emb(16, 50)
+    t = orc.tree_pruned(codes, off, emb, topk=1, exact_below=12)
+    for v in range(t["n_nodes"]):
+        C = _members(t, v)
+        want = orc.select(codes, off, C) if len(C) <= 12 else orc.select(codes, off, C, emb, 1)
+        assert (int(t["center"][v]), int(t["lpole"][v]), int(t["rpole"][v])) == want

@@ -263,6 +263,56 @@ int cnn_train_step(void *params, const msa_seqs *S, const int32_t *idx, int32_t 
                    const uint16_t *dist, int32_t n_pairs, float lr, int32_t step, float *loss,
                    void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
+/* ------------------------------------------------------------------ */
+/* Tuning table (not in the paper): the launch variant of a kernel family
+ * per (kind, alphabet size sigma, length bin), used in place of the
+ * library's default.  Thread-safe; process-wide; empty at load.
+ *   MSA_TUNE_LEV: bin = ceil(max_len / 64) of the pattern set (A of
+ *     lev_batch / lev_allpairs); value = 64-bit words per pass of the
+ *     kernel variant (4, 8, 16, 20, 24, 28, 32).  Fewer words per pass than
+ *     the longest pattern needs means several passes; more words cost
+ *     registers and so resident wavefronts.  Default: the smallest of
+ *     4, 8, 16, 24, 32 that holds the longest pattern (32 beyond).
+ *   MSA_TUNE_NW: bin = wavefronts per pair, ceil(ceil(max_len_A / 32) / 64);
+ *     value = steps between the fill's workgroup barriers (16, 32, 64;
+ *     default 32).
+ * Workspace sizes never depend on the table.  Results never depend on it
+ * (every variant computes the same exact values). */
+enum { MSA_TUNE_LEV = 0, MSA_TUNE_NW = 1 };
+
+/* Set one entry (EINVAL for an unknown kind, a key out of range or a value
+ * that is not a variant of the kind). */
+int msa_tune_set(int32_t kind, int32_t sigma, int32_t bin, int32_t value);
+/* *value = the entry, or 0 when the table has none. */
+int msa_tune_get(int32_t kind, int32_t sigma, int32_t bin, int32_t *value);
+int msa_tune_clear(void);
+/* The variants of a kind: values[0 .. *count) (ENOSPC if cap < *count). */
+int msa_tune_candidates(int32_t kind, int32_t *values, int32_t cap, int32_t *count);
+/* The table as JSON text {"arch": "<gfx name>", "entries": [[kind, sigma,
+ * bin, value], ...]} into buf (host, cap bytes with the terminating zero;
+ * *len = its length; ENOSPC when it does not fit). */
+int msa_tune_export(char *buf, size_t cap, size_t *len);
+/* Merge entries from text in the export format; EINVAL (table unchanged)
+ * if the arch differs from the current device or an entry is invalid. */
+int msa_tune_import(const char *json);
+
+/* Autotuning: time every lev_allpairs variant that needs no more passes
+ * than the default (at least two allowed) on the set A, reps timed runs
+ * each after one warm-up (same arguments as lev_allpairs; the condensed
+ * output holds the last run's exact distances), then store the fastest
+ * for (MSA_TUNE_LEV, A->sigma, ceil(A->max_len / 64)).  *best = its words
+ * per pass, *best_ms = its mean time per call.  Synchronizes the stream. */
+int msa_autotune_lev(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws_bytes,
+                     int32_t reps, int32_t *best, float *best_ms, int32_t *d_status,
+                     hipStream_t s);
+/* The same for nw_batch (same arguments as nw_batch): every barrier
+ * interval, fastest stored for (MSA_TUNE_NW, A->sigma, wavefronts per pair
+ * of A->max_len). */
+int msa_autotune_nw(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                    int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets,
+                    void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
+                    int32_t *d_status, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -95,5 +95,7 @@ int sort_by_length(const msa_seqs *S, int32_t *len_tmp, int32_t *hist, int32_t *
 int fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 int fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 int exclusive_scan_i64(int64_t *data, int64_t n, hipStream_t s);
+// The tuning table's value for (kind, sigma, bin), or `fallback` (tune.hip).
+int tuned_value(int kind, int sigma, int bin, int fallback);
 
 }  // namespace msadp

@@ -8,9 +8,12 @@
 // match table Peq[word][symbol] sits in LDS (8 KB per wavefront).  A lane's
 // vertical delta vectors (Pv, Mv) stay in VGPRs (4 per 64-row word).  The
 // only per-symbol lookup is one LDS read per word, at an address that
-// depends on the lane's text symbol.  Patterns longer than 2048 rows run as
-// several passes of 32 words; the horizontal deltas leaving a pass (2 bits
-// per text column) go through a per-lane buffer in the workspace.
+// depends on the lane's text symbol.  A kernel variant is compiled for a
+// number of words per pass (its class); longer patterns run as several
+// passes, and the horizontal deltas leaving a pass (2 bits per text column)
+// go through a per-lane buffer in the workspace.  The class comes from the
+// tuning table (tune.hip) when it holds one for the set, else it is the
+// smallest class that holds the longest pattern in one pass (at most 32).
 //
 // Per text symbol t and word k (Eq = Peq[k][t]; hin = horizontal delta
 // entering the word from below-left, +1 for the top row):
@@ -20,6 +23,8 @@
 //   Ph = (Ph << 1) | [hin > 0];  Mh = (Mh << 1) | [hin < 0];
 //   Pv = Mh | ~(Xv | Ph);  Mv = Ph & Xv.
 // The distance is m plus the sum of the horizontal deltas of the last row.
+#include <algorithm>
+
 #include "lev_core.hpp"
 
 namespace msadp {
@@ -45,7 +50,7 @@ struct AllPairsArgs {
 
 template <int WMAX>
 __global__ void __launch_bounds__(64) k_lev_allpairs(AllPairsArgs a) {
-    __shared__ uint64_t peq[kMaxWords * kSym];
+    __shared__ uint64_t peq[WMAX * kSym];
     const int lane = lane_id();
     const int64_t N = a.S.n;
     uint32_t *hb = a.hbuf ? a.hbuf + (int64_t)blockIdx.x * a.hstride * kWave + lane : nullptr;
@@ -95,7 +100,7 @@ struct GroupedArgs {
 
 template <int WMAX>
 __global__ void __launch_bounds__(64) k_lev_grouped(GroupedArgs a) {
-    __shared__ uint64_t peq[kMaxWords * kSym];
+    __shared__ uint64_t peq[WMAX * kSym];
     const int lane = lane_id();
     const int64_t total = *a.n_items;
     uint32_t *hb = a.hbuf ? a.hbuf + (int64_t)blockIdx.x * a.hstride * kWave + lane : nullptr;
@@ -165,6 +170,8 @@ __global__ void k_make_items(const int64_t *start, const int64_t *item_start, in
 }
 
 // ------------------------------------------------------------ host side
+#define MSADP_LEV_CLASSES(X) X(4) X(8) X(16) X(20) X(24) X(28) X(32)
+
 static int lev_grid(int wclass, bool grouped) {
     static int cache[2][33];
     int &g = cache[grouped][wclass];
@@ -172,7 +179,7 @@ static int lev_grid(int wclass, bool grouped) {
         switch (wclass) {
 #define MSADP_G(w) \
     case w: g = grouped ? persistent_grid(k_lev_grouped<w>) : persistent_grid(k_lev_allpairs<w>); break;
-            MSADP_G(4) MSADP_G(8) MSADP_G(16) MSADP_G(24) MSADP_G(32)
+            MSADP_LEV_CLASSES(MSADP_G)
 #undef MSADP_G
             default: g = device_cus();
         }
@@ -182,8 +189,6 @@ static int lev_grid(int wclass, bool grouped) {
 
 static int64_t hbuf_stride(int32_t text_max) { return ((int64_t)text_max + 15) / 16; }
 
-static bool needs_passes(int32_t pat_max) { return pat_max > kMaxWords * 64; }
-
 struct LevPlan {
     int64_t strideA, strideB, hstride;
     int grid, wclass;
@@ -191,11 +196,11 @@ struct LevPlan {
 
 template <class Alloc>
 static void lev_layout(Alloc &al, const msa_seqs *A, const msa_seqs *B, int64_t n_pairs,
-                       const LevPlan &pl, bool grouped) {
-    al.template take<uint8_t>((size_t)A->n * pl.strideA);
+                       bool grouped) {
+    al.template take<uint8_t>((size_t)A->n * staged_stride(A->max_len));
     al.template take<int32_t>((size_t)A->n + 1);
     if (grouped) {
-        al.template take<uint8_t>((size_t)B->n * pl.strideB);
+        al.template take<uint8_t>((size_t)B->n * staged_stride(B->max_len));
         al.template take<int32_t>((size_t)B->n + 1);
         al.template take<int64_t>((size_t)A->n + 1);   // start
         al.template take<int64_t>((size_t)A->n + 1);   // cursor / item counts
@@ -207,25 +212,25 @@ static void lev_layout(Alloc &al, const msa_seqs *A, const msa_seqs *B, int64_t 
         al.template take<int32_t>((size_t)A->max_len + 1); // length histogram
     }
     al.template take<uint32_t>(1);  // work counter
-    if (pl.hstride) al.template take<uint32_t>((size_t)pl.grid * kWave * pl.hstride);
+    // carry buffer: sized for the largest need over all classes, so that a
+    // tuning entry never outgrows a workspace sized beforehand
+    size_t hb = 0;
+    for (int c : kLevClasses)
+        if (needs_passes(A->max_len, c))
+            hb = std::max(hb, (size_t)lev_grid(c, grouped) * kWave * hbuf_stride(B->max_len));
+    if (hb) al.template take<uint32_t>(hb);
 }
 
-static LevPlan plan_grouped(const msa_seqs *A, const msa_seqs *B) {
+// forced > 0 selects the class (autotuning), else the tuning table or the default.
+static LevPlan plan_lev(const msa_seqs *A, const msa_seqs *B, bool grouped, int forced) {
     LevPlan p;
     p.strideA = staged_stride(A->max_len);
     p.strideB = staged_stride(B->max_len);
-    p.wclass = wmax_class(A->max_len);
-    p.grid = lev_grid(p.wclass, true);
-    p.hstride = needs_passes(A->max_len) ? hbuf_stride(B->max_len) : 0;
-    return p;
-}
-
-static LevPlan plan_allpairs(const msa_seqs *A) {
-    LevPlan p;
-    p.strideA = p.strideB = staged_stride(A->max_len);
-    p.wclass = wmax_class(A->max_len);
-    p.grid = lev_grid(p.wclass, false);
-    p.hstride = needs_passes(A->max_len) ? hbuf_stride(A->max_len) : 0;
+    const int words = (int)std::max<int64_t>(1, ((int64_t)A->max_len + 63) / 64);
+    p.wclass = forced > 0 ? forced
+                          : tuned_value(MSA_TUNE_LEV, A->sigma, words, wmax_class(A->max_len));
+    p.grid = lev_grid(p.wclass, grouped);
+    p.hstride = needs_passes(A->max_len, p.wclass) ? hbuf_stride(B->max_len) : 0;
     return p;
 }
 
@@ -238,7 +243,7 @@ extern "C" {
 size_t lev_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
     if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
     Sizer sz;
-    lev_layout(sz, A, B, n_pairs, plan_grouped(A, B), true);
+    lev_layout(sz, A, B, n_pairs, true);
     return sz.total();
 }
 
@@ -252,9 +257,9 @@ int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int
     if (n_pairs == 0) return MSA_OK;
     if (ia == nullptr || ib == nullptr || dist == nullptr || ws == nullptr) return MSA_EINVAL;
     if (n_pairs > 0x7fffffffLL * 64) return MSA_ERANGE;
-    const LevPlan pl = plan_grouped(A, B);
+    const LevPlan pl = plan_lev(A, B, true, 0);
     Sizer sz;
-    lev_layout(sz, A, B, n_pairs, pl, true);
+    lev_layout(sz, A, B, n_pairs, true);
     if (ws_bytes < sz.total()) return MSA_ENOSPC;
 
     Carve cv(ws, ws_bytes);
@@ -290,11 +295,11 @@ int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int
     if ((rc = fill_i32((int32_t *)counter, 1, 0, s))) return rc;
     GroupedArgs ga{SA, SB, ib, sorted, items, n_items, dist, counter, hbuf, pl.hstride, A->sigma};
     switch (pl.wclass) {
-        case 4: hipLaunchKernelGGL(k_lev_grouped<4>, dim3(pl.grid), dim3(64), 0, s, ga); break;
-        case 8: hipLaunchKernelGGL(k_lev_grouped<8>, dim3(pl.grid), dim3(64), 0, s, ga); break;
-        case 16: hipLaunchKernelGGL(k_lev_grouped<16>, dim3(pl.grid), dim3(64), 0, s, ga); break;
-        case 24: hipLaunchKernelGGL(k_lev_grouped<24>, dim3(pl.grid), dim3(64), 0, s, ga); break;
-        default: hipLaunchKernelGGL(k_lev_grouped<32>, dim3(pl.grid), dim3(64), 0, s, ga); break;
+#define MSADP_L(w) \
+    case w: hipLaunchKernelGGL(k_lev_grouped<w>, dim3(pl.grid), dim3(64), 0, s, ga); break;
+        MSADP_LEV_CLASSES(MSADP_L)
+#undef MSADP_L
+        default: return MSA_EINVAL;
     }
     return launch_status();
 }
@@ -302,19 +307,19 @@ int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int
 size_t lev_allpairs_workspace_bytes(const msa_seqs *A) {
     if (check_seqs(A)) return 0;
     Sizer sz;
-    lev_layout(sz, A, A, 0, plan_allpairs(A), false);
+    lev_layout(sz, A, A, 0, false);
     return sz.total();
 }
 
-int lev_allpairs(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws_bytes,
-                 int32_t *d_status, hipStream_t s) {
+static int allpairs_impl(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws_bytes,
+                         int32_t *d_status, hipStream_t s, int forced) {
     int rc;
     if ((rc = check_seqs(A))) return rc;
     if (A->n < 2) return MSA_OK;
     if (condensed == nullptr || ws == nullptr) return MSA_EINVAL;
-    const LevPlan pl = plan_allpairs(A);
+    const LevPlan pl = plan_lev(A, A, false, forced);
     Sizer sz;
-    lev_layout(sz, A, A, 0, pl, false);
+    lev_layout(sz, A, A, 0, false);
     if (ws_bytes < sz.total()) return MSA_ENOSPC;
     const int64_t n_items = items_upto((int64_t)A->n - 1);
     if (n_items > 0xffffffffLL) return MSA_ERANGE;
@@ -332,13 +337,64 @@ int lev_allpairs(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws_byt
     if ((rc = fill_i32((int32_t *)counter, 1, 0, s))) return rc;
     AllPairsArgs aa{SA, order, condensed, counter, hbuf, pl.hstride, n_items, A->sigma};
     switch (pl.wclass) {
-        case 4: hipLaunchKernelGGL(k_lev_allpairs<4>, dim3(pl.grid), dim3(64), 0, s, aa); break;
-        case 8: hipLaunchKernelGGL(k_lev_allpairs<8>, dim3(pl.grid), dim3(64), 0, s, aa); break;
-        case 16: hipLaunchKernelGGL(k_lev_allpairs<16>, dim3(pl.grid), dim3(64), 0, s, aa); break;
-        case 24: hipLaunchKernelGGL(k_lev_allpairs<24>, dim3(pl.grid), dim3(64), 0, s, aa); break;
-        default: hipLaunchKernelGGL(k_lev_allpairs<32>, dim3(pl.grid), dim3(64), 0, s, aa); break;
+#define MSADP_L(w) \
+    case w: hipLaunchKernelGGL(k_lev_allpairs<w>, dim3(pl.grid), dim3(64), 0, s, aa); break;
+        MSADP_LEV_CLASSES(MSADP_L)
+#undef MSADP_L
+        default: return MSA_EINVAL;
     }
     return launch_status();
+}
+
+int lev_allpairs(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws_bytes,
+                 int32_t *d_status, hipStream_t s) {
+    return allpairs_impl(A, condensed, ws, ws_bytes, d_status, s, 0);
+}
+
+int msa_autotune_lev(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws_bytes,
+                     int32_t reps, int32_t *best, float *best_ms, int32_t *d_status,
+                     hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(A))) return rc;
+    if (best == nullptr || best_ms == nullptr || reps < 1 || A->n < 2) return MSA_EINVAL;
+    const int words = (int)std::max<int64_t>(1, ((int64_t)A->max_len + 63) / 64);
+    // candidates: every class that needs no more passes than the default
+    const int dflt = wmax_class(A->max_len);
+    const int max_passes = std::max(2, (words + dflt - 1) / dflt);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MSA_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MSA_EDEVICE;
+    }
+    int bc = 0;
+    float bms = 0.0f;
+    rc = MSA_OK;
+    for (int c : kLevClasses) {
+        if ((words + c - 1) / c > max_passes) continue;
+        if ((rc = allpairs_impl(A, condensed, ws, ws_bytes, d_status, s, c))) break;   // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
+        for (int r = 0; r < reps && rc == MSA_OK; ++r)
+            rc = allpairs_impl(A, condensed, ws, ws_bytes, d_status, s, c);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = MSA_EDEVICE;
+            break;
+        }
+        ms /= (float)reps;
+        if (bc == 0 || ms < bms) {
+            bc = c;
+            bms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = bc;
+    *best_ms = bms;
+    return msa_tune_set(MSA_TUNE_LEV, A->sigma, words, bc);
 }
 
 }  // extern "C"

@@ -6,7 +6,7 @@
 
 namespace msadp {
 
-constexpr int kMaxWords = 32;  // 64-bit words per pass (2048 rows)
+constexpr int kMaxWords = 32;  // most 64-bit words per pass (2048 rows)
 constexpr int kSym = 32;       // symbol stride of the Peq table
 
 typedef const __attribute__((address_space(3))) uint64_t lds_u64;
@@ -141,7 +141,10 @@ __device__ __forceinline__ int dispatch_first(int w, lds_u64 *peq, const uint8_t
 
 // Distance between this wavefront's pattern (pat, m) and each lane's text
 // (text, n; lanes with valid == false still take part but their result is
-// ignored).  `hbuf` is this lane's carry buffer (used when m > 2048).
+// ignored).  A pattern of more than WMAX words runs as several passes (the
+// first takes the remainder, the others WMAX words each); `hbuf` is this
+// lane's carry buffer between passes (needed when m > 64 * WMAX).  peq holds
+// WMAX words of the table.
 template <int WMAX>
 __device__ __forceinline__ int lev_item(uint64_t *peq, const uint8_t *pat, int m, int sigma,
                                         const uint8_t *text, int n, bool valid, uint32_t *hbuf) {
@@ -149,19 +152,18 @@ __device__ __forceinline__ int lev_item(uint64_t *peq, const uint8_t *pat, int m
     if (m == 0) return n;
     if (nmax == 0) return m;
     const int words = (m + 63) >> 6;
-    const int passes = (words + kMaxWords - 1) / kMaxWords;
-    const int w_first = words - (passes - 1) * kMaxWords;
+    const int passes = (words + WMAX - 1) / WMAX;
+    const int w_first = words - (passes - 1) * WMAX;
     const int b_last = (m - 1) & 63;
     build_peq(peq, pat, m, 0, w_first, sigma);
     lds_u64 *tbl = (lds_u64 *)peq;
     int s = dispatch_first<WMAX>(w_first, tbl, text, n, nmax, passes == 1 ? b_last : 63,
                                  passes > 1, hbuf);
-    if constexpr (WMAX == kMaxWords)
     for (int p = 1; p < passes; ++p) {
-        const int w0 = w_first + (p - 1) * kMaxWords;
-        build_peq(peq, pat, m, w0, kMaxWords, sigma);
+        const int w0 = w_first + (p - 1) * WMAX;
+        build_peq(peq, pat, m, w0, WMAX, sigma);
         const bool last = (p == passes - 1);
-        s = lev_pass<kMaxWords, true>(tbl, text, n, nmax, last ? b_last : 63, !last, hbuf);
+        s = lev_pass<WMAX, true>(tbl, text, n, nmax, last ? b_last : 63, !last, hbuf);
     }
     return m + s;
 }
@@ -194,6 +196,8 @@ __device__ __forceinline__ int64_t triangle_row(int64_t g, int64_t hi) {
 
 // Pattern words per pass that a kernel variant is compiled for; a variant
 // holds 4 VGPRs of state per word, so small patterns get more wavefronts.
+// The tree build uses the classes of wmax_class; the pair kernels also have
+// 20 and 28, which a tuning entry may select.
 inline int wmax_class(int32_t pat_max) {
     const int w = (pat_max + 63) / 64;
     if (w <= 4) return 4;
@@ -202,6 +206,17 @@ inline int wmax_class(int32_t pat_max) {
     if (w <= 24) return 24;
     return kMaxWords;
 }
+
+constexpr int kLevClasses[] = {4, 8, 16, 20, 24, 28, 32};
+
+inline bool is_lev_class(int c) {
+    for (int x : kLevClasses)
+        if (x == c) return true;
+    return false;
+}
+
+// Passes of a class over patterns of up to pat_max rows need a carry buffer.
+inline bool needs_passes(int32_t pat_max, int wclass) { return pat_max > wclass * 64; }
 
 // Workgroups of one wavefront that fit on the device at once for `kernel`.
 template <class K>

@@ -15,8 +15,9 @@
 // text column j one step after lane g-1 did, so the horizontal delta leaving
 // word g-1 and the text symbol of column j reach lane g by a one-lane
 // wavefront shift (DPP).  Between wavefronts the same packet goes through an
-// LDS ring; wavefront w runs kLag steps behind w-1 and all wavefronts meet at
-// a barrier every kRound steps, which orders every ring write before its read.
+// LDS ring; wavefront w runs R + 64 steps behind w-1 and all wavefronts meet
+// at a barrier every R steps, which orders every ring write before its read.
+// R (16, 32 or 64) comes from the tuning table (tune.hip), default 32.
 // The equality mask of a word is rebuilt per column from the word's symbol
 // bit planes (no lookup table).  Codes are stored by anti-diagonal: the entry
 // of (column j, word g) is record (j + g) * W + g, so at every step one
@@ -25,13 +26,18 @@
 
 namespace msadp {
 
-constexpr int kRound = 32;     // steps between workgroup barriers
-constexpr int kLag = 96;       // step lag between consecutive wavefronts (>= 63 + kRound)
-constexpr int kRing = 256;     // ring entries per wavefront boundary (>= kLag - 63 + kRound)
+// Schedule of a fill with R steps between workgroup barriers.
+template <int R>
+struct Round {
+    static constexpr int kRound = R;            // steps between workgroup barriers
+    static constexpr int kLag = 64 + R;         // step lag between consecutive wavefronts
+    static constexpr int kRing = 4 * R;         // ring entries per wavefront boundary
+    static_assert(kLag >= 63 + kRound, "ring handoff needs a barrier in between");
+    static_assert(kRing >= kLag - 63 + kRound, "ring too small");
+    static_assert((kRing & (kRing - 1)) == 0, "ring size is a power of two");
+};
 constexpr int kMaxFillWaves = 16;
-
-static_assert(kLag >= 63 + kRound, "ring handoff needs a barrier in between");
-static_assert(kRing >= kLag - 63 + kRound, "ring too small");
+constexpr int kDefaultRound = 32;
 
 __host__ __device__ inline int64_t tb_words(int32_t m) { return ((int64_t)m + 31) / 32; }
 
@@ -64,8 +70,9 @@ struct FillArgs {
 // DPP control: shift the whole wavefront right by one lane.
 constexpr int kDppWaveShr1 = 0x138;
 
-template <int P>
+template <int P, int R>
 __device__ void nw_fill_pair(const FillArgs &a, int64_t p, uint32_t *ring) {
+    constexpr int kRound = Round<R>::kRound, kLag = Round<R>::kLag, kRing = Round<R>::kRing;
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     const int32_t x = a.ia[p], y = a.ib[p];
@@ -174,10 +181,10 @@ __device__ void nw_fill_pair(const FillArgs &a, int64_t p, uint32_t *ring) {
     if (g == W - 1 && a.score) a.score[p] = m + (int)(acc & 0xFFFFu) - (int)(acc >> 16);
 }
 
-template <int P>
+template <int P, int R>
 __global__ void __launch_bounds__(1024) k_nw_fill(FillArgs a) {
-    __shared__ uint32_t ring[kMaxFillWaves * kRing];
-    nw_fill_pair<P>(a, blockIdx.x, ring);
+    __shared__ uint32_t ring[kMaxFillWaves * Round<R>::kRing];
+    nw_fill_pair<P, R>(a, blockIdx.x, ring);
 }
 
 // ------------------------------------------------------------ traceback
@@ -311,24 +318,22 @@ static NwPlan plan_nw(const msa_seqs *A, const msa_seqs *B) {
     return p;
 }
 
-}  // namespace msadp
-
-using namespace msadp;
-
-extern "C" {
-
-size_t nw_tb_bytes(int32_t m, int32_t n) { return (size_t)tb_bytes(m, n); }
-
-size_t nw_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
-    if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
-    Sizer sz;
-    nw_layout(sz, A, B, plan_nw(A, B));
-    return sz.total();
+template <int R>
+static void launch_fill(int planes, dim3 grid, dim3 block, const FillArgs &fa, hipStream_t s) {
+    switch (planes) {
+        case 1: hipLaunchKernelGGL((k_nw_fill<1, R>), grid, block, 0, s, fa); break;
+        case 2: hipLaunchKernelGGL((k_nw_fill<2, R>), grid, block, 0, s, fa); break;
+        case 3: hipLaunchKernelGGL((k_nw_fill<3, R>), grid, block, 0, s, fa); break;
+        case 4: hipLaunchKernelGGL((k_nw_fill<4, R>), grid, block, 0, s, fa); break;
+        default: hipLaunchKernelGGL((k_nw_fill<5, R>), grid, block, 0, s, fa); break;
+    }
 }
 
-int nw_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
-             int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets, void *ws,
-             size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+// forced > 0 selects R (autotuning), else the tuning table or the default.
+static int nw_batch_impl(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
+                         const int32_t *ib, int64_t n_pairs, int32_t *score, uint8_t *tb,
+                         const int64_t *tb_offsets, void *ws, size_t ws_bytes, int32_t *d_status,
+                         hipStream_t s, int forced) {
     int rc;
     if ((rc = check_seqs(A)) || (rc = check_seqs(B))) return rc;
     if (n_pairs < 0) return MSA_EINVAL;
@@ -353,14 +358,82 @@ int nw_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int3
     const int waves = (int)std::max<int64_t>(1, (W + 63) / 64);
     FillArgs fa{SA, SB, ia, ib, score, tb, tb_offsets, d_status, bits_for(A->sigma)};
     dim3 grid((unsigned)n_pairs), block(64 * waves);
-    switch (fa.planes) {
-        case 1: hipLaunchKernelGGL(k_nw_fill<1>, grid, block, 0, s, fa); break;
-        case 2: hipLaunchKernelGGL(k_nw_fill<2>, grid, block, 0, s, fa); break;
-        case 3: hipLaunchKernelGGL(k_nw_fill<3>, grid, block, 0, s, fa); break;
-        case 4: hipLaunchKernelGGL(k_nw_fill<4>, grid, block, 0, s, fa); break;
-        default: hipLaunchKernelGGL(k_nw_fill<5>, grid, block, 0, s, fa); break;
+    const int R = forced > 0 ? forced : tuned_value(MSA_TUNE_NW, A->sigma, waves, kDefaultRound);
+    switch (R) {
+        case 16: launch_fill<16>(fa.planes, grid, block, fa, s); break;
+        case 32: launch_fill<32>(fa.planes, grid, block, fa, s); break;
+        case 64: launch_fill<64>(fa.planes, grid, block, fa, s); break;
+        default: return MSA_EINVAL;
     }
     return launch_status();
+}
+
+}  // namespace msadp
+
+using namespace msadp;
+
+extern "C" {
+
+size_t nw_tb_bytes(int32_t m, int32_t n) { return (size_t)tb_bytes(m, n); }
+
+size_t nw_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
+    if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
+    Sizer sz;
+    nw_layout(sz, A, B, plan_nw(A, B));
+    return sz.total();
+}
+
+int nw_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+             int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets, void *ws,
+             size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    return nw_batch_impl(A, B, ia, ib, n_pairs, score, tb, tb_offsets, ws, ws_bytes, d_status,
+                         s, 0);
+}
+
+int msa_autotune_nw(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                    int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets,
+                    void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
+                    int32_t *d_status, hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(A)) || (rc = check_seqs(B))) return rc;
+    if (best == nullptr || best_ms == nullptr || reps < 1 || n_pairs < 1) return MSA_EINVAL;
+    const int waves = (int)std::max<int64_t>(1, (tb_words(A->max_len) + 63) / 64);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MSA_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MSA_EDEVICE;
+    }
+    int br = 0;
+    float bms = 0.0f;
+    rc = MSA_OK;
+    for (int R : {16, 32, 64}) {
+        if ((rc = nw_batch_impl(A, B, ia, ib, n_pairs, score, tb, tb_offsets, ws, ws_bytes,
+                                d_status, s, R)))
+            break;   // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
+        for (int r = 0; r < reps && rc == MSA_OK; ++r)
+            rc = nw_batch_impl(A, B, ia, ib, n_pairs, score, tb, tb_offsets, ws, ws_bytes,
+                               d_status, s, R);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = MSA_EDEVICE;
+            break;
+        }
+        ms /= (float)reps;
+        if (br == 0 || ms < bms) {
+            br = R;
+            bms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = br;
+    *best_ms = bms;
+    return msa_tune_set(MSA_TUNE_NW, A->sigma, waves, br);
 }
 
 int nw_traceback(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,

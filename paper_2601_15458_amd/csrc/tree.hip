@@ -164,7 +164,7 @@ __global__ void k_zero_counter(uint32_t *c) { *c = 0; }
 // The distance passes of a level.
 template <int WMAX, int MODE>
 __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
-    __shared__ uint64_t peq[kMaxWords * kSym];
+    __shared__ uint64_t peq[WMAX * kSym];
     const int lane = lane_id();
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     const int64_t total = a.items[nq];
@@ -687,7 +687,7 @@ static TreePlan plan_tree(const msa_seqs *S) {
     p.stride = staged_stride(S->max_len);
     p.wclass = wmax_class(S->max_len);
     p.grid = tree_grid(p.wclass);
-    p.hstride = S->max_len > kMaxWords * 64 ? ((int64_t)S->max_len + 15) / 16 : 0;
+    p.hstride = needs_passes(S->max_len, p.wclass) ? ((int64_t)S->max_len + 15) / 16 : 0;
     return p;
 }
 

@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsadp.so")
 
 MSA_OK, MSA_EINVAL, MSA_ERANGE, MSA_ENOSPC, MSA_EDEVICE = 0, -1, -2, -3, -4
+MSA_TUNE_LEV, MSA_TUNE_NW = 0, 1
 DS_NAMES = {0: "ok", 1: "symbol code >= sigma", 2: "sequence index out of range",
             3: "length out of range", 4: "output capacity too small"}
 
@@ -60,6 +61,17 @@ SIGNATURES = {
     "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
     "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
                             C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
+    "msa_tune_set": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "msa_tune_get": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+    "msa_tune_clear": (C.c_int, []),
+    "msa_tune_candidates": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                      C.POINTER(C.c_int32)]),
+    "msa_tune_export": (C.c_int, [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "msa_tune_import": (C.c_int, [C.c_char_p]),
+    "msa_autotune_lev": (C.c_int, [SP, P, P, C.c_size_t, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_float), P, P]),
+    "msa_autotune_nw": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, C.c_size_t, C.c_int32,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
     "cnn_param_bytes": (C.c_size_t, []),
     "cnn_set_params": (C.c_int, [P, P, P, P]),
     "cnn_get_params": (C.c_int, [P, P, P, P, P, P]),
@@ -246,11 +258,14 @@ class NwBatch:
         self.ops_len = torch.empty(max(r.n_pairs, 1), dtype=torch.int32, device=dev)
         self.st = Status(dev)
 
-    def fill(self, stream=None):
+    def fill_args(self):
+        """nw_batch's arguments up to the workspace size."""
         r = self.r
-        rc = lib().nw_batch(C.byref(self.sa), C.byref(self.sb), _ptr(r.ia), _ptr(r.ib),
-                            r.n_pairs, _ptr(r.score), _ptr(r.tb), _ptr(r.tb_offsets),
-                            _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
+        return (C.byref(self.sa), C.byref(self.sb), _ptr(r.ia), _ptr(r.ib), r.n_pairs,
+                _ptr(r.score), _ptr(r.tb), _ptr(r.tb_offsets), _ptr(self.ws), self.wsb)
+
+    def fill(self, stream=None):
+        rc = lib().nw_batch(*self.fill_args(), _ptr(self.st.t), _stream(stream))
         _check(rc, "nw_batch")
 
     def traceback(self, stream=None):
@@ -478,6 +493,87 @@ def align(S: Seqs, use_graph=False, stream=None):
         tb.st.check("tree_build")
         msa = msa_merge(S, tree, stream=stream)
     return tree.host(), msa
+
+
+# ---------------------------------------------------------------- tuning
+def tune_set(kind: int, sigma: int, bin_: int, value: int):
+    _check(lib().msa_tune_set(kind, sigma, bin_, value), "msa_tune_set")
+
+
+def tune_get(kind: int, sigma: int, bin_: int) -> int:
+    """The table's value for the key, 0 when it holds none."""
+    v = C.c_int32(0)
+    _check(lib().msa_tune_get(kind, sigma, bin_, C.byref(v)), "msa_tune_get")
+    return v.value
+
+
+def tune_clear():
+    _check(lib().msa_tune_clear(), "msa_tune_clear")
+
+
+def tune_candidates(kind: int):
+    vals = (C.c_int32 * 16)()
+    n = C.c_int32(0)
+    _check(lib().msa_tune_candidates(kind, vals, 16, C.byref(n)), "msa_tune_candidates")
+    return [vals[i] for i in range(n.value)]
+
+
+def tune_export() -> str:
+    n = C.c_size_t(0)
+    rc = lib().msa_tune_export(None, 0, C.byref(n))
+    if rc not in (MSA_OK, MSA_ENOSPC):
+        _check(rc, "msa_tune_export")
+    buf = C.create_string_buffer(n.value + 1)
+    _check(lib().msa_tune_export(buf, n.value + 1, C.byref(n)), "msa_tune_export")
+    return buf.value.decode()
+
+
+def tune_import(text: str):
+    _check(lib().msa_tune_import(text.encode()), "msa_tune_import")
+
+
+def tune_save(path: str):
+    """Write the tuning table to a JSON cache file."""
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    with open(path, "w") as f:
+        f.write(tune_export() + "\n")
+
+
+def tune_load(path: str) -> bool:
+    """Merge a JSON cache file into the table (False if it does not exist)."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        tune_import(f.read())
+    return True
+
+
+def lev_words_bin(S: Seqs) -> int:
+    return max(1, (S.max_len + 63) // 64)
+
+
+def autotune_lev(S: Seqs, reps: int = 2, stream=None):
+    """Time the lev_allpairs variants on S and keep the fastest in the table;
+    returns (words per pass, ms per call)."""
+    ap = AllPairs(S)
+    best, ms = C.c_int32(0), C.c_float(0.0)
+    rc = lib().msa_autotune_lev(C.byref(ap.sa), _ptr(ap.out), _ptr(ap.ws), ap.wsb, int(reps),
+                                C.byref(best), C.byref(ms), _ptr(ap.st.t), _stream(stream))
+    _check(rc, "msa_autotune_lev")
+    ap.st.check("msa_autotune_lev")
+    return best.value, ms.value
+
+
+def autotune_nw(nb: "NwBatch", reps: int = 2, stream=None):
+    """Time the nw_batch variants on a prepared NwBatch and keep the fastest;
+    returns (steps between barriers, ms per call)."""
+    best, ms = C.c_int32(0), C.c_float(0.0)
+    rc = lib().msa_autotune_nw(*nb.fill_args(), int(reps), C.byref(best), C.byref(ms),
+                               _ptr(nb.st.t), _stream(stream))
+    _check(rc, "msa_autotune_nw")
+    nb.st.check("msa_autotune_nw")
+    return best.value, ms.value
 
 
 # ---------------------------------------------------------------- embedder

@@ -1,0 +1,90 @@
+"""Tuning table: host logic only (no GPU needed)."""
+import json
+
+import pytest
+
+
+def _msadp():
+    from paper_2601_15458_amd import msadp
+    return msadp
+
+
+@pytest.fixture(autouse=True)
+def _clean():
+    M = _msadp()
+    M.tune_clear()
+    yield
+    M.tune_clear()
+
+
+def test_candidates():
+    M = _msadp()
+    assert M.tune_candidates(M.MSA_TUNE_LEV) == [4, 8, 16, 20, 24, 28, 32]
+    assert M.tune_candidates(M.MSA_TUNE_NW) == [16, 32, 64]
+
+
+def test_set_get_clear():
+    M = _msadp()
+    assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 0
+    M.tune_set(M.MSA_TUNE_LEV, 4, 25, 28)
+    M.tune_set(M.MSA_TUNE_NW, 4, 3, 64)
+    assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 28
+    assert M.tune_get(M.MSA_TUNE_LEV, 5, 25) == 0
+    assert M.tune_get(M.MSA_TUNE_NW, 4, 3) == 64
+    M.tune_clear()
+    assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 0
+
+
+@pytest.mark.parametrize("kind,sigma,bin_,value", [
+    (0, 4, 25, 30),      # not a word class
+    (1, 4, 3, 48),       # not a barrier interval
+    (2, 4, 3, 32),       # unknown kind
+    (0, 1, 3, 32),       # alphabet too small
+    (0, 4, 0, 32),       # empty bin
+])
+def test_invalid_entries(kind, sigma, bin_, value):
+    M = _msadp()
+    with pytest.raises(M.MsaError) as ex:
+        M.tune_set(kind, sigma, bin_, value)
+    assert ex.value.code == M.MSA_EINVAL
+
+
+def test_export_import_round_trip():
+    M = _msadp()
+    M.tune_set(M.MSA_TUNE_LEV, 4, 25, 28)
+    M.tune_set(M.MSA_TUNE_LEV, 20, 3, 4)
+    M.tune_set(M.MSA_TUNE_NW, 4, 5, 16)
+    text = M.tune_export()
+    doc = json.loads(text)
+    assert sorted(map(tuple, doc["entries"])) == [(0, 4, 25, 28), (0, 20, 3, 4), (1, 4, 5, 16)]
+    M.tune_clear()
+    M.tune_import(text)
+    assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 28
+    assert M.tune_get(M.MSA_TUNE_LEV, 20, 3) == 4
+    assert M.tune_get(M.MSA_TUNE_NW, 4, 5) == 16
+
+
+def test_import_rejects_other_arch_and_bad_entries():
+    M = _msadp()
+    arch = json.loads(M.tune_export())["arch"]
+    M.tune_set(M.MSA_TUNE_LEV, 4, 25, 28)
+    bad = [json.dumps({"arch": arch + "x", "entries": [[0, 4, 25, 16]]}),
+           json.dumps({"arch": arch, "entries": [[0, 4, 25, 17]]}),
+           json.dumps({"arch": arch, "entries": [[0, 4, 25]]}),
+           "not json"]
+    for text in bad:
+        with pytest.raises(M.MsaError) as ex:
+            M.tune_import(text)
+        assert ex.value.code == M.MSA_EINVAL
+    assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 28      # unchanged
+
+
+def test_save_and_load(tmp_path):
+    M = _msadp()
+    M.tune_set(M.MSA_TUNE_NW, 4, 2, 64)
+    path = str(tmp_path / "tune.json")
+    M.tune_save(path)
+    M.tune_clear()
+    assert M.tune_load(path)
+    assert M.tune_get(M.MSA_TUNE_NW, 4, 2) == 64
+    assert not M.tune_load(str(tmp_path / "missing.json"))

@@ -31,7 +31,7 @@ constexpr int kKer = 5;      // kernel width
 constexpr int kLayers = 4;
 constexpr int kIn = 8;       // one-hot channels (sigma <= 8)
 constexpr int kLead = 8;     // zero rows before the first sequence
-constexpr int kTile = 128;   // rows per GEMM workgroup
+constexpr int kTile = 256;   // rows per GEMM workgroup
 
 __host__ __device__ constexpr int cin_of(int l) { return l == 0 ? kIn : kW; }
 __host__ __device__ constexpr int kd_of(int l) { return kKer * cin_of(l); }              // 40 / 640
@@ -163,10 +163,17 @@ struct ConvArgs {
     const bf16_t *relu_ref;  // rows whose sign gates the input gradient
 };
 
-// Workgroup = 4 wavefronts = 128 output rows x 128 channels; wavefront w
-// owns rows [32w, 32w + 32): 2 x 8 tiles of 16 x 16, K in steps of 32.
+// Workgroup = 8 wavefronts = kTile output rows x 128 channels; wavefront w
+// owns rows [32 w, 32 w + 32): 2 x 8 tiles of 16 x 16, K in steps of 32.
+// The A fragments (8 consecutive span elements of one row) are 16-byte
+// global loads; the weights' K slice of each step, shared by the eight
+// wavefronts, is staged in LDS ([co][32], padded) and read as 16-byte
+// fragments.
+constexpr int kBp = 40;   // LDS pitch of a staged weight row (32 + 8)
+
 template <int CIN, int KDP, int EPI>
-__global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
+__global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) bf16_t sb[kW * kBp];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * kTile + 32 * w;
@@ -181,13 +188,19 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
         arow[i] = a.X + (kLead + row0 + 16 * i + li - 2) * CIN + kq;
-    const bf16_t *brow = a.Wt + (size_t)li * KDP + kq;
+    // staging role: weight row co = t / 4, quarter q = t % 4 (8 of the 32 K)
+    const int sco = threadIdx.x >> 2, sq = (threadIdx.x & 3) * 8;
+    const bf16_t *wsrc = a.Wt + (size_t)sco * KDP + sq;
     for (int k0 = 0; k0 < KDP; k0 += 32) {
-        bf16x8 af[2], bfr[8];
+        __syncthreads();
+        *(uint4 *)(sb + sco * kBp + sq) = *(const uint4 *)(wsrc + k0);
+        bf16x8 af[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) af[i] = *(const bf16x8 *)(arow[i] + k0);
+        __syncthreads();
+        bf16x8 bfr[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bfr[j] = *(const bf16x8 *)(brow + (size_t)16 * j * KDP + k0);
+        for (int j = 0; j < 8; ++j) bfr[j] = *(const bf16x8 *)(sb + (16 * j + li) * kBp + kq);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -221,64 +234,118 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
     }
 }
 
-// Weight gradient: gW[co][kk] += sum over rows r of dZ[r][co] * span(H)[r][kk].
-// Workgroup = 128 co x 128 kk columns over a chunk of rows, staged in LDS in
-// steps of 32 rows; each wavefront owns 32 co.
-constexpr int kWgChunk = 8192;
+// Weight gradient: gW[co][kk] += sum over rows r of dZ[r][co] * span(H)[r][kk],
+// with kk = k * CIN + ci and span(H)[r][kk] = H[r + k - 2][ci]; blockIdx.x = 0
+// also adds the bias gradient gb[co] += sum over rows of dZ[r][co].
+// The reduction runs over rows, which the matrix cores take 32 at a time
+// (8 consecutive rows per lane), so each 64-row step is staged in LDS
+// transposed (channel-major): dZ as [co][row] and H, shifted by k - 2 rows,
+// as [ci][row], one copy per shift the block needs (one for CIN = 128, where
+// blockIdx.x = k covers kk in [128 k, 128 k + 128); five for the one-hot
+// layer, whose 40 columns fit one block).  A wavefront stages 16-channel
+// pieces of 64 consecutive rows, so its LDS writes go to consecutive
+// addresses; every fragment is one 16-byte LDS read.  Workgroup = 4
+// wavefronts, wavefront w owns co in [32 w, 32 w + 32) x the block's kk.
+constexpr int kWgChunk = 16384;
+constexpr int kStep = 64;            // rows staged per step
+constexpr int kTp = kStep + 8;       // LDS row pitch of the transposed tiles
+
+// Scatter 8 packed bf16 pairs (16 channels of one row) into a channel-major tile.
+__device__ __forceinline__ void put_transposed(bf16_t *t, int c0, int row, uint4 v0, uint4 v1) {
+    const uint32_t e[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        t[(c0 + 2 * q) * kTp + row] = (bf16_t)(e[q] & 0xFFFFu);
+        t[(c0 + 2 * q + 1) * kTp + row] = (bf16_t)(e[q] >> 16);
+    }
+}
 
 template <int CIN, int KDP>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_t *dZ,
-                                                    int64_t rows, float *gW) {
-    constexpr int kDzPitch = kW + 2;
-    constexpr int kXElems = 32 * CIN + KDP;
-    __shared__ bf16_t sdz[32 * kDzPitch];
-    __shared__ bf16_t sx[kXElems];
+                                                    int64_t rows, float *gW, float *gb) {
+    constexpr int NS = CIN == kW ? 1 : kKer;           // staged shifts
+    constexpr int NT = (KDP < 128 ? KDP : 128) / 16;   // 16-column tiles per block
+    constexpr int KD = kKer * CIN;
+    __shared__ __attribute__((aligned(16))) bf16_t sdz[kW * kTp];
+    __shared__ __attribute__((aligned(16))) bf16_t sh[NS * CIN * kTp];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     const int li = lane & 15, kq = 8 * (lane >> 4);
-    const int kk0 = blockIdx.y * 128;
-    const int64_t r_begin = (int64_t)blockIdx.x * kWgChunk;
+    const int kb = blockIdx.x;
+    const int kk0 = kb * 128;
+    const int64_t r_begin = (int64_t)blockIdx.y * kWgChunk;
     const int64_t r_end = min(rows, r_begin + kWgChunk);
-    f32x4 acc[2][8];
+    f32x4 acc[2][NT];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += 32) {
+        for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    float bsum = 0.0f;
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kStep) {
         __syncthreads();
-        // dZ rows [r0, r0 + 32) (rows past the end read as zero)
-        for (int e = threadIdx.x; e < 32 * kW; e += blockDim.x) {
-            const int rr = e / kW, c = e % kW;
-            sdz[rr * kDzPitch + c] = (r0 + rr < r_end) ? dZ[(kLead + r0 + rr) * kW + c] : (bf16_t)0;
+        // dZ: wavefront w stages channels [16 w, 16 w + 16) and [16 w + 64, ..) of
+        // rows r0 + lane (rows at or past the chunk end read as zero)
+        {
+            const bool live = r0 + lane < r_end;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c0 = 16 * w + 64 * h;
+                const uint4 *src = (const uint4 *)(dZ + (kLead + r0 + lane) * kW + c0);
+                const uint4 z = make_uint4(0, 0, 0, 0);
+                put_transposed(sdz, c0, lane, live ? src[0] : z, live ? src[1] : z);
+            }
         }
-        // H span base (r0 - 2) * CIN, 32 * CIN + KDP elements
-        const bf16_t *hb = H + (kLead + r0 - 2) * CIN;
-        for (int e = threadIdx.x; e < kXElems; e += blockDim.x) sx[e] = hb[e];
+        if (CIN == kW) {
+            // H rows r0 + kb - 2 + lane (inside the framed buffer: lead rows
+            // before the first row, tail rows after the last)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c0 = 16 * w + 64 * h;
+                const uint4 *src = (const uint4 *)(H + (kLead + r0 + kb - 2 + lane) * kW + c0);
+                put_transposed(sh, c0, lane, src[0], src[1]);
+            }
+        } else {
+            // one 16-byte row (8 channels) per thread and shift
+            for (int e = threadIdx.x; e < NS * kStep; e += blockDim.x) {
+                const int sk = e / kStep, rr = e % kStep;
+                const uint4 v = *(const uint4 *)(H + (kLead + r0 + sk - 2 + rr) * CIN);
+                const uint32_t q4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sh[(sk * CIN + 2 * q) * kTp + rr] = (bf16_t)(q4[q] & 0xFFFFu);
+                    sh[(sk * CIN + 2 * q + 1) * kTp + rr] = (bf16_t)(q4[q] >> 16);
+                }
+            }
+        }
         __syncthreads();
-        bf16x8 af[2], bfr[8];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int co = 32 * w + 16 * i + li;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) af[i][j] = __builtin_bit_cast(__bf16, sdz[(kq + j) * kDzPitch + co]);
+        if (kb == 0 && threadIdx.x < kW) {
+#pragma unroll 8
+            for (int rr = 0; rr < kStep; ++rr) bsum += from_bf16(sdz[threadIdx.x * kTp + rr]);
         }
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            const int kk = kk0 + 16 * n + li;
+        for (int ks = 0; ks < kStep; ks += 32) {
+            bf16x8 af[2], bfr[NT];
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                bfr[n][j] = kk < KDP ? __builtin_bit_cast(__bf16, sx[(kq + j) * CIN + kk]) : (__bf16)0.0f;
+            for (int i = 0; i < 2; ++i)
+                af[i] = *(const bf16x8 *)(sdz + (32 * w + 16 * i + li) * kTp + ks + kq);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const int kk = kk0 + 16 * n + li;
+                const int k = CIN == kW ? 0 : kk / CIN, ci = kk % CIN;
+                bfr[n] = kk < KD ? *(const bf16x8 *)(sh + ((k < NS ? k : 0) * CIN + ci) * kTp + ks + kq)
+                                 : bf16x8{};
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[i][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[n], acc[i][n], 0, 0, 0);
         }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int n = 0; n < 8; ++n)
-                acc[i][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[n], acc[i][n], 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
+        for (int n = 0; n < NT; ++n) {
             const int kk = kk0 + 16 * n + li;
             if (kk >= KDP) continue;
 #pragma unroll
@@ -287,16 +354,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_
                 atomicAdd(&gW[(size_t)co * KDP + kk], acc[i][n][r]);
             }
         }
-}
-
-// Bias gradient: gb[c] += sum of dZ[r][c] over a chunk of rows.
-__global__ void __launch_bounds__(128) k_bias_grad(const bf16_t *dZ, int64_t rows, float *gb) {
-    const int c = threadIdx.x;
-    const int64_t r_begin = (int64_t)blockIdx.x * kWgChunk;
-    const int64_t r_end = min(rows, r_begin + kWgChunk);
-    float s = 0.0f;
-    for (int64_t r = r_begin; r < r_end; ++r) s += from_bf16(dZ[(kLead + r) * kW + c]);
-    atomicAdd(&gb[c], s);
+    if (kb == 0 && threadIdx.x < kW) atomicAdd(&gb[threadIdx.x], bsum);
 }
 
 // ------------------------------------------------------------ pool, loss
@@ -441,13 +499,13 @@ static int cnn_forward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t s
         c.bias = at<float>(P, pl.b[l]);
         if (l == 0) {
             c.out = w.h[1];
-            hipLaunchKernelGGL((k_conv<kIn, kdp_of(0), kEpiRelu>), dim3(tiles), dim3(256), 0, s, c);
+            hipLaunchKernelGGL((k_conv<kIn, kdp_of(0), kEpiRelu>), dim3(tiles), dim3(512), 0, s, c);
         } else if (l < kLayers - 1) {
             c.out = w.h[l + 1];
-            hipLaunchKernelGGL((k_conv<kW, kdp_of(1), kEpiRelu>), dim3(tiles), dim3(256), 0, s, c);
+            hipLaunchKernelGGL((k_conv<kW, kdp_of(1), kEpiRelu>), dim3(tiles), dim3(512), 0, s, c);
         } else {
             c.out = w.z4;
-            hipLaunchKernelGGL((k_conv<kW, kdp_of(1), kEpiLinearF32>), dim3(tiles), dim3(256), 0, s, c);
+            hipLaunchKernelGGL((k_conv<kW, kdp_of(1), kEpiLinearF32>), dim3(tiles), dim3(512), 0, s, c);
         }
     }
     hipLaunchKernelGGL(k_pool, dim3((unsigned)std::min(b.nb, 65535)), dim3(128), 0, s, b, w.z4, w.E);
@@ -468,12 +526,11 @@ static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t 
         float *gw = at<float>(P, pl.gw[l]);
         float *gb = at<float>(P, pl.gb[l]);
         if (l == 0)
-            hipLaunchKernelGGL((k_conv_wgrad<kIn, kdp_of(0)>), dim3(chunks, 1), dim3(256), 0, s,
-                               w.h[0], dz, b.rows, gw);
+            hipLaunchKernelGGL((k_conv_wgrad<kIn, kdp_of(0)>), dim3(1, chunks), dim3(256), 0, s,
+                               w.h[0], dz, b.rows, gw, gb);
         else
-            hipLaunchKernelGGL((k_conv_wgrad<kW, kdp_of(1)>), dim3(chunks, kKer), dim3(256), 0, s,
-                               w.h[l], dz, b.rows, gw);
-        hipLaunchKernelGGL(k_bias_grad, dim3(chunks), dim3(128), 0, s, dz, b.rows, gb);
+            hipLaunchKernelGGL((k_conv_wgrad<kW, kdp_of(1)>), dim3(kKer, chunks), dim3(256), 0, s,
+                               w.h[l], dz, b.rows, gw, gb);
         if (l > 0) {
             ConvArgs c{};
             c.X = dz;
@@ -482,7 +539,7 @@ static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t 
             c.rows = b.rows;
             c.out = dzn;
             c.relu_ref = w.h[l];
-            hipLaunchKernelGGL((k_conv<kW, kKer * kW, kEpiGradRelu>), dim3(tiles), dim3(256), 0, s, c);
+            hipLaunchKernelGGL((k_conv<kW, kKer * kW, kEpiGradRelu>), dim3(tiles), dim3(512), 0, s, c);
             std::swap(dz, dzn);
         }
     }

@@ -168,12 +168,13 @@ struct ConvArgs {
 // The A fragments (8 consecutive span elements of one row) are 16-byte
 // global loads; the weights' K slice of each step, shared by the eight
 // wavefronts, is staged in LDS ([co][32], padded) and read as 16-byte
-// fragments.
+// fragments.  The slice and the A fragments of the next step are loaded
+// while the current step's MFMAs run (two LDS buffers, one barrier a step).
 constexpr int kBp = 40;   // LDS pitch of a staged weight row (32 + 8)
 
 template <int CIN, int KDP, int EPI>
 __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) bf16_t sb[kW * kBp];
+    __shared__ __attribute__((aligned(16))) bf16_t sb[2][kW * kBp];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
     const int64_t row0 = (int64_t)blockIdx.x * kTile + 32 * w;
@@ -191,44 +192,80 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     // staging role: weight row co = t / 4, quarter q = t % 4 (8 of the 32 K)
     const int sco = threadIdx.x >> 2, sq = (threadIdx.x & 3) * 8;
     const bf16_t *wsrc = a.Wt + (size_t)sco * KDP + sq;
-    for (int k0 = 0; k0 < KDP; k0 += 32) {
-        __syncthreads();
-        *(uint4 *)(sb + sco * kBp + sq) = *(const uint4 *)(wsrc + k0);
-        bf16x8 af[2];
+    // K order: 32-channel column blocks outer, kernel taps inner, so the five
+    // taps of a block re-read the same input columns (one row apart) while
+    // they are still in the L1 cache
+    constexpr int kSteps = KDP / 32;
+    constexpr int kTaps = CIN >= 32 ? kKer : kSteps;   // K steps per column block
+    auto k_of = [](int step) { return CIN >= 32 ? (step % kTaps) * CIN + (step / kTaps) * 32 : step * 32; };
+    uint4 wnext = *(const uint4 *)(wsrc + k_of(0));
+    bf16x8 anext[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = *(const bf16x8 *)(arow[i] + k0);
-        __syncthreads();
+    for (int i = 0; i < 2; ++i) anext[i] = *(const bf16x8 *)(arow[i] + k_of(0));
+    *(uint4 *)(sb[0] + sco * kBp + sq) = wnext;
+    __syncthreads();
+    for (int step = 0; step < kSteps; ++step) {
+        const int cur = step & 1;
+        bf16x8 af[2] = {anext[0], anext[1]};
+        if (step + 1 < kSteps) {
+            const int k1 = k_of(step + 1);
+            wnext = *(const uint4 *)(wsrc + k1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) anext[i] = *(const bf16x8 *)(arow[i] + k1);
+        }
         bf16x8 bfr[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bfr[j] = *(const bf16x8 *)(sb + (16 * j + li) * kBp + kq);
+        for (int j = 0; j < 8; ++j) bfr[j] = *(const bf16x8 *)(sb[cur] + (16 * j + li) * kBp + kq);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
+        if (step + 1 < kSteps) *(uint4 *)(sb[cur ^ 1] + sco * kBp + sq) = wnext;
+        __syncthreads();
     }
-    // lane holds rows 4*(lane/16) + r of each 16 x 16 tile, column lane % 16
+    // The weights are the first MFMA operand, so tile (i, j) is the
+    // transposed output: the lane holds channels 16 j + 4 (lane / 16) + r,
+    // r = 0..3, of row 16 i + lane % 16, stored as one 4-channel piece.
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
+        const int64_t row = row0 + 16 * i + li;
+        if (row >= a.rows) continue;
+        const bool data = a.rowseq[row] >= 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = row0 + 16 * i + 4 * (lane >> 4) + r;
-            if (row >= a.rows) continue;
-            const bool data = a.rowseq[row] >= 0;
+        for (int j = 0; j < 8; ++j) {
+            const int c0 = 16 * j + 4 * (lane >> 4);
+            const int64_t o = (kLead + row) * kW + c0;
+            float v[4];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int col = 16 * j + li;
-                const float v = acc[i][j][r];
-                const int64_t o = (kLead + row) * kW + col;
+            for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
+            if (EPI == kEpiLinearF32) {
+                const float4 b4 = *(const float4 *)(a.bias + c0);
+                *(float4 *)((float *)a.out + o) =
+                    data ? make_float4(v[0] + b4.x, v[1] + b4.y, v[2] + b4.z, v[3] + b4.w)
+                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            } else {
+                float z[4];
                 if (EPI == kEpiRelu) {
-                    const float z = v + a.bias[col];
-                    ((bf16_t *)a.out)[o] = to_bf16(data && z > 0.0f ? z : 0.0f);
-                } else if (EPI == kEpiLinearF32) {
-                    ((float *)a.out)[o] = data ? v + a.bias[col] : 0.0f;
+                    const float4 b4 = *(const float4 *)(a.bias + c0);
+                    const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float y = v[r] + bb[r];
+                        z[r] = data && y > 0.0f ? y : 0.0f;
+                    }
                 } else {
-                    const bool on = data && from_bf16(a.relu_ref[o]) > 0.0f;
-                    ((bf16_t *)a.out)[o] = to_bf16(on ? v : 0.0f);
+                    const uint2 ref = *(const uint2 *)(a.relu_ref + o);
+                    const uint32_t rr[2] = {ref.x, ref.y};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bf16_t h = (bf16_t)(rr[r >> 1] >> (16 * (r & 1)));
+                        z[r] = data && from_bf16(h) > 0.0f ? v[r] : 0.0f;
+                    }
                 }
+                const uint32_t p0 = (uint32_t)to_bf16(z[0]) | ((uint32_t)to_bf16(z[1]) << 16);
+                const uint32_t p1 = (uint32_t)to_bf16(z[2]) | ((uint32_t)to_bf16(z[3]) << 16);
+                *(uint2 *)((bf16_t *)a.out + o) = make_uint2(p0, p1);
             }
         }
     }
@@ -238,43 +275,54 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
 // with kk = k * CIN + ci and span(H)[r][kk] = H[r + k - 2][ci]; blockIdx.x = 0
 // also adds the bias gradient gb[co] += sum over rows of dZ[r][co].
 // The reduction runs over rows, which the matrix cores take 32 at a time
-// (8 consecutive rows per lane), so each 64-row step is staged in LDS
-// transposed (channel-major): dZ as [co][row] and H, shifted by k - 2 rows,
-// as [ci][row], one copy per shift the block needs (one for CIN = 128, where
-// blockIdx.x = k covers kk in [128 k, 128 k + 128); five for the one-hot
-// layer, whose 40 columns fit one block).  A wavefront stages 16-channel
-// pieces of 64 consecutive rows, so its LDS writes go to consecutive
-// addresses; every fragment is one 16-byte LDS read.  Workgroup = 4
-// wavefronts, wavefront w owns co in [32 w, 32 w + 32) x the block's kk.
-constexpr int kWgChunk = 16384;
-constexpr int kStep = 64;            // rows staged per step
-constexpr int kTp = kStep + 8;       // LDS row pitch of the transposed tiles
+// (8 consecutive rows per lane, row-major tiles being channel-contiguous), so
+// the fragments come from LDS through the transposing read
+// ds_read_b64_tr_b16: within each group of 16 lanes, lane 4j + q names 4
+// consecutive channels (4q .. 4q + 3 of a 16-channel tile) of row j, and
+// lane i receives channel i of the 4 rows.  Each 64-row step stages dZ rows
+// and H rows (shifted by k - 2, with a two-row halo either side for the
+// one-hot layer) row-major with 16-byte writes.  blockIdx.x = k covers
+// kk in [128 k, 128 k + 128) for CIN = 128; one block holds the one-hot
+// layer's 40 columns (5 taps x 8).  Workgroup = 4 wavefronts, wavefront w
+// owns co in [32 w, 32 w + 32) x the block's kk.
+constexpr int kWgChunk = 16384;     // rows per workgroup (128-channel layers)
+constexpr int kWgChunk0 = 2048;     // rows per workgroup (one-hot layer: one column block)
+constexpr int kStep = 64;      // rows staged per step
+constexpr int kPitch = 144;    // LDS row pitch of the 128-channel tiles (288 bytes)
+constexpr int kHalo = 2;
 
-// Scatter 8 packed bf16 pairs (16 channels of one row) into a channel-major tile.
-__device__ __forceinline__ void put_transposed(bf16_t *t, int c0, int row, uint4 v0, uint4 v1) {
-    const uint32_t e[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        t[(c0 + 2 * q) * kTp + row] = (bf16_t)(e[q] & 0xFFFFu);
-        t[(c0 + 2 * q + 1) * kTp + row] = (bf16_t)(e[q] >> 16);
-    }
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
+
+// Rows r .. r + 3 of one channel per lane (see above); p = this lane's address.
+__device__ __forceinline__ v4i16 read_tr(const bf16_t *p) {
+    return __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4i16 *)(bf16_t *)p);
+}
+
+__device__ __forceinline__ bf16x8 join_frag(v4i16 lo, v4i16 hi) {
+    const v4i16 both[2] = {lo, hi};
+    return __builtin_bit_cast(bf16x8, both);
 }
 
 template <int CIN, int KDP>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_t *dZ,
                                                     int64_t rows, float *gW, float *gb) {
-    constexpr int NS = CIN == kW ? 1 : kKer;           // staged shifts
     constexpr int NT = (KDP < 128 ? KDP : 128) / 16;   // 16-column tiles per block
     constexpr int KD = kKer * CIN;
-    __shared__ __attribute__((aligned(16))) bf16_t sdz[kW * kTp];
-    __shared__ __attribute__((aligned(16))) bf16_t sh[NS * CIN * kTp];
+    constexpr int kHRows = CIN == kW ? kStep : kStep + 2 * kHalo;
+    constexpr int kHPitch = CIN == kW ? kPitch : CIN;
+    __shared__ __attribute__((aligned(16))) bf16_t sdz[kStep * kPitch];
+    __shared__ __attribute__((aligned(16))) bf16_t sh[kHRows * kHPitch + 8];   // + zero slot
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
-    const int li = lane & 15, kq = 8 * (lane >> 4);
+    const int g = lane >> 4, t = lane & 15;
     const int kb = blockIdx.x;
     const int kk0 = kb * 128;
-    const int64_t r_begin = (int64_t)blockIdx.y * kWgChunk;
-    const int64_t r_end = min(rows, r_begin + kWgChunk);
+    constexpr int64_t kChunk = CIN == kW ? kWgChunk : kWgChunk0;
+    const int64_t r_begin = (int64_t)blockIdx.y * kChunk;
+    const int64_t r_end = min(rows, r_begin + kChunk);
+    bf16_t *zero_slot = sh + kHRows * kHPitch;
+    if (threadIdx.x < 8) zero_slot[threadIdx.x] = 0;
     f32x4 acc[2][NT];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -283,57 +331,57 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_
     float bsum = 0.0f;
     for (int64_t r0 = r_begin; r0 < r_end; r0 += kStep) {
         __syncthreads();
-        // dZ: wavefront w stages channels [16 w, 16 w + 16) and [16 w + 64, ..) of
-        // rows r0 + lane (rows at or past the chunk end read as zero)
-        {
-            const bool live = r0 + lane < r_end;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int c0 = 16 * w + 64 * h;
-                const uint4 *src = (const uint4 *)(dZ + (kLead + r0 + lane) * kW + c0);
-                const uint4 z = make_uint4(0, 0, 0, 0);
-                put_transposed(sdz, c0, lane, live ? src[0] : z, live ? src[1] : z);
-            }
+        // dZ rows r0 .. r0 + 63, 16 channels per thread and pass (rows at or
+        // past the chunk end read as zero)
+        for (int e = threadIdx.x; e < kStep * 16; e += blockDim.x) {
+            const int rr = e >> 4, c = (e & 15) * 8;
+            const bool live = r0 + rr < r_end;
+            const uint4 v = live ? *(const uint4 *)(dZ + (kLead + r0 + rr) * kW + c)
+                                 : make_uint4(0, 0, 0, 0);
+            *(uint4 *)(sdz + rr * kPitch + c) = v;
         }
         if (CIN == kW) {
-            // H rows r0 + kb - 2 + lane (inside the framed buffer: lead rows
+            // H rows r0 + kb - 2 + rr (inside the framed buffer: lead rows
             // before the first row, tail rows after the last)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int c0 = 16 * w + 64 * h;
-                const uint4 *src = (const uint4 *)(H + (kLead + r0 + kb - 2 + lane) * kW + c0);
-                put_transposed(sh, c0, lane, src[0], src[1]);
+            for (int e = threadIdx.x; e < kStep * 16; e += blockDim.x) {
+                const int rr = e >> 4, c = (e & 15) * 8;
+                *(uint4 *)(sh + rr * kPitch + c) =
+                    *(const uint4 *)(H + (kLead + r0 + kb - 2 + rr) * kW + c);
             }
         } else {
-            // one 16-byte row (8 channels) per thread and shift
-            for (int e = threadIdx.x; e < NS * kStep; e += blockDim.x) {
-                const int sk = e / kStep, rr = e % kStep;
-                const uint4 v = *(const uint4 *)(H + (kLead + r0 + sk - 2 + rr) * CIN);
-                const uint32_t q4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    sh[(sk * CIN + 2 * q) * kTp + rr] = (bf16_t)(q4[q] & 0xFFFFu);
-                    sh[(sk * CIN + 2 * q + 1) * kTp + rr] = (bf16_t)(q4[q] >> 16);
-                }
-            }
+            // H rows r0 - 2 .. r0 + 65, one 16-byte row per thread
+            for (int rr = threadIdx.x; rr < kHRows; rr += blockDim.x)
+                *(uint4 *)(sh + rr * CIN) = *(const uint4 *)(H + (kLead + r0 - kHalo + rr) * CIN);
         }
         __syncthreads();
         if (kb == 0 && threadIdx.x < kW) {
 #pragma unroll 8
-            for (int rr = 0; rr < kStep; ++rr) bsum += from_bf16(sdz[threadIdx.x * kTp + rr]);
+            for (int rr = 0; rr < kStep; ++rr) bsum += from_bf16(sdz[rr * kPitch + threadIdx.x]);
         }
 #pragma unroll
         for (int ks = 0; ks < kStep; ks += 32) {
+            const int rb = ks + 8 * g + (t >> 2);   // this lane's row of the first read
             bf16x8 af[2], bfr[NT];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                af[i] = *(const bf16x8 *)(sdz + (32 * w + 16 * i + li) * kTp + ks + kq);
+            for (int i = 0; i < 2; ++i) {
+                const bf16_t *p = sdz + rb * kPitch + 32 * w + 16 * i + 4 * (t & 3);
+                af[i] = join_frag(read_tr(p), read_tr(p + 4 * kPitch));
+            }
 #pragma unroll
             for (int n = 0; n < NT; ++n) {
-                const int kk = kk0 + 16 * n + li;
-                const int k = CIN == kW ? 0 : kk / CIN, ci = kk % CIN;
-                bfr[n] = kk < KD ? *(const bf16x8 *)(sh + ((k < NS ? k : 0) * CIN + ci) * kTp + ks + kq)
-                                 : bf16x8{};
+                const bf16_t *p;
+                int step4;
+                if (CIN == kW) {
+                    p = sh + rb * kPitch + 16 * n + 4 * (t & 3);
+                    step4 = 4 * kPitch;
+                } else {
+                    // columns kk0 + 16 n + 4 (t & 3) .. + 3 share one tap k
+                    const int kk = kk0 + 16 * n + 4 * (t & 3);
+                    const int k = kk / CIN, ci = kk % CIN;
+                    p = kk < KD ? sh + (rb + k - 2 + kHalo) * CIN + ci : zero_slot;
+                    step4 = kk < KD ? 4 * CIN : 0;
+                }
+                bfr[n] = join_frag(read_tr(p), read_tr(p + step4));
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -346,11 +394,11 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            const int kk = kk0 + 16 * n + li;
+            const int kk = kk0 + 16 * n + t;
             if (kk >= KDP) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int co = 32 * w + 16 * i + 4 * (lane >> 4) + r;
+                const int co = 32 * w + 16 * i + 4 * g + r;
                 atomicAdd(&gW[(size_t)co * KDP + kk], acc[i][n][r]);
             }
         }
@@ -358,13 +406,23 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_
 }
 
 // ------------------------------------------------------------ pool, loss
+// Mean over each sequence's rows; 8 rows in flight per thread.
 __global__ void __launch_bounds__(128) k_pool(Batch b, const float *Z4, float *E) {
     const int c = threadIdx.x;
     for (int i = blockIdx.x; i < b.nb; i += gridDim.x) {
         const int64_t r0 = b.roff[i] + 2;
         const int32_t L = b.len[b.idx[i]];
+        const float *z = Z4 + (kLead + r0) * kW + c;
+        float part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int t = 0;
+        for (; t + 8 <= L; t += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) part[u] += z[(int64_t)(t + u) * kW];
+        }
+        for (; t < L; ++t) part[0] += z[(int64_t)t * kW];
         float s = 0.0f;
-        for (int t = 0; t < L; ++t) s += Z4[(kLead + r0 + t) * kW + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += part[u];
         E[(int64_t)i * kW + c] = L > 0 ? s / (float)L : 0.0f;
     }
 }
@@ -516,6 +574,7 @@ static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t 
     const Batch &b = w.b;
     const unsigned tiles = (unsigned)((b.rows + kTile - 1) / kTile);
     const unsigned chunks = (unsigned)((b.rows + kWgChunk - 1) / kWgChunk);
+    const unsigned chunks0 = (unsigned)((b.rows + kWgChunk0 - 1) / kWgChunk0);
     int rc;
     if ((rc = zero_frame(w.dz, kW * 2, w.alloc_rows, b.rows, s))) return rc;
     if ((rc = zero_frame(w.dz2, kW * 2, w.alloc_rows, b.rows, s))) return rc;
@@ -526,7 +585,7 @@ static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t 
         float *gw = at<float>(P, pl.gw[l]);
         float *gb = at<float>(P, pl.gb[l]);
         if (l == 0)
-            hipLaunchKernelGGL((k_conv_wgrad<kIn, kdp_of(0)>), dim3(1, chunks), dim3(256), 0, s,
+            hipLaunchKernelGGL((k_conv_wgrad<kIn, kdp_of(0)>), dim3(1, chunks0), dim3(256), 0, s,
                                w.h[0], dz, b.rows, gw, gb);
         else
             hipLaunchKernelGGL((k_conv_wgrad<kW, kdp_of(1)>), dim3(kKer, chunks), dim3(256), 0, s,

@@ -1,10 +1,14 @@
 """Benchmark: all-pairs Levenshtein on 4096 DNA sequences (lengths 1000-1600).
 
 One step = one lev_allpairs call over the whole set (8,386,560 pairs): length
-binning, staging and the persistent bit-parallel kernel.  Prints one JSON
-line.  Inputs are resident on the GPU before the timed region starts.
+binning, staging and the persistent bit-parallel kernel.  Inputs are
+resident on the GPU before the timed region starts; the launch variant is
+autotuned before it.  Further legs, reported in the same JSON line: the
+512-pair NW fill + traceback ("nw") and the learned pruning of the tree
+build on 100,000 sequences ("pruned": embedder training, exact vs pruned
+build time, teacher-forced agreement, control rankers).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--nw]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
 from __future__ import annotations
 
@@ -40,12 +44,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--nw", action="store_true", help="also time the 512-pair NW batch")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the all-pairs leg (no NW, no learned pruning)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
-    ap.add_argument("--pruned", action="store_true",
-                    help="also train the embedder and time the surrogate-pruned tree build "
-                         "against the exact one (100,000 DNA sequences)")
+
     ap.add_argument("--epochs", type=int, default=2, help="embedder epochs over 2M pairs")
     ap.add_argument("--topk", type=int, default=16)
     ap.add_argument("--exact-below", type=int, default=256,
@@ -166,10 +169,13 @@ def main():
                      "frac": round(tcups / LEV_PEAK_TCUPS, 4), "traffic": None,
                      "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3)},
     }
-    if args.nw:
-        res["nw"] = bench_nw(msadp, synth, torch, args)
-    if args.pruned:
-        res["pruned"] = bench_pruned(msadp, synth, torch, args)
+    if not args.quick:
+        for name, fn in (("nw", bench_nw), ("pruned", bench_pruned)):
+            try:
+                res[name] = fn(msadp, synth, torch, args)
+            except Exception as e:   # report, keep the headline line
+                res[name] = {"error": f"{type(e).__name__}: {e}"}
+                _log(f"{name} leg failed: {e}")
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
     print(json.dumps(res), flush=True)
@@ -260,6 +266,25 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cnn_rates(learned, d, losses, t_train, positions, t_embed):
+    """Embedder throughput: a training step is a forward, an input-gradient
+    and a weight-gradient pass (3x the forward multiply-adds); the roofline
+    is the BF16 dense MFMA peak."""
+    f = learned.flops_per_position()
+    all_pos = int(np.diff(d["offsets"]).sum())
+    embed_tf = all_pos * f / t_embed / 1e12
+    train_tf = 3 * positions * f / t_train / 1e12
+    return {"train_step_ms": round(t_train / len(losses) * 1e3, 2),
+            "train_pairs_per_s": round(len(losses) * 4096 / t_train, 1),
+            "train_tflops": round(train_tf, 1),
+            "embed_seqs_per_s": round(d["n"] / t_embed, 1),
+            "embed_tflops": round(embed_tf, 1),
+            "flops_per_position": f,
+            "roofline": {"bound": "mfma", "achieved": round(embed_tf, 1), "peak": 2500.0,
+                         "unit": "TFLOP/s", "frac": round(embed_tf / 2500.0, 4),
+                         "traffic": None, "kernel": "k_conv (embedding pass, all kernels)"}}
+
+
 def bench_pruned(msadp, synth, torch, args):
     """Learned pruning on 100,000 DNA sequences of 1,000 families: train the
     embedder on 2M exact pairs, then the exact and the pruned tree build,
@@ -277,7 +302,8 @@ def bench_pruned(msadp, synth, torch, args):
     t_label = time.perf_counter() - t0
     hdist = learned.lev_labels(S, ha, hb)
     _log(f"labels {t_label:.2f} s; training {args.epochs} epochs")
-    E, losses, t_train = learned.train(S, ia, ib, dist, epochs=args.epochs, seed=13, log=_log)
+    E, losses, t_train, positions = learned.train(S, ia, ib, dist, epochs=args.epochs, seed=13,
+                                                  log=_log)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     emb = E.embed(S)
@@ -301,20 +327,30 @@ def bench_pruned(msadp, synth, torch, args):
            "train_loss_first_last": [round(float(losses[:50].mean()), 5),
                                      round(float(losses[-50:].mean()), 5)],
            "embed_s": round(t_embed, 3), "heldout_mae_edits": round(mae, 3),
+           "cnn": cnn_rates(learned, d, losses, t_train, positions, t_embed),
            "heldout_rel_err": round(rel, 4), "exact_build_s": round(t_exact, 3),
            "exact_nodes": int(exact["n_nodes"])}
-    rankers = {"cnn": emb, "length": learned.control_embeddings(S, "length"),
-               "random": learned.control_embeddings(S, "random", seed=14)}
+    off, ca, cb, corr = learned.calibrate(emb, S, d["family"])
+    _log(f"calibration on within-family pairs: y = {ca:.3f} + {cb:.4f} y_hat "
+         f"(corr {corr:.3f}) -> offset {off:.3f}")
+    out["calibration"] = {"offset": round(off, 4), "intercept": round(ca, 4),
+                          "slope": round(cb, 5), "corr": round(corr, 4)}
+    # ranker -> (embedding, offset): the calibrated network, the raw network,
+    # the length prior (shortest first) and noise
+    rankers = {"cnn": (emb, off), "cnn_raw": (emb, 0.0),
+               "shortest": (learned.control_embeddings(S, "zero"), 1.0),
+               "random": (learned.control_embeddings(S, "random", seed=14), 0.0)}
     # (ranker, topk, exact_below): pure top-k pruning of every cluster, and
     # the hybrid that keeps the full median for clusters it finds cheap
-    points = [("cnn", args.topk, 0), ("length", args.topk, 0), ("random", args.topk, 0),
-              ("cnn", args.topk, args.exact_below), ("length", args.topk, args.exact_below),
-              ("random", args.topk, args.exact_below),
-              ("cnn", args.topk, 8 * args.exact_below), ("random", args.topk, 8 * args.exact_below)]
+    points = [("cnn", args.topk, 0), ("cnn_raw", args.topk, 0), ("shortest", args.topk, 0),
+              ("random", args.topk, 0),
+              ("cnn", args.topk, args.exact_below), ("shortest", args.topk, args.exact_below),
+              ("cnn", args.topk, 8 * args.exact_below),
+              ("shortest", args.topk, 8 * args.exact_below)]
     out["points"] = []
     for name, topk, eb in points:
-        e = rankers[name]
-        b = msadp.TreeBuilder(S, emb=e, topk=topk, exact_below=eb)
+        e, eo = rankers[name]
+        b = msadp.TreeBuilder(S, emb=e, topk=topk, exact_below=eb, emb_offset=eo)
         b()
         torch.cuda.synchronize()
         times = []
@@ -325,12 +361,13 @@ def bench_pruned(msadp, synth, torch, args):
             times.append(time.perf_counter() - t0)
         b.st.check("tree_build_pruned")
         t = t.host()
-        clr = msadp.tree_eval_centers(S, exact, emb=e, topk=topk, exact_below=eb)
+        clr = msadp.tree_eval_centers(S, exact, emb=e, topk=topk, exact_below=eb, emb_offset=eo)
         agree = learned.agreement(exact, clr, min_size=17, pruned_above=max(topk, eb))
         rep = learned.reproduced_clusters(exact, t)
         nd, ex_mean, ex_max = learned.rowsum_excess(S, exact, clr, max(topk, eb))
         tp = float(np.median(times))
-        out["points"].append({"ranker": name, "topk": topk, "exact_below": eb,
+        out["points"].append({"ranker": name, "offset": round(eo, 4), "topk": topk,
+                              "exact_below": eb,
                               "build_s": round(tp, 4), "speedup": round(t_exact / tp, 2),
                               "agreement": agree, "reproduced_clusters": round(rep, 4),
                               "center_differs": nd, "rowsum_excess_mean": round(ex_mean, 6),

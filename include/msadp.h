@@ -167,23 +167,28 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
  * cluster of more than exact_below members (>= 0), emb (device
  * float[n][128], row i = embedding of input i, e.g. from cnn_embed, whose
  * distances predict f divided by the pair's mean length) ranks every member
- * x by E(x) = sum over the cluster of q(x, y) (|x| + |y|), with q = the
- * Euclidean distance min(||e_x - e_y||, 2^15) in units of 2^-16 (squares
- * added coordinate by coordinate in float32 without fused multiply-add,
- * rounded to nearest); the topk members with the least (E, input index),
- * 1 <= topk <= 1024, are the candidates.  In a cluster of at most
+ * x by E(x) = sum over the cluster, y = x included, of
+ * (q(x, y) + emb_q0) (|x| + |y|), with q = the Euclidean distance
+ * min(||e_x - e_y||, 2^15) in units of 2^-16 (squares added coordinate by
+ * coordinate in float32 without fused multiply-add, rounded to nearest) and
+ * emb_q0 <= 2^31 a calibration offset in the same units (the intercept over
+ * the slope of a linear fit of the true normalized distance on the
+ * predicted one, which shrinks a noisy predictor towards the length prior);
+ * the topk members with the least (E, input index), 1 <= topk <= 1024, are
+ * the candidates.  In a cluster of at most
  * exact_below members every member is a candidate.  The candidates get
  * exact Levenshtein row sums over the whole cluster and c is the one with
  * the least (lowest input index on ties).  Poles, split and every other
  * step stay exact, so clusters of at most max(topk, exact_below) members
  * get the same c as tree_build.  E is a 64-bit sum: it stays exact while
- * n * max(|x| + |y|) * max q < 2^64, i.e. for any n below 2^24 with lengths
- * below 2^15 and embedding distances below 2^8.  Same outputs, workspace
- * and errors as tree_build; EINVAL when emb is null or topk or exact_below
- * is out of range. */
-int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
-                      const msa_tree *T, int32_t *n_nodes, int32_t use_graph, void *ws,
-                      size_t ws_bytes, int32_t *d_status, hipStream_t s);
+ * n * max(|x| + |y|) * max(q + emb_q0) < 2^64, e.g. for any n below 2^24
+ * with lengths below 2^15 and distance plus offset below 2^8.  Same
+ * outputs, workspace and errors as tree_build; EINVAL when emb is null or
+ * topk, exact_below or emb_q0 is out of range. */
+int tree_build_pruned(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
+                      int32_t exact_below, const msa_tree *T, int32_t *n_nodes,
+                      int32_t use_graph, void *ws, size_t ws_bytes, int32_t *d_status,
+                      hipStream_t s);
 
 /* Teacher-forced evaluation of the choice of c, l, r (Alg. 1) on the
  * clusters of a given tree: for every node v < n_nodes of T (as filled by
@@ -191,16 +196,16 @@ int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, int32_t
  * mcount and perm are read), center[v], lpole[v] and rpole[v] (device
  * int32[n_nodes]) receive what the build picks for v's member set: with
  * emb == NULL the full geometric median, otherwise the pruned median of
- * tree_build_pruned (emb, topk, exact_below as there); poles are -1 for one member or
+ * tree_build_pruned (emb, emb_q0, topk, exact_below as there); poles are -1 for one member or
  * radius 0.  This is how a pruned choice is compared node by node with
  * the exact one.  The node table is copied to the host and checked
  * (breadth-first depths, disjoint in-range member ranges per depth:
  * EINVAL otherwise); perm entries outside [0, n) set MSA_DS_INDEX.
  * Workspace: tree_workspace_bytes(S).  Synchronizes the stream once. */
-int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
-                      const msa_tree *T, int32_t n_nodes, int32_t *center, int32_t *lpole,
-                      int32_t *rpole, void *ws, size_t ws_bytes, int32_t *d_status,
-                      hipStream_t s);
+int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
+                      int32_t exact_below, const msa_tree *T, int32_t n_nodes,
+                      int32_t *center, int32_t *lpole, int32_t *rpole, void *ws,
+                      size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
 /* ------------------------------------------------------------------ */
 /* Bottom-up merge (Sec. 2.2) over a tree from tree_build (T, n_nodes as

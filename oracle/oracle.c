@@ -179,10 +179,11 @@ static uint64_t emb_dist_q(const float *ex, const float *ey) {
 
 /* The estimate of f(x, y) behind the ranking, in units of 2^-17: the
  * embedder predicts f divided by the pair's mean length, so the distance
- * is scaled by |x| + |y|. */
-static uint64_t emb_estimate(const int64_t *off, const float *emb, int32_t x, int32_t y) {
+ * plus the calibration offset q0 (units of 2^-16) is scaled by |x| + |y|. */
+static uint64_t emb_estimate(const int64_t *off, const float *emb, uint32_t q0, int32_t x,
+                             int32_t y) {
     const uint64_t len = (uint64_t)((off[x + 1] - off[x]) + (off[y + 1] - off[y]));
-    return emb_dist_q(emb + (int64_t)x * 128, emb + (int64_t)y * 128) * len;
+    return (emb_dist_q(emb + (int64_t)x * 128, emb + (int64_t)y * 128) + q0) * len;
 }
 
 /* f(C[x], C[y]) for every y of the cluster. */
@@ -200,12 +201,13 @@ static int64_t *dist_row(const uint8_t *codes, const int64_t *off, const int32_t
  * f(c, l) is 0).  emb == NULL: c is the full geometric median of C
  * (Sec. 2.1).  Otherwise c is the surrogate-pruned median: if C has more
  * than exact_below members, every member x gets the estimate E(x) = sum
- * over C of emb_estimate and the topk members with the least
+ * over C (x itself included) of emb_estimate and the topk members with the least
  * (E, input index) are the candidates, else every member is one; c is the
  * candidate with the least exact sum of f over C (lowest input index on
  * ties). */
 void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
-                const float *emb, int32_t topk, int32_t exact_below, int32_t out[3]) {
+                const float *emb, uint32_t emb_q0, int32_t topk, int32_t exact_below,
+                int32_t out[3]) {
     out[1] = out[2] = -1;
     if (k == 1) { out[0] = C[0]; return; }
     int64_t best = -1;
@@ -236,7 +238,7 @@ void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int6
         #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t x = 0; x < k; ++x)
             for (int64_t y = 0; y < k; ++y)
-                E[x] += emb_estimate(off, emb, C[x], C[y]);
+                E[x] += emb_estimate(off, emb, emb_q0, C[x], C[y]);
         char *taken = (char *)calloc((size_t)k, 1);
         int64_t best_sum = 0;
         const int64_t nc = k <= exact_below ? k : (k < topk ? k : topk);
@@ -277,7 +279,7 @@ void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int6
  * L = {x : f(l, x) <= f(r, x)}, R = the rest, both in ascending order, and
  * breadth-first node numbering (L before R). */
 static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
-                         int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left, int32_t *right,
+                         uint32_t emb_q0, int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left, int32_t *right,
                          int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
                          int64_t *mstart, int64_t *mcount, int32_t *perm) {
     if (n <= 0) return 0;
@@ -294,7 +296,7 @@ static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, co
         int32_t *C = members[v];
         left[v] = right[v] = -1;
         int32_t clr[3];
-        orc_select(codes, off, C, k, emb, topk, exact_below, clr);
+        orc_select(codes, off, C, k, emb, emb_q0, topk, exact_below, clr);
         center[v] = clr[0];
         lpole[v] = clr[1];
         rpole[v] = clr[2];
@@ -343,29 +345,30 @@ int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
                  int32_t *parent, int32_t *left, int32_t *right, int32_t *center,
                  int32_t *lpole, int32_t *rpole, int32_t *depth,
                  int64_t *mstart, int64_t *mcount, int32_t *perm) {
-    return tree_impl(codes, off, n, NULL, 0, 0, parent, left, right, center, lpole, rpole, depth,
+    return tree_impl(codes, off, n, NULL, 0, 0, 0, parent, left, right, center, lpole, rpole, depth,
                      mstart, mcount, perm);
 }
 
 /* The same with the surrogate-pruned median (emb: float[n][128]). */
 int32_t orc_tree_pruned(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
-                        int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left, int32_t *right,
+                        uint32_t emb_q0, int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left, int32_t *right,
                         int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
                         int64_t *mstart, int64_t *mcount, int32_t *perm) {
     if (emb == NULL || topk < 1 || exact_below < 0) return -1;
-    return tree_impl(codes, off, n, emb, topk, exact_below, parent, left, right, center, lpole,
+    return tree_impl(codes, off, n, emb, emb_q0, topk, exact_below, parent, left, right, center, lpole,
                      rpole, depth,
                      mstart, mcount, perm);
 }
 
 /* Surrogate row sums E(x) of emb_estimate over an explicit member list
  * (for tests of the ranking step). */
-void orc_emb_rowsums(const int64_t *off, const float *emb, const int32_t *members, int64_t k,
-                     uint64_t *E) {
+void orc_emb_rowsums(const int64_t *off, const float *emb, uint32_t emb_q0,
+                     const int32_t *members, int64_t k, uint64_t *E) {
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t x = 0; x < k; ++x) {
         uint64_t s = 0;
-        for (int64_t y = 0; y < k; ++y) s += emb_estimate(off, emb, members[x], members[y]);
+        for (int64_t y = 0; y < k; ++y)
+            s += emb_estimate(off, emb, emb_q0, members[x], members[y]);
         E[x] = s;
     }
 }

@@ -34,11 +34,11 @@ def lib():
         L.orc_tree.restype = C.c_int32
         L.orc_tree.argtypes = [P, P, C.c_int32] + [P] * 10
         L.orc_tree_pruned.restype = C.c_int32
-        L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_int32, C.c_int32] + [P] * 10
+        L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_uint32, C.c_int32, C.c_int32] + [P] * 10
         L.orc_select.restype = None
-        L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_int32, C.c_int32, P]
+        L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_uint32, C.c_int32, C.c_int32, P]
         L.orc_emb_rowsums.restype = None
-        L.orc_emb_rowsums.argtypes = [P, P, P, C.c_int64, P]
+        L.orc_emb_rowsums.argtypes = [P, P, C.c_uint32, P, C.c_int64, P]
         L.orc_merge.restype = C.c_int64
         L.orc_merge.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
                                 C.c_int64]
@@ -132,9 +132,10 @@ def tree(codes, offsets):
     return out
 
 
-def tree_pruned(codes, offsets, emb, topk=16, exact_below=0):
+def tree_pruned(codes, offsets, emb, topk=16, exact_below=0, emb_q0=0):
     """Alg. 1 with the surrogate-pruned median (emb: float32 [n, 128]);
-    clusters of at most exact_below members keep the full median."""
+    clusters of at most exact_below members keep the full median; emb_q0 is
+    the calibration offset added to every embedding distance (units 2^-16)."""
     codes = _u8(codes)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     n = len(offsets) - 1
@@ -144,7 +145,8 @@ def tree_pruned(codes, offsets, emb, topk=16, exact_below=0):
     arr = {f: np.zeros(cap, dtype=np.int64 if f in ("mstart", "mcount") else np.int32)
            for f in TREE_FIELDS}
     perm = np.zeros(max(n, 1), dtype=np.int32)
-    k = lib().orc_tree_pruned(_p(codes), _p(offsets), n, _p(emb), int(topk), int(exact_below),
+    k = lib().orc_tree_pruned(_p(codes), _p(offsets), n, _p(emb), int(emb_q0), int(topk),
+                              int(exact_below),
                               *[_p(arr[f]) for f in TREE_FIELDS], _p(perm))
     if k < 0:
         raise ValueError("bad arguments")
@@ -154,7 +156,7 @@ def tree_pruned(codes, offsets, emb, topk=16, exact_below=0):
     return out
 
 
-def select(codes, offsets, members, emb=None, topk=16, exact_below=0):
+def select(codes, offsets, members, emb=None, topk=16, exact_below=0, emb_q0=0):
     """(c, l, r) that Alg. 1 picks for the cluster `members` (input indices);
     emb=None: full geometric median, else the surrogate-pruned one."""
     codes = _u8(codes)
@@ -163,18 +165,18 @@ def select(codes, offsets, members, emb=None, topk=16, exact_below=0):
     e = None if emb is None else np.ascontiguousarray(emb, dtype=np.float32)
     out = np.zeros(3, dtype=np.int32)
     lib().orc_select(_p(codes), _p(offsets), _p(mem), len(mem), None if e is None else _p(e),
-                     int(topk), int(exact_below), _p(out))
+                     int(emb_q0), int(topk), int(exact_below), _p(out))
     return tuple(int(x) for x in out)
 
 
-def emb_rowsums(offsets, emb, members):
+def emb_rowsums(offsets, emb, members, emb_q0=0):
     """Surrogate row sums E(x) over the member list: the summed embedding
-    distance times the pair's summed length, in units of 2^-16."""
+    distance (plus emb_q0) times the pair's summed length, units of 2^-16."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     emb = np.ascontiguousarray(emb, dtype=np.float32)
     members = np.ascontiguousarray(members, dtype=np.int32)
     E = np.zeros(len(members), dtype=np.uint64)
-    lib().orc_emb_rowsums(_p(offsets), _p(emb), _p(members), len(members), _p(E))
+    lib().orc_emb_rowsums(_p(offsets), _p(emb), int(emb_q0), _p(members), len(members), _p(E))
     return E
 
 

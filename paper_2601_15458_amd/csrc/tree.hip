@@ -31,6 +31,7 @@ enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 
 // scaled by kEmbScale and rounded to the nearest integer: fixed float steps
 // make the candidate ranking reproducible, and the sums are integers.
 constexpr int kMaxTopk = 1024;
+constexpr uint32_t kMaxEmbOffset = 1u << 31;   // 2^15 in units of 2^-16
 constexpr float kEmbScale = 65536.0f;   // fixed point of embedding distances (2^16)
 constexpr float kEmbCap = 32768.0f;     // embedding distances saturate here
 
@@ -59,6 +60,7 @@ struct TreeArgs {
     int32_t n;
     // surrogate-pruned medoid (emb == nullptr: exact medoid)
     const float *emb;        // [n][128] by input index
+    uint32_t emb_q0;         // calibration offset added to every surrogate distance
     int32_t topk;
     int32_t exact_below;     // clusters of at most this many members: all are candidates
     int64_t *ncand;          // per cluster candidate count (nq + 1)
@@ -438,10 +440,11 @@ __device__ __forceinline__ float emb_quarter(float acc, const float4 *x, const_f
 }
 
 // Estimated medoid row sums from the embeddings.  The embedder is trained
-// so that ||e_x - e_y|| predicts f(x, y) divided by the pair's mean length,
-// so the estimate of f(x, y) is ||e_x - e_y|| (|x| + |y|) / 2; every pair of
-// a cluster adds the surrogate distance times (|x| + |y|) to the row sums of
-// both.  One work item is a 64 x 64 tile (I, J) of the cluster's upper block
+// so that ||e_x - e_y|| predicts f(x, y) divided by the pair's mean length;
+// with a linear recalibration of that prediction (offset emb_q0, the slope
+// drops out of the ranking) the estimate of f(x, y) is proportional to
+// (||e_x - e_y|| + offset) (|x| + |y|).  Every ordered pair of a cluster,
+// x with itself included, adds it to the row sum of x.  One work item is a 64 x 64 tile (I, J) of the cluster's upper block
 // triangle: lane i keeps the embedding of member 64 I + i in registers and
 // walks the 64 members of block J, whose rows every lane needs whole and
 // reads by scalar loads.
@@ -496,7 +499,7 @@ __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
             const uint64_t qd = (uint64_t)rintf(fminf(sqrtf(acc), kEmbCap) * kEmbScale);
             // lj's top bit marks a missing member of block J
             const uint64_t w = (xv && !(lj >> 31)) ? lx + (uint64_t)lj : 0ull;
-            const uint64_t e = qd * w;
+            const uint64_t e = (qd + a.emb_q0) * w;
             rs += e;
             if (I != J) {                        // uniform per item
                 const uint64_t col = wave_sum_u64(e);
@@ -734,8 +737,8 @@ size_t tree_workspace_bytes(const msa_seqs *S) {
     return sz.total();
 }
 
-static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
-                      const msa_tree *T,
+static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
+                      int32_t exact_below, const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
                       int32_t *d_status, hipStream_t s) {
     int rc;
@@ -787,6 +790,7 @@ static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, int32_t
     (void)eval_left;
     (void)eval_right;
     a.emb = emb;
+    a.emb_q0 = emb_q0;
     a.topk = topk;
     a.exact_below = exact_below;
     a.sigma = S->sigma;
@@ -843,19 +847,22 @@ static int build_impl(const msa_seqs *S, const float *emb, int32_t topk, int32_t
 
 int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
                void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
-    return build_impl(S, nullptr, 0, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
+    return build_impl(S, nullptr, 0, 0, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
 }
 
-int tree_build_pruned(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
-                      const msa_tree *T, int32_t *n_nodes, int32_t use_graph, void *ws,
-                      size_t ws_bytes, int32_t *d_status, hipStream_t s) {
-    if (emb == nullptr || topk < 1 || topk > kMaxTopk || exact_below < 0) return MSA_EINVAL;
-    return build_impl(S, emb, topk, exact_below, T, n_nodes, use_graph, ws, ws_bytes, d_status,
-                      s);
+int tree_build_pruned(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
+                      int32_t exact_below, const msa_tree *T, int32_t *n_nodes,
+                      int32_t use_graph, void *ws, size_t ws_bytes, int32_t *d_status,
+                      hipStream_t s) {
+    if (emb == nullptr || topk < 1 || topk > kMaxTopk || exact_below < 0 ||
+        emb_q0 > kMaxEmbOffset)
+        return MSA_EINVAL;
+    return build_impl(S, emb, emb_q0, topk, exact_below, T, n_nodes, use_graph, ws, ws_bytes,
+                      d_status, s);
 }
 
-int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, int32_t exact_below,
-                      const msa_tree *T,
+int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
+                      int32_t exact_below, const msa_tree *T,
                       int32_t n_nodes, int32_t *center, int32_t *lpole, int32_t *rpole,
                       void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
     int rc;
@@ -864,7 +871,9 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, int32_t
         T->mstart == nullptr || T->mcount == nullptr || T->depth == nullptr ||
         T->perm == nullptr || ws == nullptr || n_nodes < 0)
         return MSA_EINVAL;
-    if (emb != nullptr && (topk < 1 || topk > kMaxTopk || exact_below < 0)) return MSA_EINVAL;
+    if (emb != nullptr &&
+        (topk < 1 || topk > kMaxTopk || exact_below < 0 || emb_q0 > kMaxEmbOffset))
+        return MSA_EINVAL;
     if (S->n == 0 || n_nodes == 0) return n_nodes == 0 ? MSA_OK : MSA_EINVAL;
     if (S->n >= (1 << 24)) return MSA_ERANGE;
     if (n_nodes > 2 * S->n - 1) return MSA_EINVAL;
@@ -940,6 +949,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, int32_t topk, int32_t
     a.mstart = T->mstart;
     a.mcount = T->mcount;
     a.emb = emb;
+    a.emb_q0 = emb_q0;
     a.topk = topk;
     a.exact_below = exact_below;
     a.sigma = S->sigma;

@@ -68,12 +68,14 @@ def lev_labels(S, ia, ib):
 
 def train(S, ia, ib, dist, epochs: int = 1, batch: int = 4096, lr: float = 1e-3,
           seed: int = 0, log=None):
-    """Adam on the pair loss; returns (embedder, per-step losses, seconds).
-    dist: device tensor of the pairs' exact distances."""
+    """Adam on the pair loss; returns (embedder, per-step losses, seconds,
+    sequence positions processed).  dist: device tensor of the pairs' exact
+    distances."""
     E = M.Embedder()
     E.set_params(init_params(seed, S.sigma))
     rng = np.random.default_rng(seed + 1)
     losses = []
+    positions = 0
     dist = dist.to(torch.int32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -85,12 +87,19 @@ def train(S, ia, ib, dist, epochs: int = 1, batch: int = 4096, lr: float = 1e-3,
             a, b = ia[sel], ib[sel]
             idx, inv = np.unique(np.concatenate([a, b]), return_inverse=True)
             pa, pb = inv[: len(a)], inv[len(a):]
+            positions += int(S.lengths[idx].sum())
             d = dist[torch.from_numpy(sel).to(dist.device)].to(torch.uint16)
             losses.append(E.train_step(S, idx, pa, pb, d, lr=lr))
             if log is not None and (len(losses) % 100 == 0):
                 log(f"epoch {ep} step {len(losses)} loss {np.mean(losses[-100:]):.5f}")
     torch.cuda.synchronize()
-    return E, np.asarray(losses), time.perf_counter() - t0
+    return E, np.asarray(losses), time.perf_counter() - t0, positions
+
+
+# Multiply-adds of the embedder per sequence position (kernel width 5): the
+# one-hot layer (sigma inputs) and three 128 x 128 layers.
+def flops_per_position(sigma: int = CNN_SIGMA) -> int:
+    return 2 * M.CNN_K * M.CNN_WIDTH * (sigma + 3 * M.CNN_WIDTH)
 
 
 def pair_error(emb, S, ia, ib, dist):
@@ -106,17 +115,38 @@ def pair_error(emb, S, ia, ib, dist):
 
 
 def control_embeddings(S, kind: str, seed: int = 0):
-    """Rankers without the network: 'length' puts |x| / mean length on one
-    axis (so the estimate is the length difference), 'random' is noise."""
+    """Rankers without the network.  'zero': every embedding distance is 0,
+    so with an offset the estimate is the length prior (shortest first);
+    'length': |x| / mean length on one axis (the estimate grows with the
+    length difference); 'random': Gaussian noise."""
     n = S.n
     e = np.zeros((n, M.CNN_WIDTH), np.float32)
     if kind == "length":
         e[:, 0] = S.lengths / max(float(S.lengths.mean()), 1.0)
     elif kind == "random":
         e = np.random.default_rng(seed).standard_normal((n, M.CNN_WIDTH)).astype(np.float32)
-    else:
+    elif kind != "zero":
         raise ValueError(kind)
     return torch.from_numpy(e).to(S.codes.device)
+
+
+def calibrate(emb, S, family, n_pairs: int = 20000, seed: int = 21, cap: float = 1024.0):
+    """Offset of the pruned ranking: fit the true normalized distance of
+    held-out within-family pairs (the regime of most clusters) linearly on
+    the predicted one, y ~ a + b * y_hat; the ranking only depends on
+    y_hat + a / b.  A predictor with b <= 0 carries no ranking signal and
+    gets the cap (the length prior).  Returns (offset, a, b, correlation)."""
+    ia, ib = sample_pairs(family, n_pairs, seed=seed, within=1.0)
+    d = lev_labels(S, ia, ib).to(torch.float64).cpu().numpy()
+    L = S.lengths.astype(np.float64)
+    y = d / ((L[ia] + L[ib]) / 2)
+    a_t = torch.from_numpy(np.asarray(ia, np.int64)).to(emb.device)
+    b_t = torch.from_numpy(np.asarray(ib, np.int64)).to(emb.device)
+    yh = (emb[a_t].double() - emb[b_t].double()).norm(dim=1).cpu().numpy()
+    b, a = np.polyfit(yh, y, 1)
+    corr = float(np.corrcoef(yh, y)[0, 1])
+    off = cap if b <= 0 else float(min(max(a / b, 0.0), cap))
+    return off, float(a), float(b), corr
 
 
 def agreement(tree, clr, min_size: int = 17, pruned_above: int = 16):

@@ -54,10 +54,10 @@ SIGNATURES = {
     "nw_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
     "tree_workspace_bytes": (C.c_size_t, [SP]),
     "tree_build": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
-    "tree_build_pruned": (C.c_int, [SP, P, C.c_int32, C.c_int32, P, C.POINTER(C.c_int32),
-                                    C.c_int32, P, C.c_size_t, P, P]),
-    "tree_eval_centers": (C.c_int, [SP, P, C.c_int32, C.c_int32, P, C.c_int32, P, P, P, P,
-                                    C.c_size_t, P, P]),
+    "tree_build_pruned": (C.c_int, [SP, P, C.c_uint32, C.c_int32, C.c_int32, P,
+                                    C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
+    "tree_eval_centers": (C.c_int, [SP, P, C.c_uint32, C.c_int32, C.c_int32, P, C.c_int32, P,
+                                    P, P, P, C.c_size_t, P, P]),
     "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
     "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
                             C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
@@ -372,10 +372,12 @@ class Tree:
 
 class TreeBuilder:
     """Reusable Alg. 1 builder for one sequence set.  With emb (device
-    float32 [n, 128]) the medoid is pruned to the topk members closest in
-    embedding space (tree_build_pruned)."""
+    float32 [n, 128]) the medoid is pruned to the topk members that the
+    embedding ranks first (tree_build_pruned); emb_offset is the calibration
+    offset added to every embedding distance."""
 
-    def __init__(self, S: Seqs, use_graph=False, emb=None, topk=16, exact_below=0):
+    def __init__(self, S: Seqs, use_graph=False, emb=None, topk=16, exact_below=0,
+                 emb_offset=0.0):
         self.S = S
         if emb is not None:
             if (emb.dtype != torch.float32 or emb.device != S.codes.device
@@ -384,6 +386,7 @@ class TreeBuilder:
         self.emb = emb
         self.topk = int(topk)
         self.exact_below = int(exact_below)
+        self.emb_q0 = emb_offset_q(emb_offset)
         dev = S.codes.device
         self.ss = S.struct()
         self.tree = Tree(S.n, dev)
@@ -401,7 +404,7 @@ class TreeBuilder:
                                   _stream(stream))
             _check(rc, "tree_build")
         else:
-            rc = lib().tree_build_pruned(C.byref(self.ss), _ptr(self.emb), self.topk,
+            rc = lib().tree_build_pruned(C.byref(self.ss), _ptr(self.emb), self.emb_q0, self.topk,
                                          self.exact_below, C.byref(self.ts), C.byref(nn),
                                          int(self.use_graph),
                                          _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
@@ -410,12 +413,22 @@ class TreeBuilder:
         return self.tree
 
 
-def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16, exact_below=0):
+def emb_offset_q(offset: float) -> int:
+    """A calibration offset in the library's fixed point (units of 2^-16)."""
+    q = int(round(float(offset) * 65536.0))
+    if not 0 <= q <= 1 << 31:
+        raise ValueError("emb_offset must lie in [0, 2^15]")
+    return q
+
+
+def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16, exact_below=0,
+               emb_offset=0.0):
     """Alg. 1 guide tree of S; returns host numpy arrays like the oracle's.
-    emb/topk/exact_below select the surrogate-pruned medoid (see TreeBuilder)."""
+    emb/topk/exact_below/emb_offset select the surrogate-pruned medoid (see
+    TreeBuilder)."""
     if use_graph and stream is None:
         stream = torch.cuda.Stream()
-    tb = TreeBuilder(S, use_graph, emb, topk, exact_below)
+    tb = TreeBuilder(S, use_graph, emb, topk, exact_below, emb_offset)
     with torch.cuda.stream(stream) if stream is not None else _nullctx():
         t = tb(stream)
     torch.cuda.synchronize()
@@ -423,7 +436,8 @@ def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16, exact_b
     return t.host()
 
 
-def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, exact_below=0, stream=None):
+def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, exact_below=0, emb_offset=0.0,
+                      stream=None):
     """(center, lpole, rpole) host arrays that the build picks for each node
     of `tree` (a device Tree) when that node's members are given: the full
     median (emb None) or the pruned one."""
@@ -439,7 +453,8 @@ def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, exact_below=0, stream=No
     wsb = lib().tree_workspace_bytes(C.byref(ss))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
     st = Status(dev)
-    rc = lib().tree_eval_centers(C.byref(ss), _ptr(emb), int(topk), int(exact_below),
+    rc = lib().tree_eval_centers(C.byref(ss), _ptr(emb), emb_offset_q(emb_offset), int(topk),
+                                 int(exact_below),
                                  C.byref(ts), nn,
                                  *[_ptr(o) for o in out], _ptr(ws), wsb, _ptr(st.t),
                                  _stream(stream))

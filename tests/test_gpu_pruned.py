@@ -37,7 +37,7 @@ def _equal_trees(got, want):
     assert np.array_equal(gp, wp)
 
 
-def _compare(codes, off, sigma, emb, topk, use_graph=False, exact_below=0):
+def _compare(codes, off, sigma, emb, topk, use_graph=False, exact_below=0, emb_offset=0.0):
     import torch
     M = _msadp()
     n = len(off) - 1
@@ -45,9 +45,11 @@ def _compare(codes, off, sigma, emb, topk, use_graph=False, exact_below=0):
           f"graph={use_graph}: device", flush=True)
     S = M.to_device(codes, off, sigma)
     e = torch.from_numpy(emb).to(S.codes.device)
-    got = M.tree_build(S, use_graph=use_graph, emb=e, topk=topk, exact_below=exact_below)
+    got = M.tree_build(S, use_graph=use_graph, emb=e, topk=topk, exact_below=exact_below,
+                       emb_offset=emb_offset)
     print(f"[pruned] device done ({got['n_nodes']} nodes); oracle", flush=True)
-    want = orc.tree_pruned(codes, off, emb, topk=topk, exact_below=exact_below)
+    want = orc.tree_pruned(codes, off, emb, topk=topk, exact_below=exact_below,
+                           emb_q0=M.emb_offset_q(emb_offset))
     _equal_trees(got, want)
     return got
 
@@ -63,6 +65,14 @@ def test_exact_below_and_large_topk(topk, exact_below):
     d = synth.tiny()
     _compare(d["codes"], d["offsets"], d["sigma"], _emb(40 + topk, d["n"]), topk,
              exact_below=exact_below)
+
+
+@pytest.mark.parametrize("offset", [0.3, 7.5])
+def test_calibration_offset(offset):
+    d = synth.tiny()
+    _compare(d["codes"], d["offsets"], d["sigma"], _emb(50, d["n"]), 4, emb_offset=offset)
+    codes, off = synth.random_set(51, 120, 1, 80, 4)
+    _compare(codes, off, 4, _emb(52, 120, scale=0.3), 3, exact_below=9, emb_offset=offset)
 
 
 def test_tiny_workload_graph_replay():
@@ -133,6 +143,8 @@ def test_bad_arguments():
         assert ex.value.code == M.MSA_EINVAL
     with pytest.raises(ValueError):
         M.tree_build(S, emb=e[:10], topk=4)
+    with pytest.raises(ValueError):
+        M.tree_build(S, emb=e, topk=4, emb_offset=-1.0)
 
 
 def test_teacher_forced_exact_reproduces_tree():
@@ -158,12 +170,13 @@ def test_teacher_forced_pruned_matches_oracle():
     S = M.to_device(d["codes"], d["offsets"], d["sigma"])
     t = M.tree_build(S)
     emb = _emb(38, d["n"])
-    for topk, eb in ((1, 0), (5, 0), (2, 10)):
+    for topk, eb, offset in ((1, 0, 0.0), (5, 0, 0.0), (2, 10, 0.0), (3, 0, 2.25)):
         c, l, r = M.tree_eval_centers(S, t, emb=torch.from_numpy(emb).to(S.codes.device),
-                                      topk=topk, exact_below=eb)
+                                      topk=topk, exact_below=eb, emb_offset=offset)
         for v in range(t["n_nodes"]):
             C = t["perm"][t["mstart"][v]: t["mstart"][v] + t["mcount"][v]]
-            want = orc.select(d["codes"], d["offsets"], C, emb, topk, eb)
+            want = orc.select(d["codes"], d["offsets"], C, emb, topk, eb,
+                              emb_q0=M.emb_offset_q(offset))
             assert (int(c[v]), int(l[v]), int(r[v])) == want, (topk, eb, v)
 
 

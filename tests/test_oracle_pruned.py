@@ -200,3 +200,30 @@ def test_exact_below_splits_by_size():
         C = _members(t, v)
         want = orc.select(codes, off, C) if len(C) <= 12 else orc.select(codes, off, C, emb, 1)
         assert (int(t["center"][v]), int(t["lpole"][v]), int(t["rpole"][v])) == want
+
+
+def test_calibration_offset_adds_length_prior():
+    """emb_q0 adds (q0)(|x| + |y|) per ordered pair, x with itself included."""
+    e = _emb(17, 6)
+    off = _off([5, 9, 2, 7, 3, 4])
+    mem = np.arange(6, dtype=np.int32)
+    q0 = 12345
+    E0 = orc.emb_rowsums(off, e, mem)
+    E1 = orc.emb_rowsums(off, e, mem, emb_q0=q0)
+    L = np.diff(off)
+    for x in range(6):
+        assert int(E1[x]) - int(E0[x]) == q0 * int((L[x] + L).sum())
+
+
+def test_large_offset_ranks_shortest_first():
+    """An offset far above every embedding distance leaves the length prior:
+    the candidates are the topk shortest members (lowest index on ties)."""
+    codes, off = synth.random_set(41, 40, 10, 60, 4)
+    seqs = synth.from_csr(codes, off)
+    L = np.diff(off)
+    topk = 4
+    t = orc.tree_pruned(codes, off, _emb(18, 40, scale=1e-3), topk=topk, emb_q0=1 << 30)
+    cand = np.lexsort((np.arange(40), L))[:topk]
+    sums = [sum(orc.lev(seqs[x], seqs[y]) for y in range(40)) for x in cand]
+    best = min(zip(sums, cand))[1]
+    assert t["center"][0] == best

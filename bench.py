@@ -44,8 +44,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--quick", action="store_true",
-                    help="only the all-pairs leg (no NW, no learned pruning)")
+    ap.add_argument("--legs", default="nw,pruned",
+                    help="legs after the all-pairs one: any of nw, pruned (comma list)")
+    ap.add_argument("--quick", action="store_true", help="only the all-pairs leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
 
@@ -169,8 +170,9 @@ def main():
                      "frac": round(tcups / LEV_PEAK_TCUPS, 4), "traffic": None,
                      "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3)},
     }
-    if not args.quick:
-        for name, fn in (("nw", bench_nw), ("pruned", bench_pruned)):
+    legs = [] if args.quick else [x for x in args.legs.split(",") if x]
+    for name, fn in (("nw", bench_nw), ("pruned", bench_pruned)):
+        if name in legs:
             try:
                 res[name] = fn(msadp, synth, torch, args)
             except Exception as e:   # report, keep the headline line

@@ -161,20 +161,24 @@ static int64_t dist_of(const uint8_t *codes, const int64_t *off, int32_t x, int3
 }
 
 /* Surrogate distance of two embeddings (128 floats each), in the exact
- * float32 steps the pruned medoid uses: squares of the coordinate
- * differences added one coordinate after another (each difference, square
- * and sum rounded to float, no fused multiply-add), the square root capped
- * at 2^15, then the value in units of 2^-16 rounded to the nearest integer
- * (ties to even).  Rounding decides the candidate ranking, so both sides
- * take the same float32 steps; the integer sums are then exact. */
-static uint64_t emb_dist_q(const float *ex, const float *ey) {
+ * float32 steps the pruned medoid uses: |x|^2, |y|^2 and x.y each
+ * accumulated from 0 by fused multiply-adds (one rounding each, fmaf) in
+ * coordinate order; d2 = fma(-2, x.y, |x|^2 + |y|^2), negative values read
+ * as 0; the square root capped at 2^15, then the value in units of 2^-16
+ * rounded to the nearest integer (ties to even).  Rounding decides the
+ * candidate ranking, so both sides take the same float32 steps; the
+ * integer sums are then exact. */
+static float emb_dot(const float *a, const float *b) {
     float acc = 0.0f;
-    for (int c = 0; c < 128; ++c) {
-        const float d = ex[c] - ey[c];
-        const float sq = d * d;
-        acc = acc + sq;
-    }
-    return (uint64_t)rintf(fminf(sqrtf(acc), 32768.0f) * 65536.0f);
+    for (int c = 0; c < 128; ++c) acc = fmaf(a[c], b[c], acc);
+    return acc;
+}
+
+static uint64_t emb_dist_q(const float *ex, const float *ey) {
+    const float nx = emb_dot(ex, ex), ny = emb_dot(ey, ey), dot = emb_dot(ex, ey);
+    float d2 = fmaf(-2.0f, dot, nx + ny);
+    if (!(d2 > 0.0f)) d2 = 0.0f;
+    return (uint64_t)rintf(fminf(sqrtf(d2), 32768.0f) * 65536.0f);
 }
 
 /* The estimate of f(x, y) behind the ranking, in units of 2^-17: the

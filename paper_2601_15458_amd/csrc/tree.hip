@@ -25,11 +25,13 @@ namespace msadp {
 enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 4 };
 
 // Surrogate-pruned medoid: clusters above exact_below members get exact row
-// sums for their topk best-ranked members only.  The surrogate distance of two embeddings is the square
-// root of their squared coordinate differences added in coordinate order,
-// each step rounded to float (no fused multiply-add), capped at kEmbCap,
-// scaled by kEmbScale and rounded to the nearest integer: fixed float steps
-// make the candidate ranking reproducible, and the sums are integers.
+// sums for their topk best-ranked members only.  The surrogate distance of
+// two embeddings x, y takes fixed float32 steps: the norms |x|^2, |y|^2 and
+// the dot product x.y each accumulated by fused multiply-adds in coordinate
+// order from 0, then d2 = fma(-2, x.y, |x|^2 + |y|^2) clamped at 0,
+// sqrt(d2) capped at kEmbCap, scaled by kEmbScale and rounded to the nearest
+// integer.  Fixed steps make the candidate ranking reproducible, and the
+// sums are integers.
 constexpr int kMaxTopk = 1024;
 constexpr uint32_t kMaxEmbOffset = 1u << 31;   // 2^15 in units of 2^-16
 constexpr float kEmbScale = 65536.0f;   // fixed point of embedding distances (2^16)
@@ -119,7 +121,7 @@ __global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
             if (a.emb != nullptr) {
                 const bool pruned = k > a.exact_below;
                 a.cnt[q] = pruned ? emb_tiles(k) : 0;
-                a.ncand[q] = pruned ? min<int64_t>(k, a.topk) : k;
+                a.ncand[q] = pruned ? min<int64_t>(k, a.topk) : 0;
             } else {
                 a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
             }
@@ -234,13 +236,19 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
     }
 }
 
-// c = member with the least row sum (lowest input index on ties).
+// c = member with the least row sum (lowest input index on ties).  In a
+// pruned build the clusters above exact_below members already hold c (from
+// k_pick_center_cand) and only get the work of the first pole pass.
 __global__ void __launch_bounds__(256) k_pick_center(TreeArgs a) {
     __shared__ uint64_t red[256];
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
+        if (a.emb != nullptr && k > a.exact_below) {   // uniform per block
+            if (threadIdx.x == 0) a.cnt[q] = k >= 2 ? (k + 63) / 64 : 0;
+            continue;
+        }
         uint64_t best = ~0ull;
         for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
             const int32_t orig = a.order[a.perm[ms + i]];
@@ -423,18 +431,27 @@ __global__ void k_set_desc(int32_t *desc, int32_t lo, int32_t hi) {
 // row of block J that every lane needs costs no vector-memory issue slots.
 typedef const __attribute__((address_space(4))) float const_f32;
 
-// Squared differences of one quarter (32 coordinates) of two embeddings,
-// added to acc coordinate by coordinate in float32 (no fused multiply-add).
-__device__ __forceinline__ float emb_quarter(float acc, const float4 *x, const_f32 *y) {
-#pragma clang fp contract(off)
+// Dot product of one quarter (32 coordinates) of two embeddings, added to acc
+// by fused multiply-adds in coordinate order.
+__device__ __forceinline__ float dot_quarter(float acc, const float4 *x, const_f32 *y) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        const float d0 = x[c].x - y[4 * c], d1 = x[c].y - y[4 * c + 1];
-        const float d2 = x[c].z - y[4 * c + 2], d3 = x[c].w - y[4 * c + 3];
-        acc = acc + d0 * d0;
-        acc = acc + d1 * d1;
-        acc = acc + d2 * d2;
-        acc = acc + d3 * d3;
+        acc = __builtin_fmaf(x[c].x, y[4 * c], acc);
+        acc = __builtin_fmaf(x[c].y, y[4 * c + 1], acc);
+        acc = __builtin_fmaf(x[c].z, y[4 * c + 2], acc);
+        acc = __builtin_fmaf(x[c].w, y[4 * c + 3], acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ float norm2(const float4 *x) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        acc = __builtin_fmaf(x[c].x, x[c].x, acc);
+        acc = __builtin_fmaf(x[c].y, x[c].y, acc);
+        acc = __builtin_fmaf(x[c].z, x[c].z, acc);
+        acc = __builtin_fmaf(x[c].w, x[c].w, acc);
     }
     return acc;
 }
@@ -447,7 +464,7 @@ __device__ __forceinline__ float emb_quarter(float acc, const float4 *x, const_f
 // x with itself included, adds it to the row sum of x.  One work item is a 64 x 64 tile (I, J) of the cluster's upper block
 // triangle: lane i keeps the embedding of member 64 I + i in registers and
 // walks the 64 members of block J, whose rows every lane needs whole and
-// reads by scalar loads.
+// reads by scalar loads; lane j holds |y_j|^2 of member 64 J + j.
 // Lanes sum their row; for I < J the column sums are reduced across the
 // wave.  A diagonal tile visits every ordered pair of its block and adds row
 // sums only.
@@ -481,22 +498,34 @@ __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
         const int32_t yr = a.perm[ms + (yl ? yi : 0)];
         const uint32_t yrow = (uint32_t)a.order[yr];
         const uint32_t ylen = (uint32_t)a.S.len[yr] | (yl ? 0u : 0x80000000u);
+        float ny;
+        {
+            const float4 *yp = (const float4 *)(a.emb + (int64_t)yrow * 128);
+            float4 y[32];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) y[c] = yp[c];
+            ny = norm2(y);
+        }
         const float4 *xp = (const float4 *)(a.emb + (int64_t)a.order[xr] * 128);
         float4 x[32];
 #pragma unroll
         for (int c = 0; c < 32; ++c) x[c] = xp[c];
+        const float nx = norm2(x);
         const uint64_t lx = (uint64_t)a.S.len[xr];
         const_f32 *embs = (const_f32 *)a.emb;
         uint64_t rs = 0, cs = 0;
         for (int j = 0; j < 64; ++j) {
             const uint32_t lj = __builtin_amdgcn_readlane(ylen, j);
             const_f32 *row = embs + (int64_t)__builtin_amdgcn_readlane(yrow, j) * 128;
-            float acc = 0.0f;
-            acc = emb_quarter(acc, x + 0, row + 0);
-            acc = emb_quarter(acc, x + 8, row + 32);
-            acc = emb_quarter(acc, x + 16, row + 64);
-            acc = emb_quarter(acc, x + 24, row + 96);
-            const uint64_t qd = (uint64_t)rintf(fminf(sqrtf(acc), kEmbCap) * kEmbScale);
+            const float nyj = __builtin_bit_cast(
+                float, __builtin_amdgcn_readlane(__builtin_bit_cast(uint32_t, ny), j));
+            float dot = 0.0f;
+            dot = dot_quarter(dot, x + 0, row + 0);
+            dot = dot_quarter(dot, x + 8, row + 32);
+            dot = dot_quarter(dot, x + 16, row + 64);
+            dot = dot_quarter(dot, x + 24, row + 96);
+            const float d2 = fmaxf(__builtin_fmaf(-2.0f, dot, nx + nyj), 0.0f);
+            const uint64_t qd = (uint64_t)rintf(fminf(sqrtf(d2), kEmbCap) * kEmbScale);
             // lj's top bit marks a missing member of block J
             const uint64_t w = (xv && !(lj >> 31)) ? lx + (uint64_t)lj : 0ull;
             const uint64_t e = (qd + a.emb_q0) * w;
@@ -518,11 +547,11 @@ __device__ __forceinline__ bool key_less(uint64_t s0, uint32_t i0, uint64_t s1, 
     return s0 < s1 || (s0 == s1 && i0 < i1);
 }
 
-// Candidates of each cluster, from its first candidate slot on: every member
-// of a cluster of at most exact_below members; otherwise the topk members
-// with the least estimated row sum (lowest input index on ties), by topk
-// rounds of a block-wide minimum over the members above the last pick.
-// Clears the candidates' sums and sets the work of the candidate-sum pass.
+// Candidates of each cluster above exact_below members, from its first
+// candidate slot on: the topk members with the least estimated row sum
+// (lowest input index on ties), by topk rounds of a block-wide minimum over
+// the members above the last pick.  Clears the candidates' sums and sets the
+// work of the candidate-sum pass (none for the other clusters).
 __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
     __shared__ uint64_t rs[256];
     __shared__ uint32_t ri[256];
@@ -532,9 +561,7 @@ __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
         const int64_t ms = a.mstart[v], k = a.mcount[v];
         const int64_t nc = a.ncand[q], base = a.coff[q];
         for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) a.candsum[base + j] = 0;
-        if (k <= a.exact_below) {
-            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.cand[base + i] = a.perm[ms + i];
-        } else {
+        if (k > a.exact_below) {
             uint64_t last_s = 0;
             uint32_t last_i = 0;
             bool have_last = false;
@@ -571,12 +598,19 @@ __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
 }
 
-// c = the candidate with the least exact row sum (lowest input index on ties).
+// Clusters above exact_below members: c = the candidate with the least exact
+// row sum (lowest input index on ties).  Sets the work of the full-median
+// pass that follows: the medoid triangle of every other cluster, none here
+// (the pole count of these clusters is set after that pass).
 __global__ void k_pick_center_cand(TreeArgs a) {
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const int32_t v = lvl + q;
         const int64_t k = a.mcount[v];
+        if (k <= a.exact_below) {
+            a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
+            continue;
+        }
         const int64_t nc = a.ncand[q], base = a.coff[q];
         uint64_t bs = ~0ull;
         uint32_t bi = ~0u;
@@ -589,12 +623,11 @@ __global__ void k_pick_center_cand(TreeArgs a) {
         a.center[v] = (int32_t)bi;
         a.pat[q] = a.rank_of[bi];
         a.key[q] = 0;
-        a.cnt[q] = k >= 2 ? (k + 63) / 64 : 0;
+        a.cnt[q] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
 }
 
-// The choice of c, l and r for every cluster of the level.
 template <int WMAX>
 static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s) {
     const dim3 cg(kClusterGrid), cb(256), tb(64), lg(grid);
@@ -612,6 +645,11 @@ static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s)
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
         hipLaunchKernelGGL((k_tree_lev<WMAX, kCandSum>), lg, tb, 0, s, a);
         hipLaunchKernelGGL(k_pick_center_cand, dim3(256), dim3(256), 0, s, a);
+        // clusters of at most exact_below members: the full median
+        hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+        hipLaunchKernelGGL((k_tree_lev<WMAX, kMedoid>), lg, tb, 0, s, a);
+        hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
     }
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);

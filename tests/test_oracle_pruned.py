@@ -39,28 +39,55 @@ def test_emb_distance_closed_form():
 
 def test_emb_distance_within_float32_bound():
     """|E - 2^16 (|x| + |y|) ||e_x - e_y||| stays within the float32 error of
-    128 squares added in sequence, a square root and the final rounding."""
+    three 128-term multiply-add sums, the combination, a square root and the
+    final rounding: the error of d^2 is at most ~2^-24 * 300 (|x|^2 + |y|^2),
+    which moves d by at most that over 2d."""
     e = _emb(7, 64, scale=1.0)
     off = _off(np.arange(64) + 1)
     for i in range(1, 64):
         E = orc.emb_rowsums(off, e, np.array([0, i], dtype=np.int32))
-        d = np.linalg.norm(e[0].astype(np.float64) - e[i].astype(np.float64))
+        x, y = e[0].astype(np.float64), e[i].astype(np.float64)
+        d = np.linalg.norm(x - y)
         L = 1 + (i + 1)
-        assert abs(float(E[0]) - TWO16 * L * d) <= L * (TWO16 * d * 140 * 2.0 ** -24 + 0.5)
+        err_d = 2.0 ** -24 * 300 * (x @ x + y @ y) / (2 * d)
+        assert abs(float(E[0]) - TWO16 * L * d) <= L * (TWO16 * err_d + 0.5)
+
+
+def _round_f32(q):
+    """The float32 nearest to the rational q (ties to even), exactly."""
+    from fractions import Fraction
+    f = np.float32(float(q))
+    best = None
+    for g in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        dist = abs(Fraction(float(g)) - q)
+        key = (dist, int(np.array(g).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, g)
+    return best[1]
+
+
+def _fma(a, b, c):
+    from fractions import Fraction
+    return _round_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
 
 
 def test_emb_distance_float32_steps():
-    """The oracle takes separately rounded float32 steps (no fused
-    multiply-add): the same steps spelled out with numpy float32 scalars."""
-    e = _emb(8, 20, scale=0.7)
-    off = _off(np.ones(20, dtype=np.int64))
+    """The oracle takes the stated float32 steps: sums of fused multiply-adds
+    (each rounded once, emulated here with exact rationals), then
+    fma(-2, x.y, |x|^2 + |y|^2), the square root and the rounding."""
+    e = _emb(8, 6, scale=0.7)
+    off = _off(np.ones(6, dtype=np.int64))
     f = np.float32
-    for i in range(1, 20):
-        acc = f(0.0)
+    for i in range(1, 6):
+        x, y = e[0], e[i]
+        nx = ny = dot = f(0.0)
         for c in range(128):
-            d = f(e[0, c] - e[i, c])
-            acc = f(acc + f(d * d))
-        want = 2 * int(np.rint(f(np.sqrt(acc)) * f(TWO16)))
+            nx = _fma(x[c], x[c], nx)
+            ny = _fma(y[c], y[c], ny)
+            dot = _fma(x[c], y[c], dot)
+        d2 = _fma(f(-2.0), dot, f(nx + ny))
+        d2 = d2 if d2 > 0 else f(0.0)
+        want = 2 * int(np.rint(f(np.sqrt(d2)) * f(TWO16)))
         got = orc.emb_rowsums(off, e, np.array([0, i], dtype=np.int32))
         assert int(got[0]) == want
 

@@ -35,6 +35,12 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2 * 2.4e9
 K_REF = 32
 LEV_PEAK_TCUPS = VALU_PEAK_LANE_OPS * 64 / K_REF / 1e12
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch from rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB
+# copy shows) + WRITE_SIZE on these workloads (profiles/k_lev_allpairs_dna4096.md,
+# profiles/k_nw_fill_dna512.md), by launch variant; None for a variant not measured.
+LEV_TRAFFIC = {16: 11311.2e3 * 1024, 20: 4338.5e3 * 1024, 24: 2165.1e3 * 1024,
+               28: 2071.8e3 * 1024, 32: 2095.3e3 * 1024}
+NW_FILL_TRAFFIC = {16: 7923.3e3 * 1024, 32: 8019.3e3 * 1024}
 
 
 def parse():
@@ -167,7 +173,8 @@ def main():
         "tuning": tuning,
         "roofline": {"bound": "alu", "achieved": round(tcups, 2),
                      "peak": round(LEV_PEAK_TCUPS, 1), "unit": "Tcell/s",
-                     "frac": round(tcups / LEV_PEAK_TCUPS, 4), "traffic": None,
+                     "frac": round(tcups / LEV_PEAK_TCUPS, 4),
+                     "traffic": LEV_TRAFFIC.get(tuning["chosen"] if tuning else 32),
                      "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3)},
     }
     legs = [] if args.quick else [x for x in args.legs.split(",") if x]
@@ -261,7 +268,12 @@ def bench_nw(msadp, synth, torch, args):
             "pairs_per_s": round(P / ((f + t) * 1e-3), 1),
             "tb_bytes": tb_bytes,
             "fill_hbm_gbs": round(tb_bytes / f / 1e6, 1),
-            "fill_hbm_frac": round(tb_bytes / f / 1e6 / HBM_PEAK_GBS, 4)}
+            "fill_hbm_frac": round(tb_bytes / f / 1e6 / HBM_PEAK_GBS, 4),
+            "roofline": {"bound": "hbm", "achieved": round(tb_bytes / f / 1e6, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(tb_bytes / f / 1e6 / HBM_PEAK_GBS, 4),
+                         "traffic": NW_FILL_TRAFFIC.get(tuning["chosen"] if tuning else 32),
+                         "kernel": "k_nw_fill"}}
 
 
 def _log(msg):

@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
             if (a.emb != nullptr) {
                 const bool pruned = k > a.exact_below;
                 a.cnt[q] = pruned ? emb_tiles(k) : 0;
-                a.ncand[q] = pruned ? min<int64_t>(k, a.topk) : 0;
+                a.ncand[q] = pruned ? min<int64_t>(k, a.topk) : k;
             } else {
                 a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
             }
@@ -236,19 +236,13 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
     }
 }
 
-// c = member with the least row sum (lowest input index on ties).  In a
-// pruned build the clusters above exact_below members already hold c (from
-// k_pick_center_cand) and only get the work of the first pole pass.
+// c = member with the least row sum (lowest input index on ties).
 __global__ void __launch_bounds__(256) k_pick_center(TreeArgs a) {
     __shared__ uint64_t red[256];
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
-        if (a.emb != nullptr && k > a.exact_below) {   // uniform per block
-            if (threadIdx.x == 0) a.cnt[q] = k >= 2 ? (k + 63) / 64 : 0;
-            continue;
-        }
         uint64_t best = ~0ull;
         for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
             const int32_t orig = a.order[a.perm[ms + i]];
@@ -547,11 +541,12 @@ __device__ __forceinline__ bool key_less(uint64_t s0, uint32_t i0, uint64_t s1, 
     return s0 < s1 || (s0 == s1 && i0 < i1);
 }
 
-// Candidates of each cluster above exact_below members, from its first
-// candidate slot on: the topk members with the least estimated row sum
-// (lowest input index on ties), by topk rounds of a block-wide minimum over
-// the members above the last pick.  Clears the candidates' sums and sets the
-// work of the candidate-sum pass (none for the other clusters).
+// Candidates of each cluster, from its first candidate slot on: every member
+// of a cluster of at most exact_below members (one full row sum each, which
+// keeps every work item 64 texts wide); otherwise the topk members with the
+// least estimated row sum (lowest input index on ties), by topk rounds of a
+// block-wide minimum over the members above the last pick.  Clears the
+// candidates' sums and sets the work of the candidate-sum pass.
 __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
     __shared__ uint64_t rs[256];
     __shared__ uint32_t ri[256];
@@ -561,7 +556,9 @@ __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
         const int64_t ms = a.mstart[v], k = a.mcount[v];
         const int64_t nc = a.ncand[q], base = a.coff[q];
         for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) a.candsum[base + j] = 0;
-        if (k > a.exact_below) {
+        if (k <= a.exact_below) {
+            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.cand[base + i] = a.perm[ms + i];
+        } else {
             uint64_t last_s = 0;
             uint32_t last_i = 0;
             bool have_last = false;
@@ -598,19 +595,12 @@ __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
 }
 
-// Clusters above exact_below members: c = the candidate with the least exact
-// row sum (lowest input index on ties).  Sets the work of the full-median
-// pass that follows: the medoid triangle of every other cluster, none here
-// (the pole count of these clusters is set after that pass).
+// c = the candidate with the least exact row sum (lowest input index on ties).
 __global__ void k_pick_center_cand(TreeArgs a) {
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const int32_t v = lvl + q;
         const int64_t k = a.mcount[v];
-        if (k <= a.exact_below) {
-            a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
-            continue;
-        }
         const int64_t nc = a.ncand[q], base = a.coff[q];
         uint64_t bs = ~0ull;
         uint32_t bi = ~0u;
@@ -623,7 +613,7 @@ __global__ void k_pick_center_cand(TreeArgs a) {
         a.center[v] = (int32_t)bi;
         a.pat[q] = a.rank_of[bi];
         a.key[q] = 0;
-        a.cnt[q] = 0;
+        a.cnt[q] = k >= 2 ? (k + 63) / 64 : 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
 }
@@ -645,11 +635,6 @@ static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s)
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
         hipLaunchKernelGGL((k_tree_lev<WMAX, kCandSum>), lg, tb, 0, s, a);
         hipLaunchKernelGGL(k_pick_center_cand, dim3(256), dim3(256), 0, s, a);
-        // clusters of at most exact_below members: the full median
-        hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-        hipLaunchKernelGGL((k_tree_lev<WMAX, kMedoid>), lg, tb, 0, s, a);
-        hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
     }
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);

@@ -119,9 +119,11 @@ __global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
             a.left[v] = a.right[v] = a.lpole[v] = a.rpole[v] = -1;
             a.key[q] = ~0ull;
             if (a.emb != nullptr) {
-                const bool pruned = k > a.exact_below;
+                // at most max(exact_below, topk) members: every member is a
+                // candidate and no ranking is needed
+                const bool pruned = k > a.exact_below && k > a.topk;
                 a.cnt[q] = pruned ? emb_tiles(k) : 0;
-                a.ncand[q] = pruned ? min<int64_t>(k, a.topk) : k;
+                a.ncand[q] = pruned ? a.topk : k;
             } else {
                 a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
             }
@@ -508,7 +510,8 @@ __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
         const uint64_t lx = (uint64_t)a.S.len[xr];
         const_f32 *embs = (const_f32 *)a.emb;
         uint64_t rs = 0, cs = 0;
-        for (int j = 0; j < 64; ++j) {
+        const int jn = (int)min<int64_t>(64, k - J * 64);   // members in block J
+        for (int j = 0; j < jn; ++j) {
             const uint32_t lj = __builtin_amdgcn_readlane(ylen, j);
             const_f32 *row = embs + (int64_t)__builtin_amdgcn_readlane(yrow, j) * 128;
             const float nyj = __builtin_bit_cast(
@@ -542,8 +545,8 @@ __device__ __forceinline__ bool key_less(uint64_t s0, uint32_t i0, uint64_t s1, 
 }
 
 // Candidates of each cluster, from its first candidate slot on: every member
-// of a cluster of at most exact_below members (one full row sum each, which
-// keeps every work item 64 texts wide); otherwise the topk members with the
+// of a cluster of at most max(exact_below, topk) members (one full row sum
+// each, which keeps every work item 64 texts wide); otherwise the topk members with the
 // least estimated row sum (lowest input index on ties), by topk rounds of a
 // block-wide minimum over the members above the last pick.  Clears the
 // candidates' sums and sets the work of the candidate-sum pass.
@@ -556,7 +559,7 @@ __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
         const int64_t ms = a.mstart[v], k = a.mcount[v];
         const int64_t nc = a.ncand[q], base = a.coff[q];
         for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) a.candsum[base + j] = 0;
-        if (k <= a.exact_below) {
+        if (k <= a.exact_below || k <= a.topk) {
             for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.cand[base + i] = a.perm[ms + i];
         } else {
             uint64_t last_s = 0;

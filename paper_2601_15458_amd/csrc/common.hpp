@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <atomic>
+
 #include "msadp.h"
 
 namespace msadp {
@@ -84,6 +86,9 @@ struct Sizer {
 };
 
 int check_seqs(const msa_seqs *S);
+// The current device (0 when it cannot be read) and its compute units.
+constexpr int kMaxDevices = 64;
+int current_device();
 int device_cus();
 int launch_status();
 

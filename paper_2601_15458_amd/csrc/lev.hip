@@ -172,9 +172,12 @@ __global__ void k_make_items(const int64_t *start, const int64_t *item_start, in
 // ------------------------------------------------------------ host side
 #define MSADP_LEV_CLASSES(X) X(4) X(8) X(16) X(20) X(24) X(28) X(32)
 
+// Persistent grid of a kernel variant, cached per device (concurrent first
+// calls compute the same value).
 static int lev_grid(int wclass, bool grouped) {
-    static int cache[2][33];
-    int &g = cache[grouped][wclass];
+    static std::atomic<int> cache[kMaxDevices][2][33];
+    std::atomic<int> &slot = cache[current_device()][grouped][wclass];
+    int g = slot.load(std::memory_order_relaxed);
     if (g == 0) {
         switch (wclass) {
 #define MSADP_G(w) \
@@ -183,6 +186,7 @@ static int lev_grid(int wclass, bool grouped) {
 #undef MSADP_G
             default: g = device_cus();
         }
+        slot.store(g, std::memory_order_relaxed);
     }
     return g;
 }

@@ -15,14 +15,22 @@ int launch_status() {
     return e == hipSuccess ? MSA_OK : MSA_EDEVICE;
 }
 
+int current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    return dev;
+}
+
+// Cached per device; concurrent first calls compute the same value.
 int device_cus() {
-    static int cus = 0;
+    static std::atomic<int> cache[kMaxDevices];
+    const int dev = current_device();
+    int cus = cache[dev].load(std::memory_order_relaxed);
     if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus <= 0)
             cus = 256;
+        cache[dev].store(cus, std::memory_order_relaxed);
     }
     return cus;
 }

@@ -685,15 +685,23 @@ static void level_select(const TreeArgs &a, int wclass, int grid, int egrid, hip
     }
 }
 
+// Persistent grids, cached per device (concurrent first calls compute the
+// same value).
 static int emb_grid() {
-    static int g = 0;
-    if (g == 0) g = persistent_grid(k_emb_rowsum);
+    static std::atomic<int> cache[kMaxDevices];
+    std::atomic<int> &slot = cache[current_device()];
+    int g = slot.load(std::memory_order_relaxed);
+    if (g == 0) {
+        g = persistent_grid(k_emb_rowsum);
+        slot.store(g, std::memory_order_relaxed);
+    }
     return g;
 }
 
 static int tree_grid(int wclass) {
-    static int cache[33];
-    int &g = cache[wclass];
+    static std::atomic<int> cache[kMaxDevices][33];
+    std::atomic<int> &slot = cache[current_device()][wclass];
+    int g = slot.load(std::memory_order_relaxed);
     if (g == 0) {
         switch (wclass) {
             case 4: g = persistent_grid(k_tree_lev<4, kMedoid>); break;
@@ -702,6 +710,7 @@ static int tree_grid(int wclass) {
             case 24: g = persistent_grid(k_tree_lev<24, kMedoid>); break;
             default: g = persistent_grid(k_tree_lev<32, kMedoid>); break;
         }
+        slot.store(g, std::memory_order_relaxed);
     }
     return g;
 }

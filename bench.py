@@ -4,9 +4,10 @@ One step = one lev_allpairs call over the whole set (8,386,560 pairs): length
 binning, staging and the persistent bit-parallel kernel.  Inputs are
 resident on the GPU before the timed region starts; the launch variant is
 autotuned before it.  Further legs, reported in the same JSON line: the
-512-pair NW fill + traceback ("nw") and the learned pruning of the tree
-build on 100,000 sequences ("pruned": embedder training, exact vs pruned
-build time, teacher-forced agreement, control rankers).
+512-pair NW fill + traceback ("nw"), the exact tree build of 20,000 protein
+sequences ("tree": autotuned, graph-replayed levels) and the learned pruning
+of the tree build on 100,000 sequences ("pruned": embedder training, exact
+vs pruned build time, teacher-forced agreement, control rankers).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
@@ -50,16 +51,18 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="nw,pruned",
-                    help="legs after the all-pairs one: any of nw, pruned (comma list)")
+    ap.add_argument("--legs", default="nw,tree,pruned",
+                    help="legs after the all-pairs one: any of nw, tree, pruned (comma list)")
     ap.add_argument("--quick", action="store_true", help="only the all-pairs leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
-
     ap.add_argument("--epochs", type=int, default=2, help="embedder epochs over 2M pairs")
     ap.add_argument("--topk", type=int, default=16)
     ap.add_argument("--exact-below", type=int, default=256,
                     help="hybrid point: clusters of at most this many members keep the full median")
+    ap.add_argument("--points", default="",
+                    help="pruned builds to run instead of the default set, as ranker:topk:"
+                         "exact_below items (rankers cnn, cnn_raw, shortest, random)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -178,7 +181,7 @@ def main():
                      "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3)},
     }
     legs = [] if args.quick else [x for x in args.legs.split(",") if x]
-    for name, fn in (("nw", bench_nw), ("pruned", bench_pruned)):
+    for name, fn in (("nw", bench_nw), ("tree", bench_tree), ("pruned", bench_pruned)):
         if name in legs:
             try:
                 res[name] = fn(msadp, synth, torch, args)
@@ -276,6 +279,59 @@ def bench_nw(msadp, synth, torch, args):
                          "kernel": "k_nw_fill"}}
 
 
+def tree_cells(t, L):
+    """Levenshtein cells of one exact build: per internal node the medoid
+    triangle and three pole rows (c, l and r against every member)."""
+    perm = t["perm"].astype(np.int64)
+    Lp = L[perm]
+    c1 = np.concatenate([[0], np.cumsum(Lp)])
+    c2 = np.concatenate([[0], np.cumsum(Lp * Lp)])
+    ms, mc = t["mstart"].astype(np.int64), t["mcount"].astype(np.int64)
+    v = np.flatnonzero(t["left"] >= 0)
+    s1 = c1[ms[v] + mc[v]] - c1[ms[v]]
+    s2 = c2[ms[v] + mc[v]] - c2[ms[v]]
+    poles = L[t["center"][v]] + L[t["lpole"][v]] + L[t["rpole"][v]]
+    return int(((s1 * s1 - s2) // 2 + poles * s1).sum())
+
+
+def bench_tree(msadp, synth, torch, args):
+    """Exact Alg. 1 build of the 20,000-sequence protein set: kernel class
+    autotuned, levels replayed from a HIP graph (and, for comparison,
+    launched one by one)."""
+    d = synth.protein_tree()
+    S = msadp.to_device(d["codes"], d["offsets"], d["sigma"])
+    stream = torch.cuda.Stream()
+    tuning = None
+    if not args.no_tune:
+        best, ms = msadp.autotune_tree(S, reps=1, stream=stream)
+        tuning = {"kind": "tree words per pass", "chosen": best, "ms": round(ms, 1)}
+        _log(f"tree class: {best} ({ms:.1f} ms)")
+    times = {}
+    for graph in (True, False):
+        tb = msadp.TreeBuilder(S, use_graph=graph)
+        with torch.cuda.stream(stream):
+            tb(stream)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(max(args.steps, 3)):
+                t0 = time.perf_counter()
+                tree = tb(stream)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+        tb.st.check("tree_build")
+        times[graph] = float(np.median(ts))
+        if graph:
+            host = tree.host()
+    L = np.diff(d["offsets"]).astype(np.int64)
+    cells = tree_cells(host, L)
+    tg = times[True]
+    return {"workload": "tree_build: 20,000 protein seqs (200 families, lognormal lengths "
+                        "median 350 in [50, 2000], 30% divergence), seed 3", "tuning": tuning,
+            "n_nodes": int(host["n_nodes"]), "depth": int(host["depth"].max()),
+            "build_s_graph": round(tg, 4), "build_s_launches": round(times[False], 4),
+            "cells": cells, "gcups": round(cells / tg / 1e9, 1)}
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -361,6 +417,13 @@ def bench_pruned(msadp, synth, torch, args):
               ("cnn", args.topk, args.exact_below), ("shortest", args.topk, args.exact_below),
               ("cnn", args.topk, 8 * args.exact_below),
               ("shortest", args.topk, 8 * args.exact_below)]
+    if args.points:
+        points = []
+        for item in args.points.split(","):
+            name, topk, eb = item.split(":")
+            if name not in rankers:
+                raise ValueError(f"unknown ranker {name!r} (one of {sorted(rankers)})")
+            points.append((name, int(topk), int(eb)))
     out["points"] = []
     for name, topk, eb in points:
         e, eo = rankers[name]

@@ -281,9 +281,14 @@ int cnn_train_step(void *params, const msa_seqs *S, const int32_t *idx, int32_t 
  *   MSA_TUNE_NW: bin = wavefronts per pair, ceil(ceil(max_len_A / 32) / 64);
  *     value = steps between the fill's workgroup barriers (16, 32, 64;
  *     default 32).
+ *   MSA_TUNE_TREE: bin = ceil(max_len / 64) of the set of tree_build,
+ *     tree_build_pruned and tree_eval_centers; value = 64-bit words per pass
+ *     of their Levenshtein kernels (4, 8, 16, 24, 32; default as for
+ *     MSA_TUNE_LEV).  An entry that would take more passes than the default
+ *     (and more than two) is ignored.
  * Workspace sizes never depend on the table.  Results never depend on it
  * (every variant computes the same exact values). */
-enum { MSA_TUNE_LEV = 0, MSA_TUNE_NW = 1 };
+enum { MSA_TUNE_LEV = 0, MSA_TUNE_NW = 1, MSA_TUNE_TREE = 2 };
 
 /* Set one entry (EINVAL for an unknown kind, a key out of range or a value
  * that is not a variant of the kind). */
@@ -317,6 +322,13 @@ int msa_autotune_nw(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, con
                     int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets,
                     void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
                     int32_t *d_status, hipStream_t s);
+/* The same for the exact tree_build (same arguments as tree_build; T and
+ * *n_nodes hold the last run's tree): every class within the default's
+ * passes (at least two), fastest stored for (MSA_TUNE_TREE, S->sigma,
+ * ceil(S->max_len / 64)).  S->n >= 2. */
+int msa_autotune_tree(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
+                      void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
+                      int32_t *d_status, hipStream_t s);
 
 #ifdef __cplusplus
 }

@@ -362,9 +362,6 @@ int msa_autotune_lev(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws
     if ((rc = check_seqs(A))) return rc;
     if (best == nullptr || best_ms == nullptr || reps < 1 || A->n < 2) return MSA_EINVAL;
     const int words = (int)std::max<int64_t>(1, ((int64_t)A->max_len + 63) / 64);
-    // candidates: every class that needs no more passes than the default
-    const int dflt = wmax_class(A->max_len);
-    const int max_passes = std::max(2, (words + dflt - 1) / dflt);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return MSA_EDEVICE;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -375,7 +372,7 @@ int msa_autotune_lev(const msa_seqs *A, uint16_t *condensed, void *ws, size_t ws
     float bms = 0.0f;
     rc = MSA_OK;
     for (int c : kLevClasses) {
-        if ((words + c - 1) / c > max_passes) continue;
+        if (!class_within_passes(A->max_len, c)) continue;
         if ((rc = allpairs_impl(A, condensed, ws, ws_bytes, d_status, s, c))) break;   // warm-up
         if (hipEventRecord(e0, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
         for (int r = 0; r < reps && rc == MSA_OK; ++r)

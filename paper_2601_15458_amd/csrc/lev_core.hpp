@@ -215,6 +215,24 @@ inline bool is_lev_class(int c) {
     return false;
 }
 
+// Variants of the tree build's medoid and pole kernels.
+constexpr int kTreeClasses[] = {4, 8, 16, 24, 32};
+
+inline bool is_tree_class(int c) {
+    for (int x : kTreeClasses)
+        if (x == c) return true;
+    return false;
+}
+
+// A tuned class may take at most this many passes over the longest pattern
+// (the default's count, and at least two).
+inline bool class_within_passes(int32_t pat_max, int c) {
+    const int words = pat_max > 64 ? (pat_max + 63) / 64 : 1;
+    const int dflt = wmax_class(pat_max);
+    const int max_passes = (words + dflt - 1) / dflt > 2 ? (words + dflt - 1) / dflt : 2;
+    return (words + c - 1) / c <= max_passes;
+}
+
 // Passes of a class over patterns of up to pat_max rows need a carry buffer.
 inline bool needs_passes(int32_t pat_max, int wclass) { return pat_max > wclass * 64; }
 

@@ -718,14 +718,33 @@ static int tree_grid(int wclass) {
 struct TreePlan {
     int64_t stride, hstride;
     int wclass, grid;
+    size_t hbuf_dwords;     // carry buffer: the largest any admissible class needs
 };
 
-static TreePlan plan_tree(const msa_seqs *S) {
+static int64_t tree_hstride(const msa_seqs *S, int wclass) {
+    return needs_passes(S->max_len, wclass) ? ((int64_t)S->max_len + 15) / 16 : 0;
+}
+
+// forced > 0 selects the class (autotuning); else the tuning table's entry
+// for (MSA_TUNE_TREE, sigma, pattern words) if it is an admissible class,
+// else the default.  Admissible: a tree class within class_within_passes.
+static TreePlan plan_tree(const msa_seqs *S, int forced) {
     TreePlan p;
     p.stride = staged_stride(S->max_len);
-    p.wclass = wmax_class(S->max_len);
+    const int words = (int)std::max<int64_t>(1, ((int64_t)S->max_len + 63) / 64);
+    const int tuned = tuned_value(MSA_TUNE_TREE, S->sigma, words, 0);
+    p.wclass = forced > 0 ? forced
+               : (is_tree_class(tuned) && class_within_passes(S->max_len, tuned))
+                   ? tuned
+                   : wmax_class(S->max_len);
     p.grid = tree_grid(p.wclass);
-    p.hstride = needs_passes(S->max_len, p.wclass) ? ((int64_t)S->max_len + 15) / 16 : 0;
+    p.hstride = tree_hstride(S, p.wclass);
+    p.hbuf_dwords = 0;
+    for (int c : kTreeClasses) {
+        if (!class_within_passes(S->max_len, c)) continue;
+        p.hbuf_dwords = std::max(p.hbuf_dwords,
+                                 (size_t)tree_grid(c) * kWave * (size_t)tree_hstride(S, c));
+    }
     return p;
 }
 
@@ -750,7 +769,7 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<int32_t>(n + 1);           // dl
     al.template take<int32_t>(n + 1);           // dr
     al.template take<uint32_t>(1);              // counter
-    if (p.hstride) al.template take<uint32_t>((size_t)p.grid * kWave * p.hstride);
+    if (p.hbuf_dwords) al.template take<uint32_t>(p.hbuf_dwords);
     al.template take<int64_t>(n + 1);           // candidate counts
     al.template take<int64_t>(n + 1);           // candidate offsets
     al.template take<int32_t>(n);               // candidates
@@ -768,14 +787,14 @@ extern "C" {
 size_t tree_workspace_bytes(const msa_seqs *S) {
     if (check_seqs(S)) return 0;
     Sizer sz;
-    tree_layout(sz, S, plan_tree(S));
+    tree_layout(sz, S, plan_tree(S, 0));
     return sz.total();
 }
 
 static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
                       int32_t exact_below, const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
-                      int32_t *d_status, hipStream_t s) {
+                      int32_t *d_status, hipStream_t s, int forced) {
     int rc;
     if ((rc = check_seqs(S))) return rc;
     if (T == nullptr || n_nodes == nullptr) return MSA_EINVAL;
@@ -785,7 +804,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     if (!T->parent || !T->left || !T->right || !T->center || !T->lpole || !T->rpole ||
         !T->depth || !T->mstart || !T->mcount || !T->perm || ws == nullptr)
         return MSA_EINVAL;
-    const TreePlan p = plan_tree(S);
+    const TreePlan p = plan_tree(S, forced);
     Sizer sz;
     tree_layout(sz, S, p);
     if (ws_bytes < sz.total()) return MSA_ENOSPC;
@@ -814,7 +833,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.dl = cv.take<int32_t>(n + 1);
     a.dr = cv.take<int32_t>(n + 1);
     a.counter = cv.take<uint32_t>(1);
-    a.hbuf = p.hstride ? cv.take<uint32_t>((size_t)p.grid * kWave * p.hstride) : nullptr;
+    a.hbuf = p.hbuf_dwords ? cv.take<uint32_t>(p.hbuf_dwords) : nullptr;
     a.hstride = p.hstride;
     a.ncand = cv.take<int64_t>(n + 1);
     a.coff = cv.take<int64_t>(n + 1);
@@ -882,7 +901,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
 
 int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
                void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
-    return build_impl(S, nullptr, 0, 0, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status, s);
+    return build_impl(S, nullptr, 0, 0, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status, s, 0);
 }
 
 int tree_build_pruned(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
@@ -893,7 +912,53 @@ int tree_build_pruned(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
         emb_q0 > kMaxEmbOffset)
         return MSA_EINVAL;
     return build_impl(S, emb, emb_q0, topk, exact_below, T, n_nodes, use_graph, ws, ws_bytes,
-                      d_status, s);
+                      d_status, s, 0);
+}
+
+int msa_autotune_tree(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
+                      void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
+                      int32_t *d_status, hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(S))) return rc;
+    if (best == nullptr || best_ms == nullptr || reps < 1 || S->n < 2) return MSA_EINVAL;
+    const int words = (int)std::max<int64_t>(1, ((int64_t)S->max_len + 63) / 64);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MSA_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MSA_EDEVICE;
+    }
+    int bc = 0;
+    float bms = 0.0f;
+    rc = MSA_OK;
+    for (int c : kTreeClasses) {
+        if (!class_within_passes(S->max_len, c)) continue;
+        if ((rc = build_impl(S, nullptr, 0, 0, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status,
+                             s, c)))
+            break;   // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
+        for (int r = 0; r < reps && rc == MSA_OK; ++r)
+            rc = build_impl(S, nullptr, 0, 0, 0, T, n_nodes, use_graph, ws, ws_bytes, d_status,
+                            s, c);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = MSA_EDEVICE;
+            break;
+        }
+        ms /= (float)reps;
+        if (bc == 0 || ms < bms) {
+            bc = c;
+            bms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = bc;
+    *best_ms = bms;
+    return msa_tune_set(MSA_TUNE_TREE, S->sigma, words, bc);
 }
 
 int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
@@ -912,7 +977,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     if (S->n == 0 || n_nodes == 0) return n_nodes == 0 ? MSA_OK : MSA_EINVAL;
     if (S->n >= (1 << 24)) return MSA_ERANGE;
     if (n_nodes > 2 * S->n - 1) return MSA_EINVAL;
-    const TreePlan p = plan_tree(S);
+    const TreePlan p = plan_tree(S, 0);
     Sizer sz;
     tree_layout(sz, S, p);
     if (ws_bytes < sz.total()) return MSA_ENOSPC;
@@ -970,7 +1035,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.dl = cv.take<int32_t>(n + 1);
     a.dr = cv.take<int32_t>(n + 1);
     a.counter = cv.take<uint32_t>(1);
-    a.hbuf = p.hstride ? cv.take<uint32_t>((size_t)p.grid * kWave * p.hstride) : nullptr;
+    a.hbuf = p.hbuf_dwords ? cv.take<uint32_t>(p.hbuf_dwords) : nullptr;
     a.hstride = p.hstride;
     a.ncand = cv.take<int64_t>(n + 1);
     a.coff = cv.take<int64_t>(n + 1);

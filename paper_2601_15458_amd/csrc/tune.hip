@@ -7,6 +7,8 @@
 //                     value = words per pass of the kernel variant.
 //   MSA_TUNE_NW  (1): bin = wavefronts per pair ceil(ceil(max_len_A / 32) / 64);
 //                     value = steps between workgroup barriers of the fill.
+//   MSA_TUNE_TREE (2): bin = pattern words ceil(max_len / 64) of the set;
+//                     value = words per pass of the tree build's kernels.
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -26,11 +28,13 @@ std::map<std::tuple<int, int, int>, int> g_table;
 bool valid_value(int kind, int value) {
     if (kind == MSA_TUNE_LEV) return is_lev_class(value);
     if (kind == MSA_TUNE_NW) return value == 16 || value == 32 || value == 64;
+    if (kind == MSA_TUNE_TREE) return is_tree_class(value);
     return false;
 }
 
 bool valid_key(int kind, int sigma, int bin) {
-    return (kind == MSA_TUNE_LEV || kind == MSA_TUNE_NW) && sigma >= 2 && sigma <= 33 &&
+    return (kind == MSA_TUNE_LEV || kind == MSA_TUNE_NW || kind == MSA_TUNE_TREE) &&
+           sigma >= 2 && sigma <= 33 &&
            bin >= 1 && bin <= (1 << 20);
 }
 
@@ -84,6 +88,11 @@ int msa_tune_candidates(int32_t kind, int32_t *values, int32_t cap, int32_t *cou
     int n = 0;
     if (kind == MSA_TUNE_LEV) {
         for (int c : kLevClasses) {
+            if (n < cap) values[n] = c;
+            ++n;
+        }
+    } else if (kind == MSA_TUNE_TREE) {
+        for (int c : kTreeClasses) {
             if (n < cap) values[n] = c;
             ++n;
         }

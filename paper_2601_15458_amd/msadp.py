@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsadp.so")
 
 MSA_OK, MSA_EINVAL, MSA_ERANGE, MSA_ENOSPC, MSA_EDEVICE = 0, -1, -2, -3, -4
-MSA_TUNE_LEV, MSA_TUNE_NW = 0, 1
+MSA_TUNE_LEV, MSA_TUNE_NW, MSA_TUNE_TREE = 0, 1, 2
 DS_NAMES = {0: "ok", 1: "symbol code >= sigma", 2: "sequence index out of range",
             3: "length out of range", 4: "output capacity too small"}
 
@@ -72,6 +72,8 @@ SIGNATURES = {
                                    C.POINTER(C.c_float), P, P]),
     "msa_autotune_nw": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, C.c_size_t, C.c_int32,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
+    "msa_autotune_tree": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t,
+                                    C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
     "cnn_param_bytes": (C.c_size_t, []),
     "cnn_set_params": (C.c_int, [P, P, P, P]),
     "cnn_get_params": (C.c_int, [P, P, P, P, P, P]),
@@ -588,6 +590,23 @@ def autotune_nw(nb: "NwBatch", reps: int = 2, stream=None):
                                _ptr(nb.st.t), _stream(stream))
     _check(rc, "msa_autotune_nw")
     nb.st.check("msa_autotune_nw")
+    return best.value, ms.value
+
+
+def autotune_tree(S: Seqs, reps: int = 1, use_graph=True, stream=None):
+    """Time the exact tree build per kernel class on S and keep the fastest
+    in the table; returns (words per pass, ms per build)."""
+    if use_graph and stream is None:
+        stream = torch.cuda.Stream()
+    tb = TreeBuilder(S, use_graph)
+    best, ms, nn = C.c_int32(0), C.c_float(0.0), C.c_int32(0)
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        rc = lib().msa_autotune_tree(C.byref(tb.ss), C.byref(tb.ts), C.byref(nn),
+                                     int(tb.use_graph), _ptr(tb.ws), tb.wsb, int(reps),
+                                     C.byref(best), C.byref(ms), _ptr(tb.st.t), _stream(stream))
+    _check(rc, "msa_autotune_tree")
+    torch.cuda.synchronize()
+    tb.st.check("msa_autotune_tree")
     return best.value, ms.value
 
 

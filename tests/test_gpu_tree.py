@@ -107,3 +107,95 @@ def test_protein_subset_alignment():
     rng = np.random.default_rng(34)
     sub = synth.subset(d, rng.choice(d["n"], size=150, replace=False))
     _check_msa(sub["codes"], sub["offsets"], 20, use_graph=True)
+
+
+def _check_structure(t, codes, off):
+    """Alg. 1's tree shape at any size: breadth-first numbering, children
+    partition their parent's member range, poles and centre are members,
+    and a leaf of several members holds copies of one sequence."""
+    n = len(off) - 1
+    k = int(t["n_nodes"])
+    assert 1 <= k <= 2 * n - 1
+    perm = t["perm"].astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    rank = np.empty(n, np.int64)
+    rank[perm] = np.arange(n)
+    P, L, R = (t[f].astype(np.int64) for f in ("parent", "left", "right"))
+    ms, mc, dep = (t[f].astype(np.int64) for f in ("mstart", "mcount", "depth"))
+    assert P[0] == -1 and dep[0] == 0 and ms[0] == 0 and mc[0] == n
+    internal = np.flatnonzero(L >= 0)
+    assert np.array_equal(R[internal], L[internal] + 1)
+    assert np.array_equal(L[internal], 1 + 2 * np.arange(len(internal)))   # BFS ids
+    assert (P[L[internal]] == internal).all() and (P[R[internal]] == internal).all()
+    assert (dep[L[internal]] == dep[internal] + 1).all()
+    assert (ms[L[internal]] == ms[internal]).all()
+    assert (ms[R[internal]] == ms[internal] + mc[L[internal]]).all()
+    assert (mc[L[internal]] + mc[R[internal]] == mc[internal]).all()
+    assert (mc[L[internal]] >= 1).all() and (mc[R[internal]] >= 1).all()
+    for f in ("center", "lpole", "rpole"):
+        pos = rank[t[f][internal].astype(np.int64)]
+        assert ((pos >= ms[internal]) & (pos < ms[internal] + mc[internal])).all(), f
+    leaves = np.flatnonzero(L < 0)
+    assert (R[leaves] < 0).all()
+    for v in leaves[mc[leaves] > 1]:
+        mem = perm[ms[v]: ms[v] + mc[v]]
+        first = codes[off[mem[0]]: off[mem[0] + 1]]
+        for x in mem[1:]:
+            assert np.array_equal(codes[off[x]: off[x + 1]], first)
+    return rank
+
+
+def _dist_from(codes, off, x, members):
+    return orc.lev_pairs(codes, off, codes, off, np.full(len(members), x), members)
+
+
+def test_protein_workload_full_size_sampled():
+    """The 20,000-sequence protein set (200 families, lognormal lengths) at
+    full size, with the class autotuned and the levels replayed from a HIP
+    graph: the whole tree's shape; the root's poles and split from oracle
+    distances; the root centre's row sum against sampled members; and
+    sampled smaller nodes re-derived by the oracle's Alg. 1 step."""
+    M = _msadp()
+    d = synth.protein_tree()
+    codes, off, n = d["codes"], d["offsets"], d["n"]
+    assert n == 20000
+    S = M.to_device(codes, off, d["sigma"])
+    M.tune_clear()
+    try:
+        best, ms = M.autotune_tree(S, reps=1)
+        print(f"[tree] protein {n}: autotuned class {best} ({ms:.0f} ms per build)", flush=True)
+        t = M.tree_build(S, use_graph=True)
+    finally:
+        M.tune_clear()
+    print(f"[tree] protein {n}: {t['n_nodes']} nodes; shape", flush=True)
+    _check_structure(t, codes, off)
+    allm = np.arange(n)
+    c, l, r = int(t["center"][0]), int(t["lpole"][0]), int(t["rpole"][0])
+    print("[tree] root poles and split from oracle distances", flush=True)
+    dc = _dist_from(codes, off, c, allm)
+    assert l == int(np.argmax(dc))
+    dl = _dist_from(codes, off, l, allm)
+    assert r == int(np.argmax(dl))
+    dr = _dist_from(codes, off, r, allm)
+    lc = int(t["left"][0])
+    in_left = np.zeros(n, bool)
+    in_left[t["perm"][t["mstart"][lc]: t["mstart"][lc] + t["mcount"][lc]]] = True
+    assert np.array_equal(in_left, dl <= dr)
+    rng = np.random.default_rng(35)
+    others = rng.choice(np.setdiff1d(allm, [c]), size=12, replace=False)
+    print("[tree] root centre's row sum against 12 sampled members", flush=True)
+    for x in others:
+        assert int(dc.sum()) <= int(_dist_from(codes, off, int(x), allm).sum()), x
+    internal = np.flatnonzero((t["left"] >= 0) & (t["mcount"] >= 20) & (t["mcount"] <= 200))
+    pick = rng.choice(internal, size=min(8, len(internal)), replace=False)
+    for v in pick:
+        mem = t["perm"][t["mstart"][v]: t["mstart"][v] + t["mcount"][v]]
+        print(f"[tree] node {v} ({len(mem)} members) against the oracle", flush=True)
+        want = orc.select(codes, off, mem)
+        assert (int(t["center"][v]), int(t["lpole"][v]), int(t["rpole"][v])) == want, v
+        lv = int(t["left"][v])
+        got_left = np.sort(t["perm"][t["mstart"][lv]: t["mstart"][lv] + t["mcount"][lv]])
+        ms_ = np.sort(mem)
+        dlv = _dist_from(codes, off, want[1], ms_)
+        drv = _dist_from(codes, off, want[2], ms_)
+        assert np.array_equal(got_left, ms_[dlv <= drv]), v

@@ -117,3 +117,63 @@ def test_autotune_nw():
     assert best in (16, 32, 64) and ms > 0
     ws, _ = orc.nw_pairs(ca, oa, cb, ob, ia, ia)
     assert np.array_equal(nb.r.score.cpu().numpy().astype(np.int64), ws)
+
+
+def _tree_matches_oracle(got, codes, off, want=None):
+    want = orc.tree(codes, off) if want is None else want
+    assert got["n_nodes"] == want["n_nodes"]
+    for f in orc.TREE_FIELDS:
+        assert np.array_equal(got[f].astype(np.int64), want[f].astype(np.int64)), f
+    assert np.array_equal(got["perm"], want["perm"])
+
+
+@pytest.mark.parametrize("wclass", [4, 8, 16, 24, 32])
+def test_tree_every_class(wclass):
+    """Lengths 40-500 (8 words): every tree class is admissible; class 4
+    runs two passes through the carry buffer."""
+    M = _msadp()
+    codes, off = _long_set(900 + wclass, 70, 40, 500)
+    S = M.to_device(codes, off, 4)
+    M.tune_set(M.MSA_TUNE_TREE, 4, M.lev_words_bin(S), wclass)
+    print(f"[tune] tree class {wclass}", flush=True)
+    got = M.tree_build(S, use_graph=(wclass % 16 == 0))
+    _tree_matches_oracle(got, codes, off)
+
+
+@pytest.mark.parametrize("wclass", [4, 16, 24])
+def test_tree_long_patterns_classes(wclass):
+    """Lengths 40-1700 (27 words): 16 and 24 take two passes; 4 would take
+    seven and is ignored (the default runs)."""
+    M = _msadp()
+    codes, off = _long_set(950 + wclass, 48, 40, 1700)
+    S = M.to_device(codes, off, 4)
+    M.tune_set(M.MSA_TUNE_TREE, 4, M.lev_words_bin(S), wclass)
+    print(f"[tune] tree long class {wclass}", flush=True)
+    _tree_matches_oracle(M.tree_build(S), codes, off)
+
+
+def test_pruned_tree_tuned_class():
+    M = _msadp()
+    import torch
+    codes, off = _long_set(990, 60, 40, 1700)
+    n = len(off) - 1
+    S = M.to_device(codes, off, 4)
+    M.tune_set(M.MSA_TUNE_TREE, 4, M.lev_words_bin(S), 16)
+    emb = np.random.default_rng(990).standard_normal((n, 128)).astype(np.float32)
+    demb = torch.from_numpy(emb).to(S.codes.device)
+    print("[tune] pruned tree, class 16", flush=True)
+    got = M.tree_build(S, emb=demb, topk=4, exact_below=8, emb_offset=0.25)
+    want = orc.tree_pruned(codes, off, emb, topk=4, exact_below=8,
+                           emb_q0=M.emb_offset_q(0.25))
+    _tree_matches_oracle(got, codes, off, want)
+
+
+def test_autotune_tree():
+    M = _msadp()
+    codes, off = _long_set(995, 120, 40, 1700)
+    S = M.to_device(codes, off, 4)
+    best, ms = M.autotune_tree(S, reps=1)
+    print(f"[tune] autotune tree -> class {best}, {ms:.3f} ms", flush=True)
+    assert best in (16, 24, 32) and ms > 0
+    assert M.tune_get(M.MSA_TUNE_TREE, 4, M.lev_words_bin(S)) == best
+    _tree_matches_oracle(M.tree_build(S, use_graph=True), codes, off)

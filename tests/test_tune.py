@@ -21,6 +21,7 @@ def test_candidates():
     M = _msadp()
     assert M.tune_candidates(M.MSA_TUNE_LEV) == [4, 8, 16, 20, 24, 28, 32]
     assert M.tune_candidates(M.MSA_TUNE_NW) == [16, 32, 64]
+    assert M.tune_candidates(M.MSA_TUNE_TREE) == [4, 8, 16, 24, 32]
 
 
 def test_set_get_clear():
@@ -28,7 +29,10 @@ def test_set_get_clear():
     assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 0
     M.tune_set(M.MSA_TUNE_LEV, 4, 25, 28)
     M.tune_set(M.MSA_TUNE_NW, 4, 3, 64)
+    M.tune_set(M.MSA_TUNE_TREE, 20, 32, 16)
     assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 28
+    assert M.tune_get(M.MSA_TUNE_TREE, 20, 32) == 16
+    assert M.tune_get(M.MSA_TUNE_TREE, 4, 25) == 0
     assert M.tune_get(M.MSA_TUNE_LEV, 5, 25) == 0
     assert M.tune_get(M.MSA_TUNE_NW, 4, 3) == 64
     M.tune_clear()
@@ -38,7 +42,8 @@ def test_set_get_clear():
 @pytest.mark.parametrize("kind,sigma,bin_,value", [
     (0, 4, 25, 30),      # not a word class
     (1, 4, 3, 48),       # not a barrier interval
-    (2, 4, 3, 32),       # unknown kind
+    (2, 4, 3, 20),       # a pair-kernel class the tree build does not have
+    (3, 4, 3, 32),       # unknown kind
     (0, 1, 3, 32),       # alphabet too small
     (0, 4, 0, 32),       # empty bin
 ])
@@ -54,14 +59,17 @@ def test_export_import_round_trip():
     M.tune_set(M.MSA_TUNE_LEV, 4, 25, 28)
     M.tune_set(M.MSA_TUNE_LEV, 20, 3, 4)
     M.tune_set(M.MSA_TUNE_NW, 4, 5, 16)
+    M.tune_set(M.MSA_TUNE_TREE, 20, 32, 24)
     text = M.tune_export()
     doc = json.loads(text)
-    assert sorted(map(tuple, doc["entries"])) == [(0, 4, 25, 28), (0, 20, 3, 4), (1, 4, 5, 16)]
+    assert sorted(map(tuple, doc["entries"])) == [(0, 4, 25, 28), (0, 20, 3, 4), (1, 4, 5, 16),
+                                                  (2, 20, 32, 24)]
     M.tune_clear()
     M.tune_import(text)
     assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 28
     assert M.tune_get(M.MSA_TUNE_LEV, 20, 3) == 4
     assert M.tune_get(M.MSA_TUNE_NW, 4, 5) == 16
+    assert M.tune_get(M.MSA_TUNE_TREE, 20, 32) == 24
 
 
 def test_import_rejects_other_arch_and_bad_entries():

@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_nw_fill_dna512.md), by launch variant; None for a variant not measured.
 LEV_TRAFFIC = {16: 11311.2e3 * 1024, 20: 4338.5e3 * 1024, 24: 2165.1e3 * 1024,
                28: 2071.8e3 * 1024, 32: 2095.3e3 * 1024}
-NW_FILL_TRAFFIC = {16: 7923.3e3 * 1024, 32: 8019.3e3 * 1024}
+NW_FILL_TRAFFIC = {}
 
 
 def parse():
@@ -415,6 +415,7 @@ def bench_pruned(msadp, synth, torch, args):
     points = [("cnn", args.topk, 0), ("cnn_raw", args.topk, 0), ("shortest", args.topk, 0),
               ("random", args.topk, 0),
               ("cnn", args.topk, args.exact_below), ("shortest", args.topk, args.exact_below),
+              ("cnn", args.topk, 4 * args.exact_below),
               ("cnn", args.topk, 8 * args.exact_below),
               ("shortest", args.topk, 8 * args.exact_below)]
     if args.points:

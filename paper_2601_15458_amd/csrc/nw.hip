@@ -70,11 +70,78 @@ struct FillArgs {
 // DPP control: shift the whole wavefront right by one lane.
 constexpr int kDppWaveShr1 = 0x138;
 
+typedef __attribute__((address_space(1))) uint64_t global_u64;
+
+// State of one lane of the fill between steps.
+struct FillLane {
+    uint32_t Pv, Mv;       // vertical delta vectors of the lane's word
+    uint32_t xout;         // packet sent to the next lane: symbol << 8 | hn << 1 | hp
+    uint32_t accp, accn;   // +1 / -1 horizontal deltas leaving the last row
+    uint64_t raddr;        // byte address of the lane's record at the current step
+};
+
+// One round of kRound steps of a wavefront.  kSteady: every lane's column
+// j = t - shift lies in [0, n) for the whole round, so no step needs a
+// range check.  kLast: the wavefront holding the pattern's last word (it
+// counts the score's deltas and feeds no ring; the others feed the ring and
+// count nothing).
+template <int P, int R, bool kSteady, bool kLast>
+__device__ __forceinline__ void fill_round(FillLane &L, const uint32_t (&plane)[P],
+                                           uint32_t bpos, uint32_t feed, int t0, int shift,
+                                           int n, bool word_ok, uint64_t rec_step,
+                                           uint32_t *ring_out, int lane) {
+    constexpr int kRing = Round<R>::kRing;
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const uint32_t sin = __builtin_amdgcn_readlane(feed, s);
+        const uint32_t xin = __builtin_amdgcn_update_dpp(sin, L.xout, kDppWaveShr1, 0xF, 0xF,
+                                                          false);
+        const uint32_t tc = (xin >> 8) & 0xFFu;
+        const uint32_t hp = xin & 1u, hn = (xin >> 1) & 1u;
+        // neq: bit i set iff pattern row i differs from tc
+        uint32_t neq = plane[0] ^ (uint32_t)(-(int32_t)(tc & 1u));
+#pragma unroll
+        for (int b = 1; b < P; ++b)
+            neq = bop3<NwLut::ACC_XOR>(neq, plane[b], (uint32_t)(-(int32_t)((tc >> b) & 1u)));
+        const uint32_t Pv = L.Pv, Mv = L.Mv;
+        const uint32_t eqm = bop3<NwLut::NOTA_OR_B>(neq, hn, 0u);
+        const uint32_t xv = bop3<NwLut::NOTA_OR_B2>(neq, Mv, 0u);
+        const uint32_t sum = (eqm & Pv) + Pv;
+        const uint32_t xh = bop3<NwLut::XOR_OR>(sum, Pv, eqm);
+        const uint32_t ph = bop3<NwLut::PH>(xh, Pv, Mv);
+        const uint32_t mh = Pv & xh;
+        const uint32_t mcode = bop3<NwLut::MCODE>(neq, xh, Mv);
+        const uint32_t hpo = __builtin_amdgcn_ubfe(ph, bpos, 1);
+        const uint32_t hno = __builtin_amdgcn_ubfe(mh, bpos, 1);
+        L.xout = (xin & 0xFF00u) | hpo | (hno << 1);
+        const uint32_t Ph = (ph << 1) | hp, Mh = (mh << 1) | hn;
+        const uint32_t pv_new = bop3<NwLut::PV>(Mh, xv, Ph);
+        const uint32_t mv_new = Ph & xv;
+        const int j = t0 + s - shift;
+        const bool in = kSteady || (j >= 0 && j < n);
+        // a lane keeps its initial column state until its first column
+        L.Pv = kSteady || j >= 0 ? pv_new : Pv;
+        L.Mv = kSteady || j >= 0 ? mv_new : Mv;
+        // record (M plane, U plane) as one 8-byte store
+        if ((!kLast || word_ok) && in)
+            *(global_u64 *)L.raddr = ((uint64_t)L.Pv << 32) | mcode;
+        if (kLast) {
+            if (in) {
+                L.accp += hpo;
+                L.accn += hno;
+            }
+        } else if (lane == 63 && in) {
+            ring_out[j & (kRing - 1)] = L.xout;
+        }
+        L.raddr += rec_step;
+    }
+}
+
 template <int P, int R>
 __device__ void nw_fill_pair(const FillArgs &a, int64_t p, uint32_t *ring) {
     constexpr int kRound = Round<R>::kRound, kLag = Round<R>::kLag, kRing = Round<R>::kRing;
     const int lane = lane_id();
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int32_t x = a.ia[p], y = a.ib[p];
     if (x < 0 || x >= a.A.n || y < 0 || y >= a.B.n) {
         if (threadIdx.x == 0) set_status(a.st, MSA_DS_INDEX);
@@ -119,14 +186,17 @@ __device__ void nw_fill_pair(const FillArgs &a, int64_t p, uint32_t *ring) {
     uint32_t *ring_in = ring + (w - 1) * kRing;   // written by wavefront w-1
     uint32_t *ring_out = ring + w * kRing;
 
-    uint32_t Pv = ~0u, Mv = 0u;
-    uint32_t acc = 0;          // lo 16 bits: count of +1, hi 16 bits: count of -1
-    uint32_t xout = 0;
     const int total = n + 63 + kLag * (nw - 1);
     const int rounds = (total + kRound - 1) / kRound;
     const int shift = kLag * w + lane;       // column j = t - shift
-    // record index of (t): (j + g) * W + g with j + g = t - (kLag - 64) * w
-    const int64_t sbase = -(int64_t)(kLag - 64) * w;
+    // record index at step t: (j + g) * W + g with j + g = t - (kLag - 64) * w;
+    // the address advances by W records a step (unsigned wrap-around keeps
+    // the start, which may lie before the region, exact)
+    const int64_t rec0 = -(int64_t)(kLag - 64) * w * W + g;
+    FillLane L{~0u, 0u, 0u, 0u, 0u,
+               (uint64_t)(uintptr_t)tbp + (uint64_t)(rec0 * (int64_t)sizeof(uint2))};
+    const uint64_t rec_step = (uint64_t)W * sizeof(uint2);
+    const bool last = w == nw - 1;
     for (int rnd = 0; rnd < rounds; ++rnd) {
         const int t0 = rnd * kRound;
         // feed[l] = packet entering lane 0 at step t0 + l (l < kRound)
@@ -141,44 +211,25 @@ __device__ void nw_fill_pair(const FillArgs &a, int64_t p, uint32_t *ring) {
                 else feed = ring_in[jj & (kRing - 1)];
             }
         }
-        for (int s = 0; s < kRound; ++s) {
-            const int t = t0 + s;
-            const uint32_t sin = __builtin_amdgcn_readlane(feed, s);
-            const uint32_t xin = __builtin_amdgcn_update_dpp(sin, xout, kDppWaveShr1, 0xF, 0xF,
-                                                              false);
-            const uint32_t tc = (xin >> 8) & 0xFFu;
-            const uint32_t hp = xin & 1u, hn = (xin >> 1) & 1u;
-            // neq: bit i set iff pattern row i differs from tc
-            uint32_t neq = plane[0] ^ (uint32_t)(-(int32_t)(tc & 1u));
-#pragma unroll
-            for (int b = 1; b < P; ++b)
-                neq = bop3<NwLut::ACC_XOR>(neq, plane[b], (uint32_t)(-(int32_t)((tc >> b) & 1u)));
-            const uint32_t eqm = bop3<NwLut::NOTA_OR_B>(neq, hn, 0u);
-            const uint32_t xv = bop3<NwLut::NOTA_OR_B2>(neq, Mv, 0u);
-            const uint32_t sum = (eqm & Pv) + Pv;
-            const uint32_t xh = bop3<NwLut::XOR_OR>(sum, Pv, eqm);
-            const uint32_t ph = bop3<NwLut::PH>(xh, Pv, Mv);
-            const uint32_t mh = Pv & xh;
-            const uint32_t mcode = bop3<NwLut::MCODE>(neq, xh, Mv);
-            const uint32_t hpo = __builtin_amdgcn_ubfe(ph, bpos, 1);
-            const uint32_t hno = __builtin_amdgcn_ubfe(mh, bpos, 1);
-            xout = (xin & 0xFF00u) | hpo | (hno << 1);
-            const uint32_t Ph = (ph << 1) | hp, Mh = (mh << 1) | hn;
-            const int j = t - shift;
-            // a lane keeps its initial column state until its first column
-            const uint32_t pv_new = bop3<NwLut::PV>(Mh, xv, Ph);
-            const uint32_t mv_new = Ph & xv;
-            Pv = j >= 0 ? pv_new : Pv;
-            Mv = j >= 0 ? mv_new : Mv;
-            if (word_ok && j >= 0 && j < n) {
-                const int64_t rec = ((int64_t)t + sbase) * W + g;
-                ((uint2 *)tbp)[rec] = make_uint2(mcode, Pv);
-                acc += hpo + (hno << 16);
-                if (lane == 63 && w + 1 < nw) ring_out[j & (kRing - 1)] = xout;
-            }
+        // columns of the round: lane 63 at its first step to lane 0 at its last
+        const bool steady = t0 - kLag * w - 63 >= 0 && t0 + kRound - 1 - kLag * w < n;
+        if (steady) {
+            if (last)
+                fill_round<P, R, true, true>(L, plane, bpos, feed, t0, shift, n, word_ok,
+                                             rec_step, ring_out, lane);
+            else
+                fill_round<P, R, true, false>(L, plane, bpos, feed, t0, shift, n, word_ok,
+                                              rec_step, ring_out, lane);
+        } else {
+            if (last)
+                fill_round<P, R, false, true>(L, plane, bpos, feed, t0, shift, n, word_ok,
+                                              rec_step, ring_out, lane);
+            else
+                fill_round<P, R, false, false>(L, plane, bpos, feed, t0, shift, n, word_ok,
+                                               rec_step, ring_out, lane);
         }
     }
-    if (g == W - 1 && a.score) a.score[p] = m + (int)(acc & 0xFFFFu) - (int)(acc >> 16);
+    if (g == W - 1 && a.score) a.score[p] = m + (int)L.accp - (int)L.accn;
 }
 
 template <int P, int R>

@@ -57,6 +57,23 @@ def test_word_and_wavefront_boundaries():
     _check(ca, oa, cb, ob, 4, np.array(ia), np.array(ib))
 
 
+def test_texts_of_maximum_length():
+    """Texts at the library's 65,535-symbol limit (and one above it, which
+    is refused on the host), with one and two wavefronts per pattern."""
+    M = _msadp()
+    rng = np.random.default_rng(12)
+    A = [rng.integers(0, 4, size=L).astype(np.uint8) for L in (40, 2100)]
+    B = [rng.integers(0, 4, size=L).astype(np.uint8) for L in (65535, 65000)]
+    B.append(synth.mutate(rng, np.tile(A[1], 30), 4, 0.05, 0.01, 0.01)[:65535])
+    ca, oa = synth.to_csr(A)
+    cb, ob = synth.to_csr(B)
+    _check(ca, oa, cb, ob, 4, np.array([0, 1, 0, 1]), np.array([0, 1, 2, 2]))
+    cl, ol = synth.to_csr([rng.integers(0, 4, size=65536).astype(np.uint8)])
+    with pytest.raises(M.MsaError) as ex:
+        M.nw_batch(M.to_device(ca, oa, 4), M.to_device(cl, ol, 4), np.array([0]), np.array([0]))
+    assert ex.value.code == M.MSA_ERANGE
+
+
 def test_empty_sides():
     A = [np.zeros(0, np.uint8), np.array([1, 2], np.uint8), np.array([3], np.uint8)]
     ca, oa = synth.to_csr(A)

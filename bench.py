@@ -41,7 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_nw_fill_dna512.md), by launch variant; None for a variant not measured.
 LEV_TRAFFIC = {16: 11311.2e3 * 1024, 20: 4338.5e3 * 1024, 24: 2165.1e3 * 1024,
                28: 2071.8e3 * 1024, 32: 2095.3e3 * 1024}
-NW_FILL_TRAFFIC = {}
+NW_FILL_TRAFFIC = {16: (2 * 4733 + 7885300) * 1024, 32: (2 * 6616 + 7974700) * 1024,
+                   64: (2 * 242080 + 8268300) * 1024}
 
 
 def parse():

@@ -55,7 +55,8 @@ enum {
     MSA_DS_SYMBOL = 1,     /* a symbol code >= sigma                      */
     MSA_DS_INDEX = 2,      /* a sequence index outside [0, n)             */
     MSA_DS_LENGTH = 3,     /* a length < 0 or > max_len                   */
-    MSA_DS_CAPACITY = 4    /* an output region smaller than required      */
+    MSA_DS_CAPACITY = 4,   /* an output region smaller than required      */
+    MSA_DS_VALUE = 5       /* a non-finite embedding coordinate           */
 };
 
 typedef struct msa_seqs {
@@ -168,10 +169,14 @@ int tree_build(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t u
  * float[n][128], row i = embedding of input i, e.g. from cnn_embed, whose
  * distances predict f divided by the pair's mean length) ranks every member
  * x by E(x) = sum over the cluster, y = x included, of
- * (q(x, y) + emb_q0) (|x| + |y|), with q = the Euclidean distance
- * min(||e_x - e_y||, 2^15) in units of 2^-16 (squares added coordinate by
- * coordinate in float32 without fused multiply-add, rounded to nearest) and
- * emb_q0 <= 2^31 a calibration offset in the same units (the intercept over
+ * (q(x, y) + emb_q0) (|x| + |y|), with q the Euclidean distance of the
+ * quantized embeddings, capped at 2^15, in units of 2^-16: with M = max |e|
+ * over all n x 128 coordinates, s = 6 - floor(log2 M) limited to [-20, 40]
+ * (40 when M < 2^-34), each coordinate's code is rint(e 2^s) limited to
+ * +-127, and q = rint(min(sqrt(D) 2^-s, 2^15) 2^16) in float32 (correctly
+ * rounded square root) with D the exact integer squared distance of the
+ * codes; a non-finite coordinate sets MSA_DS_VALUE.
+ * emb_q0 <= 2^31 is a calibration offset in the same units (the intercept over
  * the slope of a linear fit of the true normalized distance on the
  * predicted one, which shrinks a noisy predictor towards the length prior);
  * the topk members with the least (E, input index), 1 <= topk <= 1024, are

@@ -160,34 +160,64 @@ static int64_t dist_of(const uint8_t *codes, const int64_t *off, int32_t x, int3
     return orc_lev(codes + off[x], off[x + 1] - off[x], codes + off[y], off[y + 1] - off[y]);
 }
 
-/* Surrogate distance of two embeddings (128 floats each), in the exact
- * float32 steps the pruned medoid uses: |x|^2, |y|^2 and x.y each
- * accumulated from 0 by fused multiply-adds (one rounding each, fmaf) in
- * coordinate order; d2 = fma(-2, x.y, |x|^2 + |y|^2), negative values read
- * as 0; the square root capped at 2^15, then the value in units of 2^-16
- * rounded to the nearest integer (ties to even).  Rounding decides the
- * candidate ranking, so both sides take the same float32 steps; the
- * integer sums are then exact. */
-static float emb_dot(const float *a, const float *b) {
-    float acc = 0.0f;
-    for (int c = 0; c < 128; ++c) acc = fmaf(a[c], b[c], acc);
-    return acc;
+/* Surrogate distance of two embeddings (128 floats each).  The embeddings of
+ * the set are quantized once: with M the largest |e| over every coordinate
+ * of every row, s = 40 if M < 2^-34 (zero included), else s = 6 -
+ * floor(log2 M) limited to [-20, 40], so that M 2^s lies in [64, 128); each
+ * coordinate becomes the integer rint(e 2^s) limited to [-127, 127].  The
+ * distance of x and y is sqrt(D) 2^-s with D the squared Euclidean distance
+ * of their integer vectors (exact), in float32: the square root of D
+ * (correctly rounded; D < 2^24 is exact in float32), the product with 2^-s
+ * (exact), the cap at 2^15, then 2^16 times that rounded to the nearest
+ * integer (ties to even).  Rounding decides the candidate ranking, so both
+ * sides take these float32 steps; everything before them is integer and the
+ * sums after them are integers.  Embeddings are taken to be finite. */
+#define EMB_DIM 128
+
+static int emb_shift(const float *emb, int64_t count) {
+    float M = 0.0f;
+    for (int64_t i = 0; i < count; ++i) {
+        const float a = fabsf(emb[i]);
+        if (a > M) M = a;
+    }
+    if (!(M >= ldexpf(1.0f, 6 - 40))) return 40;
+    int E;
+    frexpf(M, &E);                 /* M = f 2^E with f in [0.5, 1): floor(log2 M) = E - 1 */
+    const int s = 6 - (E - 1);
+    return s < -20 ? -20 : (s > 40 ? 40 : s);
 }
 
-static uint64_t emb_dist_q(const float *ex, const float *ey) {
-    const float nx = emb_dot(ex, ex), ny = emb_dot(ey, ey), dot = emb_dot(ex, ey);
-    float d2 = fmaf(-2.0f, dot, nx + ny);
-    if (!(d2 > 0.0f)) d2 = 0.0f;
-    return (uint64_t)rintf(fminf(sqrtf(d2), 32768.0f) * 65536.0f);
+/* codes: int8[n][128]; returns s. */
+int32_t orc_emb_quantize(const float *emb, int64_t n, int8_t *codes) {
+    const int s = emb_shift(emb, n * EMB_DIM);
+    const float scale = ldexpf(1.0f, s);
+    for (int64_t i = 0; i < n * EMB_DIM; ++i) {
+        float v = rintf(emb[i] * scale);
+        if (v > 127.0f) v = 127.0f;
+        if (v < -127.0f) v = -127.0f;
+        codes[i] = (int8_t)v;
+    }
+    return s;
+}
+
+static uint64_t emb_dist_q(const int8_t *cx, const int8_t *cy, int shift) {
+    int64_t D = 0;
+    for (int c = 0; c < EMB_DIM; ++c) {
+        const int64_t d = (int64_t)cx[c] - (int64_t)cy[c];
+        D += d * d;
+    }
+    const float dist = sqrtf((float)D) * ldexpf(1.0f, -shift);
+    return (uint64_t)rintf(fminf(dist, 32768.0f) * 65536.0f);
 }
 
 /* The estimate of f(x, y) behind the ranking, in units of 2^-17: the
  * embedder predicts f divided by the pair's mean length, so the distance
  * plus the calibration offset q0 (units of 2^-16) is scaled by |x| + |y|. */
-static uint64_t emb_estimate(const int64_t *off, const float *emb, uint32_t q0, int32_t x,
-                             int32_t y) {
+static uint64_t emb_estimate(const int64_t *off, const int8_t *code, int shift, uint32_t q0,
+                             int32_t x, int32_t y) {
     const uint64_t len = (uint64_t)((off[x + 1] - off[x]) + (off[y + 1] - off[y]));
-    return (emb_dist_q(emb + (int64_t)x * 128, emb + (int64_t)y * 128) + q0) * len;
+    return (emb_dist_q(code + (int64_t)x * EMB_DIM, code + (int64_t)y * EMB_DIM, shift) + q0) *
+           len;
 }
 
 /* f(C[x], C[y]) for every y of the cluster. */
@@ -209,14 +239,14 @@ static int64_t *dist_row(const uint8_t *codes, const int64_t *off, const int32_t
  * (E, input index) are the candidates, else every member is one; c is the
  * candidate with the least exact sum of f over C (lowest input index on
  * ties). */
-void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
-                const float *emb, uint32_t emb_q0, int32_t topk, int32_t exact_below,
-                int32_t out[3]) {
+static void select_impl(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
+                        const int8_t *ecode, int eshift, uint32_t emb_q0, int32_t topk,
+                        int32_t exact_below, int32_t out[3]) {
     out[1] = out[2] = -1;
     if (k == 1) { out[0] = C[0]; return; }
     int64_t best = -1;
     int64_t *rowc;
-    if (emb == NULL) {
+    if (ecode == NULL) {
         /* geometric median over the whole cluster */
         int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k * k));
         #pragma omp parallel for schedule(dynamic, 1)
@@ -242,7 +272,7 @@ void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int6
         #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t x = 0; x < k; ++x)
             for (int64_t y = 0; y < k; ++y)
-                E[x] += emb_estimate(off, emb, emb_q0, C[x], C[y]);
+                E[x] += emb_estimate(off, ecode, eshift, emb_q0, C[x], C[y]);
         char *taken = (char *)calloc((size_t)k, 1);
         int64_t best_sum = 0;
         const int64_t nc = k <= exact_below ? k : (k < topk ? k : topk);
@@ -279,6 +309,21 @@ void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int6
     out[2] = C[rp];
 }
 
+/* emb: float[n_emb][128] of the whole input set (the quantization scale
+ * comes from all of it), or NULL for the full median. */
+void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
+                const float *emb, int64_t n_emb, uint32_t emb_q0, int32_t topk,
+                int32_t exact_below, int32_t out[3]) {
+    int8_t *ecode = NULL;
+    int eshift = 0;
+    if (emb != NULL) {
+        ecode = (int8_t *)malloc((size_t)(n_emb * EMB_DIM));
+        eshift = orc_emb_quantize(emb, n_emb, ecode);
+    }
+    select_impl(codes, off, C, k, ecode, eshift, emb_q0, topk, exact_below, out);
+    free(ecode);
+}
+
 /* Alg. 1 (Partition) with the choice of orc_select, then the split
  * L = {x : f(l, x) <= f(r, x)}, R = the rest, both in ascending order, and
  * breadth-first node numbering (L before R). */
@@ -295,12 +340,18 @@ static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, co
     msize[0] = n;
     parent[0] = -1; depth[0] = 0;
     int32_t n_nodes = 1;
+    int8_t *ecode = NULL;
+    int eshift = 0;
+    if (emb != NULL) {
+        ecode = (int8_t *)malloc((size_t)n * EMB_DIM);
+        eshift = orc_emb_quantize(emb, n, ecode);
+    }
     for (int32_t v = 0; v < n_nodes; ++v) {
         int64_t k = msize[v];
         int32_t *C = members[v];
         left[v] = right[v] = -1;
         int32_t clr[3];
-        orc_select(codes, off, C, k, emb, emb_q0, topk, exact_below, clr);
+        select_impl(codes, off, C, k, ecode, eshift, emb_q0, topk, exact_below, clr);
         center[v] = clr[0];
         lpole[v] = clr[1];
         rpole[v] = clr[2];
@@ -342,6 +393,7 @@ static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, co
     for (int32_t v = 0; v < n_nodes; ++v) free(members[v]);
     free(members);
     free(msize);
+    free(ecode);
     return n_nodes;
 }
 
@@ -365,16 +417,19 @@ int32_t orc_tree_pruned(const uint8_t *codes, const int64_t *off, int32_t n, con
 }
 
 /* Surrogate row sums E(x) of emb_estimate over an explicit member list
- * (for tests of the ranking step). */
-void orc_emb_rowsums(const int64_t *off, const float *emb, uint32_t emb_q0,
+ * (for tests of the ranking step); emb: float[n_emb][128], the whole set. */
+void orc_emb_rowsums(const int64_t *off, const float *emb, int64_t n_emb, uint32_t emb_q0,
                      const int32_t *members, int64_t k, uint64_t *E) {
+    int8_t *ecode = (int8_t *)malloc((size_t)(n_emb * EMB_DIM));
+    const int eshift = orc_emb_quantize(emb, n_emb, ecode);
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t x = 0; x < k; ++x) {
         uint64_t s = 0;
         for (int64_t y = 0; y < k; ++y)
-            s += emb_estimate(off, emb, emb_q0, members[x], members[y]);
+            s += emb_estimate(off, ecode, eshift, emb_q0, members[x], members[y]);
         E[x] = s;
     }
+    free(ecode);
 }
 
 /* ------------------------------------------------------------------ merge

@@ -36,9 +36,12 @@ def lib():
         L.orc_tree_pruned.restype = C.c_int32
         L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_uint32, C.c_int32, C.c_int32] + [P] * 10
         L.orc_select.restype = None
-        L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_uint32, C.c_int32, C.c_int32, P]
+        L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_int64, C.c_uint32, C.c_int32,
+                                 C.c_int32, P]
         L.orc_emb_rowsums.restype = None
-        L.orc_emb_rowsums.argtypes = [P, P, C.c_uint32, P, C.c_int64, P]
+        L.orc_emb_rowsums.argtypes = [P, P, C.c_int64, C.c_uint32, P, C.c_int64, P]
+        L.orc_emb_quantize.restype = C.c_int32
+        L.orc_emb_quantize.argtypes = [P, C.c_int64, P]
         L.orc_merge.restype = C.c_int64
         L.orc_merge.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
                                 C.c_int64]
@@ -165,19 +168,31 @@ def select(codes, offsets, members, emb=None, topk=16, exact_below=0, emb_q0=0):
     e = None if emb is None else np.ascontiguousarray(emb, dtype=np.float32)
     out = np.zeros(3, dtype=np.int32)
     lib().orc_select(_p(codes), _p(offsets), _p(mem), len(mem), None if e is None else _p(e),
-                     int(emb_q0), int(topk), int(exact_below), _p(out))
+                     0 if e is None else len(e), int(emb_q0), int(topk), int(exact_below),
+                     _p(out))
     return tuple(int(x) for x in out)
 
 
 def emb_rowsums(offsets, emb, members, emb_q0=0):
     """Surrogate row sums E(x) over the member list: the summed embedding
-    distance (plus emb_q0) times the pair's summed length, units of 2^-16."""
+    distance (plus emb_q0) times the pair's summed length, units of 2^-16.
+    emb holds the whole set (its quantization scale comes from every row)."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     emb = np.ascontiguousarray(emb, dtype=np.float32)
     members = np.ascontiguousarray(members, dtype=np.int32)
     E = np.zeros(len(members), dtype=np.uint64)
-    lib().orc_emb_rowsums(_p(offsets), _p(emb), int(emb_q0), _p(members), len(members), _p(E))
+    lib().orc_emb_rowsums(_p(offsets), _p(emb), len(emb), int(emb_q0), _p(members),
+                          len(members), _p(E))
     return E
+
+
+def emb_quantize(emb):
+    """(int8 codes [n, 128], shift s): the quantization of the surrogate
+    distance, code = rint(e 2^s) limited to +-127."""
+    emb = np.ascontiguousarray(emb, dtype=np.float32)
+    codes = np.zeros(emb.shape, dtype=np.int8)
+    s = lib().orc_emb_quantize(_p(emb), len(emb), _p(codes))
+    return codes, int(s)
 
 
 def merge(codes, offsets, sigma, t):

@@ -25,17 +25,25 @@ namespace msadp {
 enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 4 };
 
 // Surrogate-pruned medoid: clusters above exact_below members get exact row
-// sums for their topk best-ranked members only.  The surrogate distance of
-// two embeddings x, y takes fixed float32 steps: the norms |x|^2, |y|^2 and
-// the dot product x.y each accumulated by fused multiply-adds in coordinate
-// order from 0, then d2 = fma(-2, x.y, |x|^2 + |y|^2) clamped at 0,
-// sqrt(d2) capped at kEmbCap, scaled by kEmbScale and rounded to the nearest
-// integer.  Fixed steps make the candidate ranking reproducible, and the
+// sums for their topk best-ranked members only.  The embeddings are
+// quantized once per call to int8 codes with one power-of-two scale 2^s for
+// the whole set: with M = max |e| over every coordinate, s = 6 - floor(log2 M)
+// clamped to [kEmbShiftMin, kEmbShiftMax] (M below 2^(6 - kEmbShiftMax): s =
+// kEmbShiftMax), so M 2^s lies in [64, 128); a coordinate's code is
+// rint(e 2^s) clamped to +-127.  The surrogate distance of two members is
+// then sqrt(D) 2^-s with D = |c_x - c_y|^2 an exact integer (below 2^24,
+// exact in float32; its Gram part runs on the int8 matrix cores), in float32:
+// the square root (correctly rounded), the scaling (exact), the cap at
+// kEmbCap and the rounding of 2^16 times it to an integer.  Exact integers
+// up to one float32 square root make the ranking reproducible, and the row
 // sums are integers.
 constexpr int kMaxTopk = 1024;
 constexpr uint32_t kMaxEmbOffset = 1u << 31;   // 2^15 in units of 2^-16
 constexpr float kEmbScale = 65536.0f;   // fixed point of embedding distances (2^16)
 constexpr float kEmbCap = 32768.0f;     // embedding distances saturate here
+constexpr int kEmbDim = 128;
+constexpr int kEmbShiftMin = -20, kEmbShiftMax = 40;
+constexpr float kEmbCodeMax = 127.0f;
 
 struct TreeArgs {
     Staged S;
@@ -62,6 +70,9 @@ struct TreeArgs {
     int32_t n;
     // surrogate-pruned medoid (emb == nullptr: exact medoid)
     const float *emb;        // [n][128] by input index
+    int8_t *embq;            // [n][128] int8 codes by input index
+    int32_t *embn;           // [n] squared norms of the codes
+    uint32_t *emb_max;       // [2]: bits of max |e|, quantization shift s
     uint32_t emb_q0;         // calibration offset added to every surrogate distance
     int32_t topk;
     int32_t exact_below;     // clusters of at most this many members: all are candidates
@@ -422,50 +433,169 @@ __global__ void k_set_desc(int32_t *desc, int32_t lo, int32_t hi) {
     desc[2] = 0;
 }
 
-// Read-only global memory seen through the scalar unit: a load from a
-// uniform address in this address space is a scalar (SMEM) load, so the
-// row of block J that every lane needs costs no vector-memory issue slots.
-typedef const __attribute__((address_space(4))) float const_f32;
-
-// Dot product of one quarter (32 coordinates) of two embeddings, added to acc
-// by fused multiply-adds in coordinate order.
-__device__ __forceinline__ float dot_quarter(float acc, const float4 *x, const_f32 *y) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        acc = __builtin_fmaf(x[c].x, y[4 * c], acc);
-        acc = __builtin_fmaf(x[c].y, y[4 * c + 1], acc);
-        acc = __builtin_fmaf(x[c].z, y[4 * c + 2], acc);
-        acc = __builtin_fmaf(x[c].w, y[4 * c + 3], acc);
-    }
-    return acc;
+// Quantization of the embeddings (see kEmbShiftMin above).  maxbits = the
+// bit pattern of M = max |e| (a non-negative float orders like its bits).
+__device__ __forceinline__ int emb_shift_of(uint32_t maxbits) {
+    // M < 2^(6 - kEmbShiftMax), zero and subnormals included: the largest shift
+    if (maxbits < ((uint32_t)(127 + 6 - kEmbShiftMax) << 23)) return kEmbShiftMax;
+    const int L = (int)(maxbits >> 23) - 127;   // floor(log2 M) of a normal M
+    return min(max(6 - L, kEmbShiftMin), kEmbShiftMax);
 }
 
-__device__ __forceinline__ float norm2(const float4 *x) {
-    float acc = 0.0f;
+// 2^e for e in [-kEmbShiftMax, 16 - kEmbShiftMin] (a normal float).
+__device__ __forceinline__ float pow2f(int e) { return __uint_as_float((uint32_t)(127 + e) << 23); }
+
+__global__ void k_emb_reset(uint32_t *emb_max) {
+    emb_max[0] = 0;
+    emb_max[1] = 0;
+}
+
+// emb_max[0] = bits of max |e| over the n x 128 coordinates.
+__global__ void __launch_bounds__(256) k_emb_absmax(const float *emb, int64_t count,
+                                                   uint32_t *emb_max) {
+    uint32_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(emb[i]) & 0x7FFFFFFFu);
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, kWave));
+    if (lane_id() == 0) atomicMax(emb_max, m);
+}
+
+// Codes and squared code norms; a thread quantizes 4 coordinates of a row.
+__global__ void __launch_bounds__(256) k_emb_quantize(const float *emb, int32_t n,
+                                                     const uint32_t *emb_max, int8_t *embq,
+                                                     int32_t *embn, int32_t *st) {
+    const uint32_t mb = emb_max[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && mb >= 0x7F800000u) set_status(st, MSA_DS_VALUE);
+    const float scale = pow2f(emb_shift_of(mb));
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // n * 32 threads
+    const int64_t row = t >> 5;
+    int32_t sq = 0;
+    if (row < n) {
+        const float4 e = ((const float4 *)emb)[t];
+        const float ev[4] = {e.x, e.y, e.z, e.w};
+        uint32_t packed = 0;
 #pragma unroll
-    for (int c = 0; c < 32; ++c) {
-        acc = __builtin_fmaf(x[c].x, x[c].x, acc);
-        acc = __builtin_fmaf(x[c].y, x[c].y, acc);
-        acc = __builtin_fmaf(x[c].z, x[c].z, acc);
-        acc = __builtin_fmaf(x[c].w, x[c].w, acc);
+        for (int c = 0; c < 4; ++c) {
+            const float v = fminf(fmaxf(rintf(ev[c] * scale), -kEmbCodeMax), kEmbCodeMax);
+            const int32_t code = (int32_t)v;
+            sq += code * code;
+            packed |= ((uint32_t)code & 0xFFu) << (8 * c);
+        }
+        ((uint32_t *)embq)[t] = packed;
     }
-    return acc;
+    for (int o = 16; o >= 1; o >>= 1) sq += __shfl_xor(sq, o, 32);
+    if (row < n && (t & 31) == 0) embn[row] = sq;
+}
+
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+
+// Correctly rounded float32 square root of an integer 0 <= x < 2^24.  The
+// hardware square root r lies within one unit in the last place of the
+// exact one (true on every such integer), so the answer is r or a
+// neighbour: with m and p the floats below and above r, x <= m r means
+// sqrt(x) is below the midpoint of m and r, and x > p r that it is above
+// the midpoint of r and p; both products of 24-bit significands are exact
+// inside the fused multiply-add, and an integer x never falls strictly
+// between m r and that midpoint (nor between p r and the other one), so
+// the sign tests decide exactly.  x = 0 gives r = 0 and neither test fires.
+__device__ __forceinline__ float sqrt_int_rn(float x) {
+    const float r = __builtin_amdgcn_sqrtf(x);
+    const float m = __uint_as_float(__float_as_uint(r) - 1u);
+    const float p = __uint_as_float(__float_as_uint(r) + 1u);
+    const bool down = __builtin_fmaf(-m, r, x) <= 0.0f;
+    const bool upw = __builtin_fmaf(-p, r, x) > 0.0f;
+    return down ? m : (upw ? p : r);
+}
+
+// Row sums of one row tile of the Gram block: G[ta][tb][r] pairs x member
+// 16 ta + 4 g + r with y member 16 tb + l16 of their blocks.
+template <bool kCols>
+__device__ __forceinline__ void emb_tile_epilogue(
+    const v4i32 (&G)[4][4], int ta, int g, int l16, const int32_t *xn, const uint32_t *xl,
+    const uint32_t *xm, const int32_t (&ny)[4], const uint32_t (&ly)[4], const uint32_t (&ym)[4],
+    float qscale, uint64_t q0, uint64_t (&cs)[4], uint32_t (&cw)[4], uint64_t *red_r) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ta + 4 * g + r;
+        const int32_t nx = xn[row];
+        const uint32_t lx = xl[row], mx = xm[row];
+        uint64_t rs = 0;
+        uint32_t rw = 0;
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) {
+            const int32_t d2 = nx + ny[tb] - 2 * G[ta][tb][r];   // |c_x - c_y|^2, exact
+            // min(sqrt 2^-s, 2^15) 2^16 = min(sqrt 2^(16-s), 2^31): power-of-two
+            // scalings of normal floats are exact
+            const float dq = sqrt_int_rn((float)d2) * qscale;
+            const uint32_t qd = (uint32_t)rintf(fminf(dq, kEmbCap * kEmbScale));
+            const uint32_t w = (lx + ly[tb]) & mx & ym[tb];
+            rs += (uint64_t)qd * w;
+            rw += w;
+            if (kCols) {
+                cs[tb] += (uint64_t)qd * w;
+                cw[tb] += w;
+            }
+        }
+        red_r[row * 17 + l16] = rs + q0 * rw;
+    }
 }
 
 // Estimated medoid row sums from the embeddings.  The embedder is trained
 // so that ||e_x - e_y|| predicts f(x, y) divided by the pair's mean length;
 // with a linear recalibration of that prediction (offset emb_q0, the slope
 // drops out of the ranking) the estimate of f(x, y) is proportional to
-// (||e_x - e_y|| + offset) (|x| + |y|).  Every ordered pair of a cluster,
-// x with itself included, adds it to the row sum of x.  One work item is a 64 x 64 tile (I, J) of the cluster's upper block
-// triangle: lane i keeps the embedding of member 64 I + i in registers and
-// walks the 64 members of block J, whose rows every lane needs whole and
-// reads by scalar loads; lane j holds |y_j|^2 of member 64 J + j.
-// Lanes sum their row; for I < J the column sums are reduced across the
-// wave.  A diagonal tile visits every ordered pair of its block and adds row
-// sums only.
-__global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
+// (||e_x - e_y|| + offset) (|x| + |y|).  Every ordered pair of a cluster, x
+// with itself included, adds it to the row sum of x.  One work item is a
+// 64 x 64 tile (I, J) of the cluster's upper block triangle: the Gram block
+// of the int8 codes of blocks I and J (128 coordinates) takes 32 int8 MFMAs
+// (16 x 16 x 64, exact int32), then every pair's distance, weight and
+// product; row sums go through LDS to one lane per member, and for I < J so
+// do the column sums.  A diagonal tile visits every ordered pair of its
+// block and adds row sums only.  The q0 part of a sum is q0 times the summed
+// weights.
+// Where tile `it` of the level lies, and what lane L needs of it: member L
+// of block I (x) and of block J (y), by rank, input index, norm and length.
+struct EmbTile {
+    int64_t ms, k, I, J;
+    int32_t xr, yr, xo, yo, xn, yn;
+    bool xv, yv;
+};
+
+__device__ __forceinline__ EmbTile emb_locate(const TreeArgs &a, int32_t lvl, int32_t nq,
+                                              int64_t it, int lane) {
+    EmbTile t;
+    const int32_t q = find_cluster(a.items, nq, it);
+    const int64_t local = it - a.items[q];
+    t.ms = a.mstart[lvl + q];
+    t.k = a.mcount[lvl + q];
+    const int64_t nb = (t.k + 63) / 64;
+    int64_t lo = 0, hi = nb - 1;            // row I of the tile
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (tile_rows_before(mid, nb) <= local) lo = mid; else hi = mid - 1;
+    }
+    t.I = lo;
+    t.J = lo + (local - tile_rows_before(lo, nb));
+    const int64_t xi = t.I * 64 + lane, yi = t.J * 64 + lane;
+    t.xv = xi < t.k;
+    t.yv = yi < t.k;
+    t.xr = a.perm[t.ms + (t.xv ? xi : 0)];
+    t.yr = a.perm[t.ms + (t.yv ? yi : 0)];
+    t.xo = a.order[t.xr];
+    t.yo = a.order[t.yr];
+    t.xn = a.embn[t.xo];
+    t.yn = a.embn[t.yo];
+    return t;
+}
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_emb_rowsum(TreeArgs a) {
+    __shared__ uint64_t red_r[64 * 17];    // row partials (16 per member, padded)
+    __shared__ uint64_t red_c[64 * 4];     // column partials (4 per member)
+    __shared__ int32_t xo_s[64], yo_s[64], xn_s[64];
+    __shared__ uint32_t xl_s[64], xm_s[64];
     const int lane = lane_id();
+    const int l16 = lane & 15, g = lane >> 4;
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     const int64_t total = a.items[nq];
     // Clusters of a level are disjoint, so their tiles number at most n(n+1)/2.
@@ -473,70 +603,90 @@ __global__ void __launch_bounds__(64) k_emb_rowsum(TreeArgs a) {
         if (blockIdx.x == 0 && lane == 0) set_status(a.st, MSA_DS_CAPACITY);
         return;
     }
-    for (;;) {
-        const uint32_t it = next_item(a.counter);
-        if ((int64_t)it >= total) break;
-        const int32_t q = find_cluster(a.items, nq, it);
-        const int64_t local = (int64_t)it - a.items[q];
-        const int32_t v = lvl + q;
-        const int64_t ms = a.mstart[v], k = a.mcount[v];
-        const int64_t nb = (k + 63) / 64;
-        int64_t lo = 0, hi = nb - 1;            // row I of the tile
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (tile_rows_before(mid, nb) <= local) lo = mid; else hi = mid - 1;
-        }
-        const int64_t I = lo, J = I + (local - tile_rows_before(I, nb));
-        // this lane's member of block I (x) and of block J (y)
+    const float qscale = pow2f(16 - emb_shift_of(a.emb_max[0]));   // 2^(16 - s)
+    const uint64_t q0 = a.emb_q0;
+    // Tiles cost the same, so they are dealt out statically (stride = grid);
+    // the next tile's location and member data load while this one computes.
+    int64_t it = blockIdx.x;
+    EmbTile nxt{};
+    if (it < total) nxt = emb_locate(a, lvl, nq, it, lane);
+    while (it < total) {
+        const EmbTile cur = nxt;
+        const int64_t ms = cur.ms, I = cur.I, J = cur.J;
         const int64_t xi = I * 64 + lane, yi = J * 64 + lane;
-        const bool xv = xi < k, yl = yi < k;
-        const int32_t xr = a.perm[ms + (xv ? xi : 0)];
-        const int32_t yr = a.perm[ms + (yl ? yi : 0)];
-        const uint32_t yrow = (uint32_t)a.order[yr];
-        const uint32_t ylen = (uint32_t)a.S.len[yr] | (yl ? 0u : 0x80000000u);
-        float ny;
-        {
-            const float4 *yp = (const float4 *)(a.emb + (int64_t)yrow * 128);
-            float4 y[32];
+        const bool xv = cur.xv, yv = cur.yv;
+        xo_s[lane] = cur.xo;
+        yo_s[lane] = cur.yo;
+        xn_s[lane] = cur.xn;
+        xl_s[lane] = (uint32_t)a.S.len[cur.xr];
+        xm_s[lane] = xv ? ~0u : 0u;
+        const int32_t yn_l = cur.yn;
+        const uint32_t yl_l = (uint32_t)a.S.len[cur.yr], ym_l = yv ? ~0u : 0u;
+        __syncthreads();
+        // operands: A row i = x member 16 t + i, B column j = y member 16 t + j;
+        // lane group g brings coordinates 16 g .. 16 g + 15 of each 64-wide K step
+        v4i32 A[4][2], B[4][2];
 #pragma unroll
-            for (int c = 0; c < 32; ++c) y[c] = yp[c];
-            ny = norm2(y);
+        for (int t = 0; t < 4; ++t) {
+            const v4i32 *xp = (const v4i32 *)(a.embq + (int64_t)xo_s[16 * t + l16] * kEmbDim);
+            const v4i32 *yp = (const v4i32 *)(a.embq + (int64_t)yo_s[16 * t + l16] * kEmbDim);
+            A[t][0] = xp[g];
+            A[t][1] = xp[4 + g];
+            B[t][0] = yp[g];
+            B[t][1] = yp[4 + g];
         }
-        const float4 *xp = (const float4 *)(a.emb + (int64_t)a.order[xr] * 128);
-        float4 x[32];
+        v4i32 G[4][4];
 #pragma unroll
-        for (int c = 0; c < 32; ++c) x[c] = xp[c];
-        const float nx = norm2(x);
-        const uint64_t lx = (uint64_t)a.S.len[xr];
-        const_f32 *embs = (const_f32 *)a.emb;
-        uint64_t rs = 0, cs = 0;
-        const int jn = (int)min<int64_t>(64, k - J * 64);   // members in block J
-        for (int j = 0; j < jn; ++j) {
-            const uint32_t lj = __builtin_amdgcn_readlane(ylen, j);
-            const_f32 *row = embs + (int64_t)__builtin_amdgcn_readlane(yrow, j) * 128;
-            const float nyj = __builtin_bit_cast(
-                float, __builtin_amdgcn_readlane(__builtin_bit_cast(uint32_t, ny), j));
-            float dot = 0.0f;
-            dot = dot_quarter(dot, x + 0, row + 0);
-            dot = dot_quarter(dot, x + 8, row + 32);
-            dot = dot_quarter(dot, x + 16, row + 64);
-            dot = dot_quarter(dot, x + 24, row + 96);
-            const float d2 = fmaxf(__builtin_fmaf(-2.0f, dot, nx + nyj), 0.0f);
-            const uint64_t qd = (uint64_t)rintf(fminf(sqrtf(d2), kEmbCap) * kEmbScale);
-            // lj's top bit marks a missing member of block J
-            const uint64_t w = (xv && !(lj >> 31)) ? lx + (uint64_t)lj : 0ull;
-            const uint64_t e = (qd + a.emb_q0) * w;
-            rs += e;
-            if (I != J) {                        // uniform per item
-                const uint64_t col = wave_sum_u64(e);
-                cs = lane == j ? col : cs;
-            }
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) G[ta][tb] = v4i32{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < 4; ++tb)
+                    G[ta][tb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[ta][kk], B[tb][kk],
+                                                                      G[ta][tb], 0, 0, 0);
+        const int64_t it_next = it + gridDim.x;
+        if (it_next < total) nxt = emb_locate(a, lvl, nq, it_next, lane);   // uniform
+        // this lane's y members 16 tb + l16: norm, length, validity
+        int32_t ny[4];
+        uint32_t ly[4], ym[4];
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) {
+            ny[tb] = __shfl(yn_l, 16 * tb + l16, kWave);
+            ly[tb] = (uint32_t)__shfl((int)yl_l, 16 * tb + l16, kWave);
+            ym[tb] = (uint32_t)__shfl((int)ym_l, 16 * tb + l16, kWave);
         }
+        uint64_t cs[4] = {0, 0, 0, 0};
+        uint32_t cw[4] = {0, 0, 0, 0};
+        const bool cols = I != J;                // uniform per item
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta) {
+            if (cols)
+                emb_tile_epilogue<true>(G, ta, g, l16, xn_s, xl_s, xm_s, ny, ly, ym, qscale, q0,
+                                        cs, cw, red_r);
+            else
+                emb_tile_epilogue<false>(G, ta, g, l16, xn_s, xl_s, xm_s, ny, ly, ym, qscale, q0,
+                                         cs, cw, red_r);
+        }
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) red_c[(16 * tb + l16) * 4 + g] = cs[tb] + q0 * cw[tb];
+        __syncthreads();
+        uint64_t rsum = 0, csum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) rsum += red_r[lane * 17 + j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) csum += red_c[lane * 4 + j];
+        // no lane-dependent branch around the atomics (see next_item)
         atomicAdd((unsigned long long *)&a.rowsum[xv ? ms + xi : (int64_t)a.n],
-                  (unsigned long long)(xv ? rs : 0ull));
-        if (I != J)
-            atomicAdd((unsigned long long *)&a.rowsum[yl ? ms + yi : (int64_t)a.n],
-                      (unsigned long long)(yl ? cs : 0ull));
+                  (unsigned long long)(xv ? rsum : 0ull));
+        if (cols)
+            atomicAdd((unsigned long long *)&a.rowsum[yv ? ms + yi : (int64_t)a.n],
+                      (unsigned long long)(yv ? csum : 0ull));
+        __syncthreads();
+        it = it_next;
     }
 }
 
@@ -776,6 +926,22 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<uint64_t>(n);              // candidate sums
     al.template take<int32_t>(2 * n);           // child ids of an evaluated tree
     al.template take<int32_t>(2 * n);
+    al.template take<int8_t>(n * kEmbDim);      // embedding codes
+    al.template take<int32_t>(n);               // their squared norms
+    al.template take<uint32_t>(2);              // max |e|, spare
+}
+
+// Quantize the embeddings once per call (before any level).
+static int quantize_embeddings(const TreeArgs &a, hipStream_t s) {
+    if (a.emb == nullptr) return MSA_OK;
+    const int64_t count = (int64_t)a.n * kEmbDim;
+    hipLaunchKernelGGL(k_emb_reset, dim3(1), dim3(1), 0, s, a.emb_max);
+    hipLaunchKernelGGL(k_emb_absmax, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 2048)),
+                       dim3(256), 0, s, a.emb, count, a.emb_max);
+    hipLaunchKernelGGL(k_emb_quantize, dim3((unsigned)(((int64_t)a.n * 32 + 255) / 256)),
+                       dim3(256), 0, s, a.emb, a.n, (const uint32_t *)a.emb_max, a.embq, a.embn,
+                       a.st);
+    return launch_status();
 }
 
 }  // namespace msadp
@@ -843,6 +1009,9 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     int32_t *eval_right = cv.take<int32_t>(2 * n);
     (void)eval_left;
     (void)eval_right;
+    a.embq = cv.take<int8_t>(n * kEmbDim);
+    a.embn = cv.take<int32_t>(n);
+    a.emb_max = cv.take<uint32_t>(2);
     a.emb = emb;
     a.emb_q0 = emb_q0;
     a.topk = topk;
@@ -857,6 +1026,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                        a.perm);
     hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, a);
     if ((rc = launch_status())) return rc;
+    if ((rc = quantize_embeddings(a, s))) return rc;
 
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -1043,6 +1213,9 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.candsum = cv.take<uint64_t>(n);
     a.left = cv.take<int32_t>(2 * n);
     a.right = cv.take<int32_t>(2 * n);
+    a.embq = cv.take<int8_t>(n * kEmbDim);
+    a.embn = cv.take<int32_t>(n);
+    a.emb_max = cv.take<uint32_t>(2);
     a.center = center;
     a.lpole = lpole;
     a.rpole = rpole;
@@ -1063,6 +1236,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
         hipLaunchKernelGGL(k_perm_in, dim3((S->n + 255) / 256), dim3(256), 0, s, T->perm,
                            rank_of, S->n, a.perm, d_status);
         rc = launch_status();
+        if (rc == MSA_OK) rc = quantize_embeddings(a, s);
     }
     for (size_t lo = 0; rc == MSA_OK && lo < nn;) {
         size_t hi = lo + 1;

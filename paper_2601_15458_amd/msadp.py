@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libmsadp.so")
 MSA_OK, MSA_EINVAL, MSA_ERANGE, MSA_ENOSPC, MSA_EDEVICE = 0, -1, -2, -3, -4
 MSA_TUNE_LEV, MSA_TUNE_NW, MSA_TUNE_TREE = 0, 1, 2
 DS_NAMES = {0: "ok", 1: "symbol code >= sigma", 2: "sequence index out of range",
-            3: "length out of range", 4: "output capacity too small"}
+            3: "length out of range", 4: "output capacity too small",
+            5: "non-finite embedding value"}
 
 # Exported entry points and their C signatures (mirrors include/msadp.h).
 P = C.c_void_p

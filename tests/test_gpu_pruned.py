@@ -1,6 +1,7 @@
 """Surrogate-pruned Alg. 1 on the GPU against the CPU oracle (node arrays equal).
 
-The candidate ranking takes fixed float32 steps on both sides, so the
+The candidate ranking takes the same steps on both sides (int8 codes, exact
+integer squared distances, one float32 square root and rounding), so the
 pruned tree is reproduced exactly, not approximately."""
 import numpy as np
 import pytest
@@ -129,6 +130,29 @@ def test_device_embeddings_pipeline():
     got = M.tree_build(S, emb=e, topk=4)
     want = orc.tree_pruned(d["codes"], d["offsets"], e.cpu().numpy(), topk=4)
     _equal_trees(got, want)
+
+
+@pytest.mark.parametrize("scale", [1e-20, 1e-3, 3.0, 1e6, 1e12])
+def test_quantization_scales(scale):
+    """Every regime of the quantization shift: tiny values (largest shift),
+    ordinary ones, and large ones whose shift is limited (codes saturate)."""
+    d = synth.tiny()
+    emb = (_emb(40, d["n"], 1.0) * np.float32(scale)).astype(np.float32)
+    emb[11] *= np.float32(50.0)                # one row far from the rest
+    _compare(d["codes"], d["offsets"], d["sigma"], emb, 4)
+
+
+def test_non_finite_embedding_reported():
+    import torch
+    M = _msadp()
+    d = synth.tiny()
+    S = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    for bad in (np.nan, np.inf):
+        emb = _emb(41, d["n"])
+        emb[5, 3] = bad
+        e = torch.from_numpy(emb).to(S.codes.device)
+        with pytest.raises(RuntimeError, match="non-finite"):
+            M.tree_build(S, emb=e, topk=4)
 
 
 def test_bad_arguments():

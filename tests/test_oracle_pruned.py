@@ -25,7 +25,7 @@ def _off(lengths):
 
 def test_emb_distance_closed_form():
     e = np.zeros((2, 128), dtype=np.float32)
-    e[1, 0], e[1, 1] = 3.0, 4.0                    # |(3, 4)| = 5 exactly
+    e[1, 0], e[1, 1] = 3.0, 4.0                    # |(3, 4)| = 5; 2^4 (3, 4) are integers
     off = _off([7, 10])                            # |x| + |y| = 17
     E = orc.emb_rowsums(off, e, np.array([0, 1], dtype=np.int32))
     assert E.tolist() == [5 * 17 * (1 << 16)] * 2
@@ -37,59 +37,81 @@ def test_emb_distance_closed_form():
     assert E.tolist() == [17 * (1 << 31)] * 2
 
 
-def test_emb_distance_within_float32_bound():
-    """|E - 2^16 (|x| + |y|) ||e_x - e_y||| stays within the float32 error of
-    three 128-term multiply-add sums, the combination, a square root and the
-    final rounding: the error of d^2 is at most ~2^-24 * 300 (|x|^2 + |y|^2),
-    which moves d by at most that over 2d."""
+def _shift_by_definition(M):
+    """s with M 2^s in [64, 128), limited to [-20, 40] (40 below 2^-34)."""
+    import math
+    if M < 2.0 ** -34:
+        return 40
+    mant, ex = math.frexp(float(M))              # M = mant 2^ex, mant in [0.5, 1)
+    return int(min(max(6 - (ex - 1), -20), 40))
+
+
+@pytest.mark.parametrize("scale", [0.0, 1e-12, 1e-3, 0.1, 1.0, 37.0, 3e5, 1e9])
+def test_emb_quantization_rule(scale):
+    """Codes are e 2^s rounded to the nearest integer (ties to even), limited
+    to +-127, with one power-of-two scale for the set: the largest |e| lands
+    in [64, 128) unless the shift hits its limits."""
+    e = _emb(20, 40, scale=max(scale, 1e-30)) if scale else np.zeros((40, 128), np.float32)
+    codes, s = orc.emb_quantize(e)
+    M = float(np.abs(e).max())
+    assert s == _shift_by_definition(M)
+    want = np.clip(np.rint(e.astype(np.float64) * 2.0 ** s), -127, 127)   # exact in float64
+    assert np.array_equal(codes.astype(np.int64), want.astype(np.int64))
+    if 2.0 ** -34 <= M < 2.0 ** 27:
+        assert 64 <= M * 2.0 ** s < 128
+        assert np.abs(codes).max() >= 64
+        err = np.abs(e.astype(np.float64) - codes * 2.0 ** -s)
+        assert err.max() <= 2.0 ** -s               # half a step, a full one where clipped
+
+
+def test_emb_distance_within_quantization_bound():
+    """|E / (2^16 (|x| + |y|)) - ||e_x - e_y||| stays within the quantization
+    error (every coordinate moves by at most one step 2^-s, so the distance by
+    at most sqrt(128) 2^-s) plus the float32 square root and rounding."""
     e = _emb(7, 64, scale=1.0)
+    s = _shift_by_definition(np.abs(e).max())
     off = _off(np.arange(64) + 1)
     for i in range(1, 64):
         E = orc.emb_rowsums(off, e, np.array([0, i], dtype=np.int32))
         x, y = e[0].astype(np.float64), e[i].astype(np.float64)
         d = np.linalg.norm(x - y)
         L = 1 + (i + 1)
-        err_d = 2.0 ** -24 * 300 * (x @ x + y @ y) / (2 * d)
-        assert abs(float(E[0]) - TWO16 * L * d) <= L * (TWO16 * err_d + 0.5)
+        bound = np.sqrt(128) * 2.0 ** -s + (d + 1) * 2.0 ** -22
+        assert abs(float(E[0]) / (TWO16 * L) - d) <= bound + 0.5 / TWO16
 
 
-def _round_f32(q):
-    """The float32 nearest to the rational q (ties to even), exactly."""
-    from fractions import Fraction
-    f = np.float32(float(q))
-    best = None
-    for g in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
-        dist = abs(Fraction(float(g)) - q)
-        key = (dist, int(np.array(g).view(np.uint32)) & 1)
-        if best is None or key < best[0]:
-            best = (key, g)
-    return best[1]
-
-
-def _fma(a, b, c):
-    from fractions import Fraction
-    return _round_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
-
-
-def test_emb_distance_float32_steps():
-    """The oracle takes the stated float32 steps: sums of fused multiply-adds
-    (each rounded once, emulated here with exact rationals), then
-    fma(-2, x.y, |x|^2 + |y|^2), the square root and the rounding."""
+def test_emb_distance_stated_steps():
+    """The oracle takes the stated steps: integer codes, the exact squared
+    distance D of the codes (Python integers here), then in float32 sqrt(D),
+    times 2^-s, the cap at 2^15, times 2^16 and the rounding."""
     e = _emb(8, 6, scale=0.7)
     off = _off(np.ones(6, dtype=np.int64))
+    s = _shift_by_definition(np.abs(e).max())
+    c = np.clip(np.rint(e.astype(np.float64) * 2.0 ** s), -127, 127).astype(np.int64)
     f = np.float32
     for i in range(1, 6):
-        x, y = e[0], e[i]
-        nx = ny = dot = f(0.0)
-        for c in range(128):
-            nx = _fma(x[c], x[c], nx)
-            ny = _fma(y[c], y[c], ny)
-            dot = _fma(x[c], y[c], dot)
-        d2 = _fma(f(-2.0), dot, f(nx + ny))
-        d2 = d2 if d2 > 0 else f(0.0)
-        want = 2 * int(np.rint(f(np.sqrt(d2)) * f(TWO16)))
+        D = int(sum((int(c[0, k]) - int(c[i, k])) ** 2 for k in range(128)))
+        dist = f(np.sqrt(f(D))) * f(2.0 ** -s)
+        want = 2 * int(np.rint(f(min(dist, f(32768.0))) * f(TWO16)))
         got = orc.emb_rowsums(off, e, np.array([0, i], dtype=np.int32))
         assert int(got[0]) == want
+
+
+def test_emb_distance_is_a_metric_on_codes():
+    """Quantized distances are symmetric, zero on equal codes and obey the
+    triangle inequality up to the rounding of three values."""
+    e = _emb(21, 10, scale=0.3)
+    e[7] = e[3]
+    off = _off(np.ones(10, dtype=np.int64))
+    q = np.zeros((10, 10))
+    for x in range(10):
+        for y in range(10):
+            q[x, y] = int(orc.emb_rowsums(off, e, np.array([x, y], dtype=np.int32))[0]) / 2
+    assert np.array_equal(q, q.T) and q[3, 7] == 0 and np.all(np.diag(q) == 0)
+    for x in range(10):
+        for y in range(10):
+            for z in range(10):
+                assert q[x, z] <= q[x, y] + q[y, z] + 2
 
 
 def test_row_sums_are_sums_of_pairs():

@@ -215,3 +215,43 @@ def test_teacher_forced_rejects_bad_tree():
     with pytest.raises(M.MsaError) as ex:
         M.tree_eval_centers(S, bad)
     assert ex.value.code == M.MSA_EINVAL
+
+
+def test_learned_workload_full_size_sampled():
+    """The 100,000-sequence DNA set (1000 families) at full size with a fixed
+    random embedding and a calibration offset: the whole tree's shape; the
+    root's poles and split from oracle distances to the chosen centre; and
+    sampled nodes of 20-200 members re-derived by the oracle's pruned Alg. 1
+    step on their member sets (embedding quantized over the whole set)."""
+    import torch
+    from test_gpu_tree import _check_structure, _dist_from
+    M = _msadp()
+    d = synth.learned()
+    codes, off, n = d["codes"], d["offsets"], d["n"]
+    assert n == 100000
+    S = M.to_device(codes, off, d["sigma"])
+    emb = _emb(42, n, 0.3)
+    e = torch.from_numpy(emb).to(S.codes.device)
+    print(f"[pruned] learned {n}: device build", flush=True)
+    t = M.tree_build(S, use_graph=True, emb=e, topk=16, emb_offset=0.5)
+    print(f"[pruned] {t['n_nodes']} nodes; shape", flush=True)
+    _check_structure(t, codes, off)
+    allm = np.arange(n)
+    c, l, r = int(t["center"][0]), int(t["lpole"][0]), int(t["rpole"][0])
+    print("[pruned] root poles and split from oracle distances", flush=True)
+    dc = _dist_from(codes, off, c, allm)
+    assert l == int(np.argmax(dc))
+    dl = _dist_from(codes, off, l, allm)
+    assert r == int(np.argmax(dl))
+    dr = _dist_from(codes, off, r, allm)
+    lc = int(t["left"][0])
+    in_left = np.zeros(n, bool)
+    in_left[t["perm"][t["mstart"][lc]: t["mstart"][lc] + t["mcount"][lc]]] = True
+    assert np.array_equal(in_left, dl <= dr)
+    rng = np.random.default_rng(43)
+    internal = np.flatnonzero((t["left"] >= 0) & (t["mcount"] >= 20) & (t["mcount"] <= 200))
+    for v in rng.choice(internal, size=min(12, len(internal)), replace=False):
+        mem = t["perm"][t["mstart"][v]: t["mstart"][v] + t["mcount"][v]]
+        print(f"[pruned] node {v} ({len(mem)} members) against the oracle", flush=True)
+        want = orc.select(codes, off, mem, emb, 16, 0, emb_q0=M.emb_offset_q(0.5))
+        assert (int(t["center"][v]), int(t["lpole"][v]), int(t["rpole"][v])) == want, v

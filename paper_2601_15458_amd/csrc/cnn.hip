@@ -168,8 +168,8 @@ struct ConvArgs {
 // The A fragments (8 consecutive span elements of one row) are 16-byte
 // global loads; the weights' K slice of each step, shared by the eight
 // wavefronts, is staged in LDS ([co][32], padded) and read as 16-byte
-// fragments.  The slice and the A fragments of the next step are loaded
-// while the current step's MFMAs run (two LDS buffers, one barrier a step).
+// fragments.  Global loads run two steps ahead of the MFMAs, the LDS slice
+// one step (two LDS buffers, one barrier a step).
 constexpr int kBp = 40;   // LDS pitch of a staged weight row (32 + 8)
 
 template <int CIN, int KDP, int EPI>
@@ -198,20 +198,29 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     constexpr int kSteps = KDP / 32;
     constexpr int kTaps = CIN >= 32 ? kKer : kSteps;   // K steps per column block
     auto k_of = [](int step) { return CIN >= 32 ? (step % kTaps) * CIN + (step / kTaps) * 32 : step * 32; };
-    uint4 wnext = *(const uint4 *)(wsrc + k_of(0));
-    bf16x8 anext[2];
+    // Loads run two steps ahead (slot = step & 1; the loop is unrolled, so
+    // the slots are fixed registers): the weight quarter a thread stages and
+    // the A fragments of step s + 2 are requested while step s computes.
+    uint4 wq[2];
+    bf16x8 aq[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) anext[i] = *(const bf16x8 *)(arow[i] + k_of(0));
-    *(uint4 *)(sb[0] + sco * kBp + sq) = wnext;
+    for (int s0 = 0; s0 < 2 && s0 < kSteps; ++s0) {
+        wq[s0] = *(const uint4 *)(wsrc + k_of(s0));
+#pragma unroll
+        for (int i = 0; i < 2; ++i) aq[s0][i] = *(const bf16x8 *)(arow[i] + k_of(s0));
+    }
+    *(uint4 *)(sb[0] + sco * kBp + sq) = wq[0];
     __syncthreads();
+#pragma unroll
     for (int step = 0; step < kSteps; ++step) {
         const int cur = step & 1;
-        bf16x8 af[2] = {anext[0], anext[1]};
-        if (step + 1 < kSteps) {
-            const int k1 = k_of(step + 1);
-            wnext = *(const uint4 *)(wsrc + k1);
+        const bf16x8 af[2] = {aq[cur][0], aq[cur][1]};
+        const uint4 wstage = wq[cur ^ 1];          // weights of step + 1
+        if (step + 2 < kSteps) {
+            const int k2 = k_of(step + 2);
+            wq[cur] = *(const uint4 *)(wsrc + k2);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) anext[i] = *(const bf16x8 *)(arow[i] + k1);
+            for (int i = 0; i < 2; ++i) aq[cur][i] = *(const bf16x8 *)(arow[i] + k2);
         }
         bf16x8 bfr[8];
 #pragma unroll
@@ -221,7 +230,7 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
-        if (step + 1 < kSteps) *(uint4 *)(sb[cur ^ 1] + sco * kBp + sq) = wnext;
+        if (step + 1 < kSteps) *(uint4 *)(sb[cur ^ 1] + sco * kBp + sq) = wstage;
         __syncthreads();
     }
     // The weights are the first MFMA operand, so tile (i, j) is the

@@ -416,12 +416,13 @@ def bench_pruned(msadp, synth, torch, args):
                "random": (learned.control_embeddings(S, "random", seed=14), 0.0)}
     # (ranker, topk, exact_below): pure top-k pruning of every cluster, and
     # the hybrid that keeps the full median for clusters it finds cheap
+    # the four rankers at top-16; more candidates (64, 96) and the hybrid
+    # that keeps the full median for clusters of at most 2048 members, the
+    # ways to reach 99 % agreement
     points = [("cnn", args.topk, 0), ("cnn_raw", args.topk, 0), ("shortest", args.topk, 0),
               ("random", args.topk, 0),
-              ("cnn", args.topk, args.exact_below), ("shortest", args.topk, args.exact_below),
-              ("cnn", args.topk, 4 * args.exact_below),
-              ("cnn", args.topk, 8 * args.exact_below),
-              ("shortest", args.topk, 8 * args.exact_below)]
+              ("cnn", 64, 0), ("cnn", 96, 0), ("shortest", 96, 0),
+              ("cnn", args.topk, args.exact_below), ("cnn", args.topk, 8 * args.exact_below)]
     if args.points:
         points = []
         for item in args.points.split(","):

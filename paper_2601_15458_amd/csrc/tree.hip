@@ -694,15 +694,49 @@ __device__ __forceinline__ bool key_less(uint64_t s0, uint32_t i0, uint64_t s1, 
     return s0 < s1 || (s0 == s1 && i0 < i1);
 }
 
+// Ascending bitonic sort of n (a power of two, n <= kTopkSel) keys (e, i)
+// in LDS by the whole block.
+__device__ void block_sort_keys(uint64_t *e, uint32_t *id, int n) {
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const bool swap = up ? key_less(e[hi], id[hi], e[lo], id[lo])
+                                     : key_less(e[lo], id[lo], e[hi], id[hi]);
+                if (swap) {
+                    const uint64_t te = e[lo];
+                    const uint32_t ti = id[lo];
+                    e[lo] = e[hi];
+                    id[lo] = id[hi];
+                    e[hi] = te;
+                    id[hi] = ti;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+constexpr int kTopkThreads = 256;
+constexpr int kTopkSel = 2048;      // members a selection may collect in LDS
+
 // Candidates of each cluster, from its first candidate slot on: every member
 // of a cluster of at most max(exact_below, topk) members (one full row sum
-// each, which keeps every work item 64 texts wide); otherwise the topk members with the
-// least estimated row sum (lowest input index on ties), by topk rounds of a
-// block-wide minimum over the members above the last pick.  Clears the
+// each, which keeps every work item 64 texts wide); otherwise the topk members
+// with the least estimated row sum (lowest input index on ties).  Selection:
+// each thread takes the least key of its strided share of the members; T =
+// the topk-th least of those 256 keys bounds at least topk members (one per
+// thread), so the topk least keys are among the members with key <= T, which
+// are collected in LDS and sorted.  If topk exceeds the thread count or more
+// than kTopkSel members fall under T, topk rounds of a block-wide minimum
+// over the members above the last pick are taken instead.  Clears the
 // candidates' sums and sets the work of the candidate-sum pass.
-__global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
-    __shared__ uint64_t rs[256];
-    __shared__ uint32_t ri[256];
+__global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a) {
+    __shared__ uint64_t se[kTopkSel];
+    __shared__ uint32_t si[kTopkSel];
+    __shared__ uint32_t count;
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t v = lvl + q;
@@ -712,34 +746,83 @@ __global__ void __launch_bounds__(256) k_topk(TreeArgs a) {
         if (k <= a.exact_below || k <= a.topk) {
             for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.cand[base + i] = a.perm[ms + i];
         } else {
-            uint64_t last_s = 0;
-            uint32_t last_i = 0;
-            bool have_last = false;
-            for (int64_t j = 0; j < nc; ++j) {
-                uint64_t bs = ~0ull;
+            bool done = false;
+            if (nc <= kTopkThreads) {
+                // least key of this thread's share
+                uint64_t be = ~0ull;
                 uint32_t bi = ~0u;
                 for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
                     const uint64_t sv = a.rowsum[ms + i];
                     const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
-                    if (have_last && !key_less(last_s, last_i, sv, oi)) continue;
-                    if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; }
+                    if (key_less(sv, oi, be, bi)) { be = sv; bi = oi; }
                 }
-                rs[threadIdx.x] = bs;
-                ri[threadIdx.x] = bi;
+                se[threadIdx.x] = be;
+                si[threadIdx.x] = bi;
+                if (threadIdx.x == 0) count = 0;
                 __syncthreads();
-                for (int o = 128; o >= 1; o >>= 1) {
-                    if (threadIdx.x < o && key_less(rs[threadIdx.x + o], ri[threadIdx.x + o],
-                                                    rs[threadIdx.x], ri[threadIdx.x])) {
-                        rs[threadIdx.x] = rs[threadIdx.x + o];
-                        ri[threadIdx.x] = ri[threadIdx.x + o];
+                block_sort_keys(se, si, kTopkThreads);
+                const uint64_t te = se[nc - 1];
+                const uint32_t ti = si[nc - 1];
+                __syncthreads();
+                // every member with key <= (te, ti)
+                for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+                    const uint64_t sv = a.rowsum[ms + i];
+                    const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
+                    if (!key_less(te, ti, sv, oi)) {
+                        const uint32_t slot = atomicAdd(&count, 1u);
+                        if (slot < (uint32_t)kTopkSel) {
+                            se[slot] = sv;
+                            si[slot] = oi;
+                        }
+                    }
+                }
+                __syncthreads();
+                const uint32_t got = count;
+                if (got <= (uint32_t)kTopkSel) {
+                    int n2 = 1;
+                    while (n2 < (int)got) n2 <<= 1;
+                    for (int i = (int)got + threadIdx.x; i < n2; i += blockDim.x) {
+                        se[i] = ~0ull;
+                        si[i] = ~0u;
                     }
                     __syncthreads();
+                    block_sort_keys(se, si, n2);
+                    for (int64_t j = threadIdx.x; j < nc; j += blockDim.x)
+                        a.cand[base + j] = a.rank_of[si[j]];
+                    done = true;
                 }
-                last_s = rs[0];
-                last_i = ri[0];
-                have_last = true;
-                if (threadIdx.x == 0) a.cand[base + j] = a.rank_of[last_i];
                 __syncthreads();
+            }
+            if (!done) {
+                uint64_t last_s = 0;
+                uint32_t last_i = 0;
+                bool have_last = false;
+                for (int64_t j = 0; j < nc; ++j) {
+                    uint64_t bs = ~0ull;
+                    uint32_t bi = ~0u;
+                    for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+                        const uint64_t sv = a.rowsum[ms + i];
+                        const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
+                        if (have_last && !key_less(last_s, last_i, sv, oi)) continue;
+                        if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; }
+                    }
+                    se[threadIdx.x] = bs;
+                    si[threadIdx.x] = bi;
+                    __syncthreads();
+                    for (int o = kTopkThreads / 2; o >= 1; o >>= 1) {
+                        if (threadIdx.x < o && key_less(se[threadIdx.x + o], si[threadIdx.x + o],
+                                                        se[threadIdx.x], si[threadIdx.x])) {
+                            se[threadIdx.x] = se[threadIdx.x + o];
+                            si[threadIdx.x] = si[threadIdx.x + o];
+                        }
+                        __syncthreads();
+                    }
+                    last_s = se[0];
+                    last_i = si[0];
+                    have_last = true;
+                    if (threadIdx.x == 0) a.cand[base + j] = a.rank_of[last_i];
+                    __syncthreads();
+                }
             }
         }
         if (threadIdx.x == 0) a.cnt[q] = k >= 2 ? nc * ((k + 63) / 64) : 0;
@@ -783,7 +866,7 @@ static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s)
     } else {
         hipLaunchKernelGGL(k_emb_rowsum, dim3(egrid), tb, 0, s, a);
         hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.ncand, a.coff, a.desc);
-        hipLaunchKernelGGL(k_topk, cg, cb, 0, s, a);
+        hipLaunchKernelGGL(k_topk, cg, dim3(kTopkThreads), 0, s, a);
         hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
         hipLaunchKernelGGL((k_tree_lev<WMAX, kCandSum>), lg, tb, 0, s, a);

@@ -68,6 +68,15 @@ def test_exact_below_and_large_topk(topk, exact_below):
              exact_below=exact_below)
 
 
+@pytest.mark.parametrize("topk", [96, 256, 300])
+def test_larger_candidate_lists(topk):
+    """Candidate lists up to the thread count take the threshold selection,
+    above it the round-by-round one; both give the oracle's candidates."""
+    codes, off = synth.random_set(500 + topk, 900, 20, 120, 4)
+    n = len(off) - 1
+    _compare(codes, off, 4, _emb(44 + topk, n, 0.5), topk, emb_offset=0.75)
+
+
 @pytest.mark.parametrize("offset", [0.3, 7.5])
 def test_calibration_offset(offset):
     d = synth.tiny()

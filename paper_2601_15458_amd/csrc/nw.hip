@@ -275,56 +275,65 @@ __global__ void __launch_bounds__(64) k_nw_traceback(TbArgs a) {
     }
     uint8_t *out = a.ops + a.ops_off[p];
     const uint2 *rec = (const uint2 *)(a.tb + a.tb_off[p]);
-    const int64_t W = tb_words((int32_t)m);
-    int64_t i = m, j = n;
+    // lengths are below 2^16, so every coordinate fits 32 bits
+    const int32_t W = (int32_t)tb_words((int32_t)m);
+    const int32_t nn = (int32_t)n;
+    int32_t i = (int32_t)m, j = (int32_t)n;
     int64_t emitted = 0;
     uint32_t obuf = 0;
-    int64_t s_hi = -1000000, g_hi = -1000000;
+    // The tile: records of anti-diagonals s_hi - l (lane l) for words g_hi - k,
+    // reloaded when the walk leaves it.  (Loading the next tile ahead of
+    // time, halfway through the current one, measured slower.)
+    int32_t s_hi = -1000000, g_hi = -1000000;
     uint2 tile[4];
-    while (i > 0 || j > 0) {
-        uint32_t op;
-        if (i == 0) {
-            op = 2;
-        } else if (j == 0) {
-            op = 1;
-        } else {
-            const int64_t g = (i - 1) >> 5;
-            const int64_t sp = (j - 1) + g;
-            int64_t L = s_hi - sp, q = g_hi - g;
-            if (L < 0 || L >= 64 || q < 0 || q >= 4) {
-                s_hi = sp;
-                g_hi = g;
-                const int64_t sl = s_hi - lane;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int64_t gk = g_hi - k;
-                    // record (sl, gk) exists iff its column j' = sl - gk is in [0, n)
-                    const int64_t jc = sl - gk;
-                    tile[k] = (gk >= 0 && jc >= 0 && jc < n) ? rec[sl * W + gk] : make_uint2(0, 0);
-                }
-                L = 0;
-                q = 0;
-            }
-            uint32_t mw, uw;
-            switch ((int)q) {
-                case 0: mw = __builtin_amdgcn_readlane(tile[0].x, (int)L); uw = __builtin_amdgcn_readlane(tile[0].y, (int)L); break;
-                case 1: mw = __builtin_amdgcn_readlane(tile[1].x, (int)L); uw = __builtin_amdgcn_readlane(tile[1].y, (int)L); break;
-                case 2: mw = __builtin_amdgcn_readlane(tile[2].x, (int)L); uw = __builtin_amdgcn_readlane(tile[2].y, (int)L); break;
-                default: mw = __builtin_amdgcn_readlane(tile[3].x, (int)L); uw = __builtin_amdgcn_readlane(tile[3].y, (int)L); break;
-            }
-            const uint32_t bit = (uint32_t)((i - 1) & 31);
-            op = ((mw >> bit) & 1u) ? 0u : (((uw >> bit) & 1u) ? 1u : 2u);
-        }
-        if (op == 0) { --i; --j; }
-        else if (op == 1) { --i; }
-        else { --j; }
-        const int slot = (int)(emitted & 63);
-        if (lane == slot) obuf = op;
+    // one op: recorded in lane (emitted mod 64), stored 64 at a time
+    auto emit = [&](uint32_t op) {
+        obuf = lane == (int)(emitted & 63) ? op : obuf;
         ++emitted;
-        if ((emitted & 63) == 0) {
-            out[cap - emitted + (63 - lane)] = (uint8_t)obuf;
+        if ((emitted & 63) == 0) out[cap - emitted + (63 - lane)] = (uint8_t)obuf;
+    };
+    // Inside the matrix: the step's record comes from the tile, and the
+    // choice is made with selects rather than branches.
+    while (i > 0 && j > 0) {
+        const int32_t g = (i - 1) >> 5;
+        const int32_t sp = (j - 1) + g;
+        if (s_hi - sp < 0 || s_hi - sp >= 64 || g_hi - g < 0 || g_hi - g >= 4) {
+            s_hi = sp;
+            g_hi = g;
+            const int64_t sl = s_hi - lane;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t gk = g_hi - k;
+                // record (sl, gk) exists iff its column j' = sl - gk is in [0, n)
+                const int64_t jc = sl - gk;
+                tile[k] = (gk >= 0 && jc >= 0 && jc < nn) ? rec[sl * W + gk] : make_uint2(0, 0);
+            }
+            // wait for the tile here, so that the common path carries no
+            // wait (on this GPU a vector-memory wait would also wait for the
+            // pending op stores)
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
         }
+        const int L = s_hi - sp, q = g_hi - g;
+        const uint32_t m0 = __builtin_amdgcn_readlane(tile[0].x, L);
+        const uint32_t m1 = __builtin_amdgcn_readlane(tile[1].x, L);
+        const uint32_t m2 = __builtin_amdgcn_readlane(tile[2].x, L);
+        const uint32_t m3 = __builtin_amdgcn_readlane(tile[3].x, L);
+        const uint32_t u0 = __builtin_amdgcn_readlane(tile[0].y, L);
+        const uint32_t u1 = __builtin_amdgcn_readlane(tile[1].y, L);
+        const uint32_t u2 = __builtin_amdgcn_readlane(tile[2].y, L);
+        const uint32_t u3 = __builtin_amdgcn_readlane(tile[3].y, L);
+        const uint32_t mw = q == 0 ? m0 : q == 1 ? m1 : q == 2 ? m2 : m3;
+        const uint32_t uw = q == 0 ? u0 : q == 1 ? u1 : q == 2 ? u2 : u3;
+        const uint32_t bit = (uint32_t)((i - 1) & 31);
+        const uint32_t diag = (mw >> bit) & 1u, up = (uw >> bit) & 1u;
+        const uint32_t op = diag ? 0u : (up ? 1u : 2u);
+        i -= (op != 2u) ? 1 : 0;
+        j -= (op != 1u) ? 1 : 0;
+        emit(op);
     }
+    // on the first row or column only gaps remain
+    for (; i > 0; --i) emit(1u);
+    for (; j > 0; --j) emit(2u);
     const int rem = (int)(emitted & 63);
     if (rem && lane < rem) out[cap - emitted + (rem - 1 - lane)] = (uint8_t)obuf;
     // the alignment now sits in out[cap - emitted .. cap); move it to the front

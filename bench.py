@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="nw,tree,pruned",
-                    help="legs after the all-pairs one: any of nw, tree, pruned (comma list)")
+    ap.add_argument("--legs", default="nw,tree,pruned,machine",
+                    help="legs after the all-pairs one: any of nw, tree, pruned, machine "
+                         "(comma list)")
     ap.add_argument("--quick", action="store_true", help="only the all-pairs leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
@@ -182,7 +183,8 @@ def main():
                      "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3)},
     }
     legs = [] if args.quick else [x for x in args.legs.split(",") if x]
-    for name, fn in (("nw", bench_nw), ("tree", bench_tree), ("pruned", bench_pruned)):
+    for name, fn in (("nw", bench_nw), ("tree", bench_tree), ("pruned", bench_pruned),
+                     ("machine", bench_machine)):
         if name in legs:
             try:
                 res[name] = fn(msadp, synth, torch, args)
@@ -203,6 +205,46 @@ def _time_calls(torch, fn, stream, reps):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def bench_machine(msadp, synth, torch, args):
+    """Measured machine rates beside the vendor figures the roofline
+    fractions use: VALU 32-bit lane-instructions/s (independent xor/add
+    chains), MFMA operations/s for the shapes the kernels use, and HBM
+    bytes/s of a streaming copy (read + write bytes over kernel time)."""
+    stream = torch.cuda.current_stream()
+    blocks = 256 * 8                       # eight wavefronts per SIMD
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    out = {}
+    ops = msadp.probe_valu(blocks, 4096, sink, stream)
+    ms = _time_calls(torch, lambda: msadp.probe_valu(blocks, 4096, sink, stream), stream, 3)
+    out["valu_lane_ops"] = {"measured": round(ops / (ms * 1e-3) / 1e12, 2), "unit": "T/s",
+                            "vendor_single_issue": round(VALU_PEAK_LANE_OPS / 2e12, 1),
+                            "vendor_dual_issue": round(VALU_PEAK_LANE_OPS / 1e12, 1)}
+    vendor = {"bf16": 2500.0, "i8": 5000.0}
+    for kind in msadp.PROBE_MFMA:
+        per_trip = msadp.probe_mfma(kind, blocks, 1, sink, stream)
+        iters = max(1, (1 << 45) // per_trip)      # 7-14 ms at the vendor rates
+        ops = msadp.probe_mfma(kind, blocks, iters, sink, stream)
+        ms = _time_calls(torch, lambda: msadp.probe_mfma(kind, blocks, iters, sink, stream),
+                         stream, 3)
+        out["mfma_" + kind] = {"measured": round(ops / (ms * 1e-3) / 1e12, 1),
+                               "unit": "TFLOP/s" if kind.startswith("bf16") else "TOP/s",
+                               "vendor": vendor[kind.split("_")[0]]}
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    rates = {}
+    for b in (256, 512, 1024):            # the best of a few grid sizes
+        nb = msadp.probe_copy(src, dst, b, stream)
+        ms = _time_calls(torch, lambda: msadp.probe_copy(src, dst, b, stream), stream, 5)
+        rates[b] = nb / (ms * 1e-3) / 1e9
+    best = max(rates, key=rates.get)
+    out["hbm_copy"] = {"measured": round(rates[best], 1), "unit": "GB/s",
+                       "vendor": HBM_PEAK_GBS, "bytes": nb, "workgroups": best}
+    torch.cuda.synchronize()
+    del src, dst
+    return out
 
 
 def tune_lev(msadp, torch, A, ap, stream, reps=2):

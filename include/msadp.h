@@ -335,6 +335,37 @@ int msa_autotune_tree(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, in
                       void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
                       int32_t *d_status, hipStream_t s);
 
+/* ------------------------------------------------------------------ */
+/* Machine-rate probes.  These compute nothing from the method: they are
+ * the measured counterparts of the vendor peaks (VALU lane-ops/s, MFMA
+ * operations/s, HBM bytes/s) against which the roofline fractions of the
+ * kernels above are read.  Each launches one kernel of `blocks` workgroups
+ * of 256 threads on s and returns at once; the caller times the launch.
+ * They return MSA_EINVAL for blocks <= 0, iters <= 0, null pointers or an
+ * unknown kind, and MSA_EDEVICE for a failed launch. */
+
+/* Eight independent chains of 32-bit xor / add per lane (a ^= b; b += a),
+ * iters trips of 128 VALU instructions each.  sink: device, blocks * 256 uint32 (written, its
+ * values meaningless).  *ops (host) = lane-instructions of the launch. */
+int msa_probe_valu(int32_t blocks, int32_t iters, uint32_t *sink, int64_t *ops, hipStream_t s);
+
+enum {
+    MSA_PROBE_MFMA_BF16_16X16X32 = 0,   /* v_mfma_f32_16x16x32_bf16 (the CNN) */
+    MSA_PROBE_MFMA_BF16_32X32X16 = 1,   /* v_mfma_f32_32x32x16_bf16           */
+    MSA_PROBE_MFMA_I8_16X16X64 = 2,     /* v_mfma_i32_16x16x64_i8 (pair dist.) */
+    MSA_PROBE_MFMA_I8_32X32X32 = 3      /* v_mfma_i32_32x32x32_i8             */
+};
+/* Eight independent accumulators per wavefront, iters trips of sixteen
+ * matrix instructions of the given kind (two per accumulator).  sink: as above.  *ops (host) =
+ * 2 * M * N * K per instruction times the instructions of the launch. */
+int msa_probe_mfma(int32_t kind, int32_t blocks, int32_t iters, uint32_t *sink, int64_t *ops,
+                   hipStream_t s);
+
+/* Streaming copy of `bytes` (a multiple of 16) from src to dst (device,
+ * 16-byte aligned, not overlapping), 16 bytes per lane per access with
+ * non-temporal loads and stores.  bytes == 0 launches nothing. */
+int msa_probe_copy(const void *src, void *dst, size_t bytes, int32_t blocks, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

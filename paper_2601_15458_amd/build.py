@@ -11,6 +11,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 
+# Per-source extra flags.  probe.hip: keep MFMA accumulators in VGPRs, so
+# that its loops hold nothing but the matrix instructions.
+EXTRA_FLAGS = {"probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
@@ -26,7 +31,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in sources():
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = common + ["-c", src, "-o", obj]
+        cmd = common + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True)))

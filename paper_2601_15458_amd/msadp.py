@@ -82,6 +82,9 @@ SIGNATURES = {
     "cnn_embed": (C.c_int, [P, SP, P, C.c_int32, C.c_int64, P, P, C.c_size_t, P, P]),
     "cnn_train_step": (C.c_int, [P, SP, P, C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_float,
                                  C.c_int32, P, P, C.c_size_t, P, P]),
+    "msa_probe_valu": (C.c_int, [C.c_int32, C.c_int32, P, C.POINTER(C.c_int64), P]),
+    "msa_probe_mfma": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, C.POINTER(C.c_int64), P]),
+    "msa_probe_copy": (C.c_int, [P, P, C.c_size_t, C.c_int32, P]),
 }
 
 _lib = None
@@ -706,3 +709,32 @@ class Embedder:
         _check(rc, "cnn_train_step")
         st.check("cnn_train_step")
         return float(loss.item())
+
+
+# ---------------------------------------------------------- machine probes
+PROBE_MFMA = {"bf16_16x16x32": 0, "bf16_32x32x16": 1, "i8_16x16x64": 2, "i8_32x32x32": 3}
+
+
+def probe_valu(blocks: int, iters: int, sink: torch.Tensor, stream=None) -> int:
+    """Launch the VALU rate probe; returns the lane-instructions it runs."""
+    ops = C.c_int64(0)
+    _check(lib().msa_probe_valu(int(blocks), int(iters), _ptr(sink), C.byref(ops),
+                                _stream(stream)), "msa_probe_valu")
+    return ops.value
+
+
+def probe_mfma(kind: str, blocks: int, iters: int, sink: torch.Tensor, stream=None) -> int:
+    """Launch the MFMA rate probe of one shape; returns its operations."""
+    ops = C.c_int64(0)
+    _check(lib().msa_probe_mfma(PROBE_MFMA[kind], int(blocks), int(iters), _ptr(sink),
+                                C.byref(ops), _stream(stream)), "msa_probe_mfma")
+    return ops.value
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, blocks: int, stream=None) -> int:
+    """Launch the streaming copy probe over all of src; returns bytes moved."""
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nb
+    _check(lib().msa_probe_copy(_ptr(src), _ptr(dst), nb, int(blocks), _stream(stream)),
+           "msa_probe_copy")
+    return 2 * nb

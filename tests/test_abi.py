@@ -105,3 +105,21 @@ def test_nw_pattern_length_limit():
     fake = C.c_void_p(16)
     assert L.nw_batch(C.byref(a), C.byref(b), fake, fake, 1, fake, fake, fake, fake, 1 << 40,
                       None, None) == msadp.MSA_ERANGE
+
+
+def test_probe_host_validation():
+    L = msadp.lib()
+    fake = C.c_void_p(16)
+    ops = C.c_int64(0)
+    E = msadp.MSA_EINVAL
+    assert L.msa_probe_valu(0, 1, fake, C.byref(ops), None) == E
+    assert L.msa_probe_valu(1, 0, fake, C.byref(ops), None) == E
+    assert L.msa_probe_valu(1, 1, None, C.byref(ops), None) == E
+    assert L.msa_probe_mfma(4, 1, 1, fake, C.byref(ops), None) == E
+    assert L.msa_probe_mfma(-1, 1, 1, fake, C.byref(ops), None) == E
+    assert L.msa_probe_mfma(0, 1, 1, fake, None, None) == E
+    assert L.msa_probe_copy(fake, fake, 24, 1, None) == E            # not a multiple of 16
+    assert L.msa_probe_copy(C.c_void_p(8), fake, 32, 1, None) == E   # misaligned
+    assert L.msa_probe_copy(fake, fake, 32, 0, None) == E
+    assert L.msa_probe_copy(fake, fake, 0, 1, None) == msadp.MSA_OK   # nothing to launch
+    assert ops.value == 0

@@ -31,7 +31,8 @@ constexpr int kKer = 5;      // kernel width
 constexpr int kLayers = 4;
 constexpr int kIn = 8;       // one-hot channels (sigma <= 8)
 constexpr int kLead = 8;     // zero rows before the first sequence
-constexpr int kTile = 256;   // rows per GEMM workgroup
+constexpr int kRowTiles = 4; // 16-row MFMA tiles per wavefront in the conv GEMM
+constexpr int kTile = 8 * 16 * kRowTiles;   // rows per GEMM workgroup (8 wavefronts)
 
 __host__ __device__ constexpr int cin_of(int l) { return l == 0 ? kIn : kW; }
 __host__ __device__ constexpr int kd_of(int l) { return kKer * cin_of(l); }              // 40 / 640
@@ -164,7 +165,10 @@ struct ConvArgs {
 };
 
 // Workgroup = 8 wavefronts = kTile output rows x 128 channels; wavefront w
-// owns rows [32 w, 32 w + 32): 2 x 8 tiles of 16 x 16, K in steps of 32.
+// owns rows [16 R w, 16 R (w + 1)), R = kRowTiles: R x 8 tiles of 16 x 16, K
+// in steps of 32.  Each weight fragment read from LDS feeds R MFMAs, so R
+// sets the LDS bytes per FLOP (the LDS read rate, not the matrix unit, is
+// what limits the GEMM at R = 2).
 // The A fragments (8 consecutive span elements of one row) are 16-byte
 // global loads; the weights' K slice of each step, shared by the eight
 // wavefronts, is staged in LDS ([co][32], padded) and read as 16-byte
@@ -177,17 +181,17 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     __shared__ __attribute__((aligned(16))) bf16_t sb[2][kW * kBp];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * kTile + 32 * w;
-    f32x4 acc[2][8];
+    const int64_t row0 = (int64_t)blockIdx.x * kTile + 16 * kRowTiles * w;
+    f32x4 acc[kRowTiles][8];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < kRowTiles; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
     const int kq = 8 * (lane >> 4);   // this lane's first K element of a step
     const int li = lane & 15;
-    const bf16_t *arow[2];
+    const bf16_t *arow[kRowTiles];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < kRowTiles; ++i)
         arow[i] = a.X + (kLead + row0 + 16 * i + li - 2) * CIN + kq;
     // staging role: weight row co = t / 4, quarter q = t % 4 (8 of the 32 K)
     const int sco = threadIdx.x >> 2, sq = (threadIdx.x & 3) * 8;
@@ -202,31 +206,33 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     // the slots are fixed registers): the weight quarter a thread stages and
     // the A fragments of step s + 2 are requested while step s computes.
     uint4 wq[2];
-    bf16x8 aq[2][2];
+    bf16x8 aq[2][kRowTiles];
 #pragma unroll
     for (int s0 = 0; s0 < 2 && s0 < kSteps; ++s0) {
         wq[s0] = *(const uint4 *)(wsrc + k_of(s0));
 #pragma unroll
-        for (int i = 0; i < 2; ++i) aq[s0][i] = *(const bf16x8 *)(arow[i] + k_of(s0));
+        for (int i = 0; i < kRowTiles; ++i) aq[s0][i] = *(const bf16x8 *)(arow[i] + k_of(s0));
     }
     *(uint4 *)(sb[0] + sco * kBp + sq) = wq[0];
     __syncthreads();
 #pragma unroll
     for (int step = 0; step < kSteps; ++step) {
         const int cur = step & 1;
-        const bf16x8 af[2] = {aq[cur][0], aq[cur][1]};
+        bf16x8 af[kRowTiles];
+#pragma unroll
+        for (int i = 0; i < kRowTiles; ++i) af[i] = aq[cur][i];
         const uint4 wstage = wq[cur ^ 1];          // weights of step + 1
         if (step + 2 < kSteps) {
             const int k2 = k_of(step + 2);
             wq[cur] = *(const uint4 *)(wsrc + k2);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) aq[cur][i] = *(const bf16x8 *)(arow[i] + k2);
+            for (int i = 0; i < kRowTiles; ++i) aq[cur][i] = *(const bf16x8 *)(arow[i] + k2);
         }
         bf16x8 bfr[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) bfr[j] = *(const bf16x8 *)(sb[cur] + (16 * j + li) * kBp + kq);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < kRowTiles; ++i)
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
@@ -237,7 +243,7 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     // transposed output: the lane holds channels 16 j + 4 (lane / 16) + r,
     // r = 0..3, of row 16 i + lane % 16, stored as one 4-channel piece.
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kRowTiles; ++i) {
         const int64_t row = row0 + 16 * i + li;
         if (row >= a.rows) continue;
         const bool data = a.rowseq[row] >= 0;

@@ -176,6 +176,42 @@ struct ConvArgs {
 // one step (two LDS buffers, one barrier a step).
 constexpr int kBp = 40;   // LDS pitch of a staged weight row (32 + 8)
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Lane i of every 16-lane row receives lane (i + N) mod 16 of the same row
+// (DPP row rotate right by 16 - N).
+template <int N>
+__device__ __forceinline__ uint32_t row_rotl(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x120 + (16 - N), 0xF, 0xF, false);
+}
+
+// A fragment of tap N from the tap-0 fragments of a tile (lo) and of the
+// tile below it (hi): in the 16 x 32 fragment, lane i of each 16-lane row
+// holds span row i, and tap N reads span row i + N, which is lane i + N of
+// lo, or lane i + N - 16 of hi once that passes the tile.
+template <int N>
+__device__ __forceinline__ bf16x8 shift_rows(bf16x8 lo, bf16x8 hi, int li) {
+    const u32x4 a = __builtin_bit_cast(u32x4, lo), b = __builtin_bit_cast(u32x4, hi);
+    const bool from_lo = li < 16 - N;
+    u32x4 r;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t x = row_rotl<N>(a[d]), y = row_rotl<N>(b[d]);
+        r[d] = from_lo ? x : y;
+    }
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+__device__ __forceinline__ bf16x8 tap_rows(bf16x8 lo, bf16x8 hi, int tap, int li) {
+    switch (tap) {
+    case 1: return shift_rows<1>(lo, hi, li);
+    case 2: return shift_rows<2>(lo, hi, li);
+    case 3: return shift_rows<3>(lo, hi, li);
+    case 4: return shift_rows<4>(lo, hi, li);
+    default: return lo;
+    }
+}
+
 template <int CIN, int KDP, int EPI>
 __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     __shared__ __attribute__((aligned(16))) bf16_t sb[2][kW * kBp];
@@ -204,14 +240,28 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     auto k_of = [](int step) { return CIN >= 32 ? (step % kTaps) * CIN + (step / kTaps) * 32 : step * 32; };
     // Loads run two steps ahead (slot = step & 1; the loop is unrolled, so
     // the slots are fixed registers): the weight quarter a thread stages and
-    // the A fragments of step s + 2 are requested while step s computes.
+    // (one-hot layer) the A fragments of step s + 2 are requested while step
+    // s computes.  For the 128-channel layers the five taps of a column block
+    // read the same rows shifted by one, so the block's tap-0 fragments (the
+    // wavefront's tiles plus the 16 rows below them) are loaded once, a
+    // column block ahead, and taps 1-4 are rotated out of them across lanes.
+    constexpr bool kShift = CIN >= 32;
+    constexpr int kBlocks = kShift ? kSteps / kKer : 1;
+    const bf16_t *ahalo = a.X + (kLead + row0 + 16 * kRowTiles + li - 2) * CIN + kq;
     uint4 wq[2];
     bf16x8 aq[2][kRowTiles];
+    bf16x8 tq[2][kRowTiles + 1];
 #pragma unroll
-    for (int s0 = 0; s0 < 2 && s0 < kSteps; ++s0) {
-        wq[s0] = *(const uint4 *)(wsrc + k_of(s0));
+    for (int s0 = 0; s0 < 2 && s0 < kSteps; ++s0) wq[s0] = *(const uint4 *)(wsrc + k_of(s0));
+    if constexpr (kShift) {
 #pragma unroll
-        for (int i = 0; i < kRowTiles; ++i) aq[s0][i] = *(const bf16x8 *)(arow[i] + k_of(s0));
+        for (int i = 0; i < kRowTiles; ++i) tq[0][i] = *(const bf16x8 *)(arow[i]);
+        tq[0][kRowTiles] = *(const bf16x8 *)(ahalo);
+    } else {
+#pragma unroll
+        for (int s0 = 0; s0 < 2 && s0 < kSteps; ++s0)
+#pragma unroll
+            for (int i = 0; i < kRowTiles; ++i) aq[s0][i] = *(const bf16x8 *)(arow[i] + k_of(s0));
     }
     *(uint4 *)(sb[0] + sco * kBp + sq) = wq[0];
     __syncthreads();
@@ -219,14 +269,28 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     for (int step = 0; step < kSteps; ++step) {
         const int cur = step & 1;
         bf16x8 af[kRowTiles];
+        if constexpr (kShift) {
+            const int cb = step / kKer, tap = step % kKer;
+            if (tap == 0 && cb + 1 < kBlocks) {
+                const int nb = (cb + 1) & 1, k1 = (cb + 1) * 32;
 #pragma unroll
-        for (int i = 0; i < kRowTiles; ++i) af[i] = aq[cur][i];
+                for (int i = 0; i < kRowTiles; ++i) tq[nb][i] = *(const bf16x8 *)(arow[i] + k1);
+                tq[nb][kRowTiles] = *(const bf16x8 *)(ahalo + k1);
+            }
+#pragma unroll
+            for (int i = 0; i < kRowTiles; ++i) af[i] = tap_rows(tq[cb & 1][i], tq[cb & 1][i + 1], tap, li);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kRowTiles; ++i) af[i] = aq[cur][i];
+        }
         const uint4 wstage = wq[cur ^ 1];          // weights of step + 1
         if (step + 2 < kSteps) {
             const int k2 = k_of(step + 2);
             wq[cur] = *(const uint4 *)(wsrc + k2);
+            if constexpr (!kShift) {
 #pragma unroll
-            for (int i = 0; i < kRowTiles; ++i) aq[cur][i] = *(const bf16x8 *)(arow[i] + k2);
+                for (int i = 0; i < kRowTiles; ++i) aq[cur][i] = *(const bf16x8 *)(arow[i] + k2);
+            }
         }
         bf16x8 bfr[8];
 #pragma unroll

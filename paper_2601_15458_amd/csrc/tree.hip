@@ -4,7 +4,9 @@
 //   1. medoid: row sums S[x] = sum_y f(x, y) over every pair of every
 //      cluster (the triangle of each cluster, each distance added to both
 //      ends), then c = the member with the least sum;
-//   2. l = argmax_x f(c, x); 3. r = argmax_x f(l, x) (f(l, .) kept);
+//   2. l = argmax_x f(c, x) (in the pruned mode without a pass of its own:
+//      the candidate pass also keeps each candidate's farthest member);
+//   3. r = argmax_x f(l, x) (f(l, .) kept);
 //   4. f(r, .); 5. stable split: L = {x : f(l,x) <= f(r,x)}, R = the rest;
 //   6. children numbered breadth-first (L before R) after the level.
 // Ties: the least sum / the largest distance with the lowest input index
@@ -80,6 +82,9 @@ struct TreeArgs {
     int64_t *coff;           // exclusive prefix of ncand: the cluster's first candidate
     int32_t *cand;           // [n] candidate ranks, cluster by cluster
     uint64_t *candsum;       // [n] exact row sums of the candidates
+    // [n] per candidate y the largest far key (f(y, x) << 32 | ~order(x))
+    // over the cluster's members x, y itself included
+    uint64_t *candkey;
 };
 
 constexpr int kClusterGrid = 2048;
@@ -118,6 +123,12 @@ __host__ __device__ inline int64_t tile_rows_before(int64_t I, int64_t nb) {
 __host__ __device__ inline int64_t emb_tiles(int64_t k) {
     const int64_t nb = (k + 63) / 64;
     return k >= 2 ? nb * (nb + 1) / 2 : 0;
+}
+
+// Key of the farthest member: the larger distance wins, then the lower input
+// index (the tie rule of the poles).
+__device__ __forceinline__ uint64_t far_key(int d, int32_t order_y) {
+    return ((uint64_t)(uint32_t)d << 32) | (0xFFFFFFFFu - (uint32_t)order_y);
 }
 
 // Level start: reset per-node fields, member sums and the medoid work list.
@@ -226,6 +237,8 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
         // The epilogue has no lane-dependent branch (see next_item): lanes
         // without a pair write to the spare slot n or add zero.
         const int64_t slot = valid ? tpos : (int64_t)a.n;
+        // the far key of the pattern row over this item's texts
+        const uint64_t key = valid ? far_key(d, a.order[trow]) : 0ull;
         if (MODE == kMedoid) {
             atomicAdd((unsigned long long *)&a.rowsum[slot],
                       (unsigned long long)(valid ? d : 0));
@@ -234,8 +247,6 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
                       (unsigned long long)(lane == 0 ? s : 0ull));
         }
         if (MODE == kPoleMax || MODE == kPoleMaxStore) {
-            const uint64_t key =
-                valid ? (((uint64_t)d << 32) | (0xFFFFFFFFu - (uint32_t)a.order[trow])) : 0ull;
             const uint64_t m = wave_max_u64(key);
             atomicMax((unsigned long long *)&a.key[q], (unsigned long long)m);
         }
@@ -243,6 +254,9 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
             const uint64_t s = wave_sum_u64(valid ? (uint64_t)d : 0ull);
             atomicAdd((unsigned long long *)&a.candsum[cslot],
                       (unsigned long long)(lane == 0 ? s : 0ull));
+            const uint64_t m = wave_max_u64(key);
+            atomicMax((unsigned long long *)&a.candkey[cslot],
+                      (unsigned long long)(lane == 0 ? m : 0ull));
         }
         if (MODE == kPoleMaxStore) a.dl[slot] = d;
         if (MODE == kPoleStore) a.dr[slot] = d;
@@ -742,7 +756,10 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a) {
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
         const int64_t nc = a.ncand[q], base = a.coff[q];
-        for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) a.candsum[base + j] = 0;
+        for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) {
+            a.candsum[base + j] = 0;
+            a.candkey[base + j] = 0;
+        }
         if (k <= a.exact_below || k <= a.topk) {
             for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.cand[base + i] = a.perm[ms + i];
         } else {
@@ -840,15 +857,17 @@ __global__ void k_pick_center_cand(TreeArgs a) {
         const int64_t nc = a.ncand[q], base = a.coff[q];
         uint64_t bs = ~0ull;
         uint32_t bi = ~0u;
+        int64_t bj = 0;
         for (int64_t j = 0; j < nc; ++j) {
             const uint64_t sv = a.candsum[base + j];
             const uint32_t oi = (uint32_t)a.order[a.cand[base + j]];
-            if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; }
+            if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; bj = j; }
         }
         if (k == 1) bi = (uint32_t)a.order[a.perm[a.mstart[v]]];
         a.center[v] = (int32_t)bi;
         a.pat[q] = a.rank_of[bi];
-        a.key[q] = 0;
+        // c's far key, kept by the candidate pass: the first pole without a pass
+        a.key[q] = nc > 0 && k >= 2 ? a.candkey[base + bj] : 0;
         a.cnt[q] = k >= 2 ? (k + 63) / 64 : 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
@@ -872,9 +891,14 @@ static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s)
         hipLaunchKernelGGL((k_tree_lev<WMAX, kCandSum>), lg, tb, 0, s, a);
         hipLaunchKernelGGL(k_pick_center_cand, dim3(256), dim3(256), 0, s, a);
     }
+    // l = argmax f(c, x).  Pruned mode: c's far key is already in key[q]
+    // from the candidate pass, and items[] only tells k_pick_pole which
+    // clusters have work.
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-    hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMax>), lg, tb, 0, s, a);
+    if (a.emb == nullptr) {
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+        hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMax>), lg, tb, 0, s, a);
+    }
     hipLaunchKernelGGL(k_pick_pole, dim3(256), dim3(256), 0, s, a, 0);
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
@@ -1007,6 +1031,7 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<int64_t>(n + 1);           // candidate offsets
     al.template take<int32_t>(n);               // candidates
     al.template take<uint64_t>(n);              // candidate sums
+    al.template take<uint64_t>(n);              // candidate far keys
     al.template take<int32_t>(2 * n);           // child ids of an evaluated tree
     al.template take<int32_t>(2 * n);
     al.template take<int8_t>(n * kEmbDim);      // embedding codes
@@ -1088,6 +1113,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.coff = cv.take<int64_t>(n + 1);
     a.cand = cv.take<int32_t>(n);
     a.candsum = cv.take<uint64_t>(n);
+    a.candkey = cv.take<uint64_t>(n);
     int32_t *eval_left = cv.take<int32_t>(2 * n);
     int32_t *eval_right = cv.take<int32_t>(2 * n);
     (void)eval_left;
@@ -1294,6 +1320,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.coff = cv.take<int64_t>(n + 1);
     a.cand = cv.take<int32_t>(n);
     a.candsum = cv.take<uint64_t>(n);
+    a.candkey = cv.take<uint64_t>(n);
     a.left = cv.take<int32_t>(2 * n);
     a.right = cv.take<int32_t>(2 * n);
     a.embq = cv.take<int8_t>(n * kEmbDim);

@@ -20,6 +20,9 @@
  *     the same with the median taken over candidates that a learned
  *     embedding ranks first (a surrogate of this project, not the paper's).
  *   - The bottom-up merge of Sec. 2.2.
+ *   - The column counts behind the alignment-quality metrics of Sec. 2.3
+ *     (gaps per row; per pair of rows the Hamming distance, the columns
+ *     where both rows hold a residue, and how many of those differ).
  * Pairs are independent, so OpenMP spreads them over host threads; that is
  * the only concession to speed.
  *
@@ -502,4 +505,43 @@ int64_t orc_merge(const uint8_t *codes, const int64_t *off, int32_t n, int32_t s
     free(aln);
     free(width);
     return W;
+}
+
+/*
+ * Alignment-quality counts (Sec. 2.3).  msa: rows x width row-major symbol
+ * codes, `gap` the gap code.  Per row: the number of gap symbols.  Per pair
+ * (ia[p], ib[p]): hamming = columns whose two symbols differ (a column of two
+ * gaps counts as equal); aligned = columns where neither symbol is a gap
+ * (the columns the p-score looks at); mismatched = aligned columns whose
+ * symbols differ.  A plain column loop per row and per pair.
+ */
+void orc_msa_row_gaps(const uint8_t *msa, int32_t rows, int32_t width, int32_t gap,
+                      int32_t *gaps) {
+    for (int32_t i = 0; i < rows; ++i) {
+        int32_t g = 0;
+        for (int32_t c = 0; c < width; ++c) g += msa[(int64_t)i * width + c] == gap;
+        gaps[i] = g;
+    }
+}
+
+void orc_msa_pair_counts(const uint8_t *msa, int32_t rows, int32_t width, int32_t gap,
+                         const int32_t *ia, const int32_t *ib, int64_t n_pairs,
+                         int32_t *hamming, int32_t *aligned, int32_t *mismatched) {
+    (void)rows;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const uint8_t *x = msa + (int64_t)ia[p] * width;
+        const uint8_t *y = msa + (int64_t)ib[p] * width;
+        int32_t h = 0, al = 0, mm = 0;
+        for (int32_t c = 0; c < width; ++c) {
+            const int differ = x[c] != y[c];
+            const int both = x[c] != gap && y[c] != gap;
+            h += differ;
+            al += both;
+            mm += both && differ;
+        }
+        hamming[p] = h;
+        aligned[p] = al;
+        mismatched[p] = mm;
+    }
 }

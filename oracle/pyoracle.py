@@ -45,6 +45,11 @@ def lib():
         L.orc_merge.restype = C.c_int64
         L.orc_merge.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
                                 C.c_int64]
+        L.orc_msa_row_gaps.restype = None
+        L.orc_msa_row_gaps.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P]
+        L.orc_msa_pair_counts.restype = None
+        L.orc_msa_pair_counts.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64,
+                                          P, P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -208,3 +213,60 @@ def merge(codes, offsets, sigma, t):
     if W < 0:
         raise RuntimeError("oracle merge failed")
     return msa[: n * W].reshape(n, W).copy()
+
+
+# ------------------------------------------------------- alignment quality
+# Sec. 2.3 defines three metrics on a finished alignment; Table 2 adds width
+# and stretch.  Readings where the text is short of a formula: the
+# percentage of gaps is the mean over rows of gaps / width, times 100; the
+# p-score of a pair is mismatched / aligned over the columns where both rows
+# hold a residue (pairs with no such column are left out) and the table
+# reports its minimum, mean and maximum over pairs; the distortion of a pair
+# is its Hamming distance (two gaps count as equal) over the Levenshtein
+# distance of the unaligned sequences (pairs at distance 0 are left out),
+# averaged over pairs; stretch = width / longest sequence.
+QUALITY_FIELDS = ("pct_gaps", "p_min", "p_avg", "p_max", "distortion", "stretch",
+                  "n_p_pairs", "n_d_pairs")
+
+
+def msa_row_gaps(msa, gap):
+    msa = np.ascontiguousarray(msa, dtype=np.uint8)
+    rows, width = msa.shape
+    out = np.zeros(rows, dtype=np.int32)
+    lib().orc_msa_row_gaps(_p(msa), rows, width, int(gap), _p(out))
+    return out
+
+
+def msa_pair_counts(msa, gap, ia, ib):
+    """(hamming, aligned, mismatched) int32 arrays for the pairs (ia[p], ib[p])."""
+    msa = np.ascontiguousarray(msa, dtype=np.uint8)
+    rows, width = msa.shape
+    ia = np.ascontiguousarray(ia, dtype=np.int32)
+    ib = np.ascontiguousarray(ib, dtype=np.int32)
+    n = len(ia)
+    h = np.zeros(n, dtype=np.int32)
+    a = np.zeros(n, dtype=np.int32)
+    m = np.zeros(n, dtype=np.int32)
+    lib().orc_msa_pair_counts(_p(msa), rows, width, int(gap), _p(ia), _p(ib), n, _p(h), _p(a),
+                              _p(m))
+    return h, a, m
+
+
+def msa_quality(msa, gap, max_len, ia, ib, lev):
+    """The metrics of QUALITY_FIELDS over the pairs (ia, ib); lev[p] is the
+    Levenshtein distance of the two unaligned sequences of pair p."""
+    msa = np.ascontiguousarray(msa, dtype=np.uint8)
+    rows, width = msa.shape
+    gaps = msa_row_gaps(msa, gap)
+    h, a, m = msa_pair_counts(msa, gap, ia, ib)
+    lev = np.asarray(lev, dtype=np.int64)
+    pct = 100.0 * sum(float(g) / width for g in gaps) / rows if rows and width else 0.0
+    ps = [float(mm) / float(al) for mm, al in zip(m.tolist(), a.tolist()) if al > 0]
+    ds = [float(hh) / float(d) for hh, d in zip(h.tolist(), lev.tolist()) if d > 0]
+    return {"pct_gaps": pct,
+            "p_min": min(ps) if ps else 0.0,
+            "p_avg": sum(ps) / len(ps) if ps else 0.0,
+            "p_max": max(ps) if ps else 0.0,
+            "distortion": sum(ds) / len(ds) if ds else 0.0,
+            "stretch": float(width) / max_len if max_len > 0 else 0.0,
+            "n_p_pairs": len(ps), "n_d_pairs": len(ds)}

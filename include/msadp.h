@@ -336,6 +336,45 @@ int msa_autotune_tree(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, in
                       int32_t *d_status, hipStream_t s);
 
 /* ------------------------------------------------------------------ */
+/* Alignment quality (Sec. 2.3: percentage of gaps, p-score, distance
+ * distortion; Table 2 also reports width and stretch).  msa: device,
+ * rows x width row-major symbol codes as msa_merge writes them, every code
+ * in [0, gap_code], gap_code <= 63 the gap symbol.  Readings where the
+ * paper gives no formula: a column of two gaps counts as equal; the p-score
+ * of a pair is (aligned columns whose residues differ) / (columns with a
+ * residue in both rows), pairs with no such column left out, reported as
+ * min / mean / max over pairs; the distortion of a pair is its Hamming
+ * distance over the Levenshtein distance of the unaligned sequences, pairs
+ * at distance 0 left out, averaged over pairs; % gaps = 100 x the mean
+ * over rows of gaps / width; stretch = width / max_len.  A code above
+ * gap_code sets MSA_DS_SYMBOL, a pair index outside [0, rows) MSA_DS_INDEX. */
+
+/* Workspace for msa_pair_counts and msa_quality (0 for invalid sizes). */
+size_t msa_quality_workspace_bytes(int32_t rows, int32_t width, int32_t gap_code);
+
+/* Per pair p: hamming[p] = columns whose symbols differ, aligned[p] =
+ * columns where neither row holds a gap, mismatched[p] = aligned columns
+ * whose symbols differ (device int32[n_pairs] each).  Pairs (ia[p], ib[p])
+ * (device int32), or with ia == ib == NULL every pair i < j of the rows at
+ * the condensed index i*rows - i*(i+1)/2 + (j - i - 1), the order of
+ * lev_allpairs (n_pairs must then be rows*(rows-1)/2). */
+int msa_pair_counts(const uint8_t *msa, int32_t rows, int32_t width, int32_t gap_code,
+                    const int32_t *ia, const int32_t *ib, int64_t n_pairs, int32_t *hamming,
+                    int32_t *aligned, int32_t *mismatched, void *ws, size_t ws_bytes,
+                    int32_t *d_status, hipStream_t s);
+
+/* The metrics from the counts of msa_pair_counts and lev[p] (device uint16,
+ * the distance of pair p's unaligned sequences, e.g. lev_allpairs' output;
+ * NULL skips the distortion).  out: device double[8] = {pct_gaps, p_min,
+ * p_avg, p_max, distortion, stretch, pairs in the p-score, pairs in the
+ * distortion}; a metric with no pair is 0.  The sums run in a fixed order,
+ * so equal inputs give equal bits. */
+int msa_quality(const uint8_t *msa, int32_t rows, int32_t width, int32_t gap_code,
+                int32_t max_len, const int32_t *hamming, const int32_t *aligned,
+                const int32_t *mismatched, const uint16_t *lev, int64_t n_pairs, double *out,
+                void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
+/* ------------------------------------------------------------------ */
 /* Machine-rate probes.  These compute nothing from the method: they are
  * the measured counterparts of the vendor peaks (VALU lane-ops/s, MFMA
  * operations/s, HBM bytes/s) against which the roofline fractions of the

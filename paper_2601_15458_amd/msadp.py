@@ -82,6 +82,11 @@ SIGNATURES = {
     "cnn_embed": (C.c_int, [P, SP, P, C.c_int32, C.c_int64, P, P, C.c_size_t, P, P]),
     "cnn_train_step": (C.c_int, [P, SP, P, C.c_int32, C.c_int64, P, P, P, C.c_int32, C.c_float,
                                  C.c_int32, P, P, C.c_size_t, P, P]),
+    "msa_quality_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "msa_pair_counts": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int64, P, P, P,
+                                  P, C.c_size_t, P, P]),
+    "msa_quality": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, P,
+                              C.c_int64, P, P, C.c_size_t, P, P]),
     "msa_probe_valu": (C.c_int, [C.c_int32, C.c_int32, P, C.POINTER(C.c_int64), P]),
     "msa_probe_mfma": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, C.POINTER(C.c_int64), P]),
     "msa_probe_copy": (C.c_int, [P, P, C.c_size_t, C.c_int32, P]),
@@ -514,6 +519,72 @@ def align(S: Seqs, use_graph=False, stream=None):
         tb.st.check("tree_build")
         msa = msa_merge(S, tree, stream=stream)
     return tree.host(), msa
+
+
+# ------------------------------------------------------- alignment quality
+QUALITY_FIELDS = ("pct_gaps", "p_min", "p_avg", "p_max", "distortion", "stretch",
+                  "n_p_pairs", "n_d_pairs")
+
+
+def _msa_dev(msa):
+    if isinstance(msa, torch.Tensor):
+        return msa.to(device=_device(), dtype=torch.uint8).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(msa, dtype=np.uint8)).to(_device())
+
+
+class Quality:
+    """Alignment-quality metrics (msa_pair_counts, msa_quality) of one
+    alignment held on the device: rows x width codes, `gap` the gap code."""
+
+    def __init__(self, msa, gap: int):
+        self.msa = _msa_dev(msa)
+        self.rows, self.width = (int(x) for x in self.msa.shape)
+        self.gap = int(gap)
+        self.wsb = lib().msa_quality_workspace_bytes(self.rows, self.width, self.gap)
+        if self.wsb == 0:
+            raise MsaError(MSA_EINVAL, "msa_quality_workspace_bytes")
+        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=self.msa.device)
+        self.st = Status(self.msa.device)
+
+    def pair_counts(self, ia=None, ib=None, stream=None):
+        """(hamming, aligned, mismatched) int32 device tensors; all pairs
+        i < j in condensed order when ia and ib are None."""
+        dev = self.msa.device
+        if ia is None:
+            n = self.rows * (self.rows - 1) // 2
+            dia = dib = None
+        else:
+            dia, dib = _i32(ia, dev), _i32(ib, dev)
+            n = int(dia.numel())
+        h = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        al = torch.empty_like(h)
+        mm = torch.empty_like(h)
+        rc = lib().msa_pair_counts(_ptr(self.msa), self.rows, self.width, self.gap, _ptr(dia),
+                                   _ptr(dib), n, _ptr(h), _ptr(al), _ptr(mm), _ptr(self.ws),
+                                   self.wsb, _ptr(self.st.t), _stream(stream))
+        _check(rc, "msa_pair_counts")
+        return h[:n], al[:n], mm[:n]
+
+    def metrics(self, counts, max_len: int, lev=None, stream=None):
+        """Dict of QUALITY_FIELDS from pair_counts' output and the pairs'
+        Levenshtein distances (device uint16 tensor, same order) or None."""
+        h, al, mm = counts
+        n = int(h.numel())
+        for t in (h, al, mm):
+            assert t.dtype == torch.int32 and t.is_cuda and t.numel() == n and t.is_contiguous()
+        if lev is not None:
+            assert lev.dtype == torch.uint16 and lev.is_cuda and lev.is_contiguous()
+            assert lev.numel() >= n, "one distance per pair"
+        out = torch.zeros(8, dtype=torch.float64, device=self.msa.device)
+        rc = lib().msa_quality(_ptr(self.msa), self.rows, self.width, self.gap, int(max_len),
+                               _ptr(h), _ptr(al), _ptr(mm), _ptr(lev), n, _ptr(out),
+                               _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
+        _check(rc, "msa_quality")
+        v = out.cpu().numpy()
+        self.st.check("msa_quality")
+        d = dict(zip(QUALITY_FIELDS, (float(x) for x in v)))
+        d["n_p_pairs"], d["n_d_pairs"] = int(v[6]), int(v[7])
+        return d
 
 
 # ---------------------------------------------------------------- tuning

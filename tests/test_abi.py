@@ -123,3 +123,37 @@ def test_probe_host_validation():
     assert L.msa_probe_copy(fake, fake, 32, 0, None) == E
     assert L.msa_probe_copy(fake, fake, 0, 1, None) == msadp.MSA_OK   # nothing to launch
     assert ops.value == 0
+
+
+def test_quality_host_validation():
+    L = msadp.lib()
+    fake = C.c_void_p(256)
+    E = msadp.MSA_EINVAL
+    assert L.msa_quality_workspace_bytes(4, 10, 64) == 0          # gap code above 63
+    assert L.msa_quality_workspace_bytes(-1, 10, 4) == 0
+    ws = L.msa_quality_workspace_bytes(4, 10, 4)
+    assert ws > 0
+    # triangle mode needs rows*(rows-1)/2 pairs; one null pair array is invalid
+    assert L.msa_pair_counts(fake, 4, 10, 4, None, None, 5, fake, fake, fake, fake, ws, None,
+                             None) == E
+    assert L.msa_pair_counts(fake, 4, 10, 4, fake, None, 6, fake, fake, fake, fake, ws, None,
+                             None) == E
+    assert L.msa_pair_counts(None, 4, 10, 4, None, None, 6, fake, fake, fake, fake, ws, None,
+                             None) == E
+    assert L.msa_pair_counts(fake, 4, 10, 4, None, None, 6, fake, fake, fake, fake, ws - 512,
+                             None, None) == msadp.MSA_ENOSPC
+    assert L.msa_pair_counts(fake, 0, 10, 4, fake, fake, 3, fake, fake, fake, fake, ws, None,
+                             None) == E                              # pairs but no rows
+    # nothing to count: success without a launch
+    assert L.msa_pair_counts(fake, 4, 10, 4, fake, fake, 0, None, None, None, None, 0, None,
+                             None) == msadp.MSA_OK
+    assert L.msa_pair_counts(fake, 1, 10, 4, None, None, 0, None, None, None, None, 0, None,
+                             None) == msadp.MSA_OK
+    assert L.msa_quality(fake, 4, 10, 70, 10, fake, fake, fake, None, 6, fake, fake, ws, None,
+                         None) == E
+    assert L.msa_quality(fake, 4, 10, 4, 10, fake, fake, fake, None, 6, None, fake, ws, None,
+                         None) == E                                  # no output
+    assert L.msa_quality(fake, 4, 10, 4, 10, None, fake, fake, None, 6, fake, fake, ws, None,
+                         None) == E
+    assert L.msa_quality(fake, 4, 10, 4, 10, fake, fake, fake, None, 6, fake, fake, ws - 512,
+                         None, None) == msadp.MSA_ENOSPC

@@ -52,9 +52,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="nw,tree,pruned,machine",
-                    help="legs after the all-pairs one: any of nw, tree, pruned, machine "
-                         "(comma list)")
+    ap.add_argument("--legs", default="nw,tree,pruned,quality,machine",
+                    help="legs after the all-pairs one: any of nw, tree, pruned, quality, "
+                         "machine (comma list)")
     ap.add_argument("--quick", action="store_true", help="only the all-pairs leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
@@ -83,30 +83,35 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": n}), flush=True)
 
 
-def cpu_baseline(d, seconds):
+def cpu_baseline(d, seconds, device_out):
     """The oracle (plain Wagner-Fischer, OpenMP over pairs) on a seeded
-    sample of the same pairs, for about `seconds` of wall time."""
+    sample of the same pairs, for about `seconds` of wall time; its
+    distances are also compared with the device's condensed output
+    (returned as the second value: True when every sampled pair agrees)."""
     from oracle import pyoracle as orc
     n = d["n"]
     L = np.diff(d["offsets"])
     rng = np.random.default_rng(2024)
     done_cells = 0
     done_pairs = 0
+    agree = True
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         ia = rng.integers(0, n, size=512)
         ib = rng.integers(0, n, size=512)
         keep = ia != ib
         ia, ib = ia[keep], ib[keep]
-        orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], ia, ib)
+        want = orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], ia, ib)
+        i, j = np.minimum(ia, ib), np.maximum(ia, ib)
+        agree &= bool((device_out[i * n - i * (i + 1) // 2 + (j - i - 1)] == want).all())
         done_cells += int((L[ia] * L[ib]).sum())
         done_pairs += len(ia)
     dt = time.perf_counter() - t0
-    return {"value": round(done_cells / dt / 1e9, 3), "unit": "GCUPS",
-            "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"{done_pairs} seeded random pairs of the same 4096-sequence set "
-                      f"({done_cells:.3e} cells, {dt:.1f} s); pairs/s = "
-                      f"{done_pairs / dt:.1f}"}
+    return ({"value": round(done_cells / dt / 1e9, 3), "unit": "GCUPS",
+             "cores": orc.num_threads(), "kind": "oracle",
+             "sample": f"{done_pairs} seeded random pairs of the same 4096-sequence set "
+                       f"({done_cells:.3e} cells, {dt:.1f} s); pairs/s = "
+                       f"{done_pairs / dt:.1f}"}, agree)
 
 
 def main():
@@ -136,17 +141,8 @@ def main():
     torch.cuda.synchronize()
     ap.st.check("lev_allpairs")
 
-    # spot parity on a seeded sample (outside the timed region)
-    from oracle import pyoracle as orc
+    # the device distances, for the CPU-baseline leg's check of its sample
     out = ap.out[:pairs].cpu().numpy().astype(np.int64)
-    rng = np.random.default_rng(5)
-    ia = rng.integers(0, n, size=300)
-    ib = rng.integers(0, n, size=300)
-    keep = ia != ib
-    ia, ib = ia[keep], ib[keep]
-    i, j = np.minimum(ia, ib), np.maximum(ia, ib)
-    want = orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], i, j)
-    parity = bool((out[i * n - i * (i + 1) // 2 + (j - i - 1)] == want).all())
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -174,7 +170,6 @@ def main():
                                "seed 2, uint16 condensed output",
                    "pairs": pairs, "cells": cells},
         "pairs_per_s": round(pairs / (wall / args.steps), 1),
-        "parity_sample_ok": parity,
         "tuning": tuning,
         "roofline": {"bound": "alu", "achieved": round(tcups, 2),
                      "peak": round(LEV_PEAK_TCUPS, 1), "unit": "Tcell/s",
@@ -184,7 +179,7 @@ def main():
     }
     legs = [] if args.quick else [x for x in args.legs.split(",") if x]
     for name, fn in (("nw", bench_nw), ("tree", bench_tree), ("pruned", bench_pruned),
-                     ("machine", bench_machine)):
+                     ("quality", bench_quality), ("machine", bench_machine)):
         if name in legs:
             try:
                 res[name] = fn(msadp, synth, torch, args)
@@ -192,7 +187,7 @@ def main():
                 res[name] = {"error": f"{type(e).__name__}: {e}"}
                 _log(f"{name} leg failed: {e}")
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+        res["cpu_baseline"], res["parity_sample_ok"] = cpu_baseline(d, args.cpu_seconds, out)
     print(json.dumps(res), flush=True)
 
 
@@ -205,6 +200,53 @@ def _time_calls(torch, fn, stream, reps):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def bench_quality(msadp, synth, torch, args):
+    """Alignment quality (Sec. 2.3 and the Table 2 columns) of the
+    4096-sequence set's own alignment: guide tree and merge on the device,
+    then the pair counts over all 8,386,560 pairs and the metrics, the
+    distortion against the all-pairs Levenshtein distances."""
+    d = synth.allpairs()
+    n = d["n"]
+    A = msadp.to_device(d["codes"], d["offsets"], d["sigma"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree, msa = msadp.align(A, use_graph=True)
+    t_align = time.perf_counter() - t0
+    lev = msadp.lev_allpairs(A)
+    gap = d["sigma"]
+    Q = msadp.Quality(msa, gap)
+    max_len = int(np.diff(d["offsets"]).max())
+    stream = torch.cuda.current_stream()
+    counts = Q.pair_counts(stream=stream)
+    q = Q.metrics(counts, max_len, lev=lev, stream=stream)
+    reps = max(args.steps, 3)
+    ms_counts = _time_calls(torch, lambda: Q.pair_counts(stream=stream), stream, reps)
+    ms_metrics = _time_calls(torch, lambda: Q.metrics(counts, max_len, lev=lev, stream=stream),
+                             stream, reps)
+    Q.st.check("msa_pair_counts")
+    # every row pair of an alignment costs at least the two sequences'
+    # Levenshtein distance (the counts' parity with the oracle is in tests/)
+    bound = bool((counts[0].cpu().numpy() >= lev.cpu().numpy()).all())
+    pairs = n * (n - 1) // 2
+    rows, width = msa.shape
+    words = -(-width // 32)
+    nb = max(1, int(gap).bit_length())
+    ops = pairs * words * (2 * nb + 4)           # VALU lane-ops of the pair-count kernel
+    achieved = ops / (ms_counts * 1e-3) / 1e12
+    peak = VALU_PEAK_LANE_OPS / 1e12
+    return {"workload": "alignment quality: the 4096-sequence DNA set (lengths U{1000..1600}, "
+                        "seed 2) aligned on the device, all 8,386,560 row pairs",
+            "align_s": round(t_align, 3), "width": int(width),
+            "metrics": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in q.items()},
+            "pair_counts_ms": round(ms_counts, 3), "metrics_ms": round(ms_metrics, 3),
+            "pairs_per_s": round(pairs / (ms_counts * 1e-3), 1),
+            "hamming_ge_lev_all_pairs": bound,
+            "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1),
+                         "unit": "T lane-ops/s", "frac": round(achieved / peak, 4),
+                         "traffic": None, "kernel": "k_qual_tri",
+                         "ops_per_pair_word": 2 * nb + 4}}
 
 
 def bench_machine(msadp, synth, torch, args):

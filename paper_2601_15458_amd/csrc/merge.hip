@@ -28,7 +28,8 @@ struct MergeArgs {
     const int32_t *center;
     const int32_t *left, *right;
     const int64_t *mstart, *mcount;
-    int32_t *width;          // per node
+    int32_t *width;          // per node (at most width_cap)
+    int32_t *over;           // set to 1 when a node's width exceeds width_cap
     int32_t *st;
     uint8_t gap;
 };
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(256) k_write_leaves(MergeArgs a, Staged S, con
                 dst[c] = a.gap;
         }
         if (threadIdx.x == 0) {
-            if (w > a.width_cap) set_status(a.st, MSA_DS_CAPACITY);
+            if (w > a.width_cap) *a.over = 1;
             a.width[v] = min(w, a.width_cap);
         }
     }
@@ -95,7 +96,7 @@ __global__ void __launch_bounds__(256) k_merge_maps(MergeArgs a, const int32_t *
         if (threadIdx.x == 0) {
             base_l = 0;
             base_r = 0;
-            if (W > a.width_cap) set_status(a.st, MSA_DS_CAPACITY);
+            if (W > a.width_cap) *a.over = 1;
             a.width[v] = min(W, a.width_cap);
         }
         __syncthreads();
@@ -193,6 +194,7 @@ static void merge_layout(Alloc &al, const msa_seqs *S, int32_t n_nodes, int32_t 
     al.template take<uint8_t>(n * p.pitch);            // matrix A
     al.template take<uint8_t>(n * p.pitch);            // matrix B
     al.template take<int32_t>((size_t)n_nodes);        // widths
+    al.template take<int32_t>(1);                      // width overflow flag
     al.template take<int32_t>(n);                      // pos_of
     al.template take<int32_t>(n);                      // node ids of a level
     al.template take<uint8_t>(n * (size_t)width_cap / 2 + 16);  // center rows A
@@ -247,6 +249,7 @@ int msa_merge(const msa_seqs *S, const msa_tree *T, int32_t n_nodes, int32_t wid
     uint8_t *mat0 = cv.take<uint8_t>(n * pl.pitch);
     uint8_t *mat1 = cv.take<uint8_t>(n * pl.pitch);
     int32_t *width = cv.take<int32_t>((size_t)n_nodes);
+    int32_t *over = cv.take<int32_t>(1);
     int32_t *pos_of = cv.take<int32_t>(n);
     int32_t *ids = cv.take<int32_t>(n);
     uint8_t *ca = cv.take<uint8_t>(n * (size_t)width_cap / 2 + 16);
@@ -301,7 +304,9 @@ int msa_merge(const msa_seqs *S, const msa_tree *T, int32_t n_nodes, int32_t wid
     a.mstart = T->mstart;
     a.mcount = T->mcount;
     a.width = width;
+    a.over = over;
     a.st = d_status;
+    if ((rc = fill_i32(over, 1, 0, s))) return rc;
     a.gap = (uint8_t)S->sigma;
     uint8_t *cur = mat0, *next = mat1;
     std::vector<int32_t> wv(n_nodes, 0);
@@ -380,8 +385,12 @@ int msa_merge(const msa_seqs *S, const msa_tree *T, int32_t n_nodes, int32_t wid
                                map_off);
             if ((rc = launch_status())) return rc;
         }
-        // keep this level's host vectors alive until their copies have run
-        if (hipStreamSynchronize(s)) return MSA_EDEVICE;
+        // keep this level's host vectors alive until their copies have run;
+        // a width beyond width_cap ends the merge with MSA_ENOSPC
+        int32_t over_h = 0;
+        if (hipMemcpyAsync(&over_h, over, 4, hipMemcpyDeviceToHost, s) || hipStreamSynchronize(s))
+            return MSA_EDEVICE;
+        if (over_h) return MSA_ENOSPC;
         std::swap(cur, next);
         vend = vbeg;
     }

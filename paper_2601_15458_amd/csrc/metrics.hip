@@ -14,12 +14,12 @@
 //      codes), the columns with a residue in both rows are ~(gx | gy), and
 //      three population counts add the Hamming distance, the aligned columns
 //      and the aligned columns that differ.  The triangle variant gives a
-//      wavefront four rows i (uniform, scalar loads) against 64 rows j (one
-//      per lane), so each loaded word of row j serves four pairs.
+//      wavefront 16 rows i (staged in LDS, read as broadcasts) against 64
+//      rows j (one per lane), so each loaded word of row j serves 16 pairs.
 //   3. k_qual_reduce + k_qual_final: the per-pair ratios (p-score over the
 //      aligned columns, Hamming over Levenshtein) and per-row gap fractions
 //      summed in a fixed order (fixed grid, tree reduction per block, block
-//      partials summed in block order), so repeated calls agree bit for bit.
+//      partials folded in a fixed pattern), so repeated calls agree bit for bit.
 #include <algorithm>
 
 #include "common.hpp"
@@ -28,8 +28,9 @@ namespace msadp {
 namespace {
 
 constexpr int kQualThreads = 256;
-constexpr int kQualRows = 4;          // rows i per wavefront item (triangle)
-constexpr int kReduceBlocks = 256;
+constexpr int kQualRows = 16;         // rows i per wavefront item (triangle)
+constexpr int kQualGroups = kQualRows / 4;   // 16-byte groups of 4 rows
+constexpr int kReduceBlocks = 2048;   // enough wavefronts to hide load latency
 constexpr int kMaxPlanes = 6;         // codes up to 63
 
 inline int planes_of(int32_t gap_code) {
@@ -55,30 +56,32 @@ __device__ __forceinline__ const uint32_t *plane(const QualArgs &a, int b) {
     return a.planes + (int64_t)b * a.words * a.rows_pad;
 }
 
+// One wavefront per (row, 64 columns): lane l reads column 64 k + l (one
+// coalesced 64-byte load), and one ballot per plane gives two words.
 __global__ void __launch_bounds__(kQualThreads) k_qual_planes(QualArgs a, int nb) {
-    const int64_t total = a.words * a.rows_pad;
-    for (int64_t t = (int64_t)blockIdx.x * kQualThreads + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * kQualThreads) {
-        const int64_t w = t / a.rows_pad;
-        const int64_t r = t % a.rows_pad;
-        const uint8_t *row = a.msa + (r < a.rows ? r : 0) * (int64_t)a.width;
-        uint32_t g = 0, sb[kMaxPlanes] = {0, 0, 0, 0, 0, 0};
-        bool bad = false;
-        for (int c = 0; c < 32; ++c) {
-            const int64_t col = w * 32 + c;
-            if (col >= a.width || r >= a.rows) {
-                g |= 1u << c;
-                continue;
-            }
-            const uint32_t code = row[col];
-            bad |= code > (uint32_t)a.gap;
-            g |= (uint32_t)(code == (uint32_t)a.gap) << c;
-            for (int b = 0; b < kMaxPlanes; ++b) sb[b] |= ((code >> b) & 1u) << c;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t chunks = (a.words + 1) / 2;             // 64-column chunks per row
+    const int64_t total = chunks * a.rows_pad;
+    const int64_t wave = (int64_t)blockIdx.x * (kQualThreads / kWave) +
+                         (int64_t)uniform(threadIdx.x / kWave);
+    const int64_t nwaves = (int64_t)gridDim.x * (kQualThreads / kWave);
+    for (int64_t t = wave; t < total; t += nwaves) {
+        const int64_t k = t / a.rows_pad, r = t % a.rows_pad;    // uniform
+        const int64_t col = 64 * k + lane;
+        const bool in = r < a.rows && col < a.width;
+        const uint32_t code = in ? a.msa[r * (int64_t)a.width + col] : 0u;
+        if (in && code > (uint32_t)a.gap) set_status(a.st, MSA_DS_SYMBOL);
+        const uint64_t g = __ballot(!in || code == (uint32_t)a.gap);
+        const int64_t o = 2 * k * a.rows_pad + r;            // word 2k of row r
+        const bool second = 2 * k + 1 < a.words;
+        if (lane == 0) a.planes[o] = (uint32_t)g;
+        if (lane == 1 && second) a.planes[o + a.rows_pad] = (uint32_t)(g >> 32);
+        for (int b = 0; b < nb; ++b) {
+            const uint64_t m = __ballot((code >> b) & 1u);
+            uint32_t *pb = a.planes + (int64_t)(b + 1) * a.words * a.rows_pad + o;
+            if (lane == 0) pb[0] = (uint32_t)m;
+            if (lane == 1 && second) pb[a.rows_pad] = (uint32_t)(m >> 32);
         }
-        if (bad) set_status(a.st, MSA_DS_SYMBOL);
-        const int64_t o = w * a.rows_pad + r;
-        a.planes[o] = g;
-        for (int b = 0; b < nb; ++b) a.planes[(int64_t)(b + 1) * a.words * a.rows_pad + o] = sb[b];
     }
 }
 
@@ -101,38 +104,68 @@ __device__ __forceinline__ void word_counts(uint32_t gx, const uint32_t (&sx)[NB
 }
 
 // All pairs i < j of the rows, stored at the condensed index
-// i * rows - i (i + 1) / 2 + (j - i - 1).  Item = (4 rows i, 64 rows j).
+// i * rows - i (i + 1) / 2 + (j - i - 1).  Item = (16 rows i, 64 rows j).
+constexpr int kQualChunk = 64;        // words of the rows i staged in LDS at a time
+
 template <int NB>
 __global__ void __launch_bounds__(kQualThreads) k_qual_tri(QualArgs a,
                                                            const uint32_t *__restrict__ pl,
                                                            PairOut o) {
-    // pl = a.planes, read-only here, so the rows i (uniform) come through
-    // scalar loads
+    // The rows i of a wavefront's item, kQualChunk words at a time, staged
+    // in the wavefront's own LDS slice: [plane][word][group] -> 4 rows'
+    // words (consecutive in the word-major layout: one 16-byte load each).
+    __shared__ uint4 si[kQualThreads / kWave][NB + 1][kQualChunk][kQualGroups];
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (int64_t)blockIdx.x * (kQualThreads / kWave) +
-                         (int64_t)uniform(threadIdx.x / kWave);
+    const int wv = threadIdx.x / kWave;
+    const int64_t wave = (int64_t)blockIdx.x * (kQualThreads / kWave) + (int64_t)uniform(wv);
     const int64_t nwaves = (int64_t)gridDim.x * (kQualThreads / kWave);
     const int64_t ni = (a.rows + kQualRows - 1) / kQualRows, nj = (a.rows + kWave - 1) / kWave;
     const int64_t n = a.rows;
+    const int64_t ps = a.words * a.rows_pad;              // plane stride
     for (int64_t it = wave; it < ni * nj; it += nwaves) {
         const int64_t i0 = (it / nj) * kQualRows, j0 = (it % nj) * kWave;   // uniform
         if (j0 + kWave - 1 <= i0) continue;              // no j above these rows i (uniform)
         const int64_t j = j0 + lane;                     // < rows_pad
         int32_t h[kQualRows] = {}, al[kQualRows] = {}, mm[kQualRows] = {};
-        const int64_t ps = a.words * a.rows_pad;         // plane stride
-        const uint32_t *pj = pl + j, *pi = pl + i0;      // pi uniform; i0 + 3 < rows_pad
-        for (int64_t w = 0; w < a.words; ++w, pj += a.rows_pad, pi += a.rows_pad) {
-            const uint32_t gy = pj[0];
-            uint32_t sy[NB];
+        const uint32_t *pj = pl + j;
+        for (int64_t w0 = 0; w0 < a.words; w0 += kQualChunk) {
+            const int cw = (int)(a.words - w0 < kQualChunk ? a.words - w0 : kQualChunk);
+            // reads of the previous chunk are done before it is overwritten
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int e = lane; e < (NB + 1) * cw * kQualGroups; e += kWave) {
+                const int q = e % kQualGroups, bw = e / kQualGroups;
+                const int b = bw / cw, w = bw % cw;      // i0 + 15 < rows_pad
+                si[wv][b][w][q] =
+                    *(const uint4 *)(pl + b * ps + (w0 + w) * a.rows_pad + i0 + 4 * q);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+            for (int w = 0; w < cw; ++w, pj += a.rows_pad) {
+                const uint32_t gy = pj[0];
+                uint32_t sy[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) sy[b] = pj[(b + 1) * ps];
+                for (int b = 0; b < NB; ++b) sy[b] = pj[(b + 1) * ps];
 #pragma unroll
-            for (int r = 0; r < kQualRows; ++r) {
-                const uint32_t gx = pi[r];
-                uint32_t sx[NB];
+                for (int q = 0; q < kQualGroups; ++q) {
+                    const uint4 g4 = si[wv][0][w][q];       // same address in every lane
+                    uint4 s4[NB];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) sx[b] = pi[(b + 1) * ps + r];
-                word_counts<NB>(gx, sx, gy, sy, h[r], al[r], mm[r]);
+                    for (int b = 0; b < NB; ++b) s4[b] = si[wv][b + 1][w][q];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int r = 4 * q + k;
+                        const uint32_t gx = k == 0 ? g4.x : k == 1 ? g4.y : k == 2 ? g4.z : g4.w;
+                        uint32_t sx[NB];
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            sx[b] = k == 0 ? s4[b].x : k == 1 ? s4[b].y : k == 2 ? s4[b].z : s4[b].w;
+                        word_counts<NB>(gx, sx, gy, sy, h[r], al[r], mm[r]);
+                    }
+                }
             }
         }
 #pragma unroll
@@ -233,20 +266,43 @@ __global__ void __launch_bounds__(kQualThreads) k_qual_reduce(QualArgs a, const 
 }
 
 // out: pct_gaps, p_min, p_avg, p_max, distortion, stretch, n_p_pairs, n_d_pairs.
-__global__ void k_qual_final(const double *part, int nblocks, int32_t rows, int32_t width,
-                             int32_t max_len, double *out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Combine two partial tuples (sums add, minimum, maximum).
+__device__ __forceinline__ void combine(double (&v)[kPart], const double *q) {
+    v[0] += q[0];
+    v[1] += q[1];
+    v[2] = q[2] < v[2] ? q[2] : v[2];
+    v[3] = q[3] > v[3] ? q[3] : v[3];
+    v[4] += q[4];
+    v[5] += q[5];
+    v[6] += q[6];
+}
+
+// One workgroup: thread t folds block partials t, t + 256, ... in order, then
+// a fixed tree over the threads; the result does not depend on timing.
+__global__ void __launch_bounds__(kQualThreads) k_qual_final(const double *part, int nblocks,
+                                                             int32_t rows, int32_t width,
+                                                             int32_t max_len, double *out) {
+    __shared__ double red[kQualThreads][kPart];
+    const int t = threadIdx.x;
     double v[kPart] = {0.0, 0.0, __builtin_inf(), -__builtin_inf(), 0.0, 0.0, 0.0};
-    for (int b = 0; b < nblocks; ++b) {
-        const double *q = part + (int64_t)b * kPart;
-        v[0] += q[0];
-        v[1] += q[1];
-        v[2] = q[2] < v[2] ? q[2] : v[2];
-        v[3] = q[3] > v[3] ? q[3] : v[3];
-        v[4] += q[4];
-        v[5] += q[5];
-        v[6] += q[6];
+    for (int b = t; b < nblocks; b += kQualThreads) combine(v, part + (int64_t)b * kPart);
+#pragma unroll
+    for (int k = 0; k < kPart; ++k) red[t][k] = v[k];
+    __syncthreads();
+    for (int off = kQualThreads / 2; off >= 1; off >>= 1) {
+        if (t < off) {
+            double w[kPart];
+#pragma unroll
+            for (int k = 0; k < kPart; ++k) w[k] = red[t][k];
+            combine(w, red[t + off]);
+#pragma unroll
+            for (int k = 0; k < kPart; ++k) red[t][k] = w[k];
+        }
+        __syncthreads();
     }
+    if (t != 0) return;
+#pragma unroll
+    for (int k = 0; k < kPart; ++k) v[k] = red[0][k];
     const bool anyp = v[4] > 0.0, anyd = v[6] > 0.0;
     out[0] = rows > 0 && width > 0 ? 100.0 * v[0] / (double)rows : 0.0;
     out[1] = anyp ? v[2] : 0.0;
@@ -308,9 +364,10 @@ static int qual_setup(const uint8_t *msa, int32_t rows, int32_t width, int32_t g
     a.planes = cv.take<uint32_t>(planes_bytes(rows, width, gap_code) / 4);
     a.st = d_status;
     *part = cv.take<double>((size_t)kReduceBlocks * kPart);
-    const int64_t total = a.words * a.rows_pad;
-    if (total > 0) {
-        const unsigned grid = (unsigned)std::min<int64_t>((total + kQualThreads - 1) / kQualThreads,
+    const int64_t tasks = (a.words + 1) / 2 * a.rows_pad;  // one wavefront each
+    if (tasks > 0) {
+        const int64_t per_block = kQualThreads / kWave;
+        const unsigned grid = (unsigned)std::min<int64_t>((tasks + per_block - 1) / per_block,
                                                           (int64_t)device_cus() * 64);
         hipLaunchKernelGGL(k_qual_planes, dim3(grid), dim3(kQualThreads), 0, s, a,
                            planes_of(gap_code));
@@ -361,7 +418,7 @@ extern "C" int msa_quality(const uint8_t *msa, int32_t rows, int32_t width, int3
         return rc;
     hipLaunchKernelGGL(k_qual_reduce, dim3(kReduceBlocks), dim3(kQualThreads), 0, s, a, hamming,
                        aligned, mismatched, lev, n_pairs, part);
-    hipLaunchKernelGGL(k_qual_final, dim3(1), dim3(64), 0, s, (const double *)part, kReduceBlocks,
-                       rows, width, max_len, out);
+    hipLaunchKernelGGL(k_qual_final, dim3(1), dim3(kQualThreads), 0, s, (const double *)part,
+                       kReduceBlocks, rows, width, max_len, out);
     return launch_status();
 }

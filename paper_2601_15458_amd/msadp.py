@@ -498,8 +498,10 @@ def msa_merge(S: Seqs, tree: Tree, width_cap=None, tb_cap=1 << 30, stream=None):
         w = C.c_int32(0)
         rc = lib().msa_merge(C.byref(ss), C.byref(ts), tree.n_nodes, cap, tb_cap, _ptr(out),
                              pitch, C.byref(w), _ptr(ws), wsb, _ptr(st.t), _stream(stream))
-        if rc == MSA_ENOSPC and width_cap is None and cap < 32768:
+        if rc == MSA_ENOSPC and width_cap is None and (cap < 32768 or tb_cap < (1 << 36)):
+            # the width or one level's traceback codes did not fit: grow both
             cap = min(32768, cap * 2)
+            tb_cap = min(1 << 36, tb_cap * 2)
             continue
         _check(rc, "msa_merge")
         torch.cuda.synchronize()

@@ -245,7 +245,7 @@ def bench_quality(msadp, synth, torch, args):
             "hamming_ge_lev_all_pairs": bound,
             "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1),
                          "unit": "T lane-ops/s", "frac": round(achieved / peak, 4),
-                         "traffic": None, "kernel": "k_qual_tri",
+                         "traffic": None, "kernel": "k_qual_planes + k_qual_tri (one call)",
                          "ops_per_pair_word": 2 * nb + 4}}
 
 

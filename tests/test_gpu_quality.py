@@ -103,3 +103,35 @@ def test_pair_index_out_of_range_reported():
     with pytest.raises(RuntimeError, match="index"):
         Q.st.check("msa_pair_counts")
     del counts
+
+
+def test_full_size_alignment_of_the_4096_set():
+    # the configuration the bench times: the 4096-sequence set aligned on the
+    # device, all 8,386,560 row pairs; counts checked on a seeded sample,
+    # metrics against the oracle over every pair (same distances as input)
+    import torch
+    M = _msadp()
+    d = synth.allpairs()
+    n = d["n"]
+    A = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    _, msa = M.align(A, use_graph=True)
+    lev = M.lev_allpairs(A)
+    Q = M.Quality(msa, d["sigma"])
+    counts = Q.pair_counts()
+    max_len = int(np.diff(d["offsets"]).max())
+    got = Q.metrics(counts, max_len, lev=lev)
+    host = [t.cpu().numpy() for t in counts]
+    rng = np.random.default_rng(31)
+    ia = rng.integers(0, n, size=20000)
+    ib = rng.integers(0, n, size=20000)
+    keep = ia != ib
+    i, j = np.minimum(ia[keep], ib[keep]), np.maximum(ia[keep], ib[keep])
+    c = i * n - i * (i + 1) // 2 + (j - i - 1)
+    want = orc.msa_pair_counts(msa, d["sigma"], i, j)
+    for g, w in zip(host, want):
+        assert np.array_equal(g[c], w)
+    ti, tj = np.triu_indices(n, 1)
+    wq = orc.msa_quality(msa, d["sigma"], max_len, ti, tj, lev.cpu().numpy())
+    _check_metrics(got, wq)
+    assert (host[0] >= lev.cpu().numpy()).all()
+    torch.cuda.synchronize()

@@ -202,6 +202,17 @@ __device__ __forceinline__ bf16x8 shift_rows(bf16x8 lo, bf16x8 hi, int li) {
     return __builtin_bit_cast(bf16x8, r);
 }
 
+// DPP controls: row_shl:1 (lane i of a 16-lane row takes lane i + 1) and
+// row_shr:n (lane i takes lane i - n); lanes with no source keep `old`.
+constexpr int kDppRowShl1 = 0x101;
+constexpr int kDppRowShr = 0x110;
+
+template <int N>
+__device__ __forceinline__ float shr_rows(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppRowShr + N, 0xF,
+                                                      0xF, false));
+}
+
 __device__ __forceinline__ bf16x8 tap_rows(bf16x8 lo, bf16x8 hi, int tap, int li) {
     switch (tap) {
     case 1: return shift_rows<1>(lo, hi, li);
@@ -306,6 +317,47 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     // The weights are the first MFMA operand, so tile (i, j) is the
     // transposed output: the lane holds channels 16 j + 4 (lane / 16) + r,
     // r = 0..3, of row 16 i + lane % 16, stored as one 4-channel piece.
+    if constexpr (EPI == kEpiLinearF32) {
+        // Last layer: only its mean over each sequence is used, so the rows
+        // are summed here.  Within each 16-row tile (one 16-lane DPP row per
+        // channel group) a segmented inclusive scan keyed by the sequence id
+        // leaves the sum of each sequence's rows of the tile in the lane of
+        // its last row, which alone is stored (k_pool adds the tiles).
+#pragma unroll
+        for (int i = 0; i < kRowTiles; ++i) {
+            const int64_t row = row0 + 16 * i + li;
+            const int sid = row < a.rows ? a.rowseq[row] : -1;
+            const int below = __builtin_amdgcn_update_dpp(-3, sid, kDppRowShl1, 0xF, 0xF, false);
+            const bool last = sid >= 0 && below != sid;
+            // all-ones where the lane n above holds the same sequence: the
+            // sums are masked with it, so every lane runs every DPP move (a
+            // lane that skipped one would hand 0 to the lane below it)
+            int same[4];
+            same[0] = -(int)(__builtin_amdgcn_update_dpp(-2, sid, kDppRowShr + 1, 0xF, 0xF, false) == sid);
+            same[1] = -(int)(__builtin_amdgcn_update_dpp(-2, sid, kDppRowShr + 2, 0xF, 0xF, false) == sid);
+            same[2] = -(int)(__builtin_amdgcn_update_dpp(-2, sid, kDppRowShr + 4, 0xF, 0xF, false) == sid);
+            same[3] = -(int)(__builtin_amdgcn_update_dpp(-2, sid, kDppRowShr + 8, 0xF, 0xF, false) == sid);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c0 = 16 * j + 4 * (lane >> 4);
+                const float4 b4 = *(const float4 *)(a.bias + c0);
+                const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+                float v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    v[r] = __int_as_float(__float_as_int(acc[i][j][r] + bb[r]) & -(int)(sid >= 0));
+                    v[r] += __int_as_float(__float_as_int(shr_rows<1>(v[r])) & same[0]);
+                    v[r] += __int_as_float(__float_as_int(shr_rows<2>(v[r])) & same[1]);
+                    v[r] += __int_as_float(__float_as_int(shr_rows<4>(v[r])) & same[2]);
+                    v[r] += __int_as_float(__float_as_int(shr_rows<8>(v[r])) & same[3]);
+                }
+                if (last)
+                    *(float4 *)((float *)a.out + (kLead + row) * kW + c0) =
+                        make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < kRowTiles; ++i) {
         const int64_t row = row0 + 16 * i + li;
@@ -318,12 +370,7 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
             float v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
-            if (EPI == kEpiLinearF32) {
-                const float4 b4 = *(const float4 *)(a.bias + c0);
-                *(float4 *)((float *)a.out + o) =
-                    data ? make_float4(v[0] + b4.x, v[1] + b4.y, v[2] + b4.z, v[3] + b4.w)
-                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            } else {
+            {
                 float z[4];
                 if (EPI == kEpiRelu) {
                     const float4 b4 = *(const float4 *)(a.bias + c0);
@@ -485,23 +532,23 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_
 }
 
 // ------------------------------------------------------------ pool, loss
-// Mean over each sequence's rows; 8 rows in flight per thread.
+// Mean over each sequence's rows.  The last layer stored, for every 16-row
+// tile (tiles start at multiples of 16) that holds rows of the sequence, the
+// sum of those rows at the row of the tile where the sequence's rows end:
+// min(last data row, tile end).  The tiles are added in order.
 __global__ void __launch_bounds__(128) k_pool(Batch b, const float *Z4, float *E) {
     const int c = threadIdx.x;
     for (int i = blockIdx.x; i < b.nb; i += gridDim.x) {
         const int64_t r0 = b.roff[i] + 2;
         const int32_t L = b.len[b.idx[i]];
-        const float *z = Z4 + (kLead + r0) * kW + c;
-        float part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int t = 0;
-        for (; t + 8 <= L; t += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) part[u] += z[(int64_t)(t + u) * kW];
-        }
-        for (; t < L; ++t) part[0] += z[(int64_t)t * kW];
         float s = 0.0f;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s += part[u];
+        if (L > 0) {
+            const int64_t r1 = r0 + L - 1;
+            for (int64_t t = r0 / 16; t <= r1 / 16; ++t) {
+                const int64_t e = r1 < 16 * t + 15 ? r1 : 16 * t + 15;
+                s += Z4[(kLead + e) * kW + c];
+            }
+        }
         E[(int64_t)i * kW + c] = L > 0 ? s / (float)L : 0.0f;
     }
 }
@@ -538,13 +585,28 @@ __global__ void k_labels(Batch b, const int32_t *pa, const int32_t *pb, const ui
 }
 
 // Mean-pool backward: dZ4[r][c] = dE[seq][c] / L on data rows, 0 elsewhere.
+// Thread = 8 channels of one row (one 16-byte store); a workgroup covers 16
+// rows per trip.
 __global__ void __launch_bounds__(128) k_pool_bwd(Batch b, const float *dE, bf16_t *dZ4) {
-    const int c = threadIdx.x;
-    for (int64_t r = blockIdx.x; r < b.rows; r += gridDim.x) {
+    const int c = (threadIdx.x & 15) * 8;
+    for (int64_t r = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 4); r < b.rows;
+         r += (int64_t)gridDim.x * 8) {
         const int32_t i = b.rowseq[r];
-        float v = 0.0f;
-        if (i >= 0) v = dE[(int64_t)i * kW + c] / (float)b.len[b.idx[i]];
-        dZ4[(kLead + r) * kW + c] = to_bf16(v);
+        float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (i >= 0) {
+            const float L = (float)b.len[b.idx[i]];
+            const float4 e0 = *(const float4 *)(dE + (int64_t)i * kW + c);
+            const float4 e1 = *(const float4 *)(dE + (int64_t)i * kW + c + 4);
+            const float e[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = e[k] / L;
+        }
+        uint4 o;
+        o.x = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+        o.y = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+        o.z = (uint32_t)to_bf16(v[4]) | ((uint32_t)to_bf16(v[5]) << 16);
+        o.w = (uint32_t)to_bf16(v[6]) | ((uint32_t)to_bf16(v[7]) << 16);
+        *(uint4 *)(dZ4 + (kLead + r) * kW + c) = o;
     }
 }
 
@@ -657,8 +719,8 @@ static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t 
     int rc;
     if ((rc = zero_frame(w.dz, kW * 2, w.alloc_rows, b.rows, s))) return rc;
     if ((rc = zero_frame(w.dz2, kW * 2, w.alloc_rows, b.rows, s))) return rc;
-    hipLaunchKernelGGL(k_pool_bwd, dim3((unsigned)std::min<int64_t>(b.rows, 65535)), dim3(128), 0, s,
-                       b, w.dE, w.dz);
+    hipLaunchKernelGGL(k_pool_bwd, dim3((unsigned)std::min<int64_t>((b.rows + 7) / 8, 65535)),
+                       dim3(128), 0, s, b, w.dE, w.dz);
     bf16_t *dz = w.dz, *dzn = w.dz2;
     for (int l = kLayers - 1; l >= 0; --l) {
         float *gw = at<float>(P, pl.gw[l]);

@@ -33,6 +33,10 @@ constexpr int kIn = 8;       // one-hot channels (sigma <= 8)
 constexpr int kLead = 8;     // zero rows before the first sequence
 constexpr int kRowTiles = 4; // 16-row MFMA tiles per wavefront in the conv GEMM
 constexpr int kTile = 8 * 16 * kRowTiles;   // rows per GEMM workgroup (8 wavefronts)
+// Rows per workgroup for R row tiles per wavefront (the one-hot layer, two
+// K-steps only, takes R = 1: fewer registers, more wavefronts in flight).
+__host__ __device__ constexpr int conv_tile(int R) { return 8 * 16 * R; }
+constexpr int kRowTiles0 = 1;
 
 __host__ __device__ constexpr int cin_of(int l) { return l == 0 ? kIn : kW; }
 __host__ __device__ constexpr int kd_of(int l) { return kKer * cin_of(l); }              // 40 / 640
@@ -175,6 +179,7 @@ struct ConvArgs {
 // fragments.  Global loads run two steps ahead of the MFMAs, the LDS slice
 // one step (two LDS buffers, one barrier a step).
 constexpr int kBp = 40;   // LDS pitch of a staged weight row (32 + 8)
+constexpr int kOp = 136;  // LDS pitch of a staged output row (128 + 8)
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -223,22 +228,22 @@ __device__ __forceinline__ bf16x8 tap_rows(bf16x8 lo, bf16x8 hi, int tap, int li
     }
 }
 
-template <int CIN, int KDP, int EPI>
+template <int CIN, int KDP, int EPI, int RT = kRowTiles>
 __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     __shared__ __attribute__((aligned(16))) bf16_t sb[2][kW * kBp];
     const int lane = lane_id();
     const int w = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * kTile + 16 * kRowTiles * w;
-    f32x4 acc[kRowTiles][8];
+    const int64_t row0 = (int64_t)blockIdx.x * conv_tile(RT) + 16 * RT * w;
+    f32x4 acc[RT][8];
 #pragma unroll
-    for (int i = 0; i < kRowTiles; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
     const int kq = 8 * (lane >> 4);   // this lane's first K element of a step
     const int li = lane & 15;
-    const bf16_t *arow[kRowTiles];
+    const bf16_t *arow[RT];
 #pragma unroll
-    for (int i = 0; i < kRowTiles; ++i)
+    for (int i = 0; i < RT; ++i)
         arow[i] = a.X + (kLead + row0 + 16 * i + li - 2) * CIN + kq;
     // staging role: weight row co = t / 4, quarter q = t % 4 (8 of the 32 K)
     const int sco = threadIdx.x >> 2, sq = (threadIdx.x & 3) * 8;
@@ -258,41 +263,41 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
     // column block ahead, and taps 1-4 are rotated out of them across lanes.
     constexpr bool kShift = CIN >= 32;
     constexpr int kBlocks = kShift ? kSteps / kKer : 1;
-    const bf16_t *ahalo = a.X + (kLead + row0 + 16 * kRowTiles + li - 2) * CIN + kq;
+    const bf16_t *ahalo = a.X + (kLead + row0 + 16 * RT + li - 2) * CIN + kq;
     uint4 wq[2];
-    bf16x8 aq[2][kRowTiles];
-    bf16x8 tq[2][kRowTiles + 1];
+    bf16x8 aq[2][RT];
+    bf16x8 tq[2][RT + 1];
 #pragma unroll
     for (int s0 = 0; s0 < 2 && s0 < kSteps; ++s0) wq[s0] = *(const uint4 *)(wsrc + k_of(s0));
     if constexpr (kShift) {
 #pragma unroll
-        for (int i = 0; i < kRowTiles; ++i) tq[0][i] = *(const bf16x8 *)(arow[i]);
-        tq[0][kRowTiles] = *(const bf16x8 *)(ahalo);
+        for (int i = 0; i < RT; ++i) tq[0][i] = *(const bf16x8 *)(arow[i]);
+        tq[0][RT] = *(const bf16x8 *)(ahalo);
     } else {
 #pragma unroll
         for (int s0 = 0; s0 < 2 && s0 < kSteps; ++s0)
 #pragma unroll
-            for (int i = 0; i < kRowTiles; ++i) aq[s0][i] = *(const bf16x8 *)(arow[i] + k_of(s0));
+            for (int i = 0; i < RT; ++i) aq[s0][i] = *(const bf16x8 *)(arow[i] + k_of(s0));
     }
     *(uint4 *)(sb[0] + sco * kBp + sq) = wq[0];
     __syncthreads();
 #pragma unroll
     for (int step = 0; step < kSteps; ++step) {
         const int cur = step & 1;
-        bf16x8 af[kRowTiles];
+        bf16x8 af[RT];
         if constexpr (kShift) {
             const int cb = step / kKer, tap = step % kKer;
             if (tap == 0 && cb + 1 < kBlocks) {
                 const int nb = (cb + 1) & 1, k1 = (cb + 1) * 32;
 #pragma unroll
-                for (int i = 0; i < kRowTiles; ++i) tq[nb][i] = *(const bf16x8 *)(arow[i] + k1);
-                tq[nb][kRowTiles] = *(const bf16x8 *)(ahalo + k1);
+                for (int i = 0; i < RT; ++i) tq[nb][i] = *(const bf16x8 *)(arow[i] + k1);
+                tq[nb][RT] = *(const bf16x8 *)(ahalo + k1);
             }
 #pragma unroll
-            for (int i = 0; i < kRowTiles; ++i) af[i] = tap_rows(tq[cb & 1][i], tq[cb & 1][i + 1], tap, li);
+            for (int i = 0; i < RT; ++i) af[i] = tap_rows(tq[cb & 1][i], tq[cb & 1][i + 1], tap, li);
         } else {
 #pragma unroll
-            for (int i = 0; i < kRowTiles; ++i) af[i] = aq[cur][i];
+            for (int i = 0; i < RT; ++i) af[i] = aq[cur][i];
         }
         const uint4 wstage = wq[cur ^ 1];          // weights of step + 1
         if (step + 2 < kSteps) {
@@ -300,14 +305,14 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
             wq[cur] = *(const uint4 *)(wsrc + k2);
             if constexpr (!kShift) {
 #pragma unroll
-                for (int i = 0; i < kRowTiles; ++i) aq[cur][i] = *(const bf16x8 *)(arow[i] + k2);
+                for (int i = 0; i < RT; ++i) aq[cur][i] = *(const bf16x8 *)(arow[i] + k2);
             }
         }
         bf16x8 bfr[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) bfr[j] = *(const bf16x8 *)(sb[cur] + (16 * j + li) * kBp + kq);
 #pragma unroll
-        for (int i = 0; i < kRowTiles; ++i)
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
@@ -324,7 +329,7 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
         // leaves the sum of each sequence's rows of the tile in the lane of
         // its last row, which alone is stored (k_pool adds the tiles).
 #pragma unroll
-        for (int i = 0; i < kRowTiles; ++i) {
+        for (int i = 0; i < RT; ++i) {
             const int64_t row = row0 + 16 * i + li;
             const int sid = row < a.rows ? a.rowseq[row] : -1;
             const int below = __builtin_amdgcn_update_dpp(-3, sid, kDppRowShl1, 0xF, 0xF, false);
@@ -358,11 +363,16 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
         }
         return;
     }
+    // bf16 outputs: each 16-row tile goes through the wavefront's LDS slice
+    // so that the stores are whole rows (4 rows of 256 bytes per store)
+    // instead of 8-byte pieces spread over 16 rows.
+    __shared__ __attribute__((aligned(16))) bf16_t so[8][16 * kOp];
+    bf16_t *sw = so[w];
 #pragma unroll
-    for (int i = 0; i < kRowTiles; ++i) {
-        const int64_t row = row0 + 16 * i + li;
-        if (row >= a.rows) continue;
-        const bool data = a.rowseq[row] >= 0;
+    for (int i = 0; i < RT; ++i) {
+        const int64_t rbase = row0 + 16 * i;
+        const int64_t row = rbase + li;                  // < the allocated rows
+        const bool data = row < a.rows && a.rowseq[row] >= 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int c0 = 16 * j + 4 * (lane >> 4);
@@ -391,9 +401,22 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
                 }
                 const uint32_t p0 = (uint32_t)to_bf16(z[0]) | ((uint32_t)to_bf16(z[1]) << 16);
                 const uint32_t p1 = (uint32_t)to_bf16(z[2]) | ((uint32_t)to_bf16(z[3]) << 16);
-                *(uint2 *)((bf16_t *)a.out + o) = make_uint2(p0, p1);
+                *(uint2 *)(sw + li * kOp + c0) = make_uint2(p0, p1);
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int rr = 4 * k + (lane >> 4), c = 8 * (lane & 15);
+            const uint4 piece = *(const uint4 *)(sw + rr * kOp + c);
+            if (rbase + rr < a.rows)
+                *(uint4 *)((bf16_t *)a.out + (kLead + rbase + rr) * kW + c) = piece;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -698,7 +721,9 @@ static int cnn_forward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t s
         c.bias = at<float>(P, pl.b[l]);
         if (l == 0) {
             c.out = w.h[1];
-            hipLaunchKernelGGL((k_conv<kIn, kdp_of(0), kEpiRelu>), dim3(tiles), dim3(512), 0, s, c);
+            hipLaunchKernelGGL((k_conv<kIn, kdp_of(0), kEpiRelu, kRowTiles0>),
+                               dim3((unsigned)((b.rows + conv_tile(kRowTiles0) - 1) / conv_tile(kRowTiles0))),
+                               dim3(512), 0, s, c);
         } else if (l < kLayers - 1) {
             c.out = w.h[l + 1];
             hipLaunchKernelGGL((k_conv<kW, kdp_of(1), kEpiRelu>), dim3(tiles), dim3(512), 0, s, c);

@@ -373,10 +373,22 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
         const int64_t rbase = row0 + 16 * i;
         const int64_t row = rbase + li;                  // < the allocated rows
         const bool data = row < a.rows && a.rowseq[row] >= 0;
+        if (EPI == kEpiGradRelu) {
+            // the gating rows come in the same way, whole rows into the slice
+            // (each lane then reads and overwrites only its own pieces)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int rr = 4 * k + (lane >> 4), c = 8 * (lane & 15);
+                *(uint4 *)(sw + rr * kOp + c) =
+                    *(const uint4 *)(a.relu_ref + (kLead + rbase + rr) * kW + c);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int c0 = 16 * j + 4 * (lane >> 4);
-            const int64_t o = (kLead + row) * kW + c0;
             float v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
@@ -391,7 +403,7 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
                         z[r] = data && y > 0.0f ? y : 0.0f;
                     }
                 } else {
-                    const uint2 ref = *(const uint2 *)(a.relu_ref + o);
+                    const uint2 ref = *(const uint2 *)(sw + li * kOp + c0);
                     const uint32_t rr[2] = {ref.x, ref.y};
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {

@@ -446,7 +446,7 @@ __global__ void __launch_bounds__(512) k_conv(ConvArgs a) {
 // kk in [128 k, 128 k + 128) for CIN = 128; one block holds the one-hot
 // layer's 40 columns (5 taps x 8).  Workgroup = 4 wavefronts, wavefront w
 // owns co in [32 w, 32 w + 32) x the block's kk.
-constexpr int kWgChunk = 16384;     // rows per workgroup (128-channel layers)
+constexpr int kWgChunk = 4096;      // rows per workgroup (128-channel layers)
 constexpr int kWgChunk0 = 2048;     // rows per workgroup (one-hot layer: one column block)
 constexpr int kStep = 64;      // rows staged per step
 constexpr int kPitch = 144;    // LDS row pitch of the 128-channel tiles (288 bytes)

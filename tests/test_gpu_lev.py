@@ -56,8 +56,9 @@ def test_related_long_pairs_cross_pass_boundary():
     _check_pairs(codes, off, codes, off, 4, ia.ravel(), ib.ravel())
 
 
-def test_all_binary_strings_up_to_length_6():
-    strs = [s for L in range(7) for s in itertools.product((0, 1), repeat=L)]
+def test_all_binary_strings_up_to_length_8():
+    # every ordered pair of the 511 binary strings of length 0..8 (261,121 pairs)
+    strs = [s for L in range(9) for s in itertools.product((0, 1), repeat=L)]
     seqs = [np.array(s, dtype=np.uint8) for s in strs]
     codes, off = synth.to_csr(seqs)
     n = len(seqs)

@@ -30,6 +30,17 @@ def _check(codes_a, off_a, codes_b, off_b, sigma, ia, ib):
         assert np.array_equal(ops[p], wops[p]), (p, len(ops[p]), len(wops[p]))
 
 
+def test_all_binary_strings_up_to_length_5():
+    # every ordered pair of the 63 binary strings of length 0..5: scores and
+    # the walked alignments (ties everywhere on a binary alphabet)
+    import itertools
+    strs = [s for L in range(6) for s in itertools.product((0, 1), repeat=L)]
+    codes, off = synth.to_csr([np.array(s, dtype=np.uint8) for s in strs])
+    n = len(strs)
+    ia, ib = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    _check(codes, off, codes, off, 2, ia.ravel(), ib.ravel())
+
+
 @pytest.mark.parametrize("sigma", [2, 4, 5, 21])
 def test_random_pairs(sigma):
     codes, off = synth.random_set(400 + sigma, 60, 0, 500, sigma)

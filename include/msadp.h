@@ -288,7 +288,7 @@ int cnn_train_step(void *params, const msa_seqs *S, const int32_t *idx, int32_t 
  *     default 32).
  *   MSA_TUNE_TREE: bin = ceil(max_len / 64) of the set of tree_build,
  *     tree_build_pruned and tree_eval_centers; value = 64-bit words per pass
- *     of their Levenshtein kernels (4, 8, 16, 24, 32; default as for
+ *     of their Levenshtein kernels (4, 8, 16, 20, 24, 32; default as for
  *     MSA_TUNE_LEV).  An entry that would take more passes than the default
  *     (and more than two) is ignored.
  * Workspace sizes never depend on the table.  Results never depend on it

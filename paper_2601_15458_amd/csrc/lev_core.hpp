@@ -216,7 +216,7 @@ inline bool is_lev_class(int c) {
 }
 
 // Variants of the tree build's medoid and pole kernels.
-constexpr int kTreeClasses[] = {4, 8, 16, 24, 32};
+constexpr int kTreeClasses[] = {4, 8, 16, 20, 24, 32};
 
 inline bool is_tree_class(int c) {
     for (int x : kTreeClasses)

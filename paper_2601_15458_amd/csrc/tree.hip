@@ -927,6 +927,7 @@ static void level_pass(const TreeArgs &a, int wclass, int grid, int egrid, hipSt
         case 4: launch_passes<4>(a, grid, egrid, s); break;
         case 8: launch_passes<8>(a, grid, egrid, s); break;
         case 16: launch_passes<16>(a, grid, egrid, s); break;
+        case 20: launch_passes<20>(a, grid, egrid, s); break;
         case 24: launch_passes<24>(a, grid, egrid, s); break;
         default: launch_passes<32>(a, grid, egrid, s); break;
     }
@@ -937,6 +938,7 @@ static void level_select(const TreeArgs &a, int wclass, int grid, int egrid, hip
         case 4: launch_select<4>(a, grid, egrid, s); break;
         case 8: launch_select<8>(a, grid, egrid, s); break;
         case 16: launch_select<16>(a, grid, egrid, s); break;
+        case 20: launch_select<20>(a, grid, egrid, s); break;
         case 24: launch_select<24>(a, grid, egrid, s); break;
         default: launch_select<32>(a, grid, egrid, s); break;
     }
@@ -964,6 +966,7 @@ static int tree_grid(int wclass) {
             case 4: g = persistent_grid(k_tree_lev<4, kMedoid>); break;
             case 8: g = persistent_grid(k_tree_lev<8, kMedoid>); break;
             case 16: g = persistent_grid(k_tree_lev<16, kMedoid>); break;
+            case 20: g = persistent_grid(k_tree_lev<20, kMedoid>); break;
             case 24: g = persistent_grid(k_tree_lev<24, kMedoid>); break;
             default: g = persistent_grid(k_tree_lev<32, kMedoid>); break;
         }

@@ -127,7 +127,7 @@ def _tree_matches_oracle(got, codes, off, want=None):
     assert np.array_equal(got["perm"], want["perm"])
 
 
-@pytest.mark.parametrize("wclass", [4, 8, 16, 24, 32])
+@pytest.mark.parametrize("wclass", [4, 8, 16, 20, 24, 32])
 def test_tree_every_class(wclass):
     """Lengths 40-500 (8 words): every tree class is admissible; class 4
     runs two passes through the carry buffer."""
@@ -140,7 +140,7 @@ def test_tree_every_class(wclass):
     _tree_matches_oracle(got, codes, off)
 
 
-@pytest.mark.parametrize("wclass", [4, 16, 24])
+@pytest.mark.parametrize("wclass", [4, 16, 20, 24])
 def test_tree_long_patterns_classes(wclass):
     """Lengths 40-1700 (27 words): 16 and 24 take two passes; 4 would take
     seven and is ignored (the default runs)."""
@@ -174,6 +174,6 @@ def test_autotune_tree():
     S = M.to_device(codes, off, 4)
     best, ms = M.autotune_tree(S, reps=1)
     print(f"[tune] autotune tree -> class {best}, {ms:.3f} ms", flush=True)
-    assert best in (16, 24, 32) and ms > 0
+    assert best in (16, 20, 24, 32) and ms > 0
     assert M.tune_get(M.MSA_TUNE_TREE, 4, M.lev_words_bin(S)) == best
     _tree_matches_oracle(M.tree_build(S, use_graph=True), codes, off)

@@ -21,7 +21,7 @@ def test_candidates():
     M = _msadp()
     assert M.tune_candidates(M.MSA_TUNE_LEV) == [4, 8, 16, 20, 24, 28, 32]
     assert M.tune_candidates(M.MSA_TUNE_NW) == [16, 32, 64]
-    assert M.tune_candidates(M.MSA_TUNE_TREE) == [4, 8, 16, 24, 32]
+    assert M.tune_candidates(M.MSA_TUNE_TREE) == [4, 8, 16, 20, 24, 32]
 
 
 def test_set_get_clear():
@@ -42,7 +42,7 @@ def test_set_get_clear():
 @pytest.mark.parametrize("kind,sigma,bin_,value", [
     (0, 4, 25, 30),      # not a word class
     (1, 4, 3, 48),       # not a barrier interval
-    (2, 4, 3, 20),       # a pair-kernel class the tree build does not have
+    (2, 4, 3, 28),       # a pair-kernel class the tree build does not have
     (3, 4, 3, 32),       # unknown kind
     (0, 1, 3, 32),       # alphabet too small
     (0, 4, 0, 32),       # empty bin

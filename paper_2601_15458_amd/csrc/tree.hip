@@ -212,13 +212,19 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
         int64_t tpos, prow_pos = -1;
         int32_t prow;
         int64_t cslot = 0;
+        int64_t tend = ms + k;                   // texts are positions [.., tend)
         if (MODE == kMedoid) {
-            const int64_t u = triangle_row(local, k - 1);
-            const int64_t p = k - 1 - u;
-            const int64_t blk = local - items_upto(u - 1);
-            prow_pos = ms + p;
+            // Member u (the longer of each pair: members are in length order)
+            // is the pattern of members 0 .. u-1, which cost fewer bit
+            // columns than the other way round and round up fewer rows; the
+            // members with the most texts come first.
+            const int64_t r = items_upto(k - 1) - 1 - local;
+            const int64_t u = triangle_row(r, k - 1);
+            const int64_t blk = r - items_upto(u - 1);
+            prow_pos = ms + u;
             prow = a.perm[prow_pos];
-            tpos = ms + p + 1 + blk * 64 + lane;
+            tpos = ms + blk * 64 + lane;
+            tend = ms + u;
         } else if (MODE == kCandSum) {
             const int64_t nblk = (k + 63) / 64;
             const int64_t j = local / nblk, blk = local % nblk;
@@ -229,7 +235,7 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
             prow = a.pat[q];
             tpos = ms + local * 64 + lane;
         }
-        const bool valid = tpos < ms + k;
+        const bool valid = tpos < tend;
         const int32_t trow = a.perm[valid ? tpos : ms];
         const int d = lev_item<WMAX>(peq, a.S.codes + (int64_t)prow * a.S.stride, a.S.len[prow],
                                      a.sigma, a.S.codes + (int64_t)trow * a.S.stride,

@@ -121,7 +121,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
-              "of the pair triangle is described in DESIGN.md but not built", file=sys.stderr)
+              "of the pair triangle is designed but not built", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2601_15458_amd import msadp, synth

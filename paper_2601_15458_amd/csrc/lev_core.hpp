@@ -60,7 +60,7 @@ __device__ __forceinline__ int lev_pass(lds_u64 *peq, const uint8_t *text, int n
         uint32_t cw = CIN ? hbuf[(j0 >> 4) * kWave] : 0x55555555u;
         uint32_t ow = 0;
         uint32_t c0 = cur.x, c1 = cur.y, c2 = cur.z, c3 = cur.w;
-        const int steps = min(16, nmax - j0);
+        const int steps = (int)uniform((uint32_t)min(16, nmax - j0));
         for (int jj = 0; jj < steps; ++jj) {
             const uint32_t t = c0 & 0xFFu;
             c0 = __builtin_amdgcn_alignbyte(c1, c0, 1);
@@ -115,12 +115,10 @@ __device__ __forceinline__ int lev_pass(lds_u64 *peq, const uint8_t *text, int n
                 asm volatile("" : "+v"(cph), "+v"(cmh), "+v"(pl[k]), "+v"(ph[k]), "+v"(ml[k]),
                              "+v"(mh[k]));
             }
-            if (cout) {
-                ow |= (dp | (dn << 1)) << (2 * jj);
-            } else {
-                const int d = (int)dp - (int)dn;
-                score += (j0 + jj < n) ? d : 0;
-            }
+            // both outputs every column (no branch in the loop): the carry
+            // word is stored only when cout, the score used only by a last pass
+            ow |= (dp | (dn << 1)) << (2 * jj);
+            score += (j0 + jj < n) ? (int)dp - (int)dn : 0;
         }
         if (cout) hbuf[(j0 >> 4) * kWave] = ow;
         cur = nxt;

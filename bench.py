@@ -39,8 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB
 # copy shows) + WRITE_SIZE on these workloads (profiles/k_lev_allpairs_dna4096.md,
 # profiles/k_nw_fill_dna512.md), by launch variant; None for a variant not measured.
-LEV_TRAFFIC = {16: 11311.2e3 * 1024, 20: 4338.5e3 * 1024, 24: 2165.1e3 * 1024,
-               28: 2071.8e3 * 1024, 32: 2095.3e3 * 1024}
+LEV_TRAFFIC = {16: 11297.3e3 * 1024, 20: 4331.5e3 * 1024, 24: 2176.4e3 * 1024,
+               28: 2086.9e3 * 1024, 32: 2091.1e3 * 1024}
 NW_FILL_TRAFFIC = {16: (2 * 4733 + 7885300) * 1024, 32: (2 * 6616 + 7974700) * 1024,
                    64: (2 * 242080 + 8268300) * 1024}
 

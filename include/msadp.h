@@ -80,10 +80,17 @@ int msa_version(void);
 /* Workspace for lev_batch over n_pairs pairs drawn from A and B. */
 size_t lev_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs);
 
-/* dist[p] = lev(A[ia[p]], B[ib[p]]) for p in [0, n_pairs).
- * ia, ib: device int32[n_pairs]; dist: device uint16[n_pairs].
- * Pairs are grouped by ia on the device so that every wavefront shares one
- * pattern; any order of pairs is correct. */
+/* dist[p] = lev(A[ia[p]], B[ib[p]]) for p in [0, n_pairs) (A and B share
+ * sigma; two descriptions of the same set are staged once).
+ * ia, ib: device int32[n_pairs]; dist: device uint16[n_pairs].  Any order
+ * of pairs is correct; the pairs are scheduled on the device in one
+ * persistent launch, in one of two layouts (MSA_TUNE_PAIRS below):
+ * pairs grouped by ia, 64 pairs of one pattern per wavefront, groups
+ * longest pattern first and each group's texts longest first; or, when the
+ * patterns are short enough, one pair per lane with the longer sequence as
+ * its pattern, binned by pattern words and ordered by text length, longest
+ * first (for sparse lists with few pairs per sequence).  A pair with an
+ * index out of range sets MSA_DS_INDEX and dist[p] = 0xFFFF. */
 int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
               int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes,
               int32_t *d_status, hipStream_t s);
@@ -291,9 +298,16 @@ int cnn_train_step(void *params, const msa_seqs *S, const int32_t *idx, int32_t 
  *     of their Levenshtein kernels (4, 8, 16, 20, 24, 32; default as for
  *     MSA_TUNE_LEV).  An entry that would take more passes than the default
  *     (and more than two) is ignored.
+ *   MSA_TUNE_PAIRS: bin = ceil(max(A->max_len, B->max_len) / 64) of a
+ *     lev_batch call; value = lanes that share one pattern table: 1 (every
+ *     lane holds its own pair and pattern, pairs binned by pattern words and
+ *     text length) or 64 (pairs grouped by A sequence, a wavefront takes 64
+ *     pairs of one pattern).  1 needs patterns of at most 32 / sigma' words
+ *     (sigma' = 4, 8, 32 for sigma <= 4, <= 8, <= 32) and is the default when
+ *     they fit; an entry of 1 that does not fit is ignored.
  * Workspace sizes never depend on the table.  Results never depend on it
  * (every variant computes the same exact values). */
-enum { MSA_TUNE_LEV = 0, MSA_TUNE_NW = 1, MSA_TUNE_TREE = 2 };
+enum { MSA_TUNE_LEV = 0, MSA_TUNE_NW = 1, MSA_TUNE_TREE = 2, MSA_TUNE_PAIRS = 3 };
 
 /* Set one entry (EINVAL for an unknown kind, a key out of range or a value
  * that is not a variant of the kind). */
@@ -327,6 +341,15 @@ int msa_autotune_nw(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, con
                     int64_t n_pairs, int32_t *score, uint8_t *tb, const int64_t *tb_offsets,
                     void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
                     int32_t *d_status, hipStream_t s);
+/* The same for the pair-list layout of lev_batch (same arguments as
+ * lev_batch; dist holds the last run's exact distances): both layouts when
+ * the patterns fit the per-lane one, fastest stored for (MSA_TUNE_PAIRS,
+ * A->sigma, ceil(max(A->max_len, B->max_len) / 64)); *best = 1 or 64.
+ * n_pairs >= 1. */
+int msa_autotune_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
+                       const int32_t *ib, int64_t n_pairs, uint16_t *dist, void *ws,
+                       size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
+                       int32_t *d_status, hipStream_t s);
 /* The same for the exact tree_build (same arguments as tree_build; T and
  * *n_nodes hold the last run's tree): every class within the default's
  * passes (at least two), fastest stored for (MSA_TUNE_TREE, S->sigma,

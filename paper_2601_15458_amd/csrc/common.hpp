@@ -78,9 +78,10 @@ struct Carve {
 struct Sizer {
     size_t cur = 0;
     template <class T>
-    void take(size_t count) {
+    T *take(size_t count) {
         cur = (cur + 255) / 256 * 256;
         cur += count * sizeof(T);
+        return nullptr;
     }
     size_t total() const { return cur + 256; }
 };
@@ -100,6 +101,14 @@ int sort_by_length(const msa_seqs *S, int32_t *len_tmp, int32_t *hist, int32_t *
 int fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 int fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 int exclusive_scan_i64(int64_t *data, int64_t n, hipStream_t s);
+// lev_batch with a forced pair-list layout (1 = one pattern per lane, 64 =
+// shared patterns; 0 = the tuning table or the default; -1 = the default
+// layout and word class, tuning table not read) (lev.hip).
+int lev_batch_impl(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                   int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes,
+                   int32_t *d_status, hipStream_t s, int forced);
+// Workspace of lev_batch_impl; untuned: for forced == -1 only.
+size_t lev_batch_ws_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs, bool untuned);
 // The tuning table's value for (kind, sigma, bin), or `fallback` (tune.hip).
 int tuned_value(int kind, int sigma, int bin, int fallback);
 

@@ -78,17 +78,36 @@ __global__ void __launch_bounds__(64) k_lev_allpairs(AllPairsArgs a) {
     }
 }
 
-// --------------------------------------------------------- grouped pairs
+// ------------------------------------------------------------ pair lists
+// Two layouts for an explicit pair list, chosen per call:
+//
+//  * Shared pattern ("grouped"): pairs are grouped by their A sequence and a
+//    wavefront takes up to 64 pairs of one group, whose match table sits once
+//    in LDS.  Inside a group the pairs are ordered by text length, longest
+//    first, and groups run longest pattern first, so a wavefront's texts have
+//    nearly equal lengths and the largest items start first.  Good when every
+//    sequence has many partners.
+//  * One pattern per lane ("lanes"): each lane holds one pair, with the longer
+//    sequence as its pattern (the distance is symmetric) and its own match
+//    table in LDS.  Pairs are binned by pattern words and, inside a bin,
+//    ordered by text length, longest first; a wavefront takes 64 consecutive
+//    pairs of one bin.  For sparse lists (a few partners per sequence), where
+//    shared-pattern wavefronts would leave most lanes idle.  It needs patterns
+//    of at most 32 / sigma' words (sigma' = 4, 8 or 32 for sigma <= 4, <= 8,
+//    <= 32): 512 rows of DNA.
 struct Item {
-    int64_t start;    // first position in the grouped pair list
-    int32_t pattern;  // index into A
+    int64_t start;    // first position in the ordered pair list
+    int32_t key;      // grouped: the pattern (index into A); lanes: pattern words
     int32_t count;    // pairs in this item (<= 64)
 };
+
+constexpr int kSwapBit = 62;   // lanes layout: the pattern is B's sequence
+constexpr int64_t kPairMask = (1ll << kSwapBit) - 1;
 
 struct GroupedArgs {
     Staged A, B;
     const int32_t *ib;
-    const int64_t *sorted;   // pair ids grouped by ia
+    const int64_t *sorted;   // pair ids grouped by ia, ordered inside groups
     const Item *items;
     const int64_t *n_items;  // device count
     uint16_t *out;
@@ -111,8 +130,8 @@ __global__ void __launch_bounds__(64) k_lev_grouped(GroupedArgs a) {
         const bool valid = lane < I.count;
         const int64_t pid = a.sorted[I.start + (valid ? lane : 0)];
         const int32_t jb = a.ib[pid];
-        const uint8_t *pat = a.A.codes + (int64_t)I.pattern * a.A.stride;
-        const int m = a.A.len[I.pattern];
+        const uint8_t *pat = a.A.codes + (int64_t)I.key * a.A.stride;
+        const int m = a.A.len[I.key];
         const uint8_t *text = a.B.codes + (int64_t)jb * a.B.stride;
         const int n = a.B.len[jb];
         const int d = lev_item<WMAX>(peq, pat, m, a.sigma, text, n, valid, hb);
@@ -120,12 +139,64 @@ __global__ void __launch_bounds__(64) k_lev_grouped(GroupedArgs a) {
     }
 }
 
+struct LanesArgs {
+    Staged A, B;             // staged with one common stride
+    const int32_t *ia, *ib;
+    const int64_t *sorted;   // pair ids (bit kSwapBit: B's sequence is the pattern)
+    const Item *items;
+    const int64_t *n_items;
+    uint16_t *out;
+    uint32_t *counter;
+};
+
+// WMAX words per pattern at most, SP = sigma' symbol rows per word.
+template <int WMAX, int SP>
+__global__ void __launch_bounds__(64) k_lev_lanes(LanesArgs a) {
+    __shared__ uint64_t tbl[WMAX * SP * kWave];
+    const int lane = lane_id();
+    const int64_t total = *a.n_items;
+    for (;;) {
+        const uint32_t it = next_item(a.counter);
+        if ((int64_t)it >= total) break;
+        const Item I = a.items[it];
+        const bool valid = lane < I.count;
+        const int64_t e = a.sorted[I.start + (valid ? lane : 0)];
+        const int64_t pid = e & kPairMask;
+        const bool swap = (e >> kSwapBit) & 1;
+        const int32_t x = a.ia[pid], y = a.ib[pid];
+        const uint8_t *sa = a.A.codes + (int64_t)x * a.A.stride;
+        const uint8_t *sb = a.B.codes + (int64_t)y * a.B.stride;
+        const int la = a.A.len[x], lb = a.B.len[y];
+        const uint8_t *pat = swap ? sb : sa;
+        const uint8_t *text = swap ? sa : sb;
+        const int m = swap ? lb : la, n = swap ? la : lb;
+        const int W = (int)uniform((uint32_t)I.key);
+        const int nmax = (int)uniform((uint32_t)wave_max(valid ? n : 0));
+        int d;
+        if (W == 0) {
+            d = n;                  // both sequences empty
+        } else if (nmax == 0) {
+            d = m;                  // every text empty
+        } else {
+            build_lane_peq<SP>(tbl, pat, m, W);
+            d = m + dispatch_lanes<WMAX, SP>(W, (lds_u64 *)tbl + lane, text, n, nmax,
+                                             (m - 1) & 63);
+        }
+        if (valid) a.out[pid] = (uint16_t)d;
+    }
+}
+
+__device__ __forceinline__ bool pair_ok(int32_t x, int32_t y, int32_t na, int32_t nb) {
+    return x >= 0 && x < na && y >= 0 && y < nb;
+}
+
+// grouped layout: pairs per A sequence
 __global__ void k_pair_hist(const int32_t *ia, const int32_t *ib, int64_t np, int32_t na,
                             int32_t nb, int64_t *counts, uint16_t *out, int32_t *st) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t x = ia[p], y = ib[p];
-        if (x < 0 || x >= na || y < 0 || y >= nb) {
+        if (!pair_ok(x, y, na, nb)) {
             set_status(st, MSA_DS_INDEX);
             if (out) out[p] = 0xFFFF;
             continue;
@@ -139,52 +210,185 @@ __global__ void k_pair_scatter(const int32_t *ia, const int32_t *ib, int64_t np,
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
          p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t x = ia[p], y = ib[p];
-        if (x < 0 || x >= na || y < 0 || y >= nb) continue;
+        if (!pair_ok(x, y, na, nb)) continue;
         const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&cursor[x], 1ull);
         sorted[pos] = p;
     }
 }
 
-// nitems[g] = ceil(count_g / 64) where count_g = start[g+1] - start[g]
-__global__ void k_item_counts(const int64_t *start, int32_t ng, int64_t *nitems) {
-    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g > ng) return;
-    if (g == ng) { nitems[g] = 0; return; }
-    nitems[g] = (start[g + 1] - start[g] + 63) / 64;
+// One workgroup per group: a counting sort of the group's pairs into 64 text
+// length buckets, longest first (the order inside a bucket is unspecified).
+__global__ void __launch_bounds__(256) k_group_sort(const int64_t *start, const int64_t *sorted,
+                                                    const int32_t *ib, const int32_t *lenB,
+                                                    int32_t bmax, int64_t *sorted2) {
+    __shared__ unsigned long long h[64];
+    const int g = blockIdx.x, t = threadIdx.x;
+    const int64_t s0 = start[g], c = start[g + 1] - s0;
+    if (c <= 64) {   // one work item: its order does not matter
+        for (int64_t i = t; i < c; i += blockDim.x) sorted2[s0 + i] = sorted[s0 + i];
+        return;
+    }
+    if (t < 64) h[t] = 0;
+    __syncthreads();
+    for (int64_t i = t; i < c; i += blockDim.x) {
+        const int32_t n = lenB[ib[sorted[s0 + i]]];
+        atomicAdd(&h[63 - (int)((int64_t)n * 64 / ((int64_t)bmax + 1))], 1ull);
+    }
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long acc = 0;
+        for (int b = 0; b < 64; ++b) {
+            const unsigned long long v = h[b];
+            h[b] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    for (int64_t i = t; i < c; i += blockDim.x) {
+        const int64_t pid = sorted[s0 + i];
+        const int32_t n = lenB[ib[pid]];
+        const unsigned long long pos =
+            atomicAdd(&h[63 - (int)((int64_t)n * 64 / ((int64_t)bmax + 1))], 1ull);
+        sorted2[s0 + (int64_t)pos] = pid;
+    }
 }
 
-__global__ void k_make_items(const int64_t *start, const int64_t *item_start, int32_t ng,
-                             Item *items, int64_t *n_items) {
-    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g == 0) *n_items = item_start[ng];
-    if (g >= ng) return;
+// nitems[r] = work items of the group at rank r, longest pattern first
+// (order: ascending length ranks of A).
+__global__ void k_rank_item_counts(const int64_t *start, const int32_t *order, int32_t ng,
+                                   int64_t *nitems) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > ng) return;
+    if (r == ng) {
+        nitems[r] = 0;
+        return;
+    }
+    const int32_t g = order[ng - 1 - r];
+    nitems[r] = (start[g + 1] - start[g] + 63) / 64;
+}
+
+__global__ void k_rank_make_items(const int64_t *start, const int64_t *item_start,
+                                  const int32_t *order, int32_t ng, Item *items,
+                                  int64_t *n_items) {
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0) *n_items = item_start[ng];
+    if (r >= ng) return;
+    const int32_t g = order[ng - 1 - r];
     const int64_t c = start[g + 1] - start[g];
-    const int64_t base = item_start[g];
+    const int64_t base = item_start[r];
     for (int64_t b = 0; b * 64 < c; ++b) {
         Item I;
         I.start = start[g] + b * 64;
-        I.pattern = g;
+        I.key = g;
         I.count = (int32_t)min<int64_t>(64, c - b * 64);
         items[base + b] = I;
     }
 }
 
+// lanes layout: key = (wmax - pattern words) * nb + (nb - 1 - text length / 4),
+// so that ascending keys run the most pattern words first and, inside a
+// words bin, the longest texts first.
+__device__ __forceinline__ int32_t lanes_key(int la, int lb, int wmax, int nb, bool *swap) {
+    *swap = lb > la;
+    const int P = max(la, lb), T = min(la, lb);
+    return (wmax - ((P + 63) >> 6)) * nb + (nb - 1 - (T >> 2));
+}
+
+__global__ void k_lanes_hist(const int32_t *ia, const int32_t *ib, int64_t np, const int32_t *lenA,
+                             const int32_t *lenB, int32_t na, int32_t nb_seq, int32_t wmax,
+                             int32_t nb, int64_t *counts, uint16_t *out, int32_t *st) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = ia[p], y = ib[p];
+        if (!pair_ok(x, y, na, nb_seq)) {
+            set_status(st, MSA_DS_INDEX);
+            if (out) out[p] = 0xFFFF;
+            continue;
+        }
+        bool sw;
+        const int32_t key = lanes_key(lenA[x], lenB[y], wmax, nb, &sw);
+        atomicAdd((unsigned long long *)&counts[key], 1ull);
+    }
+}
+
+__global__ void k_lanes_scatter(const int32_t *ia, const int32_t *ib, int64_t np,
+                                const int32_t *lenA, const int32_t *lenB, int32_t na,
+                                int32_t nb_seq, int32_t wmax, int32_t nb, int64_t *cursor,
+                                int64_t *sorted) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = ia[p], y = ib[p];
+        if (!pair_ok(x, y, na, nb_seq)) continue;
+        bool sw;
+        const int32_t key = lanes_key(lenA[x], lenB[y], wmax, nb, &sw);
+        const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&cursor[key], 1ull);
+        sorted[pos] = p | ((int64_t)sw << kSwapBit);
+    }
+}
+
+// Items of 64 consecutive pairs inside each words bin; start[] is the
+// exclusive scan of the key counts ((wmax + 1) * nb + 1 entries).
+constexpr int kLanesMaxWords = 8;
+__global__ void k_lanes_items(const int64_t *start, int32_t wmax, int32_t nb, Item *items,
+                              int64_t *n_items) {
+    __shared__ int64_t base[kLanesMaxWords + 2];
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int b = 0; b <= wmax; ++b) {
+            base[b] = acc;
+            acc += (start[(b + 1) * nb] - start[b * nb] + 63) / 64;
+        }
+        base[wmax + 1] = acc;
+        if (blockIdx.x == 0) *n_items = acc;
+    }
+    __syncthreads();
+    const int64_t total = base[wmax + 1];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int b = 0;
+        while (base[b + 1] <= i) ++b;
+        const int64_t s0 = start[b * nb], c = start[(b + 1) * nb] - s0, k = i - base[b];
+        Item I;
+        I.start = s0 + k * 64;
+        I.key = wmax - b;
+        I.count = (int32_t)min<int64_t>(64, c - k * 64);
+        items[i] = I;
+    }
+}
+
 // ------------------------------------------------------------ host side
 #define MSADP_LEV_CLASSES(X) X(4) X(8) X(16) X(20) X(24) X(28) X(32)
+// Lanes-layout variants: (most pattern words, sigma').
+#define MSADP_LANES_CLASSES(X) X(8, 4) X(4, 8) X(1, 32)
+
+enum { kAllPairsKernel = 0, kGroupedKernel = 1, kLanesKernel = 2 };
 
 // Persistent grid of a kernel variant, cached per device (concurrent first
-// calls compute the same value).
-static int lev_grid(int wclass, bool grouped) {
-    static std::atomic<int> cache[kMaxDevices][2][33];
-    std::atomic<int> &slot = cache[current_device()][grouped][wclass];
+// calls compute the same value).  Lanes variants are keyed by their words.
+static int lev_grid(int wclass, int kind) {
+    static std::atomic<int> cache[kMaxDevices][3][33];
+    std::atomic<int> &slot = cache[current_device()][kind][wclass];
     int g = slot.load(std::memory_order_relaxed);
     if (g == 0) {
-        switch (wclass) {
-#define MSADP_G(w) \
-    case w: g = grouped ? persistent_grid(k_lev_grouped<w>) : persistent_grid(k_lev_allpairs<w>); break;
-            MSADP_LEV_CLASSES(MSADP_G)
+        if (kind == kLanesKernel) {
+            switch (wclass) {
+#define MSADP_G(w, sp) \
+    case w: g = persistent_grid(k_lev_lanes<w, sp>); break;
+                MSADP_LANES_CLASSES(MSADP_G)
 #undef MSADP_G
-            default: g = device_cus();
+                default: g = device_cus();
+            }
+        } else {
+            switch (wclass) {
+#define MSADP_G(w)                                                                      \
+    case w:                                                                             \
+        g = kind == kGroupedKernel ? persistent_grid(k_lev_grouped<w>)                  \
+                                   : persistent_grid(k_lev_allpairs<w>);                \
+        break;
+                MSADP_LEV_CLASSES(MSADP_G)
+#undef MSADP_G
+                default: g = device_cus();
+            }
         }
         slot.store(g, std::memory_order_relaxed);
     }
@@ -203,39 +407,272 @@ static void lev_layout(Alloc &al, const msa_seqs *A, const msa_seqs *B, int64_t 
                        bool grouped) {
     al.template take<uint8_t>((size_t)A->n * staged_stride(A->max_len));
     al.template take<int32_t>((size_t)A->n + 1);
-    if (grouped) {
-        al.template take<uint8_t>((size_t)B->n * staged_stride(B->max_len));
-        al.template take<int32_t>((size_t)B->n + 1);
-        al.template take<int64_t>((size_t)A->n + 1);   // start
-        al.template take<int64_t>((size_t)A->n + 1);   // cursor / item counts
-        al.template take<int64_t>((size_t)n_pairs);    // sorted pair ids
-        al.template take<Item>((size_t)n_pairs);       // items
-        al.template take<int64_t>(1);                  // item count
-    } else {
-        al.template take<int32_t>((size_t)A->n);           // order
-        al.template take<int32_t>((size_t)A->max_len + 1); // length histogram
-    }
+    al.template take<int32_t>((size_t)A->n);           // order
+    al.template take<int32_t>((size_t)A->max_len + 1); // length histogram
     al.template take<uint32_t>(1);  // work counter
     // carry buffer: sized for the largest need over all classes, so that a
     // tuning entry never outgrows a workspace sized beforehand
     size_t hb = 0;
     for (int c : kLevClasses)
         if (needs_passes(A->max_len, c))
-            hb = std::max(hb, (size_t)lev_grid(c, grouped) * kWave * hbuf_stride(B->max_len));
+            hb = std::max(hb, (size_t)lev_grid(c, grouped ? kGroupedKernel : kAllPairsKernel) *
+                                  kWave * hbuf_stride(B->max_len));
     if (hb) al.template take<uint32_t>(hb);
 }
 
-// forced > 0 selects the class (autotuning), else the tuning table or the default.
+// forced > 0 selects the class (autotuning), forced < 0 the default, else
+// the tuning table or the default.
 static LevPlan plan_lev(const msa_seqs *A, const msa_seqs *B, bool grouped, int forced) {
     LevPlan p;
     p.strideA = staged_stride(A->max_len);
     p.strideB = staged_stride(B->max_len);
     const int words = (int)std::max<int64_t>(1, ((int64_t)A->max_len + 63) / 64);
+    const int dflt = wmax_class(A->max_len);
     p.wclass = forced > 0 ? forced
-                          : tuned_value(MSA_TUNE_LEV, A->sigma, words, wmax_class(A->max_len));
-    p.grid = lev_grid(p.wclass, grouped);
+               : forced < 0 ? dflt
+                            : tuned_value(MSA_TUNE_LEV, A->sigma, words, dflt);
+    p.grid = lev_grid(p.wclass, grouped ? kGroupedKernel : kAllPairsKernel);
     p.hstride = needs_passes(A->max_len, p.wclass) ? hbuf_stride(B->max_len) : 0;
     return p;
+}
+
+// ------------------------------------------------ pair-list planning
+// Two descriptions of one set (same device pointers and sizes) are staged once.
+static bool same_set(const msa_seqs *A, const msa_seqs *B) {
+    return A->codes == B->codes && A->offsets == B->offsets && A->n == B->n &&
+           A->sigma == B->sigma && A->max_len == B->max_len && A->packed_2bit == B->packed_2bit;
+}
+
+// The lanes variant for the alphabet, and whether patterns of up to the
+// longer set's max_len fit it.
+static bool lanes_fit(const msa_seqs *A, const msa_seqs *B, int *wmax, int *sp) {
+    *sp = A->sigma <= 4 ? 4 : A->sigma <= 8 ? 8 : 32;
+    *wmax = 32 / *sp;
+    return std::max(A->max_len, B->max_len) <= 64 * *wmax;
+}
+
+static int pair_words_bin(const msa_seqs *A, const msa_seqs *B) {
+    return (int)std::max<int64_t>(1, ((int64_t)std::max(A->max_len, B->max_len) + 63) / 64);
+}
+
+// Workspace pieces of the grouped layout (pointers are null with a Sizer).
+struct GroupedWs {
+    Staged SA, SB;
+    int32_t *order, *hist;
+    int64_t *start, *cursor, *sorted, *sorted2, *n_items;
+    Item *items;
+    uint32_t *counter, *hbuf;
+};
+
+static int64_t grouped_item_bound(const msa_seqs *A, int64_t n_pairs) {
+    return std::min<int64_t>(n_pairs, n_pairs / 64 + A->n) + 1;
+}
+
+template <class Alloc>
+static GroupedWs carve_grouped(Alloc &al, const msa_seqs *A, const msa_seqs *B, int64_t n_pairs,
+                               const LevPlan &pl, bool all_classes) {
+    GroupedWs w;
+    w.SA = Staged{al.template take<uint8_t>((size_t)A->n * pl.strideA),
+                  al.template take<int32_t>((size_t)A->n + 1), pl.strideA, A->n};
+    if (same_set(A, B)) {
+        w.SB = w.SA;
+    } else {
+        w.SB = Staged{al.template take<uint8_t>((size_t)B->n * pl.strideB),
+                      al.template take<int32_t>((size_t)B->n + 1), pl.strideB, B->n};
+    }
+    w.order = al.template take<int32_t>((size_t)A->n);
+    w.hist = al.template take<int32_t>((size_t)A->max_len + 1);
+    w.start = al.template take<int64_t>((size_t)A->n + 1);
+    w.cursor = al.template take<int64_t>((size_t)A->n + 1);
+    w.sorted = al.template take<int64_t>((size_t)n_pairs);
+    w.sorted2 = al.template take<int64_t>((size_t)n_pairs);
+    w.items = al.template take<Item>((size_t)grouped_item_bound(A, n_pairs));
+    w.n_items = al.template take<int64_t>(1);
+    w.counter = al.template take<uint32_t>(1);
+    // carry buffer: with all_classes, the largest need over every class, so
+    // that a tuning entry never outgrows a workspace sized beforehand
+    size_t hb = 0;
+    if (all_classes) {
+        for (int c : kLevClasses)
+            if (needs_passes(A->max_len, c))
+                hb = std::max(hb, (size_t)lev_grid(c, kGroupedKernel) * kWave *
+                                      hbuf_stride(B->max_len));
+    } else if (pl.hstride) {
+        hb = (size_t)pl.grid * kWave * pl.hstride;
+    }
+    w.hbuf = hb ? al.template take<uint32_t>(hb) : nullptr;
+    return w;
+}
+
+struct LanesWs {
+    Staged SA, SB;
+    int64_t *counts, *cursor, *sorted, *n_items;
+    Item *items;
+    uint32_t *counter;
+};
+
+template <class Alloc>
+static LanesWs carve_lanes(Alloc &al, const msa_seqs *A, const msa_seqs *B, int64_t n_pairs,
+                           int wmax) {
+    LanesWs w;
+    const int64_t stride = staged_stride(std::max(A->max_len, B->max_len));
+    w.SA = Staged{al.template take<uint8_t>((size_t)A->n * stride),
+                  al.template take<int32_t>((size_t)A->n + 1), stride, A->n};
+    if (same_set(A, B)) {
+        w.SB = w.SA;
+    } else {
+        w.SB = Staged{al.template take<uint8_t>((size_t)B->n * stride),
+                      al.template take<int32_t>((size_t)B->n + 1), stride, B->n};
+    }
+    const int nb = 16 * wmax + 1;
+    w.counts = al.template take<int64_t>((size_t)(wmax + 1) * nb + 1);
+    w.cursor = al.template take<int64_t>((size_t)(wmax + 1) * nb + 1);
+    w.sorted = al.template take<int64_t>((size_t)n_pairs);
+    w.items = al.template take<Item>((size_t)(n_pairs / 64 + wmax + 2));
+    w.n_items = al.template take<int64_t>(1);
+    w.counter = al.template take<uint32_t>(1);
+    return w;
+}
+
+// Workspace of a pair list: enough for either layout and, in the grouped one,
+// for the carry buffers of every word class (so that no tuning entry can
+// outgrow it).  untuned: only what the default layout and class need.
+static size_t pairs_ws_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs,
+                             bool untuned) {
+    int wmax, sp;
+    const bool fit = lanes_fit(A, B, &wmax, &sp);
+    size_t total = 0;
+    if (!untuned || !fit) {
+        Sizer sg;
+        const LevPlan pl = plan_lev(A, B, true, untuned ? -1 : 0);
+        carve_grouped(sg, A, B, n_pairs, pl, !untuned);
+        total = sg.total();
+    }
+    if (fit) {
+        Sizer sl;
+        carve_lanes(sl, A, B, n_pairs, wmax);
+        total = std::max(total, sl.total());
+    }
+    return total;
+}
+
+static int run_grouped(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                       int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes,
+                       bool untuned, int32_t *d_status, hipStream_t s) {
+    int rc;
+    const LevPlan pl = plan_lev(A, B, true, untuned ? -1 : 0);
+    Carve cv(ws, ws_bytes);
+    const GroupedWs w = carve_grouped(cv, A, B, n_pairs, pl, false);
+    if (!cv.ok()) return MSA_ENOSPC;
+    // A's length ranks (the staged lengths are written again, identically, by
+    // the staging below)
+    if ((rc = sort_by_length(A, w.SA.len, w.hist, w.order, d_status, s))) return rc;
+    if ((rc = stage_set(A, nullptr, w.SA, d_status, s))) return rc;
+    if (!same_set(A, B) && (rc = stage_set(B, nullptr, w.SB, d_status, s))) return rc;
+    if ((rc = fill_i64(w.start, (int64_t)A->n + 1, 0, s))) return rc;
+    const int64_t pg = std::min<int64_t>((n_pairs + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs, A->n,
+                       B->n, w.start, dist, d_status);
+    if ((rc = exclusive_scan_i64(w.start, (int64_t)A->n + 1, s))) return rc;
+    if (hipMemcpyAsync(w.cursor, w.start, sizeof(int64_t) * ((size_t)A->n + 1),
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MSA_EDEVICE;
+    hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs,
+                       A->n, B->n, w.cursor, w.sorted);
+    if (A->n > 0)
+        hipLaunchKernelGGL(k_group_sort, dim3((unsigned)A->n), dim3(256), 0, s, w.start,
+                           w.sorted, ib, w.SB.len, B->max_len, w.sorted2);
+    const unsigned gg = (unsigned)((A->n + 1 + 255) / 256);
+    hipLaunchKernelGGL(k_rank_item_counts, dim3(gg), dim3(256), 0, s, w.start, w.order, A->n,
+                       w.cursor);
+    if ((rc = exclusive_scan_i64(w.cursor, (int64_t)A->n + 1, s))) return rc;
+    hipLaunchKernelGGL(k_rank_make_items, dim3(gg), dim3(256), 0, s, w.start, w.cursor, w.order,
+                       A->n, w.items, w.n_items);
+    if ((rc = fill_i32((int32_t *)w.counter, 1, 0, s))) return rc;
+    GroupedArgs ga{w.SA,   w.SB,   ib,       w.sorted2,  w.items, w.n_items,
+                   dist,   w.counter, w.hbuf, pl.hstride, A->sigma};
+    switch (pl.wclass) {
+#define MSADP_L(wc) \
+    case wc: hipLaunchKernelGGL(k_lev_grouped<wc>, dim3(pl.grid), dim3(64), 0, s, ga); break;
+        MSADP_LEV_CLASSES(MSADP_L)
+#undef MSADP_L
+        default: return MSA_EINVAL;
+    }
+    return launch_status();
+}
+
+static int run_lanes(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                     int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes, int wmax,
+                     int32_t *d_status, hipStream_t s) {
+    int rc;
+    Carve cv(ws, ws_bytes);
+    const LanesWs w = carve_lanes(cv, A, B, n_pairs, wmax);
+    if (!cv.ok()) return MSA_ENOSPC;
+    const int nb = 16 * wmax + 1;
+    const int64_t nkeys = (int64_t)(wmax + 1) * nb;
+    if ((rc = stage_set(A, nullptr, w.SA, d_status, s))) return rc;
+    if (!same_set(A, B) && (rc = stage_set(B, nullptr, w.SB, d_status, s))) return rc;
+    if ((rc = fill_i64(w.counts, nkeys + 1, 0, s))) return rc;
+    const int64_t pg = std::min<int64_t>((n_pairs + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_lanes_hist, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs,
+                       w.SA.len, w.SB.len, A->n, B->n, wmax, nb, w.counts, dist, d_status);
+    if ((rc = exclusive_scan_i64(w.counts, nkeys + 1, s))) return rc;
+    if (hipMemcpyAsync(w.cursor, w.counts, sizeof(int64_t) * (size_t)(nkeys + 1),
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MSA_EDEVICE;
+    hipLaunchKernelGGL(k_lanes_scatter, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs,
+                       w.SA.len, w.SB.len, A->n, B->n, wmax, nb, w.cursor, w.sorted);
+    const int64_t ig = std::max<int64_t>(1, std::min<int64_t>((n_pairs / 64 + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_lanes_items, dim3((unsigned)ig), dim3(256), 0, s, w.counts, wmax, nb,
+                       w.items, w.n_items);
+    if ((rc = fill_i32((int32_t *)w.counter, 1, 0, s))) return rc;
+    LanesArgs la{w.SA, w.SB, ia, ib, w.sorted, w.items, w.n_items, dist, w.counter};
+    switch (wmax) {
+#define MSADP_L(wc, sp)                                                                     \
+    case wc:                                                                                \
+        hipLaunchKernelGGL((k_lev_lanes<wc, sp>), dim3(lev_grid(wc, kLanesKernel)), dim3(64), 0, \
+                           s, la);                                                          \
+        break;
+        MSADP_LANES_CLASSES(MSADP_L)
+#undef MSADP_L
+        default: return MSA_EINVAL;
+    }
+    return launch_status();
+}
+
+// The pair-list layout: forced (1 = lanes, 64 = grouped; autotuning), else
+// (forced == 0) the tuning table, else lanes whenever the patterns fit it.
+static int pairs_layout(const msa_seqs *A, const msa_seqs *B, int forced, int *wmax) {
+    int sp;
+    const bool fit = lanes_fit(A, B, wmax, &sp);
+    const int dflt = fit ? 1 : kWave;
+    const int v = forced > 0    ? forced
+                  : forced == 0 ? tuned_value(MSA_TUNE_PAIRS, A->sigma, pair_words_bin(A, B), dflt)
+                                : dflt;
+    return (v == 1 && fit) ? 1 : kWave;
+}
+
+size_t lev_batch_ws_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs, bool untuned) {
+    if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
+    return pairs_ws_bytes(A, B, n_pairs, untuned);
+}
+
+int lev_batch_impl(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                   int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes,
+                   int32_t *d_status, hipStream_t s, int forced) {
+    int rc;
+    if ((rc = check_seqs(A)) || (rc = check_seqs(B))) return rc;
+    if (n_pairs < 0) return MSA_EINVAL;
+    if (A->sigma != B->sigma) return MSA_EINVAL;
+    if (n_pairs == 0) return MSA_OK;
+    if (ia == nullptr || ib == nullptr || dist == nullptr || ws == nullptr) return MSA_EINVAL;
+    if (n_pairs > 0x7fffffffLL * 64) return MSA_ERANGE;
+    const bool untuned = forced < 0;
+    if (ws_bytes < pairs_ws_bytes(A, B, n_pairs, untuned)) return MSA_ENOSPC;
+    int wmax;
+    if (pairs_layout(A, B, forced, &wmax) == 1)
+        return run_lanes(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, wmax, d_status, s);
+    return run_grouped(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, untuned, d_status, s);
 }
 
 }  // namespace msadp
@@ -245,67 +682,59 @@ using namespace msadp;
 extern "C" {
 
 size_t lev_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
-    if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
-    Sizer sz;
-    lev_layout(sz, A, B, n_pairs, true);
-    return sz.total();
+    return lev_batch_ws_bytes(A, B, n_pairs, false);
 }
 
 int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
               int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes, int32_t *d_status,
               hipStream_t s) {
+    return lev_batch_impl(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, d_status, s, 0);
+}
+
+int msa_autotune_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
+                       const int32_t *ib, int64_t n_pairs, uint16_t *dist, void *ws,
+                       size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
+                       int32_t *d_status, hipStream_t s) {
     int rc;
     if ((rc = check_seqs(A)) || (rc = check_seqs(B))) return rc;
-    if (n_pairs < 0) return MSA_EINVAL;
-    if (A->sigma != B->sigma) return MSA_EINVAL;
-    if (n_pairs == 0) return MSA_OK;
-    if (ia == nullptr || ib == nullptr || dist == nullptr || ws == nullptr) return MSA_EINVAL;
-    if (n_pairs > 0x7fffffffLL * 64) return MSA_ERANGE;
-    const LevPlan pl = plan_lev(A, B, true, 0);
-    Sizer sz;
-    lev_layout(sz, A, B, n_pairs, true);
-    if (ws_bytes < sz.total()) return MSA_ENOSPC;
-
-    Carve cv(ws, ws_bytes);
-    Staged SA{cv.take<uint8_t>((size_t)A->n * pl.strideA), cv.take<int32_t>((size_t)A->n + 1),
-              pl.strideA, A->n};
-    Staged SB{cv.take<uint8_t>((size_t)B->n * pl.strideB), cv.take<int32_t>((size_t)B->n + 1),
-              pl.strideB, B->n};
-    int64_t *start = cv.take<int64_t>((size_t)A->n + 1);
-    int64_t *cursor = cv.take<int64_t>((size_t)A->n + 1);
-    int64_t *sorted = cv.take<int64_t>((size_t)n_pairs);
-    Item *items = cv.take<Item>((size_t)n_pairs);
-    int64_t *n_items = cv.take<int64_t>(1);
-    uint32_t *counter = cv.take<uint32_t>(1);
-    uint32_t *hbuf = pl.hstride ? cv.take<uint32_t>((size_t)pl.grid * kWave * pl.hstride) : nullptr;
-
-    if ((rc = stage_set(A, nullptr, SA, d_status, s))) return rc;
-    if ((rc = stage_set(B, nullptr, SB, d_status, s))) return rc;
-    if ((rc = fill_i64(start, (int64_t)A->n + 1, 0, s))) return rc;
-    const int64_t pg = std::min<int64_t>((n_pairs + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs, A->n,
-                       B->n, start, dist, d_status);
-    if ((rc = exclusive_scan_i64(start, (int64_t)A->n + 1, s))) return rc;
-    if (hipMemcpyAsync(cursor, start, sizeof(int64_t) * ((size_t)A->n + 1),
-                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (best == nullptr || best_ms == nullptr || reps < 1 || n_pairs < 1) return MSA_EINVAL;
+    int wmax, sp;
+    const bool fit = lanes_fit(A, B, &wmax, &sp);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MSA_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return MSA_EDEVICE;
-    hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs,
-                       A->n, B->n, cursor, sorted);
-    const unsigned gg = (unsigned)((A->n + 1 + 255) / 256);
-    hipLaunchKernelGGL(k_item_counts, dim3(gg), dim3(256), 0, s, start, A->n, cursor);
-    if ((rc = exclusive_scan_i64(cursor, (int64_t)A->n + 1, s))) return rc;
-    hipLaunchKernelGGL(k_make_items, dim3(gg), dim3(256), 0, s, start, cursor, A->n, items,
-                       n_items);
-    if ((rc = fill_i32((int32_t *)counter, 1, 0, s))) return rc;
-    GroupedArgs ga{SA, SB, ib, sorted, items, n_items, dist, counter, hbuf, pl.hstride, A->sigma};
-    switch (pl.wclass) {
-#define MSADP_L(w) \
-    case w: hipLaunchKernelGGL(k_lev_grouped<w>, dim3(pl.grid), dim3(64), 0, s, ga); break;
-        MSADP_LEV_CLASSES(MSADP_L)
-#undef MSADP_L
-        default: return MSA_EINVAL;
     }
-    return launch_status();
+    int bv = 0;
+    float bms = 0.0f;
+    rc = MSA_OK;
+    for (int v : {kWave, 1}) {
+        if (v == 1 && !fit) continue;
+        if ((rc = lev_batch_impl(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, d_status, s, v)))
+            break;   // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
+        for (int r = 0; r < reps && rc == MSA_OK; ++r)
+            rc = lev_batch_impl(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, d_status, s, v);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = MSA_EDEVICE;
+            break;
+        }
+        ms /= (float)reps;
+        if (bv == 0 || ms < bms) {
+            bv = v;
+            bms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = bv;
+    *best_ms = bms;
+    return msa_tune_set(MSA_TUNE_PAIRS, A->sigma, pair_words_bin(A, B), bv);
 }
 
 size_t lev_allpairs_workspace_bytes(const msa_seqs *A) {

@@ -10,6 +10,8 @@ constexpr int kMaxWords = 32;  // most 64-bit words per pass (2048 rows)
 constexpr int kSym = 32;       // symbol stride of the Peq table
 
 typedef const __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(3))) uint64_t lds_w64;
+typedef __attribute__((address_space(3))) uint32_t lds_w32;
 
 struct Lut {
     static constexpr uint8_t XOR_OR = MSADP_LUT((A ^ B) | C);     // Xh
@@ -41,8 +43,12 @@ __device__ __forceinline__ void build_peq(uint64_t *peq, const uint8_t *pat, int
 //   CIN: the horizontal deltas entering word 0 come from `hbuf` (2 bits per
 //        column: bit 2q = +1, bit 2q+1 = -1), else they are +1 (top row).
 //   cout: write the deltas leaving the last word to `hbuf` instead of adding
-//        them to the score.  `b` is the bit of the last row in word W-1.
-template <int W, bool CIN>
+//        them to the score.  `b` is the bit of the last row in word W-1 (it
+//        may differ between lanes).
+//   TS, KS: the match word of symbol t and word k is peq[t * TS + k * KS]
+//        (a wavefront's shared table: 1, kSym; a lane's own table, with peq
+//        already offset to the lane: kWave, sigma' * kWave).
+template <int W, bool CIN, int TS = 1, int KS = kSym>
 __device__ __forceinline__ int lev_pass(lds_u64 *peq, const uint8_t *text, int n, int nmax,
                                         int b, bool cout, uint32_t *hbuf) {
     uint32_t pl[W], ph[W], ml[W], mh[W];
@@ -71,17 +77,17 @@ __device__ __forceinline__ int lev_pass(lds_u64 *peq, const uint8_t *text, int n
             uint32_t cph = cw << 31;
             uint32_t cmh = (cw & 2u) << 30;
             cw >>= 2;
-            lds_u64 *pe = peq + t;   // this lane's symbol row of the table
+            lds_u64 *pe = peq + t * TS;   // this lane's symbol row of the table
             uint32_t dp = 0, dn = 0;
             // Eq of word k+2 is requested while word k computes; the
             // scheduling barriers keep each word's temporaries short-lived.
-            uint64_t eq0 = pe[0], eq1 = W > 1 ? pe[kSym] : 0;
+            uint64_t eq0 = pe[0], eq1 = W > 1 ? pe[KS] : 0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const uint64_t e = (k & 1) ? eq1 : eq0;
                 if (k + 2 < W) {
-                    if (k & 1) eq1 = pe[(k + 2) * kSym];
-                    else eq0 = pe[(k + 2) * kSym];
+                    if (k & 1) eq1 = pe[(k + 2) * KS];
+                    else eq0 = pe[(k + 2) * KS];
                 }
                 const uint32_t el = (uint32_t)e, eh = (uint32_t)(e >> 32);
                 const uint32_t elm = el | (cmh >> 31);
@@ -134,6 +140,63 @@ __device__ __forceinline__ int dispatch_first(int w, lds_u64 *peq, const uint8_t
     } else {
         if (w == W) return lev_pass<W, false>(peq, text, n, nmax, b, cout, hbuf);
         return dispatch_first<WMAX, W + 1>(w, peq, text, n, nmax, b, cout, hbuf);
+    }
+}
+
+// A lane's own match table for its pattern (pat, m; words [0, nw)), for
+// wavefronts whose lanes hold different patterns: tbl[(k * SP + c) * kWave +
+// lane] has bit i set iff pat[k * 64 + i] == c, for c < SP (symbols >= SP
+// never occur).  Rows past m hold the staged zero padding: they only feed
+// rows below the last one, which no result reads.  Each lane ORs one bit per
+// pattern symbol into its own entries (no two lanes share an entry).
+template <int SP>
+__device__ __forceinline__ void build_lane_peq(uint64_t *tbl, const uint8_t *pat, int m,
+                                               int nw) {
+    const int lane = lane_id();
+    lds_w64 *t64 = (lds_w64 *)tbl;
+    for (int k = 0; k < nw; ++k) {
+#pragma unroll
+        for (int c = 0; c < SP; ++c) t64[(k * SP + c) * kWave + lane] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint4 *pp = (const uint4 *)pat;
+    for (int k = 0; k < nw; ++k) {
+        // 32-bit halves: entry e of the table is dwords 2e (rows 0-31), 2e+1
+        lds_w32 *row = (lds_w32 *)(t64 + k * SP * kWave + lane);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int chunk = k * 4 + q;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (chunk * 16 < m) v = pp[chunk];
+            const uint32_t d4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+#pragma unroll
+                for (int by = 0; by < 4; ++by) {
+                    const int i = q * 16 + w * 4 + by;   // row within the word
+                    const uint32_t c = (d4[w] >> (8 * by)) & 0xFFu;
+                    __hip_atomic_fetch_or(row + c * (2 * kWave) + (i >> 5), 1u << (i & 31),
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int WMAX, int SP, int W = 1>
+__device__ __forceinline__ int dispatch_lanes(int w, lds_u64 *tbl, const uint8_t *text, int n,
+                                              int nmax, int b) {
+    if constexpr (W > WMAX) {
+        return 0;
+    } else {
+        if (w == W)
+            return lev_pass<W, false, kWave, SP * kWave>(tbl, text, n, nmax, b, false, nullptr);
+        return dispatch_lanes<WMAX, SP, W + 1>(w, tbl, text, n, nmax, b);
     }
 }
 

@@ -7,6 +7,8 @@
 //                     value = words per pass of the kernel variant.
 //   MSA_TUNE_NW  (1): bin = wavefronts per pair ceil(ceil(max_len_A / 32) / 64);
 //                     value = steps between workgroup barriers of the fill.
+//   MSA_TUNE_PAIRS (3): bin = pattern words of the longer set of a pair list;
+//                     value = lanes sharing one pattern table (1 or 64).
 //   MSA_TUNE_TREE (2): bin = pattern words ceil(max_len / 64) of the set;
 //                     value = words per pass of the tree build's kernels.
 #include <cstdio>
@@ -29,11 +31,13 @@ bool valid_value(int kind, int value) {
     if (kind == MSA_TUNE_LEV) return is_lev_class(value);
     if (kind == MSA_TUNE_NW) return value == 16 || value == 32 || value == 64;
     if (kind == MSA_TUNE_TREE) return is_tree_class(value);
+    if (kind == MSA_TUNE_PAIRS) return value == 1 || value == kWave;
     return false;
 }
 
 bool valid_key(int kind, int sigma, int bin) {
-    return (kind == MSA_TUNE_LEV || kind == MSA_TUNE_NW || kind == MSA_TUNE_TREE) &&
+    return (kind == MSA_TUNE_LEV || kind == MSA_TUNE_NW || kind == MSA_TUNE_TREE ||
+            kind == MSA_TUNE_PAIRS) &&
            sigma >= 2 && sigma <= 33 &&
            bin >= 1 && bin <= (1 << 20);
 }
@@ -98,6 +102,11 @@ int msa_tune_candidates(int32_t kind, int32_t *values, int32_t cap, int32_t *cou
         }
     } else if (kind == MSA_TUNE_NW) {
         for (int r : {16, 32, 64}) {
+            if (n < cap) values[n] = r;
+            ++n;
+        }
+    } else if (kind == MSA_TUNE_PAIRS) {
+        for (int r : {1, kWave}) {
             if (n < cap) values[n] = r;
             ++n;
         }

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsadp.so")
 
 MSA_OK, MSA_EINVAL, MSA_ERANGE, MSA_ENOSPC, MSA_EDEVICE = 0, -1, -2, -3, -4
-MSA_TUNE_LEV, MSA_TUNE_NW, MSA_TUNE_TREE = 0, 1, 2
+MSA_TUNE_LEV, MSA_TUNE_NW, MSA_TUNE_TREE, MSA_TUNE_PAIRS = 0, 1, 2, 3
 DS_NAMES = {0: "ok", 1: "symbol code >= sigma", 2: "sequence index out of range",
             3: "length out of range", 4: "output capacity too small",
             5: "non-finite embedding value"}
@@ -73,6 +73,8 @@ SIGNATURES = {
                                    C.POINTER(C.c_float), P, P]),
     "msa_autotune_nw": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, C.c_size_t, C.c_int32,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
+    "msa_autotune_pairs": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, C.c_size_t, C.c_int32,
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
     "msa_autotune_tree": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t,
                                     C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
     "cnn_param_bytes": (C.c_size_t, []),
@@ -197,23 +199,40 @@ class Status:
             raise RuntimeError(f"{where}: device reported {DS_NAMES.get(v, v)}")
 
 
+class LevBatch:
+    """Reusable lev_batch launcher: pairs on the device, workspace sized once."""
+
+    def __init__(self, A: Seqs, B: Seqs, ia, ib, out=None):
+        dev = A.codes.device
+        self.A, self.B = A, B
+        self.ia, self.ib = _i32(ia, dev), _i32(ib, dev)
+        self.n_pairs = self.ia.numel()
+        if out is None:
+            out = torch.empty(max(self.n_pairs, 1), dtype=torch.uint16, device=dev)
+        self.out = out
+        self.sa, self.sb = A.struct(), B.struct()
+        self.wsb = lib().lev_workspace_bytes(C.byref(self.sa), C.byref(self.sb), self.n_pairs)
+        self.ws = torch.empty(max(self.wsb, 1), dtype=torch.uint8, device=dev)
+        self.st = Status(dev)
+
+    def args(self):
+        """lev_batch's arguments up to the workspace size."""
+        return (C.byref(self.sa), C.byref(self.sb), _ptr(self.ia), _ptr(self.ib), self.n_pairs,
+                _ptr(self.out), _ptr(self.ws), self.wsb)
+
+    def __call__(self, stream=None):
+        rc = lib().lev_batch(*self.args(), _ptr(self.st.t), _stream(stream))
+        _check(rc, "lev_batch")
+        return self.out[: self.n_pairs]
+
+
 def lev_batch(A: Seqs, B: Seqs, ia, ib, out=None, stream=None, check=True):
     """uint16 distances lev(A[ia[p]], B[ib[p]])."""
-    dev = A.codes.device
-    ia, ib = _i32(ia, dev), _i32(ib, dev)
-    n_pairs = ia.numel()
-    if out is None:
-        out = torch.empty(max(n_pairs, 1), dtype=torch.uint16, device=dev)
-    sa, sb = A.struct(), B.struct()
-    wsb = lib().lev_workspace_bytes(C.byref(sa), C.byref(sb), n_pairs)
-    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
-    st = Status(dev)
-    rc = lib().lev_batch(C.byref(sa), C.byref(sb), _ptr(ia), _ptr(ib), n_pairs, _ptr(out),
-                         _ptr(ws), wsb, _ptr(st.t), _stream(stream))
-    _check(rc, "lev_batch")
+    lb = LevBatch(A, B, ia, ib, out)
+    res = lb(stream)
     if check:
-        st.check("lev_batch")
-    return out[:n_pairs]
+        lb.st.check("lev_batch")
+    return res
 
 
 class AllPairs:
@@ -657,6 +676,22 @@ def autotune_lev(S: Seqs, reps: int = 2, stream=None):
     _check(rc, "msa_autotune_lev")
     ap.st.check("msa_autotune_lev")
     return best.value, ms.value
+
+
+def autotune_pairs(lb: "LevBatch", reps: int = 2, stream=None):
+    """Time the lev_batch pair layouts on a prepared LevBatch and keep the
+    fastest; returns (lanes per pattern table: 1 or 64, ms per call)."""
+    best, ms = C.c_int32(0), C.c_float(0.0)
+    rc = lib().msa_autotune_pairs(*lb.args(), int(reps), C.byref(best), C.byref(ms),
+                                  _ptr(lb.st.t), _stream(stream))
+    _check(rc, "msa_autotune_pairs")
+    lb.st.check("msa_autotune_pairs")
+    return best.value, ms.value
+
+
+def pairs_words_bin(A: Seqs, B: Seqs) -> int:
+    """Tuning-table bin of a lev_batch call (MSA_TUNE_PAIRS)."""
+    return max(1, (max(A.max_len, B.max_len) + 63) // 64)
 
 
 def autotune_nw(nb: "NwBatch", reps: int = 2, stream=None):

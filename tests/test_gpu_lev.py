@@ -18,18 +18,34 @@ def _msadp():
     return msadp
 
 
-def _check_pairs(codes_a, off_a, codes_b, off_b, sigma, ia, ib, packed=False):
+def lanes_fit(sigma, max_len):
+    """Whether lev_batch's one-pattern-per-lane layout holds these patterns."""
+    sp = 4 if sigma <= 4 else 8 if sigma <= 8 else 32
+    return max_len <= 64 * (32 // sp)
+
+
+def _check_pairs(codes_a, off_a, codes_b, off_b, sigma, ia, ib, packed=False, same=False):
+    """lev_batch in every pair layout that fits (64 lanes per pattern table,
+    and one pattern per lane) against the oracle, bit for bit."""
     M = _msadp()
     if packed:
         A = M.to_device(M.pack_2bit_host(codes_a), off_a, sigma, packed_2bit=True)
-        B = M.to_device(M.pack_2bit_host(codes_b), off_b, sigma, packed_2bit=True)
+        B = A if same else M.to_device(M.pack_2bit_host(codes_b), off_b, sigma, packed_2bit=True)
     else:
         A = M.to_device(codes_a, off_a, sigma)
-        B = M.to_device(codes_b, off_b, sigma)
-    got = M.lev_batch(A, B, ia, ib).cpu().numpy().astype(np.int64)
+        B = A if same else M.to_device(codes_b, off_b, sigma)
     want = orc.lev_pairs(codes_a, off_a, codes_b, off_b, ia, ib)
-    bad = np.flatnonzero(got != want)
-    assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[:5]} got {got[bad[:5]]} want {want[bad[:5]]}"
+    layouts = [64] + ([1] if lanes_fit(sigma, max(A.max_len, B.max_len)) else [])
+    try:
+        for v in layouts:
+            M.tune_set(M.MSA_TUNE_PAIRS, sigma, M.pairs_words_bin(A, B), v)
+            got = M.lev_batch(A, B, ia, ib).cpu().numpy().astype(np.int64)
+            bad = np.flatnonzero(got != want)
+            assert len(bad) == 0, (f"layout {v}: {len(bad)} mismatches, first {bad[:5]} "
+                                   f"got {got[bad[:5]]} want {want[bad[:5]]}")
+    finally:
+        M.tune_clear()
+    return layouts
 
 
 def test_word_boundary_lengths_all_pairings():
@@ -82,6 +98,93 @@ def test_packed_2bit_input():
     ia = rng.integers(0, 80, size=2000)
     ib = rng.integers(0, 80, size=2000)
     _check_pairs(codes, off, codes, off, 4, ia, ib, packed=True)
+
+
+LANE_BOUNDARY = [0, 1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 255, 256, 257, 300, 447,
+                 448, 449, 511, 512]
+
+
+@pytest.mark.parametrize("same", [False, True])
+def test_lanes_layout_word_boundaries(same):
+    """Patterns up to 512 rows (8 words: the per-lane layout for DNA), every
+    ordered pairing, so both the A and the B sequence serve as pattern."""
+    rng = np.random.default_rng(111)
+    seqs = [rng.integers(0, 4, size=L).astype(np.uint8) for L in LANE_BOUNDARY]
+    seqs += [synth.mutate(rng, s, 4, 0.1, 0.02, 0.02)[:512] for s in seqs[8:]]
+    codes, off = synth.to_csr(seqs)
+    n = len(seqs)
+    ia, ib = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    assert _check_pairs(codes, off, codes, off, 4, ia.ravel(), ib.ravel(), same=same) == [64, 1]
+
+
+@pytest.mark.parametrize("sigma,hi", [(2, 512), (3, 500), (5, 256), (8, 256), (9, 64), (20, 64),
+                                      (32, 64)])
+def test_lanes_layout_alphabets(sigma, hi):
+    """Each per-lane variant (sigma' = 4, 8, 32) at its longest patterns,
+    two different sets (patterns drawn from either)."""
+    ca, oa = synth.random_set(900 + sigma, 120, 0, hi, sigma)
+    cb, ob = synth.random_set(950 + sigma, 90, 0, hi, sigma)
+    rng = np.random.default_rng(sigma)
+    ia = rng.integers(0, 120, size=5000)
+    ib = rng.integers(0, 90, size=5000)
+    assert _check_pairs(ca, oa, cb, ob, sigma, ia, ib) == [64, 1]
+
+
+def test_sparse_pairs_learned_workload_sampled():
+    """The 2 M training-label batch over the 100,000-sequence DNA set (lengths
+    100-500, about 20 pairs per sequence), in the layout lev_batch picks by
+    default (one pattern per lane); 30,000 sampled pairs recomputed by the
+    oracle, length bounds on every pair."""
+    from paper_2601_15458_amd import learned
+    M = _msadp()
+    d = synth.learned()
+    S = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    ia, ib = learned.sample_pairs(d["family"], 2_000_000, seed=11)
+    got = M.lev_batch(S, S, ia, ib).cpu().numpy().astype(np.int64)
+    L = np.diff(d["offsets"])
+    assert (got >= np.abs(L[ia] - L[ib])).all() and (got <= np.maximum(L[ia], L[ib])).all()
+    pick = np.random.default_rng(5).choice(len(ia), 30000, replace=False)
+    want = orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], ia[pick], ib[pick])
+    assert (got[pick] == want).all()
+
+
+def test_random_pair_list_allpairs_set():
+    """8,386,560 random pairs of the 4096-sequence set (shared-pattern
+    layout: about 2000 pairs per pattern): 20,000 sampled pairs recomputed by
+    the oracle, and every pair equal to lev_allpairs' entry."""
+    M = _msadp()
+    d = synth.allpairs()
+    n = d["n"]
+    A = M.to_device(d["codes"], d["offsets"], d["sigma"])
+    rng = np.random.default_rng(8)
+    ia = rng.integers(0, n, size=n * (n - 1) // 2).astype(np.int32)
+    ib = rng.integers(0, n, size=n * (n - 1) // 2).astype(np.int32)
+    got = M.lev_batch(A, A, ia, ib).cpu().numpy().astype(np.int64)
+    pick = rng.choice(len(ia), 20000, replace=False)
+    want = orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], ia[pick], ib[pick])
+    assert (got[pick] == want).all()
+    cond = M.lev_allpairs(A).cpu().numpy().astype(np.int64)
+    i, j = np.minimum(ia, ib).astype(np.int64), np.maximum(ia, ib).astype(np.int64)
+    off = i != j
+    idx = i[off] * n - i[off] * (i[off] + 1) // 2 + (j[off] - i[off] - 1)
+    assert (got[off] == cond[idx]).all() and (got[~off] == 0).all()
+
+
+def test_autotune_pairs_picks_a_layout():
+    M = _msadp()
+    codes, off = synth.random_set(77, 500, 100, 500, 4)
+    A = M.to_device(codes, off, 4)
+    rng = np.random.default_rng(9)
+    ia, ib = rng.integers(0, 500, 20000), rng.integers(0, 500, 20000)
+    lb = M.LevBatch(A, A, ia, ib)
+    try:
+        best, ms = M.autotune_pairs(lb, reps=2)
+        assert best in (1, 64) and ms > 0
+        assert M.tune_get(M.MSA_TUNE_PAIRS, 4, M.pairs_words_bin(A, A)) == best
+        want = orc.lev_pairs(codes, off, codes, off, ia, ib)
+        assert (lb().cpu().numpy().astype(np.int64) == want).all()
+    finally:
+        M.tune_clear()
 
 
 def test_tiny_workload_allpairs_and_batch():
@@ -150,3 +253,12 @@ def test_device_detected_errors():
     A = M.to_device(codes, off, 4)
     with pytest.raises(RuntimeError, match="index"):
         M.lev_batch(A, A, [0], [5])
+    # both layouts flag the bad pair and leave 0xFFFF in its slot
+    for v in (64, 1):
+        M.tune_set(M.MSA_TUNE_PAIRS, 4, 1, v)
+        try:
+            got = M.lev_batch(A, A, [0, 1, -1], [1, 0, 0], check=False).cpu().numpy()
+        finally:
+            M.tune_clear()
+        assert got[2] == 0xFFFF and got[0] == got[1] == orc.lev_pairs(
+            codes, off, codes, off, np.array([0]), np.array([1]))[0]

@@ -95,6 +95,24 @@ int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int
               int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes,
               int32_t *d_status, hipStream_t s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lev_batch
+ * with its workspace in a fixed device array of the library instead of a
+ * caller buffer.  Same arguments (less the workspace), results and errors as
+ * lev_batch, with the default layout and word class (the tuning table is not
+ * read), and MSA_ENOSPC, before anything is launched, when that needs more
+ * than MSA_NOALLOC_SCRATCH_BYTES of workspace (about 64 MiB; e.g. 100,000
+ * sequences of up to 500 symbols with 1 M pairs fit).  It calls no
+ * allocating routine.  Each GPU the library runs on holds its own copy of
+ * the array until the process ends, set up on the first call on that device
+ * (MSA_EDEVICE if that fails).  All calls on one GPU share the array: calls
+ * that overlap on one GPU (other streams, other host threads) race and must
+ * be serialized by the caller. */
+#define MSA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int lev_batch_noalloc(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
+                      const int32_t *ib, int64_t n_pairs, uint16_t *dist, int32_t *d_status,
+                      hipStream_t s);
+
 /* Workspace for lev_allpairs over the set A. */
 size_t lev_allpairs_workspace_bytes(const msa_seqs *A);
 

@@ -47,6 +47,7 @@ SIGNATURES = {
     "msa_version": (C.c_int, []),
     "lev_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
     "lev_batch": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, C.c_size_t, P, P]),
+    "lev_batch_noalloc": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P]),
     "lev_allpairs_workspace_bytes": (C.c_size_t, [SP]),
     "lev_allpairs": (C.c_int, [SP, P, P, C.c_size_t, P, P]),
     "nw_tb_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
@@ -233,6 +234,27 @@ def lev_batch(A: Seqs, B: Seqs, ia, ib, out=None, stream=None, check=True):
     if check:
         lb.st.check("lev_batch")
     return res
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def lev_batch_noalloc(A: Seqs, B: Seqs, ia, ib, out=None, stream=None, check=True):
+    """lev_batch with the library's fixed device workspace (no workspace
+    buffer is allocated here; inputs and the output are the caller's)."""
+    dev = A.codes.device
+    ia, ib = _i32(ia, dev), _i32(ib, dev)
+    n_pairs = ia.numel()
+    if out is None:
+        out = torch.empty(max(n_pairs, 1), dtype=torch.uint16, device=dev)
+    sa, sb = A.struct(), B.struct()
+    st = Status(dev)
+    rc = lib().lev_batch_noalloc(C.byref(sa), C.byref(sb), _ptr(ia), _ptr(ib), n_pairs,
+                                 _ptr(out), _ptr(st.t), _stream(stream))
+    _check(rc, "lev_batch_noalloc")
+    if check:
+        st.check("lev_batch_noalloc")
+    return out[:n_pairs]
 
 
 class AllPairs:

@@ -213,8 +213,8 @@ def test_allpairs_ragged_small_sets():
 
 def test_allpairs_workload_full_size_sampled():
     """The 4096-sequence all-pairs batch as the benchmark runs it; a seeded
-    sample of pairs plus every pair of the 8 shortest and 8 longest
-    sequences is recomputed by the oracle."""
+    sample of pairs plus every pair that touches one of the 8 shortest or 8
+    longest sequences (65,520 pairs) is recomputed by the oracle."""
     M = _msadp()
     d = synth.allpairs()
     n = d["n"]
@@ -226,13 +226,20 @@ def test_allpairs_workload_full_size_sampled():
     rng = np.random.default_rng(77)
     ia = list(rng.integers(0, n, size=1500))
     ib = list(rng.integers(0, n, size=1500))
-    for x in ext:
-        for y in range(0, n, 97):
-            ia.append(x)
-            ib.append(y)
     ia, ib = np.array(ia), np.array(ib)
     keep = ia != ib
     ia, ib = ia[keep], ib[keep]
+    # every pair touching an extreme sequence, each unordered pair once
+    ex_i, ex_j = [], []
+    ext_set = set(int(x) for x in ext)
+    for x in ext:
+        for y in range(n):
+            if y != x and not (y in ext_set and y < x):
+                ex_i.append(x)
+                ex_j.append(y)
+    assert len(ex_i) == 16 * (n - 1) - 16 * 15 // 2
+    ia = np.concatenate([ia, ex_i])
+    ib = np.concatenate([ib, ex_j])
     i, j = np.minimum(ia, ib), np.maximum(ia, ib)
     idx = i * n - i * (i + 1) // 2 + (j - i - 1)
     want = orc.lev_pairs(d["codes"], d["offsets"], d["codes"], d["offsets"], ia, ib)

@@ -57,9 +57,11 @@ def test_tiny_workload_tree_graph_replay():
 
 
 def test_protein_subset_tree():
+    """A seeded 1000-sequence subset of the 20,000-sequence protein set
+    (about 1.8e11 oracle cells): node arrays equal the oracle's."""
     d = synth.protein_tree()
     rng = np.random.default_rng(33)
-    sub = synth.subset(d, rng.choice(d["n"], size=300, replace=False))
+    sub = synth.subset(d, rng.choice(d["n"], size=1000, replace=False))
     _compare(sub["codes"], sub["offsets"], 20, use_graph=True)
 
 
@@ -103,9 +105,11 @@ def test_hand_worked_alignment():
 
 
 def test_protein_subset_alignment():
+    """Guide tree and merge of a seeded 1000-sequence protein subset, byte
+    equal to the oracle's alignment."""
     d = synth.protein_tree()
     rng = np.random.default_rng(34)
-    sub = synth.subset(d, rng.choice(d["n"], size=150, replace=False))
+    sub = synth.subset(d, rng.choice(d["n"], size=1000, replace=False))
     _check_msa(sub["codes"], sub["offsets"], 20, use_graph=True)
 
 

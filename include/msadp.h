@@ -156,6 +156,44 @@ int nw_traceback(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const 
                  uint8_t *ops, const int64_t *ops_offsets, int32_t *ops_len,
                  int32_t *d_status, hipStream_t s);
 
+/* ------------------------------------------------------------------ */
+/* Needleman-Wunsch with a substitution score matrix and affine gaps: the cost
+ * model of the paper's experiments (Sec. 2.4: substitution matrices for
+ * residues, gap opening charged ten times the extension; the matrix and
+ * costs are the caller's).  Reading where the paper gives no formula: a run
+ * of k gap symbols in one row scores -(open + k * ext), and the aligner
+ * maximizes the sum of sub[a_i * sigma + b_j] over aligned pairs minus the
+ * penalties of all gap runs (Gotoh's three-state recurrence).  Among the
+ * best-scoring alignments the one returned is the one whose op string read
+ * backwards is smallest with M < D < I (the order of the unit-cost walk).
+ * sub: HOST int32[sigma * sigma] (row = symbol of a), |sub| <= 2048;
+ * 0 <= open, 0 <= ext, open + ext <= 2048 (EINVAL otherwise); a pattern
+ * (A sequence) of more than 16384 symbols returns MSA_ERANGE (A->max_len)
+ * or sets MSA_DS_LENGTH.  Scores are int32 (exact for every admitted
+ * input). */
+
+/* Bytes of traceback codes for one pair (one byte per cell plus a small
+ * layout overhead; 0 when m == 0 or n == 0). */
+size_t gotoh_tb_bytes(int32_t m, int32_t n);
+
+size_t gotoh_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs);
+
+/* Fill: score[p] (may be null) = the best score of pair (A[ia[p]], B[ib[p]])
+ * and its traceback codes in tb[tb_offsets[p] ..] (each region at least
+ * gotoh_tb_bytes(m, n) bytes, 16-byte aligned; layout private to
+ * gotoh_traceback).  The score table is copied to the device before the
+ * call returns. */
+int gotoh_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                int64_t n_pairs, const int32_t *sub, int32_t open, int32_t ext, int32_t *score,
+                uint8_t *tb, const int64_t *tb_offsets, void *ws, size_t ws_bytes,
+                int32_t *d_status, hipStream_t s);
+
+/* The alignments of a gotoh_batch call (same A, B, ia, ib, tb, tb_offsets),
+ * in the op format of nw_traceback (regions of m + n bytes). */
+int gotoh_traceback(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+                    int64_t n_pairs, const uint8_t *tb, const int64_t *tb_offsets, uint8_t *ops,
+                    const int64_t *ops_offsets, int32_t *ops_len, int32_t *d_status,
+                    hipStream_t s);
 
 /* ------------------------------------------------------------------ */
 /* Guide tree by Alg. 1 (Partition, Sec. 2.1): recursive split of the set

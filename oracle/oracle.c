@@ -16,6 +16,10 @@
  *     value (Sec. 2.2 step 2 aligns the two centers and records the gap
  *     positions; the tie order diag > up > left is this project's reading,
  *     the paper names none).
+ *   - Needleman-Wunsch with a substitution score matrix and affine gaps
+ *     (Gotoh's three matrices in full), the cost model of Sec. 2.4, with
+ *     the walk that returns the best-scoring alignment whose backward op
+ *     string is smallest (M < D < I).
  *   - Alg. 1 (Partition) with the full geometric median (Sec. 2.1), and
  *     the same with the median taken over candidates that a learned
  *     embedding ranks first (a surrogate of this project, not the paper's).
@@ -137,6 +141,119 @@ void orc_nw_pairs(const uint8_t *ca, const int64_t *oa, const uint8_t *cb,
         int64_t m = oa[ia[p] + 1] - oa[ia[p]], n = ob[ib[p] + 1] - ob[ib[p]];
         score[p] = orc_nw(a, m, b, n, ops ? ops + ops_off[p] : NULL,
                           ops ? ops_len + p : NULL);
+    }
+}
+
+/* ------------------------------------------------------------ affine NW
+ * Global alignment under the cost model of the paper's experiments
+ * (Sec. 2.4): a substitution score matrix for aligned residues and affine
+ * gaps, opening charged ten times the extension there (the ratio is the
+ * caller's here).  Reading, as the paper gives no formula: a run of k gap
+ * symbols in one row scores -(open + k * ext), and the aligner maximizes
+ *   sum over M columns of sub[a_i * sigma + b_j]  -  sum over gap runs of
+ *   (open + ext * run length),
+ * where a run is a maximal stretch of consecutive D ops or of consecutive I
+ * ops.  Gotoh's three matrices, in full:
+ *   E[i][j] = best prefix score of a[1..i], b[1..j] ending with I,
+ *   F[i][j] = ... ending with D,  H[i][j] = ... ending with anything:
+ *   E[i][j] = max(E[i][j-1] - ext, H[i][j-1] - open - ext)
+ *   F[i][j] = max(F[i-1][j] - ext, H[i-1][j] - open - ext)
+ *   H[i][j] = max(H[i-1][j-1] + sub[a_i][b_j], E[i][j], F[i][j])
+ *   H[0][0] = 0;  H[i][0] = F[i][0] = -(open + i ext);
+ *   H[0][j] = E[0][j] = -(open + j ext);  E[i][0], F[0][j] = -infinity.
+ * The alignment returned is, among those of the best score, the one whose
+ * op string read backwards is smallest with M < D < I (the order of the
+ * unit-cost walk).  It is found by walking back from (m, n) and taking at
+ * each step the least op through which some best-scoring prefix completes
+ * the part already chosen.  `need` is the score the remaining prefix must
+ * reach, counted with a bonus of `open` when the prefix ends in the same gap
+ * op that the chosen part starts with (the two then form one run).  The
+ * best prefix ending with M, D or I at (i, j) scores H[i-1][j-1] + sub, F,
+ * E; a candidate completes iff that plus its bonus equals `need` (it can
+ * never exceed it).  Scores here stay far inside int32 (|sub| and open +
+ * ext at most 2048, lengths at most 65535). */
+#define ORC_NEG_INF (-(1 << 30))
+
+int64_t orc_gotoh(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+                  const int32_t *sub, int32_t sigma, int32_t open, int32_t ext,
+                  uint8_t *ops, int64_t *ops_len) {
+    const int64_t w = n + 1;
+    const size_t cells = (size_t)((m + 1) * w);
+    int32_t *H = (int32_t *)malloc(sizeof(int32_t) * cells);
+    int32_t *E = (int32_t *)malloc(sizeof(int32_t) * cells);
+    int32_t *F = (int32_t *)malloc(sizeof(int32_t) * cells);
+    H[0] = 0;
+    E[0] = F[0] = ORC_NEG_INF;
+    for (int64_t j = 1; j <= n; ++j) {
+        H[j] = E[j] = -(open + (int32_t)j * ext);
+        F[j] = ORC_NEG_INF;
+    }
+    for (int64_t i = 1; i <= m; ++i) {
+        H[i * w] = F[i * w] = -(open + (int32_t)i * ext);
+        E[i * w] = ORC_NEG_INF;
+        for (int64_t j = 1; j <= n; ++j) {
+            const int64_t c = i * w + j;
+            const int32_t e1 = E[c - 1] - ext, e2 = H[c - 1] - open - ext;
+            const int32_t f1 = F[c - w] - ext, f2 = H[c - w] - open - ext;
+            E[c] = e1 > e2 ? e1 : e2;
+            F[c] = f1 > f2 ? f1 : f2;
+            int32_t h = H[c - w - 1] + sub[a[i - 1] * sigma + b[j - 1]];
+            if (E[c] > h) h = E[c];
+            if (F[c] > h) h = F[c];
+            H[c] = h;
+        }
+    }
+    const int64_t score = H[m * w + n];
+    if (ops != NULL) {
+        int64_t i = m, j = n, k = 0, need = score;
+        int last = -1;   /* first op of the part already chosen (-1: none) */
+        while (i > 0 || j > 0) {
+            const int64_t c = i * w + j;
+            const int64_t bd = last == 1 ? open : 0, bi = last == 2 ? open : 0;
+            int op;
+            if (i > 0 && j > 0 && H[c - w - 1] + sub[a[i - 1] * sigma + b[j - 1]] == need)
+                op = 0;
+            else if (i > 0 && F[c] + bd == need)
+                op = 1;
+            else
+                op = 2;   /* E[c] + bi == need: the only op left */
+            if (op == 0) {
+                need -= sub[a[i - 1] * sigma + b[j - 1]];
+                --i; --j;
+            } else if (op == 1) {
+                need = need - bd + open + ext;
+                --i;
+            } else {
+                need = need - bi + open + ext;
+                --j;
+            }
+            ops[k++] = (uint8_t)op;
+            last = op;
+        }
+        for (int64_t x = 0, y = k - 1; x < y; ++x, --y) {
+            uint8_t t = ops[x]; ops[x] = ops[y]; ops[y] = t;
+        }
+        *ops_len = k;
+    }
+    free(H);
+    free(E);
+    free(F);
+    return score;
+}
+
+/* Affine NW over pairs (ops as for orc_nw_pairs; ops may be NULL). */
+void orc_gotoh_pairs(const uint8_t *ca, const int64_t *oa, const uint8_t *cb,
+                     const int64_t *ob, const int32_t *ia, const int32_t *ib,
+                     int64_t n_pairs, const int32_t *sub, int32_t sigma, int32_t open,
+                     int32_t ext, int64_t *score, uint8_t *ops, const int64_t *ops_off,
+                     int64_t *ops_len) {
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const uint8_t *a = ca + oa[ia[p]];
+        const uint8_t *b = cb + ob[ib[p]];
+        int64_t m = oa[ia[p] + 1] - oa[ia[p]], n = ob[ib[p] + 1] - ob[ib[p]];
+        score[p] = orc_gotoh(a, m, b, n, sub, sigma, open, ext,
+                             ops ? ops + ops_off[p] : NULL, ops ? ops_len + p : NULL);
     }
 }
 

@@ -31,6 +31,12 @@ def lib():
         L.orc_nw.argtypes = [P, C.c_int64, P, C.c_int64, P, P]
         L.orc_nw_pairs.restype = None
         L.orc_nw_pairs.argtypes = [P, P, P, P, P, P, C.c_int64, P, P, P, P]
+        L.orc_gotoh.restype = C.c_int64
+        L.orc_gotoh.argtypes = [P, C.c_int64, P, C.c_int64, P, C.c_int32, C.c_int32,
+                                C.c_int32, P, P]
+        L.orc_gotoh_pairs.restype = None
+        L.orc_gotoh_pairs.argtypes = [P, P, P, P, P, P, C.c_int64, P, C.c_int32, C.c_int32,
+                                      C.c_int32, P, P, P, P]
         L.orc_tree.restype = C.c_int32
         L.orc_tree.argtypes = [P, P, C.c_int32] + [P] * 10
         L.orc_tree_pruned.restype = C.c_int32
@@ -116,6 +122,44 @@ def nw_pairs(ca, oa, cb, ob, ia, ib, with_ops=True):
     ops_len = np.zeros(P, dtype=np.int64)
     lib().orc_nw_pairs(_p(ca), _p(oa), _p(cb), _p(ob), _p(ia), _p(ib), P, _p(score),
                        _p(ops), _p(ops_off), _p(ops_len))
+    return score, [ops[ops_off[p]: ops_off[p] + ops_len[p]].copy() for p in range(P)]
+
+
+def gotoh(a, b, sub, open_, ext):
+    """(score, ops) of the affine-gap alignment of one pair (see orc_gotoh):
+    sub is the sigma x sigma score matrix, a gap run of k scores -(open + k ext)."""
+    a, b = _u8(a), _u8(b)
+    sub = np.ascontiguousarray(sub, dtype=np.int32)
+    sigma = sub.shape[0]
+    ops = np.zeros(len(a) + len(b) + 1, dtype=np.uint8)
+    n = np.zeros(1, dtype=np.int64)
+    s = lib().orc_gotoh(_p(a), len(a), _p(b), len(b), _p(sub), sigma, int(open_), int(ext),
+                        _p(ops), _p(n))
+    return int(s), ops[: int(n[0])].copy()
+
+
+def gotoh_pairs(ca, oa, cb, ob, ia, ib, sub, open_, ext, with_ops=True):
+    """Scores (int64[P]) and, if asked, the op arrays of affine-gap alignments."""
+    ca, cb = _u8(ca), _u8(cb)
+    oa = np.ascontiguousarray(oa, dtype=np.int64)
+    ob = np.ascontiguousarray(ob, dtype=np.int64)
+    ia = np.ascontiguousarray(ia, dtype=np.int32)
+    ib = np.ascontiguousarray(ib, dtype=np.int32)
+    sub = np.ascontiguousarray(sub, dtype=np.int32)
+    sigma = sub.shape[0]
+    P = len(ia)
+    score = np.zeros(P, dtype=np.int64)
+    if not with_ops:
+        lib().orc_gotoh_pairs(_p(ca), _p(oa), _p(cb), _p(ob), _p(ia), _p(ib), P, _p(sub), sigma,
+                              int(open_), int(ext), _p(score), None, None, None)
+        return score, None
+    cap = (oa[ia + 1] - oa[ia]) + (ob[ib + 1] - ob[ib])
+    ops_off = np.zeros(P + 1, dtype=np.int64)
+    np.cumsum(cap, out=ops_off[1:])
+    ops = np.zeros(max(int(ops_off[-1]), 1), dtype=np.uint8)
+    ops_len = np.zeros(P, dtype=np.int64)
+    lib().orc_gotoh_pairs(_p(ca), _p(oa), _p(cb), _p(ob), _p(ia), _p(ib), P, _p(sub), sigma,
+                          int(open_), int(ext), _p(score), _p(ops), _p(ops_off), _p(ops_len))
     return score, [ops[ops_off[p]: ops_off[p] + ops_len[p]].copy() for p in range(P)]
 
 

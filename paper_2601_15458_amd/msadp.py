@@ -54,6 +54,11 @@ SIGNATURES = {
     "nw_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
     "nw_batch": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, C.c_size_t, P, P]),
     "nw_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
+    "gotoh_tb_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "gotoh_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
+    "gotoh_batch": (C.c_int, [SP, SP, P, P, C.c_int64, P, C.c_int32, C.c_int32, P, P, P, P,
+                              C.c_size_t, P, P]),
+    "gotoh_traceback": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P, P, P, P, P]),
     "tree_workspace_bytes": (C.c_size_t, [SP]),
     "tree_build": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
     "tree_build_pruned": (C.c_int, [SP, P, C.c_uint32, C.c_int32, C.c_int32, P,
@@ -379,6 +384,74 @@ def nw_traceback(A: Seqs, B: Seqs, r: NwResult, stream=None, check=True):
     if check:
         st.check("nw_traceback")
     return ops, ops_off, ops_len[: r.n_pairs]
+
+
+class GotohBatch:
+    """Affine-gap NW (substitution matrix `sub`, sigma x sigma, a gap run of
+    k scoring -(open + k ext)) over fixed pairs: buffers sized once; fill()
+    computes scores and traceback codes, traceback() the alignments."""
+
+    def __init__(self, A: Seqs, B: Seqs, ia, ib, sub, open_: int, ext: int):
+        dev = A.codes.device
+        self.A, self.B = A, B
+        self.ia_h = np.ascontiguousarray(ia.cpu().numpy() if isinstance(ia, torch.Tensor) else ia,
+                                         dtype=np.int32)
+        self.ib_h = np.ascontiguousarray(ib.cpu().numpy() if isinstance(ib, torch.Tensor) else ib,
+                                         dtype=np.int32)
+        self.n_pairs = P_ = len(self.ia_h)
+        self.sub = np.ascontiguousarray(sub, dtype=np.int32)
+        self.open, self.ext = int(open_), int(ext)
+        # sizes only: an index out of range is reported by the device
+        self.m = A.lengths[np.clip(self.ia_h, 0, max(A.n - 1, 0))] if P_ else np.zeros(0, np.int64)
+        self.n = B.lengths[np.clip(self.ib_h, 0, max(B.n - 1, 0))] if P_ else np.zeros(0, np.int64)
+        sizes = np.array([lib().gotoh_tb_bytes(int(a), int(b)) for a, b in zip(self.m, self.n)],
+                         dtype=np.int64)
+        sizes = (sizes + 255) // 256 * 256
+        tb_off = np.zeros(P_ + 1, dtype=np.int64)
+        np.cumsum(sizes, out=tb_off[1:])
+        self.tb = torch.empty(max(int(tb_off[-1]), 256), dtype=torch.uint8, device=dev)
+        self.tb_off = torch.from_numpy(tb_off).to(dev)
+        self.score = torch.empty(max(P_, 1), dtype=torch.int32, device=dev)
+        self.ia, self.ib = _i32(self.ia_h, dev), _i32(self.ib_h, dev)
+        self.sa, self.sb = A.struct(), B.struct()
+        self.wsb = lib().gotoh_workspace_bytes(C.byref(self.sa), C.byref(self.sb), P_)
+        self.ws = torch.empty(max(self.wsb, 1), dtype=torch.uint8, device=dev)
+        caps = (self.m + self.n).astype(np.int64)
+        self.ops_off = np.zeros(P_ + 1, dtype=np.int64)
+        np.cumsum(caps, out=self.ops_off[1:])
+        self.ops = torch.empty(max(int(self.ops_off[-1]), 1), dtype=torch.uint8, device=dev)
+        self.ops_off_d = torch.from_numpy(self.ops_off).to(dev)
+        self.ops_len = torch.empty(max(P_, 1), dtype=torch.int32, device=dev)
+        self.st = Status(dev)
+
+    def fill(self, stream=None):
+        rc = lib().gotoh_batch(C.byref(self.sa), C.byref(self.sb), _ptr(self.ia), _ptr(self.ib),
+                               self.n_pairs, self.sub.ctypes.data_as(C.c_void_p), self.open,
+                               self.ext, _ptr(self.score), _ptr(self.tb), _ptr(self.tb_off),
+                               _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
+        _check(rc, "gotoh_batch")
+        return self.score[: self.n_pairs]
+
+    def traceback(self, stream=None):
+        rc = lib().gotoh_traceback(C.byref(self.sa), C.byref(self.sb), _ptr(self.ia),
+                                   _ptr(self.ib), self.n_pairs, _ptr(self.tb), _ptr(self.tb_off),
+                                   _ptr(self.ops), _ptr(self.ops_off_d), _ptr(self.ops_len),
+                                   _ptr(self.st.t), _stream(stream))
+        _check(rc, "gotoh_traceback")
+
+    def results(self):
+        """(scores int64[P], list of op arrays) on the host."""
+        self.st.check("gotoh")
+        sc = self.score[: self.n_pairs].cpu().numpy().astype(np.int64)
+        return sc, split_ops(self.ops, self.ops_off, self.ops_len[: self.n_pairs])
+
+
+def gotoh(A: Seqs, B: Seqs, ia, ib, sub, open_: int, ext: int, stream=None):
+    """Scores and alignments of affine-gap NW over the pairs (host arrays)."""
+    g = GotohBatch(A, B, ia, ib, sub, open_, ext)
+    g.fill(stream)
+    g.traceback(stream)
+    return g.results()
 
 
 def split_ops(ops, ops_off, ops_len):

@@ -101,3 +101,35 @@ def render(a, b, ops, gap):
         else:
             ra.append(gap); rb.append(b[j]); j += 1
     return ra, rb
+
+
+def affine_score(a, b, ops, sub, open_, ext):
+    """Score of an op string: substitution scores of the M columns minus
+    (open + ext * length) for every maximal run of D ops or of I ops."""
+    i = j = 0
+    score = 0
+    prev = None
+    for o in ops:
+        if o == 0:
+            score += int(sub[a[i]][b[j]])
+            i += 1
+            j += 1
+        else:
+            score -= ext + (open_ if prev != o else 0)
+            if o == 1:
+                i += 1
+            else:
+                j += 1
+        prev = o
+    return score
+
+
+def best_affine_alignment(a, b, sub, open_, ext):
+    """(max affine score, the best-scoring op string whose reversal is
+    lexicographically smallest with M < D < I), by listing every alignment."""
+    best = None
+    for ops in all_alignments(len(a), len(b)):
+        key = (-affine_score(a, b, ops, sub, open_, ext), tuple(reversed(ops)))
+        if best is None or key < best[0]:
+            best = (key, ops)
+    return -best[0][0], list(best[1])

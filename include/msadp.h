@@ -113,6 +113,21 @@ int lev_batch_noalloc(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
                       const int32_t *ib, int64_t n_pairs, uint16_t *dist, int32_t *d_status,
                       hipStream_t s);
 
+/* Exact banded Levenshtein for long, similar pairs (Ukkonen's band,
+ * verified): dist[p] = lev(A[ia[p]], B[ib[p]]) whenever it is at most kmax,
+ * else 0xFFFF (the caller recomputes such pairs with lev_batch).  Only the
+ * cells of the diagonal band that holds every alignment of cost <= K are
+ * computed, starting from K = max(k0, |m - n| + 2) and doubling up to kmax
+ * while the banded value exceeds K (a banded value <= K is exact).
+ * k_used[p] (device int32, may be null) receives the K that verified the
+ * pair, or -1.  1 <= k0 <= kmax <= 4000; one wavefront per pair holds the
+ * pattern's match table and the text in LDS: A->max_len / 64 * sigma * 8 +
+ * B->max_len bytes, at most 64 KiB (MSA_ERANGE otherwise). */
+size_t lev_band_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs);
+int lev_band(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
+             int64_t n_pairs, int32_t k0, int32_t kmax, uint16_t *dist, int32_t *k_used,
+             void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
 /* Workspace for lev_allpairs over the set A. */
 size_t lev_allpairs_workspace_bytes(const msa_seqs *A);
 

@@ -48,6 +48,9 @@ SIGNATURES = {
     "lev_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
     "lev_batch": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, C.c_size_t, P, P]),
     "lev_batch_noalloc": (C.c_int, [SP, SP, P, P, C.c_int64, P, P, P]),
+    "lev_band_workspace_bytes": (C.c_size_t, [SP, SP, C.c_int64]),
+    "lev_band": (C.c_int, [SP, SP, P, P, C.c_int64, C.c_int32, C.c_int32, P, P, P, C.c_size_t,
+                           P, P]),
     "lev_allpairs_workspace_bytes": (C.c_size_t, [SP]),
     "lev_allpairs": (C.c_int, [SP, P, P, C.c_size_t, P, P]),
     "nw_tb_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
@@ -239,6 +242,43 @@ def lev_batch(A: Seqs, B: Seqs, ia, ib, out=None, stream=None, check=True):
     if check:
         lb.st.check("lev_batch")
     return res
+
+
+BAND_NONE = 0xFFFF
+
+
+class LevBand:
+    """Reusable exact banded Levenshtein launcher (lev_band): distances up to
+    kmax, 0xFFFF beyond; k_used holds the band threshold that verified each."""
+
+    def __init__(self, A: Seqs, B: Seqs, ia, ib, k0: int = 256, kmax: int = 4000):
+        dev = A.codes.device
+        self.A, self.B = A, B
+        self.ia, self.ib = _i32(ia, dev), _i32(ib, dev)
+        self.n_pairs = self.ia.numel()
+        self.k0, self.kmax = int(k0), int(kmax)
+        self.out = torch.empty(max(self.n_pairs, 1), dtype=torch.uint16, device=dev)
+        self.k_used = torch.empty(max(self.n_pairs, 1), dtype=torch.int32, device=dev)
+        self.sa, self.sb = A.struct(), B.struct()
+        self.wsb = lib().lev_band_workspace_bytes(C.byref(self.sa), C.byref(self.sb),
+                                                  self.n_pairs)
+        self.ws = torch.empty(max(self.wsb, 1), dtype=torch.uint8, device=dev)
+        self.st = Status(dev)
+
+    def __call__(self, stream=None):
+        rc = lib().lev_band(C.byref(self.sa), C.byref(self.sb), _ptr(self.ia), _ptr(self.ib),
+                            self.n_pairs, self.k0, self.kmax, _ptr(self.out), _ptr(self.k_used),
+                            _ptr(self.ws), self.wsb, _ptr(self.st.t), _stream(stream))
+        _check(rc, "lev_band")
+        return self.out[: self.n_pairs]
+
+
+def lev_band(A: Seqs, B: Seqs, ia, ib, k0: int = 256, kmax: int = 4000, stream=None):
+    """(distances uint16 (0xFFFF above kmax), verifying thresholds int32)."""
+    lb = LevBand(A, B, ia, ib, k0, kmax)
+    d = lb(stream)
+    lb.st.check("lev_band")
+    return d, lb.k_used[: lb.n_pairs]
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20

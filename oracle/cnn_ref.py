@@ -38,6 +38,16 @@ def init_params(seed: int, sigma: int = 4, width: int = 128, layers: int = 4, K:
     return params
 
 
+def bf16(x):
+    """Round to the nearest bfloat16 (8-bit significand, ties to even), as a
+    float64 array: the storage format the device keeps activations and
+    gradient rows in."""
+    f = np.asarray(x, np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def one_hot(x, sigma):
     x = np.asarray(x, dtype=np.int64)
     H = np.zeros((len(x), sigma))
@@ -58,21 +68,30 @@ def conv(H, W, b):
     return Z
 
 
-def forward(params, x, sigma):
-    """Embedding of one sequence and the per-layer cache for backward."""
+def _same(x):
+    return x
+
+
+def forward(params, x, sigma, store=_same):
+    """Embedding of one sequence and the per-layer cache for backward.
+
+    store: applied to every hidden activation H_1 .. H_{n-1} as it is kept
+    (identity: exact float64; a rounding function emulates a storage format)."""
     H = one_hot(x, sigma)
     cache = [H]
     n = len(params)
     for l, (W, b) in enumerate(params):
         Z = conv(H, W, b)
-        H = np.maximum(Z, 0.0) if l < n - 1 else Z
+        H = store(np.maximum(Z, 0.0)) if l < n - 1 else Z
         cache.append((Z, H))
     e = H.mean(axis=0)
     return e, cache
 
 
-def backward(params, cache, de):
-    """Gradients (dW, db per layer) given dL/de for one sequence."""
+def backward(params, cache, de, store=_same):
+    """Gradients (dW, db per layer) given dL/de for one sequence.
+
+    store: applied to every layer's output gradient dZ as it is kept."""
     n = len(params)
     L = cache[0].shape[0]
     dH = np.tile(de / L, (L, 1))              # mean pool
@@ -80,7 +99,8 @@ def backward(params, cache, de):
     for l in range(n - 1, -1, -1):
         W, b = params[l]
         Z, H = cache[l + 1]
-        dZ = dH * (Z > 0) if l < n - 1 else dH
+        # the ReLU passes where the kept activation is positive
+        dZ = store(dH * (H > 0) if l < n - 1 else dH)
         Hin = cache[0] if l == 0 else cache[l][1]
         K = W.shape[0]
         pad = K // 2
@@ -105,12 +125,13 @@ def embed(params, seqs, sigma):
     return np.stack([forward(params, s, sigma)[0] for s in seqs])
 
 
-def pair_loss_and_grads(params, seqs, ia, ib, labels, sigma):
-    """Mean squared error of ||e_a - e_b|| against labels, and its gradients."""
+def pair_loss_and_grads(params, seqs, ia, ib, labels, sigma, store=_same):
+    """Mean squared error of ||e_a - e_b|| against labels, and its gradients
+    (store: see forward and backward)."""
     caches = {}
     embs = {}
     for i in set(np.asarray(ia).tolist()) | set(np.asarray(ib).tolist()):
-        embs[i], caches[i] = forward(params, seqs[i], sigma)
+        embs[i], caches[i] = forward(params, seqs[i], sigma, store)
     P = len(ia)
     loss = 0.0
     dE = {i: np.zeros_like(embs[i]) for i in embs}
@@ -124,7 +145,7 @@ def pair_loss_and_grads(params, seqs, ia, ib, labels, sigma):
         dE[b] -= g
     total = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
     for i, de in dE.items():
-        gi = backward(params, caches[i], de)
+        gi = backward(params, caches[i], de, store)
         total = [(tw + gw, tb + gb) for (tw, tb), (gw, gb) in zip(total, gi)]
     return loss, total
 

@@ -467,7 +467,10 @@ __device__ __forceinline__ bf16x8 join_frag(v4i16 lo, v4i16 hi) {
 
 template <int CIN, int KDP>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_t *dZ,
-                                                    int64_t rows, float *gW, float *gb) {
+                                                    int64_t rows, float *part, float *part_b) {
+    // this chunk's partial sums: part[chunk][co][kk], part_b[chunk][co]
+    float *gW = part + (size_t)blockIdx.y * kW * KDP;
+    float *gb = part_b + (size_t)blockIdx.y * kW;
     constexpr int NT = (KDP < 128 ? KDP : 128) / 16;   // 16-column tiles per block
     constexpr int KD = kKer * CIN;
     constexpr int kHRows = CIN == kW ? kStep : kStep + 2 * kHalo;
@@ -560,10 +563,134 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t *H, const bf16_
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int co = 32 * w + 16 * i + 4 * g + r;
-                atomicAdd(&gW[(size_t)co * KDP + kk], acc[i][n][r]);
+                gW[(size_t)co * KDP + kk] = acc[i][n][r];
             }
         }
-    if (kb == 0 && threadIdx.x < kW) atomicAdd(&gb[threadIdx.x], bsum);
+    if (kb == 0 && threadIdx.x < kW) gb[threadIdx.x] = bsum;
+}
+
+// Weight gradient of the 128-channel layers with every tap from one staging
+// of the rows: a workgroup takes a 4096-row chunk and one half of the output
+// channels (64 co) against all 640 columns kk = k * 128 + ci, so a row's H is
+// read twice and its dZ once (each half reads its own 64 channels).  Each
+// 64-row step stages the chunk's 64 dZ rows (the half's channels) and the 68
+// H rows r0 - 2 .. r0 + 65 that the five taps need; the next step's rows are
+// loaded into registers while the current one computes.  Eight wavefronts:
+// wavefront w owns the half's 4 co tiles x column tiles 5 w .. 5 w + 4 (20
+// matrix tiles, 80 accumulators).  The chunk's sums go to its own slice of
+// a partial buffer (no atomics); every workgroup also sums its 64 channels
+// of dZ over the chunk's rows (bias gradient).
+constexpr int kWgRows = 4096;
+constexpr int kHRows2 = kStep + 2 * kHalo;   // 68
+constexpr int kZPitch = 72;                  // LDS row pitch of the 64-channel dZ tile
+
+__global__ void __launch_bounds__(512) k_conv_wgrad_h(const bf16_t *H, const bf16_t *dZ,
+                                                      int64_t rows, float *part,
+                                                      float *part_b) {
+    constexpr int KDP = kKer * kW;   // 640
+    __shared__ __attribute__((aligned(16))) bf16_t sdz[kStep * kZPitch];
+    __shared__ __attribute__((aligned(16))) bf16_t sh[kHRows2 * kPitch];
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int g = lane >> 4, t = lane & 15;
+    const int tid = threadIdx.x;
+    const int half = blockIdx.x;
+    const int64_t r_begin = (int64_t)blockIdx.y * kWgRows;
+    const int64_t r_end = min(rows, r_begin + kWgRows);
+    const int cz = 64 * half;        // first dZ channel (co) of the half
+    const int kt0 = 5 * w;           // first column tile (of 40)
+    f32x4 acc[4][5];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int u = 0; u < 5; ++u) acc[i][u] = f32x4{0, 0, 0, 0};
+    float bsum = 0.0f;
+    // 16-byte pieces of a step: dZ 64 rows x 8, H 68 rows x 16
+    uint4 pz, ph[3];
+    auto load = [&](int64_t r0) {
+        {
+            const int rr = tid >> 3, c = (tid & 7) * 8;
+            pz = r0 + rr < r_end ? *(const uint4 *)(dZ + (kLead + r0 + rr) * kW + cz + c)
+                                 : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int e = tid + 512 * q, rr = e >> 4, c = (e & 15) * 8;
+            // rows r0 - 2 .. r0 + 65 lie inside the framed buffer (lead and
+            // tail rows); dZ rows past the chunk are zero, so the H rows they
+            // meet contribute nothing
+            ph[q] = e < kHRows2 * 16 ? *(const uint4 *)(H + (kLead + r0 - kHalo + rr) * kW + c)
+                                     : make_uint4(0, 0, 0, 0);
+        }
+    };
+    load(r_begin);
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kStep) {
+        __syncthreads();
+        *(uint4 *)(sdz + (tid >> 3) * kZPitch + (tid & 7) * 8) = pz;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int e = tid + 512 * q, rr = e >> 4, c = (e & 15) * 8;
+            if (e < kHRows2 * 16) *(uint4 *)(sh + rr * kPitch + c) = ph[q];
+        }
+        __syncthreads();
+        if (r0 + kStep < r_end) load(r0 + kStep);
+        if (tid < 64) {
+#pragma unroll 8
+            for (int rr = 0; rr < kStep; ++rr) bsum += from_bf16(sdz[rr * kZPitch + tid]);
+        }
+#pragma unroll
+        for (int ks = 0; ks < kStep; ks += 32) {
+            const int rb = ks + 8 * g + (t >> 2);   // this lane's row of the first read
+            bf16x8 af[4], bfr[5];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bf16_t *p = sdz + rb * kZPitch + 16 * i + 4 * (t & 3);
+                af[i] = join_frag(read_tr(p), read_tr(p + 4 * kZPitch));
+            }
+#pragma unroll
+            for (int u = 0; u < 5; ++u) {
+                const int kk = 16 * (kt0 + u);
+                const int k = kk >> 7, ci0 = kk & (kW - 1);   // tap, first channel
+                const bf16_t *p = sh + (rb + k) * kPitch + ci0 + 4 * (t & 3);
+                bfr[u] = join_frag(read_tr(p), read_tr(p + 4 * kPitch));
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int u = 0; u < 5; ++u)
+                    acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[u], acc[i][u],
+                                                                        0, 0, 0);
+        }
+    }
+    float *gW = part + (size_t)blockIdx.y * kW * KDP;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+            const int kk = 16 * (kt0 + u) + t;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = cz + 16 * i + 4 * g + r;
+                gW[(size_t)co * KDP + kk] = acc[i][u][r];
+            }
+        }
+    if (tid < 64) part_b[(size_t)blockIdx.y * kW + cz + tid] = bsum;
+}
+
+// gW = sum of the chunks' partial sums, chunk 0 first (a fixed order, so equal
+// inputs give equal bits); the same for the bias.
+__global__ void k_wgrad_reduce(const float *part, const float *part_b, int32_t chunks,
+                               int32_t n, float *gW, float *gb) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n + kW; i += gridDim.x * blockDim.x) {
+        const bool bias = i >= n;
+        const float *src = bias ? part_b + (i - n) : part + i;
+        const int64_t stride = bias ? kW : n;
+        float sum = 0.0f;
+#pragma unroll 8
+        for (int c = 0; c < chunks; ++c) sum += src[(int64_t)c * stride];
+        if (bias) gb[i - n] = sum;
+        else gW[i] = sum;
+    }
 }
 
 // ------------------------------------------------------------ pool, loss
@@ -588,11 +715,12 @@ __global__ void __launch_bounds__(128) k_pool(Batch b, const float *Z4, float *E
     }
 }
 
-// One wavefront per pair: pred = ||E[a] - E[b]||; loss += (pred - y)^2 / P;
-// dE[a] += g, dE[b] -= g with g = 2 (pred - y) / P * (E[a] - E[b]) / pred.
+// One wavefront per pair: pred = ||E[a] - E[b]||, r = pred - y; the pair's
+// gradient row G[p] = 2 r / (P pred) (E[a] - E[b]) (added to dE[a],
+// subtracted from dE[b] by k_seq_grad) and r2[p] = r^2 / P.
 __global__ void __launch_bounds__(64) k_pair_loss(const float *E, const int32_t *pa,
                                                  const int32_t *pb, const float *label,
-                                                 int32_t P, float *dE, float *loss) {
+                                                 int32_t P, float *G, float *r2) {
     const int lane = lane_id();
     const int p = blockIdx.x;
     const int a = pa[p], bq = pb[p];
@@ -603,11 +731,69 @@ __global__ void __launch_bounds__(64) k_pair_loss(const float *E, const int32_t 
     const float pred = sqrtf(ss);
     const float r = pred - label[p];
     const float scale = pred > 0.0f ? 2.0f * r / ((float)P * pred) : 0.0f;
-    atomicAdd(&dE[(int64_t)a * kW + lane], scale * d0);
-    atomicAdd(&dE[(int64_t)a * kW + lane + 64], scale * d1);
-    atomicAdd(&dE[(int64_t)bq * kW + lane], -scale * d0);
-    atomicAdd(&dE[(int64_t)bq * kW + lane + 64], -scale * d1);
-    if (lane == 0) atomicAdd(loss, r * r / (float)P);
+    G[(int64_t)p * kW + lane] = scale * d0;
+    G[(int64_t)p * kW + lane + 64] = scale * d1;
+    if (lane == 0) r2[p] = r * r / (float)P;
+}
+
+// The pairs of each batch sequence, as entries 2p (the sequence is a) and
+// 2p + 1 (it is b) in a CSR list: counts, then a scatter (any order).
+__global__ void k_pair_count(const int32_t *pa, const int32_t *pb, int32_t P, int32_t *cnt) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        atomicAdd(&cnt[pa[p]], 1);
+        atomicAdd(&cnt[pb[p]], 1);
+    }
+}
+
+__global__ void k_pair_fill(const int32_t *pa, const int32_t *pb, int32_t P, int64_t *cursor,
+                            int32_t *list) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        list[atomicAdd((unsigned long long *)&cursor[pa[p]], 1ull)] = 2 * p;
+        list[atomicAdd((unsigned long long *)&cursor[pb[p]], 1ull)] = 2 * p + 1;
+    }
+}
+
+// dE[i] = sum of +G[p] (entries 2p) and -G[p] (entries 2p + 1) of sequence
+// i's list, taken in increasing entry order whatever order the scatter left
+// (one wavefront per sequence; lists hold a few entries).
+__global__ void __launch_bounds__(64) k_seq_grad(const int64_t *start, const int32_t *list,
+                                                const float *G, int32_t nb, float *dE) {
+    const int lane = lane_id();
+    for (int i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int64_t s0 = start[i];
+        const int32_t k = (int32_t)(start[i + 1] - s0);
+        float a0 = 0.0f, a1 = 0.0f;
+        int32_t prev = -1;
+        for (int32_t r = 0; r < k; ++r) {
+            int32_t mn = 0x7fffffff;
+            for (int32_t e = lane; e < k; e += 64) {
+                const int32_t v = list[s0 + e];
+                mn = (v > prev && v < mn) ? v : mn;
+            }
+            for (int o = 32; o >= 1; o >>= 1) mn = min(mn, __shfl_xor(mn, o, kWave));
+            const int32_t pq = mn >> 1;
+            const float sg = (mn & 1) ? -1.0f : 1.0f;
+            a0 += sg * G[(int64_t)pq * kW + lane];
+            a1 += sg * G[(int64_t)pq * kW + lane + 64];
+            prev = mn;
+        }
+        dE[(int64_t)i * kW + lane] = a0;
+        dE[(int64_t)i * kW + lane + 64] = a1;
+    }
+}
+
+// loss = sum of r2 in a fixed order: strided per-thread sums, then a tree.
+__global__ void __launch_bounds__(1024) k_sum_fixed(const float *x, int32_t n, float *out) {
+    __shared__ float part[1024];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 1024) s += x[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0];
 }
 
 // Regression target of a pair: lev(a, b) / ((|a| + |b|) / 2).
@@ -659,11 +845,12 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, 
     }
 }
 
-__global__ void k_zero_f32(float *p, int64_t n) {
+__global__ void k_widen_i32(const int32_t *a, int64_t n, int64_t *b) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0f;
+        b[i] = a[i];
 }
+
 
 // ------------------------------------------------------------ host side
 struct CnnWork {
@@ -673,8 +860,19 @@ struct CnnWork {
     bf16_t *dz;              // gradient rows (two buffers)
     bf16_t *dz2;
     float *E, *dE, *loss, *label;
+    float *part, *part_b;    // weight-gradient partial sums per row chunk
+    float *G, *r2;           // per-pair gradient rows and squared errors
+    int32_t *cnt, *list;     // pairs of each batch sequence (CSR)
+    int64_t *pstart, *pcur;
     int64_t alloc_rows;
 };
+
+static int64_t wgrad_chunks(int64_t rows) { return (rows + kWgRows - 1) / kWgRows; }
+static int64_t wgrad_chunks0(int64_t rows) { return (rows + kWgChunk0 - 1) / kWgChunk0; }
+static size_t wgrad_part_floats(int64_t rows) {
+    return std::max((size_t)wgrad_chunks(rows) * kW * kd_of(1),
+                    (size_t)wgrad_chunks0(rows) * kW * kdp_of(0));
+}
 
 // Tail: the last tile's overhang plus the longest span (8 rows) past it.
 constexpr int kTail = 64;
@@ -700,6 +898,14 @@ static void cnn_layout(Alloc &al, int32_t nb, int64_t rows, const msa_seqs *S, b
         al.template take<float>((size_t)nb * kW);
         al.template take<float>(1);
         al.template take<float>((size_t)n_pairs);
+        al.template take<float>(wgrad_part_floats(rows));
+        al.template take<float>((size_t)std::max(wgrad_chunks(rows), wgrad_chunks0(rows)) * kW);
+        al.template take<float>((size_t)n_pairs * kW);
+        al.template take<float>((size_t)n_pairs);
+        al.template take<int32_t>((size_t)nb + 1);
+        al.template take<int32_t>(2 * (size_t)n_pairs);
+        al.template take<int64_t>((size_t)nb + 1);
+        al.template take<int64_t>((size_t)nb + 1);
     }
 }
 
@@ -751,8 +957,8 @@ static int cnn_forward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t s
 static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t s) {
     const Batch &b = w.b;
     const unsigned tiles = (unsigned)((b.rows + kTile - 1) / kTile);
-    const unsigned chunks = (unsigned)((b.rows + kWgChunk - 1) / kWgChunk);
-    const unsigned chunks0 = (unsigned)((b.rows + kWgChunk0 - 1) / kWgChunk0);
+    const unsigned chunks = (unsigned)wgrad_chunks(b.rows);
+    const unsigned chunks0 = (unsigned)wgrad_chunks0(b.rows);
     int rc;
     if ((rc = zero_frame(w.dz, kW * 2, w.alloc_rows, b.rows, s))) return rc;
     if ((rc = zero_frame(w.dz2, kW * 2, w.alloc_rows, b.rows, s))) return rc;
@@ -762,12 +968,17 @@ static int cnn_backward(void *P, const ParamLayout &pl, CnnWork &w, hipStream_t 
     for (int l = kLayers - 1; l >= 0; --l) {
         float *gw = at<float>(P, pl.gw[l]);
         float *gb = at<float>(P, pl.gb[l]);
-        if (l == 0)
+        if (l == 0) {
             hipLaunchKernelGGL((k_conv_wgrad<kIn, kdp_of(0)>), dim3(1, chunks0), dim3(256), 0, s,
-                               w.h[0], dz, b.rows, gw, gb);
-        else
-            hipLaunchKernelGGL((k_conv_wgrad<kW, kdp_of(1)>), dim3(kKer, chunks), dim3(256), 0, s,
-                               w.h[l], dz, b.rows, gw, gb);
+                               w.h[0], dz, b.rows, w.part, w.part_b);
+            hipLaunchKernelGGL(k_wgrad_reduce, dim3((kW * kdp_of(0) + kW + 255) / 256), dim3(256),
+                               0, s, w.part, w.part_b, (int32_t)chunks0, kW * kdp_of(0), gw, gb);
+        } else {
+            hipLaunchKernelGGL(k_conv_wgrad_h, dim3(2, chunks), dim3(512), 0, s, w.h[l], dz,
+                               b.rows, w.part, w.part_b);
+            hipLaunchKernelGGL(k_wgrad_reduce, dim3((kW * kdp_of(1) + kW + 255) / 256), dim3(256),
+                               0, s, w.part, w.part_b, (int32_t)chunks, kW * kdp_of(1), gw, gb);
+        }
         if (l > 0) {
             ConvArgs c{};
             c.X = dz;
@@ -813,6 +1024,14 @@ static int setup(const msa_seqs *S, const int32_t *idx, int32_t nb, int64_t tota
         w.dE = cv.take<float>((size_t)nb * kW);
         w.loss = cv.take<float>(1);
         w.label = cv.take<float>((size_t)n_pairs);
+        w.part = cv.take<float>(wgrad_part_floats(rows));
+        w.part_b = cv.take<float>((size_t)std::max(wgrad_chunks(rows), wgrad_chunks0(rows)) * kW);
+        w.G = cv.take<float>((size_t)n_pairs * kW);
+        w.r2 = cv.take<float>((size_t)n_pairs);
+        w.cnt = cv.take<int32_t>((size_t)nb + 1);
+        w.list = cv.take<int32_t>(2 * (size_t)n_pairs);
+        w.pstart = cv.take<int64_t>((size_t)nb + 1);
+        w.pcur = cv.take<int64_t>((size_t)nb + 1);
     }
     if ((rc = stage_set(S, nullptr, st, d_status, s))) return rc;
     hipLaunchKernelGGL(k_frame_lengths, dim3((nb + 256) / 256), dim3(256), 0, s, w.b, d_status);
@@ -931,16 +1150,22 @@ int cnn_train_step(void *P, const msa_seqs *S, const int32_t *idx, int32_t n_idx
     hipLaunchKernelGGL(k_labels, dim3((n_pairs + 255) / 256), dim3(256), 0, s, w.b, pa, pb, dist,
                        n_pairs, w.label);
     if ((rc = cnn_forward(P, pl, w, s))) return rc;
-    hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, s, w.dE, (int64_t)n_idx * kW);
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, w.loss, (int64_t)1);
-    for (int l = 0; l < kLayers; ++l) {
-        hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, s, at<float>(P, pl.gw[l]),
-                           (int64_t)kW * kdp_of(l));
-        hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(128), 0, s, at<float>(P, pl.gb[l]),
-                           (int64_t)kW);
-    }
+    // pair loss and embedding gradient, summed in fixed orders
     hipLaunchKernelGGL(k_pair_loss, dim3(n_pairs), dim3(64), 0, s, w.E, pa, pb, w.label, n_pairs,
-                       w.dE, w.loss);
+                       w.G, w.r2);
+    hipLaunchKernelGGL(k_sum_fixed, dim3(1), dim3(1024), 0, s, w.r2, n_pairs, w.loss);
+    if ((rc = fill_i32(w.cnt, (int64_t)n_idx + 1, 0, s))) return rc;
+    const unsigned pg = (unsigned)std::min((n_pairs + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_pair_count, dim3(pg), dim3(256), 0, s, pa, pb, n_pairs, w.cnt);
+    hipLaunchKernelGGL(k_widen_i32, dim3((n_idx + 1 + 255) / 256), dim3(256), 0, s, w.cnt,
+                       (int64_t)n_idx + 1, w.pstart);
+    if ((rc = exclusive_scan_i64(w.pstart, (int64_t)n_idx + 1, s))) return rc;
+    if (hipMemcpyAsync(w.pcur, w.pstart, sizeof(int64_t) * ((size_t)n_idx + 1),
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MSA_EDEVICE;
+    hipLaunchKernelGGL(k_pair_fill, dim3(pg), dim3(256), 0, s, pa, pb, n_pairs, w.pcur, w.list);
+    hipLaunchKernelGGL(k_seq_grad, dim3((unsigned)std::min(n_idx, 65535)), dim3(64), 0, s,
+                       w.pstart, w.list, w.G, n_idx, w.dE);
     if ((rc = cnn_backward(P, pl, w, s))) return rc;
     if (lr > 0.0f) {
         const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;

@@ -19,12 +19,24 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def _bf16(x):
-    """Round float64 to the nearest bfloat16 (ties to even), as the device does."""
-    f = np.asarray(x, np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+_bf16 = ref.bf16
+
+# Tolerances.  The device keeps weights, hidden activations and gradient rows
+# in BF16 (8-bit significand) and sums in FP32.  The reference is evaluated
+# twice in float64: exactly, and rounding the same values to BF16 at the
+# same points (store=ref.bf16).  The difference of the two, the storage gap,
+# is what BF16 storage alone does to a tensor: small for the embedding
+# (6e-4), a few percent for weight gradients that sum many rows with
+# cancellation (1.4-2.9 % at 2,000 rows, up to 4.9 % at 24,000 rows,
+# measured on the CPU from the two references alone).  Two BF16 evaluations
+# of the model (the device and the rounding reference) round different
+# FP32/float64 values, so past the first differing rounding they drift
+# apart by a fraction of that gap (measured up to a third of it).  The
+# bounds: the device within TIGHT + gap / 2 of the rounding reference and
+# within TIGHT + 1.25 gap of the exact one, that is, as close to the exact
+# model as an independent BF16-storage evaluation is (measured 0.97 to
+# 1.02 gap).
+TIGHT = 3e-3
 
 
 def _setup(seed=1, n=48, lo=1, hi=90):
@@ -44,46 +56,93 @@ def _setup(seed=1, n=48, lo=1, hi=90):
 def test_forward_matches_reference():
     M, S, emb, params, seqs = _setup()
     got = emb.embed(S).cpu().numpy()
-    # reference with the weights the device holds (bf16) and exact arithmetic
     pq = [(_bf16(W), b) for W, b in params]
-    want = ref.embed(pq, seqs, 4)
-    err = rel_l2(got, want)
-    print("embedding rel L2", err)
-    assert err < 2e-2, err
+    emul = np.stack([ref.forward(pq, x, 4, store=_bf16)[0] for x in seqs])
+    exact = ref.embed(pq, seqs, 4)
+    e_emul, e_exact, gap = rel_l2(got, emul), rel_l2(got, exact), rel_l2(emul, exact)
+    print(f"embedding rel L2: vs BF16-storage reference {e_emul:.2e}, vs exact {e_exact:.2e} "
+          f"(storage gap {gap:.2e})")
+    assert e_emul < TIGHT + gap / 2
+    assert e_exact < TIGHT + 1.25 * gap
     # against the unrounded float64 model as well
     assert rel_l2(got, ref.embed(params, seqs, 4)) < 3e-2
+
+
+def _grad_check(M, S, emb, params, seqs, pa, pb):
+    """Device gradients against the BF16-storage reference (TIGHT) and the
+    exact float64 reference (storage gap + TIGHT), per tensor."""
+    d = orc.lev_pairs(*synth.to_csr(seqs), *synth.to_csr(seqs), pa, pb)
+    emb.train_step(S, np.arange(S.n), pa, pb, d.astype(np.uint16), lr=0.0)
+    _, grads = emb.get()
+    y = ref.pair_labels(d, [len(seqs[i]) for i in pa], [len(seqs[i]) for i in pb])
+    pq = [(_bf16(W), b) for W, b in params]
+    _, exact = ref.pair_loss_and_grads(pq, seqs, pa, pb, y, 4)
+    _, emul = ref.pair_loss_and_grads(pq, seqs, pa, pb, y, 4, store=_bf16)
+    for l in range(4):
+        gW, gb = grads[l]
+        if l == 0:
+            gW = gW[:, :4, :]        # one-hot channels beyond sigma carry no gradient
+        for name, g, we, wx in (("dW", gW, emul[l][0], exact[l][0]),
+                                ("db", gb, emul[l][1], exact[l][1])):
+            if l == 3 and name == "db":
+                # the last bias gradient is exactly zero: the mean pool hands
+                # dE to every row and each pair adds +g and -g to its ends
+                scale = np.linalg.norm(exact[l][0])
+                e1 = float(np.linalg.norm(g - we) / scale)
+                e2 = float(np.linalg.norm(g - wx) / scale)
+                gap = float(np.linalg.norm(we - wx) / scale)
+            else:
+                e1, e2, gap = rel_l2(g, we), rel_l2(g, wx), rel_l2(we, wx)
+            print(f"layer {l} {name}: vs BF16-storage reference {e1:.2e}, vs exact {e2:.4f} "
+                  f"(storage gap {gap:.4f})")
+            assert e1 < TIGHT + gap / 2, (l, name, e1, gap)
+            assert e2 < TIGHT + 1.25 * gap, (l, name, e2, gap)
 
 
 def test_gradients_match_reference():
     M, S, emb, params, seqs = _setup(seed=2, n=40, lo=5, hi=70)
     rng = np.random.default_rng(3)
-    P = 64
-    pa = rng.integers(0, S.n, size=P)
-    pb = rng.integers(0, S.n, size=P)
-    d = orc.lev_pairs(*synth.to_csr(seqs), *synth.to_csr(seqs), pa, pb)
+    pa = rng.integers(0, S.n, size=64)
+    pb = rng.integers(0, S.n, size=64)
+    _grad_check(M, S, emb, params, seqs, pa, pb)
+
+
+def test_gradients_match_reference_many_chunks():
+    """About 24,000 rows (180 sequences of 100-200 symbols): the weight
+    gradients of every layer span several row chunks (2048 rows for the
+    one-hot layer, 4096 for the others) and their fixed-order sum."""
+    M, S, emb, params, seqs = _setup(seed=8, n=180, lo=100, hi=200)
+    rng = np.random.default_rng(9)
+    pa = rng.integers(0, S.n, size=512)
+    pb = rng.integers(0, S.n, size=512)
+    rows = sum(len(x) + 4 for x in seqs)
+    assert rows >= 12 * 2048
+    _grad_check(M, S, emb, params, seqs, pa, pb)
+
+
+def test_training_step_is_deterministic():
+    """Equal inputs give equal bits: gradients of two identical steps, and
+    weights after three Adam steps run twice from the same start."""
+    M, S, emb, params, seqs = _setup(seed=10, n=120, lo=60, hi=160)
+    rng = np.random.default_rng(11)
+    pa = rng.integers(0, S.n, size=700)
+    pb = rng.integers(0, S.n, size=700)
+    d = orc.lev_pairs(*synth.to_csr(seqs), *synth.to_csr(seqs), pa, pb).astype(np.uint16)
     idx = np.arange(S.n)
-    emb.train_step(S, idx, pa, pb, d.astype(np.uint16), lr=0.0)
-    _, grads = emb.get()
-    y = ref.pair_labels(d, [len(seqs[i]) for i in pa], [len(seqs[i]) for i in pb])
-    pq = [(_bf16(W), b) for W, b in params]
-    _, want = ref.pair_loss_and_grads(pq, seqs, pa, pb, y, 4)
-    for l in range(4):
-        gW, gb = grads[l]
-        wW, wb = want[l]
-        if l == 0:
-            gW = gW[:, :4, :]        # one-hot channels beyond sigma carry no gradient
-        e1 = rel_l2(gW, wW)
-        if l == 3:
-            # the last bias gradient is exactly zero: the mean pool hands
-            # dE to every row and each pair adds +g and -g to its two ends
-            e2 = float(np.linalg.norm(gb - wb) / np.linalg.norm(wW))
-        else:
-            e2 = rel_l2(gb, wb)
-        print(f"layer {l}: dW rel {e1:.4f}  db rel {e2:.4f}")
-        # BF16 storage of activations and of each layer's gradient rows
-        # (relative rounding 2^-9 per value, compounded over 4 layers each
-        # way, with cancellation in the sums) allows a few percent.
-        assert e1 < 5e-2 and e2 < 5e-2, (l, e1, e2)
+    emb.train_step(S, idx, pa, pb, d, lr=0.0)
+    _, g1 = emb.get()
+    emb.train_step(S, idx, pa, pb, d, lr=0.0)
+    _, g2 = emb.get()
+    for (a, b), (c, e) in zip(g1, g2):
+        assert np.array_equal(a, c) and np.array_equal(b, e)
+    runs = []
+    for _ in range(2):
+        emb.set_params(params)
+        losses = [emb.train_step(S, idx, pa, pb, d, lr=1e-3) for _ in range(3)]
+        runs.append((losses, emb.get()[0]))
+    assert runs[0][0] == runs[1][0]
+    for (a, b), (c, e) in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(a, c) and np.array_equal(b, e)
 
 
 def test_adam_update_matches_reference():

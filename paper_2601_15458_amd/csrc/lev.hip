@@ -149,7 +149,8 @@ struct LanesArgs {
     uint32_t *counter;
 };
 
-// WMAX words per pattern at most, SP = sigma' symbol rows per word.
+// WMAX words per pattern at most, SP = sigma' symbol rows per word (SP = 2:
+// two bit planes per word, for alphabets of at most 4 symbols).
 template <int WMAX, int SP>
 __global__ void __launch_bounds__(64) k_lev_lanes(LanesArgs a) {
     __shared__ uint64_t tbl[WMAX * SP * kWave];
@@ -178,9 +179,15 @@ __global__ void __launch_bounds__(64) k_lev_lanes(LanesArgs a) {
         } else if (nmax == 0) {
             d = m;                  // every text empty
         } else {
-            build_lane_peq<SP>(tbl, pat, m, W);
-            d = m + dispatch_lanes<WMAX, SP>(W, (lds_u64 *)tbl + lane, text, n, nmax,
-                                             (m - 1) & 63);
+            if constexpr (SP == 2) {
+                build_lane_planes((uint4 *)tbl, pat, m, W);
+                d = m + dispatch_planes<WMAX>(W, (lds_u128 *)tbl + lane, text, n, nmax,
+                                              (m - 1) & 63);
+            } else {
+                build_lane_peq<SP>(tbl, pat, m, W);
+                d = m + dispatch_lanes<WMAX, SP>(W, (lds_u64 *)tbl + lane, text, n, nmax,
+                                                 (m - 1) & 63);
+            }
         }
         if (valid) a.out[pid] = (uint16_t)d;
     }
@@ -294,11 +301,28 @@ __device__ __forceinline__ int32_t lanes_key(int la, int lb, int wmax, int nb, b
     return (wmax - ((P + 63) >> 6)) * nb + (nb - 1 - (T >> 2));
 }
 
-__global__ void k_lanes_hist(const int32_t *ia, const int32_t *ib, int64_t np, const int32_t *lenA,
-                             const int32_t *lenB, int32_t na, int32_t nb_seq, int32_t wmax,
-                             int32_t nb, int64_t *counts, uint16_t *out, int32_t *st) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
-         p += (int64_t)gridDim.x * blockDim.x) {
+// Lanes-layout binning, privatized: the keys are few (at most 9 x 129), so a
+// global atomic per pair would queue thousands of adds on each counter.  A
+// workgroup takes a fixed range of pairs, counts its keys in LDS and adds
+// each nonzero count to the global counter once; the scatter recounts the
+// same range, reserves each key's slots with one global add and places its
+// pairs from an LDS cursor.
+constexpr int kMaxLaneKeys = 9 * 129 + 1;
+constexpr int kBinPairsPerBlock = 8192;
+
+__global__ void __launch_bounds__(256) k_lanes_hist(const int32_t *ia, const int32_t *ib,
+                                                    int64_t np, const int32_t *lenA,
+                                                    const int32_t *lenB, int32_t na,
+                                                    int32_t nb_seq, int32_t wmax, int32_t nb,
+                                                    int64_t *counts, uint16_t *out,
+                                                    int32_t *st) {
+    __shared__ uint32_t h[kMaxLaneKeys];
+    const int nkeys = (wmax + 1) * nb;
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * kBinPairsPerBlock;
+    const int64_t p1 = min(np, p0 + kBinPairsPerBlock);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const int32_t x = ia[p], y = ib[p];
         if (!pair_ok(x, y, na, nb_seq)) {
             set_status(st, MSA_DS_INDEX);
@@ -306,22 +330,45 @@ __global__ void k_lanes_hist(const int32_t *ia, const int32_t *ib, int64_t np, c
             continue;
         }
         bool sw;
-        const int32_t key = lanes_key(lenA[x], lenB[y], wmax, nb, &sw);
-        atomicAdd((unsigned long long *)&counts[key], 1ull);
+        atomicAdd(&h[lanes_key(lenA[x], lenB[y], wmax, nb, &sw)], 1u);
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x)
+        if (h[k]) atomicAdd((unsigned long long *)&counts[k], (unsigned long long)h[k]);
 }
 
-__global__ void k_lanes_scatter(const int32_t *ia, const int32_t *ib, int64_t np,
-                                const int32_t *lenA, const int32_t *lenB, int32_t na,
-                                int32_t nb_seq, int32_t wmax, int32_t nb, int64_t *cursor,
-                                int64_t *sorted) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
-         p += (int64_t)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(256) k_lanes_scatter(const int32_t *ia, const int32_t *ib,
+                                                       int64_t np, const int32_t *lenA,
+                                                       const int32_t *lenB, int32_t na,
+                                                       int32_t nb_seq, int32_t wmax, int32_t nb,
+                                                       int64_t *cursor, int64_t *sorted) {
+    __shared__ uint32_t h[kMaxLaneKeys];
+    __shared__ int64_t base[kMaxLaneKeys];
+    const int nkeys = (wmax + 1) * nb;
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    const int64_t p0 = (int64_t)blockIdx.x * kBinPairsPerBlock;
+    const int64_t p1 = min(np, p0 + kBinPairsPerBlock);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int32_t x = ia[p], y = ib[p];
+        if (!pair_ok(x, y, na, nb_seq)) continue;
+        bool sw;
+        atomicAdd(&h[lanes_key(lenA[x], lenB[y], wmax, nb, &sw)], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nkeys; k += blockDim.x) {
+        base[k] = h[k] ? (int64_t)atomicAdd((unsigned long long *)&cursor[k],
+                                            (unsigned long long)h[k])
+                       : 0;
+        h[k] = 0;
+    }
+    __syncthreads();
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const int32_t x = ia[p], y = ib[p];
         if (!pair_ok(x, y, na, nb_seq)) continue;
         bool sw;
         const int32_t key = lanes_key(lenA[x], lenB[y], wmax, nb, &sw);
-        const int64_t pos = (int64_t)atomicAdd((unsigned long long *)&cursor[key], 1ull);
+        const int64_t pos = base[key] + atomicAdd(&h[key], 1u);
         sorted[pos] = p | ((int64_t)sw << kSwapBit);
     }
 }
@@ -359,7 +406,7 @@ __global__ void k_lanes_items(const int64_t *start, int32_t wmax, int32_t nb, It
 // ------------------------------------------------------------ host side
 #define MSADP_LEV_CLASSES(X) X(4) X(8) X(16) X(20) X(24) X(28) X(32)
 // Lanes-layout variants: (most pattern words, sigma').
-#define MSADP_LANES_CLASSES(X) X(8, 4) X(4, 8) X(1, 32)
+#define MSADP_LANES_CLASSES(X) X(8, 2) X(4, 8) X(1, 32)
 
 enum { kAllPairsKernel = 0, kGroupedKernel = 1, kLanesKernel = 2 };
 
@@ -446,8 +493,8 @@ static bool same_set(const msa_seqs *A, const msa_seqs *B) {
 // The lanes variant for the alphabet, and whether patterns of up to the
 // longer set's max_len fit it.
 static bool lanes_fit(const msa_seqs *A, const msa_seqs *B, int *wmax, int *sp) {
-    *sp = A->sigma <= 4 ? 4 : A->sigma <= 8 ? 8 : 32;
-    *wmax = 32 / *sp;
+    *sp = A->sigma <= 4 ? 2 : A->sigma <= 8 ? 8 : 32;   // 2: bit planes
+    *wmax = A->sigma <= 4 ? 8 : 32 / *sp;
     return std::max(A->max_len, B->max_len) <= 64 * *wmax;
 }
 
@@ -613,7 +660,7 @@ static int run_lanes(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, co
     if ((rc = stage_set(A, nullptr, w.SA, d_status, s))) return rc;
     if (!same_set(A, B) && (rc = stage_set(B, nullptr, w.SB, d_status, s))) return rc;
     if ((rc = fill_i64(w.counts, nkeys + 1, 0, s))) return rc;
-    const int64_t pg = std::min<int64_t>((n_pairs + 255) / 256, 8192);
+    const int64_t pg = (n_pairs + kBinPairsPerBlock - 1) / kBinPairsPerBlock;
     hipLaunchKernelGGL(k_lanes_hist, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs,
                        w.SA.len, w.SB.len, A->n, B->n, wmax, nb, w.counts, dist, d_status);
     if ((rc = exclusive_scan_i64(w.counts, nkeys + 1, s))) return rc;

@@ -188,6 +188,134 @@ __device__ __forceinline__ void build_lane_peq(uint64_t *tbl, const uint8_t *pat
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Two-bit alphabets (sigma <= 4): a lane's pattern as two bit planes per
+// word instead of four match masks (half the LDS, so twice the wavefronts
+// per CU).  tbl[k * kWave + lane] = (plane 0 lo, hi, plane 1 lo, hi) of word
+// k, plane b holding bit b of each row's symbol.  Built in registers: the
+// bit b of the four symbols of a dword is gathered into four adjacent bits
+// by one multiply (bits at 0, 8, 16, 24 times 2^28 + 2^21 + 2^14 + 2^7 land
+// at 28 .. 31 with no carries between the partial products).
+__device__ __forceinline__ void build_lane_planes(uint4 *tbl, const uint8_t *pat, int m, int nw) {
+    const int lane = lane_id();
+    const uint4 *pp = (const uint4 *)pat;
+    for (int k = 0; k < nw; ++k) {
+        uint32_t p0l = 0, p0h = 0, p1l = 0, p1h = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int chunk = k * 4 + q;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (chunk * 16 < m) v = pp[chunk];
+            const uint32_t d4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t b0 = ((d4[w] & 0x01010101u) * 0x10204080u) >> 28;
+                const uint32_t b1 = (((d4[w] >> 1) & 0x01010101u) * 0x10204080u) >> 28;
+                const int sh = 4 * ((q * 4 + w) & 7);   // row 4 (4q + w) within its half
+                if (q < 2) {
+                    p0l |= b0 << sh;
+                    p1l |= b1 << sh;
+                } else {
+                    p0h |= b0 << sh;
+                    p1h |= b1 << sh;
+                }
+            }
+        }
+        tbl[k * kWave + lane] = make_uint4(p0l, p0h, p1l, p1h);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(3))) u32x4 lds_u128;
+
+// lev_pass for a lane's bit-plane table (first and only pass; see lev_pass).
+// The match mask of symbol t is (P0 ^ m0) & (P1 ^ m1) with mb = all ones
+// where bit b of t is 0.
+template <int W>
+__device__ __forceinline__ int lev_pass_planes(lds_u128 *tbl, const uint8_t *text, int n,
+                                               int nmax, int b) {
+    constexpr uint8_t kAndXor = MSADP_LUT(A & (B ^ C));
+    uint32_t pl[W], ph[W], ml[W], mh[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        pl[k] = ph[k] = ~0u;
+        ml[k] = mh[k] = 0u;
+    }
+    int score = 0;
+    const uint4 *tp = (const uint4 *)text;
+    uint4 cur = tp[0];
+    for (int j0 = 0; j0 < nmax; j0 += 16) {
+        uint4 nxt = cur;
+        if (j0 + 16 < nmax) nxt = tp[(j0 >> 4) + 1];
+        uint32_t c0 = cur.x, c1 = cur.y, c2 = cur.z, c3 = cur.w;
+        const int steps = (int)uniform((uint32_t)min(16, nmax - j0));
+        for (int jj = 0; jj < steps; ++jj) {
+            const uint32_t t = c0 & 0xFFu;
+            c0 = __builtin_amdgcn_alignbyte(c1, c0, 1);
+            c1 = __builtin_amdgcn_alignbyte(c2, c1, 1);
+            c2 = __builtin_amdgcn_alignbyte(c3, c2, 1);
+            c3 >>= 8;
+            const uint32_t m0 = (t & 1u) - 1u, m1 = ((t >> 1) & 1u) - 1u;
+            uint32_t cph = 1u << 31, cmh = 0u;   // top row: +1
+            uint32_t dp = 0, dn = 0;
+            u32x4 q0 = tbl[0], q1 = {0u, 0u, 0u, 0u};
+            if (W > 1) q1 = tbl[kWave];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const u32x4 q = (k & 1) ? q1 : q0;
+                if (k + 2 < W) {
+                    if (k & 1) q1 = tbl[(k + 2) * kWave];
+                    else q0 = tbl[(k + 2) * kWave];
+                }
+                const uint32_t el = bop3<kAndXor>(q.x ^ m0, q.z, m1);
+                const uint32_t eh = bop3<kAndXor>(q.y ^ m0, q.w, m1);
+                const uint32_t elm = el | (cmh >> 31);
+                const uint32_t xvl = el | ml[k], xvh = eh | mh[k];
+                unsigned int cy, cy2;
+                const uint32_t sl = __builtin_addc(elm & pl[k], pl[k], 0u, &cy);
+                const uint32_t sh = __builtin_addc(eh & ph[k], ph[k], cy, &cy2);
+                const uint32_t xhl = bop3<Lut::XOR_OR>(sl, pl[k], elm);
+                const uint32_t xhh = bop3<Lut::XOR_OR>(sh, ph[k], eh);
+                const uint32_t phl = bop3<Lut::PH>(xhl, pl[k], ml[k]);
+                const uint32_t phh = bop3<Lut::PH>(xhh, ph[k], mh[k]);
+                const uint32_t mhl = pl[k] & xhl, mhh = ph[k] & xhh;
+                if (k == W - 1) {
+                    const uint64_t P = ((uint64_t)phh << 32) | phl;
+                    const uint64_t M = ((uint64_t)mhh << 32) | mhl;
+                    dp = (uint32_t)(P >> b) & 1u;
+                    dn = (uint32_t)(M >> b) & 1u;
+                }
+                const uint32_t Phl = shl1_carry(phl, cph), Phh = shl1_carry(phh, phl);
+                const uint32_t Mhl = shl1_carry(mhl, cmh), Mhh = shl1_carry(mhh, mhl);
+                cph = phh;
+                cmh = mhh;
+                pl[k] = bop3<Lut::PV>(Mhl, xvl, Phl);
+                ph[k] = bop3<Lut::PV>(Mhh, xvh, Phh);
+                ml[k] = Phl & xvl;
+                mh[k] = Phh & xvh;
+                asm volatile("" : "+v"(cph), "+v"(cmh), "+v"(pl[k]), "+v"(ph[k]), "+v"(ml[k]),
+                             "+v"(mh[k]));
+            }
+            score += (j0 + jj < n) ? (int)dp - (int)dn : 0;
+        }
+        cur = nxt;
+    }
+    return score;
+}
+
+template <int WMAX, int W = 1>
+__device__ __forceinline__ int dispatch_planes(int w, lds_u128 *tbl, const uint8_t *text, int n,
+                                               int nmax, int b) {
+    if constexpr (W > WMAX) {
+        return 0;
+    } else {
+        if (w == W) return lev_pass_planes<W>(tbl, text, n, nmax, b);
+        return dispatch_planes<WMAX, W + 1>(w, tbl, text, n, nmax, b);
+    }
+}
+
 template <int WMAX, int SP, int W = 1>
 __device__ __forceinline__ int dispatch_lanes(int w, lds_u64 *tbl, const uint8_t *text, int n,
                                               int nmax, int b) {

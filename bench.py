@@ -3,11 +3,16 @@
 One step = one lev_allpairs call over the whole set (8,386,560 pairs): length
 binning, staging and the persistent bit-parallel kernel.  Inputs are
 resident on the GPU before the timed region starts; the launch variant is
-autotuned before it.  Further legs, reported in the same JSON line: the
-512-pair NW fill + traceback ("nw"), the exact tree build of 20,000 protein
-sequences ("tree": autotuned, graph-replayed levels) and the learned pruning
-of the tree build on 100,000 sequences ("pruned": embedder training, exact
-vs pruned build time, teacher-forced agreement, control rankers).
+autotuned before it.  Further legs, reported in the same JSON line: pair
+lists through lev_batch ("pairs": the 2 M training labels of the learned
+workload and 8.4 M random pairs of the all-pairs set), the 512-pair NW fill
++ traceback ("nw"), the same pairs under an affine-gap score matrix
+("gotoh") and by the exact banded distance ("band"), the exact tree build of
+20,000 protein sequences ("tree": autotuned, graph-replayed levels), the
+learned pruning of the tree build on 100,000 sequences ("pruned": embedder
+training, exact vs pruned build time, teacher-forced agreement, control
+rankers, alignment quality of the pruned trees' alignments) and the
+alignment-quality metrics ("quality") and machine rates ("machine").
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
@@ -36,13 +41,36 @@ VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2 * 2.4e9
 K_REF = 32
 LEV_PEAK_TCUPS = VALU_PEAK_LANE_OPS * 64 / K_REF / 1e12
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch from rocprofv3 FETCH_SIZE (x2, the factor a plain 1 GiB
-# copy shows) + WRITE_SIZE on these workloads (profiles/k_lev_allpairs_dna4096.md,
-# profiles/k_nw_fill_dna512.md), by launch variant; None for a variant not measured.
-LEV_TRAFFIC = {16: 11297.3e3 * 1024, 20: 4331.5e3 * 1024, 24: 2176.4e3 * 1024,
-               28: 2086.9e3 * 1024, 32: 2091.1e3 * 1024}
-NW_FILL_TRAFFIC = {16: (2 * 4733 + 7885300) * 1024, 32: (2 * 6616 + 7974700) * 1024,
-                   64: (2 * 242080 + 8268300) * 1024}
+# HBM traffic of a kernel comes from rocprofv3 counter runs recorded in
+# profiles/counters.json (FETCH_SIZE x its copy-calibration factor +
+# WRITE_SIZE, per launch), each entry stamped with a hash of the kernel's
+# source files; it is reported only while those files are unchanged.
+COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted(kernel, variant=None):
+    """The recorded counter entry of a kernel (and launch variant) if its
+    sources are unchanged since the counters were taken, else None."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except OSError:
+        return None
+    e = c.get(kernel)
+    if e is None or source_hash(e["sources"]) != e["source_hash"]:
+        return None
+    if variant is not None:
+        return e.get("variants", {}).get(str(variant))
+    return e
 
 
 def parse():
@@ -52,9 +80,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="nw,tree,pruned,quality,machine",
-                    help="legs after the all-pairs one: any of nw, tree, pruned, quality, "
-                         "machine (comma list)")
+    ap.add_argument("--legs", default="pairs,nw,gotoh,band,tree,pruned,quality,machine",
+                    help="legs after the all-pairs one: any of pairs, nw, gotoh, band, tree, "
+                         "pruned, quality, machine (comma list)")
     ap.add_argument("--quick", action="store_true", help="only the all-pairs leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
@@ -158,6 +186,9 @@ def main():
     ms = float(np.mean(call_ms))
     ap.st.check("lev_allpairs")
     tcups = cells / (ms * 1e-3) / 1e12
+    chosen = tuning["chosen"] if tuning else 32
+    ce = counted("k_lev_allpairs", chosen)
+    traffic = ce["hbm_bytes"] if ce else None
     res = {
         "metric": METRIC,
         "value": round(cells / (wall / args.steps) / 1e9, 1),
@@ -174,11 +205,22 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(tcups, 2),
                      "peak": round(LEV_PEAK_TCUPS, 1), "unit": "Tcell/s",
                      "frac": round(tcups / LEV_PEAK_TCUPS, 4),
-                     "traffic": LEV_TRAFFIC.get(tuning["chosen"] if tuning else 32),
-                     "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3)},
+                     "traffic": traffic,
+                     "kernel": "k_lev_allpairs", "call_ms_mean": round(ms, 3),
+                     "peak_basis": "32 VALU lane-ops per 64-cell word step at 78.6 T "
+                                   "lane-ops/s (dual issue)"},
     }
+    if ce and ce.get("valu_insts"):
+        # the chip's own count: VALU instructions x 64 lanes over the call
+        lane_ops = ce["valu_insts"] * 64 / (ms * 1e-3) / 1e12
+        res["roofline"]["counted_valu"] = {
+            "lane_ops_per_s": round(lane_ops, 2), "unit": "T/s",
+            "frac_of_78.6": round(lane_ops / (VALU_PEAK_LANE_OPS / 1e12), 4),
+            "valu_per_word_step": ce.get("valu_per_word_step"),
+            "dual_issue_share": ce.get("valu2_share")}
     legs = [] if args.quick else [x for x in args.legs.split(",") if x]
-    for name, fn in (("nw", bench_nw), ("tree", bench_tree), ("pruned", bench_pruned),
+    for name, fn in (("pairs", bench_pairs), ("nw", bench_nw), ("gotoh", bench_gotoh),
+                     ("band", bench_band), ("tree", bench_tree), ("pruned", bench_pruned),
                      ("quality", bench_quality), ("machine", bench_machine)):
         if name in legs:
             try:
@@ -360,8 +402,113 @@ def bench_nw(msadp, synth, torch, args):
             "roofline": {"bound": "hbm", "achieved": round(tb_bytes / f / 1e6, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(tb_bytes / f / 1e6 / HBM_PEAK_GBS, 4),
-                         "traffic": NW_FILL_TRAFFIC.get(tuning["chosen"] if tuning else 32),
+                         "traffic": (counted("k_nw_fill", tuning["chosen"] if tuning else 32)
+                                     or {}).get("hbm_bytes"),
                          "kernel": "k_nw_fill"}}
+
+
+def bench_pairs(msadp, synth, torch, args):
+    """Pair lists through lev_batch, layout autotuned: the 2,000,000 training
+    pairs of the learned workload (100,000 DNA sequences of 100-500, about 20
+    pairs per sequence: one pattern per lane) and 8,386,560 random pairs of
+    the all-pairs set (about 2,000 per sequence: shared patterns)."""
+    from paper_2601_15458_amd import learned
+    stream = torch.cuda.current_stream()
+    out = {}
+    work = []
+    d = synth.learned()
+    S = msadp.to_device(d["codes"], d["offsets"], d["sigma"])
+    ia, ib = learned.sample_pairs(d["family"], 2_000_000, seed=11)
+    work.append(("labels", "2,000,000 training pairs (50 % within-family) of 100,000 DNA "
+                 "seqs, lengths 100-500, seed 5/11", S, ia, ib, np.diff(d["offsets"])))
+    a = synth.allpairs()
+    n = a["n"]
+    A = msadp.to_device(a["codes"], a["offsets"], a["sigma"])
+    rng = np.random.default_rng(8)
+    np_ = n * (n - 1) // 2
+    work.append(("random_allpairs_set", "8,386,560 uniform random pairs of the 4096 DNA seqs "
+                 "(lengths 1000-1600), seed 2/8", A, rng.integers(0, n, np_).astype(np.int32),
+                 rng.integers(0, n, np_).astype(np.int32), np.diff(a["offsets"])))
+    for name, desc, X, xa, xb, L in work:
+        lb = msadp.LevBatch(X, X, xa, xb)
+        best, _ = msadp.autotune_pairs(lb, reps=2, stream=stream)
+        ms = _time_calls(torch, lambda: lb(stream), stream, max(args.steps, 3))
+        lb.st.check("lev_batch")
+        cells = float((L[xa].astype(np.float64) * L[xb]).sum())
+        tc = cells / (ms * 1e-3) / 1e12
+        out[name] = {"workload": desc, "pairs": int(len(xa)), "cells": cells,
+                     "layout": {1: "one pattern per lane", 64: "shared patterns"}[best],
+                     "ms": round(ms, 3), "t_cells_per_s": round(tc, 1),
+                     "pairs_per_s": round(len(xa) / (ms * 1e-3), 1),
+                     "frac_of_157.3": round(tc / LEV_PEAK_TCUPS, 4)}
+        _log(f"pairs {name}: {ms:.2f} ms, {tc:.1f} T cells/s ({out[name]['layout']})")
+        del lb
+    return out
+
+
+def _dna_scores():
+    """Stand-in nucleotide matrix (+5 match, -4 mismatch): the paper's
+    extended-IUPAC table is not available here."""
+    return np.where(np.eye(4, dtype=bool), 5, -4).astype(np.int32)
+
+
+def bench_gotoh(msadp, synth, torch, args):
+    """The 512 long DNA pairs under the cost model of Sec. 2.4: a substitution
+    matrix (stand-in) and affine gaps with opening ten times the extension
+    (open 10, extension 1): fill (one code byte per cell) and traceback."""
+    d = synth.nw_long()
+    P = d["n_pairs"]
+    A = msadp.to_device(d["a_codes"], d["a_offsets"], 4)
+    B = msadp.to_device(d["b_codes"], d["b_offsets"], 4)
+    g = msadp.GotohBatch(A, B, np.arange(P), np.arange(P), _dna_scores(), 10, 1)
+    stream = torch.cuda.current_stream()
+    g.fill(stream)
+    g.traceback(stream)
+    torch.cuda.synchronize()
+    g.st.check("gotoh")
+    la = np.diff(d["a_offsets"])
+    lb = np.diff(d["b_offsets"])
+    cells = int((la * lb).sum())
+    reps = max(args.steps, 3)
+    f = _time_calls(torch, lambda: g.fill(stream), stream, reps)
+    t = _time_calls(torch, lambda: g.traceback(stream), stream, reps)
+    tb = int(sum(msadp.lib().gotoh_tb_bytes(int(a), int(b)) for a, b in zip(la, lb)))
+    return {"workload": "gotoh_batch+gotoh_traceback: 512 DNA pairs, lengths U{5000..10000}, "
+                        "10% divergence, +5/-4 matrix, open 10, extension 1, seed 4",
+            "cells": cells, "fill_ms": round(f, 3), "traceback_ms": round(t, 3),
+            "fill_gcups": round(cells / f / 1e6, 1),
+            "gcups_fill_plus_traceback": round(cells / (f + t) / 1e6, 1),
+            "tb_bytes": tb, "fill_hbm_gbs": round(tb / f / 1e6, 1)}
+
+
+def bench_band(msadp, synth, torch, args):
+    """Exact banded Levenshtein (lev_band) on the 512 long DNA pairs, against
+    the full-matrix fill of the same pairs: effective GCUPS = all m x n cells
+    over the banded time."""
+    d = synth.nw_long()
+    P = d["n_pairs"]
+    A = msadp.to_device(d["a_codes"], d["a_offsets"], 4)
+    B = msadp.to_device(d["b_codes"], d["b_offsets"], 4)
+    la = np.diff(d["a_offsets"])
+    lb = np.diff(d["b_offsets"])
+    cells = int((la * lb).sum())
+    stream = torch.cuda.current_stream()
+    reps = max(args.steps, 3)
+    out = {"workload": "lev_band: 512 DNA pairs, lengths U{5000..10000}, 10% divergence, "
+                       "seed 4", "cells": cells, "by_k0": {}}
+    for k0 in (256, 2048):
+        band = msadp.LevBand(A, B, np.arange(P), np.arange(P), k0, 4000)
+        band(stream)
+        ms = _time_calls(torch, lambda: band(stream), stream, reps)
+        band.st.check("lev_band")
+        ku = band.k_used[:P].cpu().numpy()
+        out["by_k0"][k0] = {"ms": round(ms, 3), "effective_gcups": round(cells / ms / 1e6, 1),
+                            "k_used_max": int(ku.max()), "verified": int((ku > 0).sum())}
+    nb = msadp.NwBatch(A, B, np.arange(P), np.arange(P))
+    full = _time_calls(torch, lambda: nb.fill(stream), stream, reps)
+    out["full_matrix_fill_ms"] = round(full, 3)
+    out["full_matrix_gcups"] = round(cells / full / 1e6, 1)
+    return out
 
 
 def tree_cells(t, L):
@@ -467,16 +614,45 @@ def bench_pruned(msadp, synth, torch, args):
     mae, rel = learned.pair_error(emb, S, ha, hb, hdist)
     _log(f"trained in {t_train:.1f} s, held-out MAE {mae:.2f} edits ({rel:.4f} rel); "
          "exact build")
-    # both builds replay each level from a HIP graph on their own stream
+    # both builds replay each level from a HIP graph on their own stream, and
+    # both are timed the same way: one warm-up build, then the median of
+    # timed builds (device tree; the host copy is outside the timing)
     stream = torch.cuda.Stream()
     exact_b = msadp.TreeBuilder(S, use_graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    times = []
     with torch.cuda.stream(stream):
-        exact = exact_b(stream).host()
-    torch.cuda.synchronize()
-    t_exact = time.perf_counter() - t0
+        exact_dev = exact_b(stream)
+        torch.cuda.synchronize()
+        for _ in range(max(1, min(args.steps, 2))):
+            t0 = time.perf_counter()
+            exact_dev = exact_b(stream)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
     exact_b.st.check("tree_build")
+    t_exact = float(np.median(times))
+    exact = exact_dev.host()
+    # alignment quality (Sec. 2.3 metrics) of the exact tree's alignment on a
+    # seeded 10,000-row subsample, as the paper measures large alignments
+    sub = np.sort(np.random.default_rng(15).choice(d["n"], 10_000, replace=False))
+    sub_d = synth.subset(d, sub)
+    S_sub = msadp.to_device(sub_d["codes"], sub_d["offsets"], sub_d["sigma"])
+    lev_sub = msadp.lev_allpairs(S_sub)
+    max_len_sub = int(np.diff(sub_d["offsets"]).max())
+
+    def msa_quality_of(tree_dev):
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            msa = msadp.msa_merge(S, tree_dev, stream=stream)
+        t_merge = time.perf_counter() - t0
+        Q = msadp.Quality(msa[sub], d["sigma"])
+        q = Q.metrics(Q.pair_counts(), max_len_sub, lev=lev_sub)
+        q = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in q.items()}
+        q["width"] = int(msa.shape[1])
+        q["merge_s"] = round(t_merge, 3)
+        return q
+
+    exact_quality = msa_quality_of(exact_dev)
+    _log(f"exact tree alignment: {exact_quality}")
     _log(f"exact build {t_exact:.2f} s ({exact['n_nodes']} nodes); pruned builds")
     out = {"workload": "tree build: 100,000 DNA seqs (1,000 families x 100, mutate d=0.30, "
                        "lengths 100-500, seed 5)",
@@ -487,7 +663,9 @@ def bench_pruned(msadp, synth, torch, args):
            "embed_s": round(t_embed, 3), "heldout_mae_edits": round(mae, 3),
            "cnn": cnn_rates(learned, d, losses, t_train, positions, t_embed),
            "heldout_rel_err": round(rel, 4), "exact_build_s": round(t_exact, 3),
-           "exact_nodes": int(exact["n_nodes"])}
+           "exact_nodes": int(exact["n_nodes"]),
+           "alignment_quality": {"rows": "seeded 10,000-row subsample (seed 15), all pairs",
+                                 "exact_tree": exact_quality}}
     off, ca, cb, corr = learned.calibrate(emb, S, d["family"])
     _log(f"calibration on within-family pairs: y = {ca:.3f} + {cb:.4f} y_hat "
          f"(corr {corr:.3f}) -> offset {off:.3f}")
@@ -515,6 +693,7 @@ def bench_pruned(msadp, synth, torch, args):
                 raise ValueError(f"unknown ranker {name!r} (one of {sorted(rankers)})")
             points.append((name, int(topk), int(eb)))
     out["points"] = []
+    quality_points = {("cnn", args.topk, 0), ("cnn", 96, 0), ("shortest", 96, 0)}
     for name, topk, eb in points:
         e, eo = rankers[name]
         b = msadp.TreeBuilder(S, use_graph=True, emb=e, topk=topk, exact_below=eb,
@@ -529,6 +708,9 @@ def bench_pruned(msadp, synth, torch, args):
                 torch.cuda.synchronize()
                 times.append(time.perf_counter() - t0)
         b.st.check("tree_build_pruned")
+        quality = None
+        if (name, topk, eb) in quality_points:
+            quality = msa_quality_of(t)
         t = t.host()
         clr = msadp.tree_eval_centers(S, exact, emb=e, topk=topk, exact_below=eb, emb_offset=eo)
         agree = learned.agreement(exact, clr, min_size=17, pruned_above=max(topk, eb))
@@ -541,7 +723,7 @@ def bench_pruned(msadp, synth, torch, args):
                               "agreement": agree, "reproduced_clusters": round(rep, 4),
                               "center_differs": nd, "rowsum_excess_mean": round(ex_mean, 6),
                               "rowsum_excess_max": round(ex_max, 6),
-                              "nodes": int(t["n_nodes"])})
+                              "nodes": int(t["n_nodes"]), "alignment_quality": quality})
         _log(f"{name} topk={topk} exact_below={eb}: build {tp:.3f} s, speedup "
              f"{t_exact / tp:.1f}x, agreement {agree}, reproduced {rep:.4f}, "
              f"excess over {nd} differing centers mean {ex_mean:.2e} max {ex_max:.2e}")

@@ -23,6 +23,9 @@
  *   - Alg. 1 (Partition) with the full geometric median (Sec. 2.1), and
  *     the same with the median taken over candidates that a learned
  *     embedding ranks first (a surrogate of this project, not the paper's).
+ *   - Insertion of new sequences into an existing tree (Sec. 5 names it
+ *     as future work; the routing and re-partition rules are this
+ *     project's reading, stated at orc_tree_insert).
  *   - The bottom-up merge of Sec. 2.2.
  *   - The column counts behind the alignment-quality metrics of Sec. 2.3
  *     (gaps per row; per pair of rows the Hamming distance, the columns
@@ -523,6 +526,179 @@ int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
                  int64_t *mstart, int64_t *mcount, int32_t *perm) {
     return tree_impl(codes, off, n, NULL, 0, 0, 0, parent, left, right, center, lpole, rpole, depth,
                      mstart, mcount, perm);
+}
+
+/* ------------------------------------------------------- online insertion
+ * Sec. 5 names adding new sequences to an existing clustering, guide tree
+ * and alignment as future work and gives no procedure.  This project's
+ * reading, kept as close to Alg. 1 as an update can be:
+ *   1. Routing.  A new sequence x starts at the root.  At an internal node
+ *      with poles l and r it goes to the left child if f(l, x) <= f(r, x)
+ *      and to the right child otherwise (the split rule of Alg. 1), down to
+ *      a leaf.  Internal nodes keep their center and poles.
+ *   2. Re-partition.  Every leaf that receives new sequences is replaced by
+ *      Alg. 1 (full median, same tie rules) run on its old members and its
+ *      new ones together; leaves that receive none stay as they are.
+ *   3. Numbering.  The result is renumbered breadth-first from the root
+ *      (a level's children after the level, in the order of their parents,
+ *      L before R), so the node table reads like one built by Alg. 1:
+ *      depth from the root, a node's member range its L child's range
+ *      followed by its R child's.
+ * The alignment of the updated set is the merge of Sec. 2.2 along the
+ * updated tree (orc_merge).
+ *
+ * Sequences 0 .. n_old-1 are the ones the tree `in_*` (n_nodes_old nodes,
+ * perm over n_old positions) was built on; n_old .. n-1 are new.  Output
+ * arrays hold up to 2n - 1 nodes and n perm entries.  Returns the node
+ * count, or -1 on bad input. */
+typedef struct {
+    int32_t left, right, center, lpole, rpole;
+    int32_t *mem;       /* members of a leaf, in range order */
+    int64_t nmem;
+} ins_node;
+
+static void ins_grow(ins_node **nodes, int64_t *cap, int64_t need) {
+    if (need <= *cap) return;
+    int64_t c = *cap ? *cap : 16;
+    while (c < need) c *= 2;
+    *nodes = (ins_node *)realloc(*nodes, sizeof(ins_node) * (size_t)c);
+    *cap = c;
+}
+
+int32_t orc_tree_insert(const uint8_t *codes, const int64_t *off, int32_t n, int32_t n_old,
+                        int32_t n_nodes_old, const int32_t *in_left, const int32_t *in_right,
+                        const int32_t *in_center, const int32_t *in_lpole,
+                        const int32_t *in_rpole, const int64_t *in_mstart,
+                        const int64_t *in_mcount, const int32_t *in_perm,
+                        int32_t *parent, int32_t *left, int32_t *right, int32_t *center,
+                        int32_t *lpole, int32_t *rpole, int32_t *depth,
+                        int64_t *mstart, int64_t *mcount, int32_t *perm) {
+    if (n_old < 1 || n < n_old || n_nodes_old < 1 || n_nodes_old > 2 * n_old - 1) return -1;
+    int64_t cap = 0, nn = n_nodes_old;
+    ins_node *T = NULL;
+    ins_grow(&T, &cap, nn);
+    for (int32_t v = 0; v < n_nodes_old; ++v) {
+        T[v].left = in_left[v];
+        T[v].right = in_right[v];
+        T[v].center = in_center[v];
+        T[v].lpole = in_lpole[v];
+        T[v].rpole = in_rpole[v];
+        T[v].mem = NULL;
+        T[v].nmem = 0;
+        if (in_left[v] < 0) {
+            T[v].nmem = in_mcount[v];
+            T[v].mem = (int32_t *)malloc(sizeof(int32_t) * (size_t)(in_mcount[v] + (n - n_old)));
+            for (int64_t i = 0; i < in_mcount[v]; ++i) T[v].mem[i] = in_perm[in_mstart[v] + i];
+        }
+    }
+    /* 1. routing: new members are appended to their leaf in index order */
+    for (int32_t x = n_old; x < n; ++x) {
+        int32_t v = 0;
+        for (int64_t steps = 0; T[v].left >= 0; ++steps) {
+            if (steps > n_nodes_old) return -1;
+            const int64_t dl = dist_of(codes, off, T[v].lpole, x);
+            const int64_t dr = dist_of(codes, off, T[v].rpole, x);
+            v = dl <= dr ? T[v].left : T[v].right;
+        }
+        T[v].mem[T[v].nmem++] = x;
+    }
+    /* 2. re-partition every leaf that grew: Alg. 1 on its members (sorted,
+     * so that the lowest-index tie rule is the same on the subset) */
+    for (int32_t v = 0; v < n_nodes_old; ++v) {
+        if (T[v].left >= 0 || T[v].nmem == in_mcount[v]) continue;
+        const int64_t k = T[v].nmem;
+        int32_t *C = T[v].mem;
+        for (int64_t i = 1; i < k; ++i)          /* insertion sort, ascending */
+            for (int64_t j = i; j > 0 && C[j - 1] > C[j]; --j) {
+                int32_t t = C[j]; C[j] = C[j - 1]; C[j - 1] = t;
+            }
+        int64_t tot = 0;
+        for (int64_t i = 0; i < k; ++i) tot += off[C[i] + 1] - off[C[i]];
+        uint8_t *sc = (uint8_t *)malloc((size_t)tot + 1);
+        int64_t *so = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k + 1));
+        so[0] = 0;
+        for (int64_t i = 0; i < k; ++i) {
+            const int64_t len = off[C[i] + 1] - off[C[i]];
+            memcpy(sc + so[i], codes + off[C[i]], (size_t)len);
+            so[i + 1] = so[i] + len;
+        }
+        const int64_t cs = 2 * k;
+        int32_t *sp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(7 * cs));
+        int64_t *sm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * cs));
+        int32_t *sperm = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        int32_t *s_par = sp, *s_l = sp + cs, *s_r = sp + 2 * cs, *s_c = sp + 3 * cs;
+        int32_t *s_lp = sp + 4 * cs, *s_rp = sp + 5 * cs, *s_d = sp + 6 * cs;
+        int64_t *s_ms = sm, *s_mc = sm + cs;
+        const int32_t sn = tree_impl(sc, so, (int32_t)k, NULL, 0, 0, 0, s_par, s_l, s_r, s_c,
+                                     s_lp, s_rp, s_d, s_ms, s_mc, sperm);
+        /* subtree node u > 0 becomes node base + u - 1; its root is v */
+        const int64_t base = nn;
+        ins_grow(&T, &cap, nn + sn - 1);
+        nn += sn - 1;
+        for (int32_t u = 0; u < sn; ++u) {
+            const int64_t w = u == 0 ? v : base + u - 1;
+            T[w].left = s_l[u] < 0 ? -1 : (int32_t)(base + s_l[u] - 1);
+            T[w].right = s_r[u] < 0 ? -1 : (int32_t)(base + s_r[u] - 1);
+            T[w].center = C[s_c[u]];
+            T[w].lpole = s_lp[u] < 0 ? -1 : C[s_lp[u]];
+            T[w].rpole = s_rp[u] < 0 ? -1 : C[s_rp[u]];
+            if (u > 0) { T[w].mem = NULL; T[w].nmem = 0; }
+            if (s_l[u] < 0) {
+                int32_t *mem = (int32_t *)malloc(sizeof(int32_t) * (size_t)s_mc[u]);
+                for (int64_t i = 0; i < s_mc[u]; ++i) mem[i] = C[sperm[s_ms[u] + i]];
+                if (u == 0) free(T[w].mem);
+                T[w].mem = mem;
+                T[w].nmem = s_mc[u];
+            }
+        }
+        if (sn > 1) { free(C); T[v].mem = NULL; T[v].nmem = 0; }
+        free(sc); free(so); free(sp); free(sm); free(sperm);
+    }
+    /* 3. breadth-first renumbering, then member ranges and perm */
+    int32_t *bfs = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+    int32_t *id = (int32_t *)malloc(sizeof(int32_t) * (size_t)nn);
+    int64_t head = 0, tail = 0;
+    bfs[tail++] = 0;
+    id[0] = 0;
+    parent[0] = -1;
+    depth[0] = 0;
+    while (head < tail) {
+        const int32_t j = (int32_t)head;
+        const int32_t w = bfs[head++];
+        center[j] = T[w].center;
+        lpole[j] = T[w].lpole;
+        rpole[j] = T[w].rpole;
+        left[j] = right[j] = -1;
+        if (T[w].left >= 0) {
+            const int32_t a = (int32_t)tail, b = (int32_t)tail + 1;
+            bfs[tail++] = T[w].left;
+            bfs[tail++] = T[w].right;
+            id[T[w].left] = a;
+            id[T[w].right] = b;
+            left[j] = a;
+            right[j] = b;
+            parent[a] = parent[b] = j;
+            depth[a] = depth[b] = depth[j] + 1;
+        }
+    }
+    const int32_t total = (int32_t)tail;
+    for (int32_t j = total - 1; j >= 0; --j)
+        mcount[j] = left[j] < 0 ? T[bfs[j]].nmem : mcount[left[j]] + mcount[right[j]];
+    mstart[0] = 0;
+    for (int32_t j = 0; j < total; ++j) {
+        if (left[j] >= 0) {
+            mstart[left[j]] = mstart[j];
+            mstart[right[j]] = mstart[j] + mcount[left[j]];
+        } else {
+            const ins_node *t = &T[bfs[j]];
+            for (int64_t i = 0; i < t->nmem; ++i) perm[mstart[j] + i] = t->mem[i];
+        }
+    }
+    for (int64_t w = 0; w < nn; ++w) free(T[w].mem);
+    free(T);
+    free(bfs);
+    free(id);
+    return total;
 }
 
 /* The same with the surrogate-pruned median (emb: float[n][128]). */

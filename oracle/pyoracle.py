@@ -39,6 +39,8 @@ def lib():
                                       C.c_int32, P, P, P, P]
         L.orc_tree.restype = C.c_int32
         L.orc_tree.argtypes = [P, P, C.c_int32] + [P] * 10
+        L.orc_tree_insert.restype = C.c_int32
+        L.orc_tree_insert.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32] + [P] * 18
         L.orc_tree_pruned.restype = C.c_int32
         L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_uint32, C.c_int32, C.c_int32] + [P] * 10
         L.orc_select.restype = None
@@ -183,6 +185,34 @@ def tree(codes, offsets):
     out["n_nodes"] = int(k)
     return out
 
+
+
+def tree_insert(codes, offsets, n_old, t):
+    """Online insertion (orc_tree_insert): sequences n_old.. of the set are
+    routed into the tree ``t`` built on the first n_old, the leaves they
+    reach are re-partitioned by Alg. 1, and the tree is renumbered
+    breadth-first.  Returns a tree dict over the whole set."""
+    codes = _u8(codes)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(offsets) - 1
+    k0 = int(t["n_nodes"])
+    src = {f: np.ascontiguousarray(t[f][:k0], dtype=np.int64 if f in ("mstart", "mcount")
+                                   else np.int32) for f in TREE_FIELDS}
+    src_perm = np.ascontiguousarray(t["perm"][:n_old], dtype=np.int32)
+    cap = max(2 * n - 1, 1)
+    arr = {f: np.zeros(cap, dtype=np.int64 if f in ("mstart", "mcount") else np.int32)
+           for f in TREE_FIELDS}
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    k = lib().orc_tree_insert(_p(codes), _p(offsets), n, int(n_old), k0,
+                              *[_p(src[f]) for f in ("left", "right", "center", "lpole",
+                                                     "rpole", "mstart", "mcount")],
+                              _p(src_perm), *[_p(arr[f]) for f in TREE_FIELDS], _p(perm))
+    if k < 0:
+        raise ValueError("oracle tree_insert: bad input")
+    out = {f: arr[f][:k].copy() for f in TREE_FIELDS}
+    out["perm"] = perm[:n].copy()
+    out["n_nodes"] = int(k)
+    return out
 
 def tree_pruned(codes, offsets, emb, topk=16, exact_below=0, emb_q0=0):
     """Alg. 1 with the surrogate-pruned median (emb: float32 [n, 128]);

@@ -290,6 +290,39 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                       int32_t *center, int32_t *lpole, int32_t *rpole, void *ws,
                       size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
+/* Online insertion of new sequences into a tree (Sec. 5 names online
+ * updates of the clusters, guide tree and alignment as future work and
+ * gives no procedure; the reading here).  S holds n_old sequences (inputs
+ * 0 .. n_old-1, the set T_old was built on by tree_build, n_nodes_old
+ * nodes) followed by the new ones (inputs n_old .. S->n-1).
+ *   1. Every new x starts at the root; at an internal node with poles l, r
+ *      it goes to the left child if f(l, x) <= f(r, x), else to the right
+ *      (Alg. 1's split rule), down to a leaf.  Internal nodes keep their
+ *      center and poles.
+ *   2. Each leaf that receives new sequences is replaced by Alg. 1 (the
+ *      full median, tie rules as tree_build) on its old and new members.
+ *   3. The result is renumbered breadth-first from the root (children after
+ *      their level, in parent order, L before R), with member ranges and
+ *      perm as tree_build lays them out.
+ * T_new (device, capacity 2 S->n - 1 nodes and S->n perm entries, not
+ * overlapping T_old) receives the tree of all S->n sequences and *n_nodes_new
+ * (host) its node count; msa_merge(S, T_new, ...) then aligns the grown set.
+ * Only left, right, center, lpole, rpole, mstart, mcount and perm of T_old
+ * are read.  Routing computes one lev_batch of (pole, x) pairs per tree
+ * depth and synchronizes the stream once per depth; the grown leaves are
+ * re-partitioned together by the level passes of tree_build.  Members of a
+ * leaf that holds copies of one sequence come in unspecified order.
+ * Errors: MSA_EINVAL for n_old outside [1, S->n], n_nodes_old outside
+ * [1, 2 n_old - 1], null pointers, or a child cycle in T_old; MSA_ERANGE for
+ * S->n >= 2^24; MSA_ENOSPC for a workspace below
+ * tree_insert_workspace_bytes(S, n_old, n_nodes_old).  Node or pole ids out
+ * of range in T_old set MSA_DS_INDEX (*n_nodes_new is then 0 or the tree
+ * incomplete). */
+size_t tree_insert_workspace_bytes(const msa_seqs *S, int32_t n_old, int32_t n_nodes_old);
+int tree_insert(const msa_seqs *S, int32_t n_old, const msa_tree *T_old, int32_t n_nodes_old,
+                const msa_tree *T_new, int32_t *n_nodes_new, void *ws, size_t ws_bytes,
+                int32_t *d_status, hipStream_t s);
+
 /* ------------------------------------------------------------------ */
 /* Bottom-up merge (Sec. 2.2) over a tree from tree_build (T, n_nodes as
  * returned).  A leaf's alignment is its sequence.  For an internal node the

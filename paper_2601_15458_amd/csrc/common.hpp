@@ -111,5 +111,15 @@ int lev_batch_impl(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, cons
 size_t lev_batch_ws_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs, bool untuned);
 // The tuning table's value for (kind, sigma, bin), or `fallback` (tune.hip).
 int tuned_value(int kind, int sigma, int bin, int fallback);
+// K disjoint root clusters for a tree build: cluster f holds the input
+// indices mem[start[f] .. start[f+1]), m = start[K] in all (tree.hip).
+struct Forest {
+    int32_t K;
+    const int32_t *mem;
+    const int64_t *start;
+    int64_t m;
+};
+int tree_build_forest(const msa_seqs *S, const Forest &fr, const msa_tree *T, int32_t *n_nodes,
+                      void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
 }  // namespace msadp

@@ -423,6 +423,30 @@ __global__ void k_tree_root(TreeArgs a) {
     a.desc[2] = 0;
 }
 
+// Level 0 of a forest: K root clusters whose members (input indices) fill
+// positions fstart[f] .. fstart[f+1) of mem, one cluster after another.
+__global__ void __launch_bounds__(256) k_forest_root(TreeArgs a, int32_t K, const int32_t *mem,
+                                                    const int64_t *fstart, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) {
+        const int32_t x = mem[i];
+        const bool ok = x >= 0 && x < a.n;
+        if (!ok) set_status(a.st, MSA_DS_INDEX);
+        a.perm[i] = a.rank_of[ok ? x : 0];
+    }
+    if (i < K) {
+        a.parent[i] = -1;
+        a.depth[i] = 0;
+        a.mstart[i] = fstart[i];
+        a.mcount[i] = fstart[i + 1] - fstart[i];
+    }
+    if (i == 0) {
+        a.desc[0] = 0;
+        a.desc[1] = K;
+        a.desc[2] = 0;
+    }
+}
+
 __global__ void k_rank_of(const int32_t *order, int32_t n, int32_t *rank_of, int32_t *perm) {
     const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -1065,6 +1089,12 @@ static int quantize_embeddings(const TreeArgs &a, hipStream_t s) {
 
 using namespace msadp;
 
+static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
+                      int32_t exact_below, const msa_tree *T,
+                      int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
+                      int32_t *d_status, hipStream_t s, int forced,
+                      const Forest *fr = nullptr);
+
 extern "C" {
 
 size_t tree_workspace_bytes(const msa_seqs *S) {
@@ -1077,7 +1107,8 @@ size_t tree_workspace_bytes(const msa_seqs *S) {
 static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
                       int32_t exact_below, const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
-                      int32_t *d_status, hipStream_t s, int forced) {
+                      int32_t *d_status, hipStream_t s, int forced,
+                      const Forest *fr) {
     int rc;
     if ((rc = check_seqs(S))) return rc;
     if (T == nullptr || n_nodes == nullptr) return MSA_EINVAL;
@@ -1142,7 +1173,15 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     if ((rc = stage_set(S, order, a.S, d_status, s))) return rc;
     hipLaunchKernelGGL(k_rank_of, dim3((S->n + 255) / 256), dim3(256), 0, s, order, S->n, rank_of,
                        a.perm);
-    hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, a);
+    int32_t total = 1;
+    if (fr == nullptr) {
+        hipLaunchKernelGGL(k_tree_root, dim3(1), dim3(1), 0, s, a);
+    } else {
+        const int64_t span = std::max<int64_t>(fr->m, fr->K);
+        hipLaunchKernelGGL(k_forest_root, dim3((unsigned)((span + 255) / 256)), dim3(256), 0, s,
+                           a, fr->K, fr->mem, fr->start, fr->m);
+        total = fr->K;
+    }
     if ((rc = launch_status())) return rc;
     if ((rc = quantize_embeddings(a, s))) return rc;
 
@@ -1158,8 +1197,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
             return MSA_EDEVICE;
         }
     }
-    int32_t total = 1;
-    int32_t host_desc[3] = {0, 1, 0};
+    int32_t host_desc[3] = {0, total, 0};
     rc = MSA_OK;
     for (int level = 0; level < S->n; ++level) {
         if (use_graph) {
@@ -1370,3 +1408,15 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
 }
 
 }  // extern "C"
+
+// Alg. 1 on each of K disjoint member lists at once (the full median): the
+// same level passes as tree_build, started from K roots.  Node ids are
+// breadth-first over the forest (roots 0 .. K-1).  T holds up to 2m nodes
+// and S->n perm entries (the first m are the forest's, as input indices).
+int msadp::tree_build_forest(const msa_seqs *S, const Forest &fr, const msa_tree *T,
+                             int32_t *n_nodes, void *ws, size_t ws_bytes, int32_t *d_status,
+                             hipStream_t s) {
+    if (fr.K < 1 || fr.m < fr.K || fr.m > S->n || fr.mem == nullptr || fr.start == nullptr)
+        return MSA_EINVAL;
+    return build_impl(S, nullptr, 0, 0, 0, T, n_nodes, 0, ws, ws_bytes, d_status, s, 0, &fr);
+}

@@ -68,6 +68,9 @@ SIGNATURES = {
                                     C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
     "tree_eval_centers": (C.c_int, [SP, P, C.c_uint32, C.c_int32, C.c_int32, P, C.c_int32, P,
                                     P, P, P, C.c_size_t, P, P]),
+    "tree_insert_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32]),
+    "tree_insert": (C.c_int, [SP, C.c_int32, P, C.c_int32, P, C.POINTER(C.c_int32), P,
+                              C.c_size_t, P, P]),
     "msa_merge_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32, C.c_size_t]),
     "msa_merge": (C.c_int, [SP, P, C.c_int32, C.c_int32, C.c_size_t, P, C.c_int64,
                             C.POINTER(C.c_int32), P, C.c_size_t, P, P]),
@@ -599,6 +602,31 @@ def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16, exact_b
     torch.cuda.synchronize()
     tb.st.check("tree_build")
     return t.host()
+
+
+def tree_insert(S: Seqs, n_old: int, tree, stream=None) -> Tree:
+    """Online insertion: S holds the n_old sequences `tree` (a device Tree or
+    a host dict from tree_build) was built on, followed by new ones.  Each
+    new sequence is routed down by the poles' split rule, the leaves that
+    receive some are re-partitioned by Alg. 1, and the tree is renumbered
+    breadth-first (tree_insert in the library).  Returns a device Tree over
+    all of S; msa_merge(S, tree) aligns the grown set."""
+    dev = S.codes.device
+    if isinstance(tree, dict):
+        tree = Tree.from_host(tree, dev)
+    out = Tree(S.n, dev)
+    ss, to, tn = S.struct(), tree.struct(), out.struct()
+    wsb = lib().tree_insert_workspace_bytes(C.byref(ss), int(n_old), tree.n_nodes)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = Status(dev)
+    nn = C.c_int32(0)
+    rc = lib().tree_insert(C.byref(ss), int(n_old), C.byref(to), tree.n_nodes, C.byref(tn),
+                           C.byref(nn), _ptr(ws), wsb, _ptr(st.t), _stream(stream))
+    _check(rc, "tree_insert")
+    torch.cuda.synchronize()
+    st.check("tree_insert")
+    out.n_nodes = nn.value
+    return out
 
 
 def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, exact_below=0, emb_offset=0.0,

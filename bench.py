@@ -80,9 +80,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--legs", default="pairs,nw,gotoh,band,tree,pruned,quality,machine",
+    ap.add_argument("--legs", default="pairs,nw,gotoh,band,tree,insert,pruned,quality,machine",
                     help="legs after the all-pairs one: any of pairs, nw, gotoh, band, tree, "
-                         "pruned, quality, machine (comma list)")
+                         "insert, pruned, quality, machine (comma list)")
     ap.add_argument("--quick", action="store_true", help="only the all-pairs leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
@@ -220,7 +220,8 @@ def main():
             "dual_issue_share": ce.get("valu2_share")}
     legs = [] if args.quick else [x for x in args.legs.split(",") if x]
     for name, fn in (("pairs", bench_pairs), ("nw", bench_nw), ("gotoh", bench_gotoh),
-                     ("band", bench_band), ("tree", bench_tree), ("pruned", bench_pruned),
+                     ("band", bench_band), ("tree", bench_tree), ("insert", bench_insert),
+                     ("pruned", bench_pruned),
                      ("quality", bench_quality), ("machine", bench_machine)):
         if name in legs:
             try:
@@ -524,6 +525,77 @@ def tree_cells(t, L):
     s2 = c2[ms[v] + mc[v]] - c2[ms[v]]
     poles = L[t["center"][v]] + L[t["lpole"][v]] + L[t["rpole"][v]]
     return int(((s1 * s1 - s2) // 2 + poles * s1).sum())
+
+
+def bench_insert(msadp, synth, torch, args):
+    """Online insertion: 1,000 sequences of the learned workload's families
+    (seeded choice) inserted into the exact tree of the other 99,000, against
+    rebuilding the tree of all 100,000; both trees' alignments get the
+    Sec. 2.3 metrics on the same 10,000 rows (the 1,000 new and 9,000 old)."""
+    from paper_2601_15458_amd import learned
+    d = synth.learned()
+    n = d["n"]
+    rng = np.random.default_rng(42)
+    new = np.sort(rng.choice(n, size=1000, replace=False))
+    keep = np.setdiff1d(np.arange(n), new)
+    order = np.concatenate([keep, new])
+    allset = synth.subset(d, order)
+    n_old = len(keep)
+    o = allset["offsets"]
+    S_old = msadp.to_device(allset["codes"][: o[n_old]], o[: n_old + 1], d["sigma"])
+    S = msadp.to_device(allset["codes"], allset["offsets"], d["sigma"])
+    stream = torch.cuda.current_stream()
+    old_b = msadp.TreeBuilder(S_old)
+    t0 = time.perf_counter()
+    old = old_b(stream)
+    torch.cuda.synchronize()
+    t_old = time.perf_counter() - t0
+    old_b.st.check("tree_build")
+    _log(f"insert: old tree of {n_old} in {t_old:.2f} s")
+    msadp.tree_insert(S, n_old, old)          # warm-up
+    ts = []
+    for _ in range(max(3, min(args.steps, 5))):
+        t0 = time.perf_counter()
+        grown = msadp.tree_insert(S, n_old, old)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_ins = float(np.median(ts))
+    full_b = msadp.TreeBuilder(S)
+    t0 = time.perf_counter()
+    full = full_b(stream)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    full_b.st.check("tree_build")
+    sub = np.sort(np.concatenate([np.arange(n_old, n),
+                                  rng.choice(n_old, 9000, replace=False)]))
+    sub_d = synth.subset(allset, sub)
+    S_sub = msadp.to_device(sub_d["codes"], sub_d["offsets"], d["sigma"])
+    lev_sub = msadp.lev_allpairs(S_sub)
+    max_len_sub = int(np.diff(sub_d["offsets"]).max())
+
+    def quality(tree):
+        t0 = time.perf_counter()
+        msa = msadp.msa_merge(S, tree)
+        t_merge = time.perf_counter() - t0
+        Q = msadp.Quality(msa[sub], d["sigma"])
+        q = Q.metrics(Q.pair_counts(), max_len_sub, lev=lev_sub)
+        q = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in q.items()}
+        q["width"] = int(msa.shape[1])
+        q["merge_s"] = round(t_merge, 3)
+        return q
+
+    gh, fh = grown.host(), full.host()
+    out = {"workload": "tree_insert: 1,000 of the 100,000 learned-workload DNA seqs (seed 42) "
+                       "into the exact tree of the other 99,000",
+           "old_build_s": round(t_old, 3), "insert_s": round(t_ins, 4),
+           "rebuild_s": round(t_full, 3), "speedup_vs_rebuild": round(t_full / t_ins, 1),
+           "nodes_old": int(old.n_nodes), "nodes_inserted": int(gh["n_nodes"]),
+           "nodes_rebuilt": int(fh["n_nodes"]),
+           "rebuilt_clusters_kept": round(learned.reproduced_clusters(fh, gh), 4),
+           "alignment_quality": {"rows": "the 1,000 new and 9,000 seeded old rows, all pairs",
+                                 "inserted": quality(grown), "rebuilt": quality(full)}}
+    _log(f"insert: {out}")
+    return out
 
 
 def bench_tree(msadp, synth, torch, args):

@@ -82,7 +82,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--legs", default="pairs,nw,gotoh,band,tree,insert,pruned,quality,machine",
                     help="legs after the all-pairs one: any of pairs, nw, gotoh, band, tree, "
-                         "insert, pruned, quality, machine (comma list)")
+                         "insert, cnn, pruned, quality, machine (comma list; cnn is not in "
+                         "the default set, the pruned leg trains and embeds too)")
     ap.add_argument("--quick", action="store_true", help="only the all-pairs leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch variants (no autotuning before timing)")
@@ -221,7 +222,7 @@ def main():
     legs = [] if args.quick else [x for x in args.legs.split(",") if x]
     for name, fn in (("pairs", bench_pairs), ("nw", bench_nw), ("gotoh", bench_gotoh),
                      ("band", bench_band), ("tree", bench_tree), ("insert", bench_insert),
-                     ("pruned", bench_pruned),
+                     ("cnn", bench_cnn), ("pruned", bench_pruned),
                      ("quality", bench_quality), ("machine", bench_machine)):
         if name in legs:
             try:
@@ -657,6 +658,39 @@ def cnn_rates(learned, d, losses, t_train, positions, t_embed):
             "roofline": {"bound": "mfma", "achieved": round(embed_tf, 1), "peak": 2500.0,
                          "unit": "TFLOP/s", "frac": round(embed_tf / 2500.0, 4),
                          "traffic": None, "kernel": "k_conv (embedding pass, all kernels)"}}
+
+
+def bench_cnn(msadp, synth, torch, args):
+    """The embedder alone on the learned workload: training on the 2M
+    labelled pairs (args.epochs epochs of 4096-pair steps) and one embedding
+    pass over the 100,000 sequences; then two fresh runs of the first 50
+    steps from the same seed, whose weights must agree bit for bit."""
+    from paper_2601_15458_amd import learned
+    d = synth.learned()
+    S = msadp.to_device(d["codes"], d["offsets"], d["sigma"])
+    ia, ib = learned.sample_pairs(d["family"], 2_000_000, seed=11)
+    dist = learned.lev_labels(S, ia, ib)
+    E, losses, t_train, positions = learned.train(S, ia, ib, dist, epochs=args.epochs, seed=13)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.embed(S)
+    torch.cuda.synchronize()
+    t_embed = time.perf_counter() - t0
+    out = {"workload": "cnn_train_step + cnn_embed: 100,000 DNA seqs (lengths 100-500), "
+                       "2M pairs, batches of 4096, seed 5/11/13",
+           "epochs": args.epochs, "steps": len(losses),
+           "loss_first_last": [round(float(losses[:50].mean()), 5),
+                               round(float(losses[-50:].mean()), 5)],
+           "rates": cnn_rates(learned, d, losses, t_train, positions, t_embed)}
+    sel = 50 * 4096
+    weights = []
+    for _ in range(2):
+        E2, _, _, _ = learned.train(S, ia[:sel], ib[:sel], dist[:sel], epochs=1, seed=13)
+        weights.append(E2.get()[0])
+    out["bit_identical_weights_two_runs_50_steps"] = all(
+        np.array_equal(a, c) and np.array_equal(b, e)
+        for (a, b), (c, e) in zip(weights[0], weights[1]))
+    return out
 
 
 def bench_pruned(msadp, synth, torch, args):

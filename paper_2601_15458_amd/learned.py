@@ -143,6 +143,18 @@ def calibrate(emb, S, family, n_pairs: int = 20000, seed: int = 21, cap: float =
     a_t = torch.from_numpy(np.asarray(ia, np.int64)).to(emb.device)
     b_t = torch.from_numpy(np.asarray(ib, np.int64)).to(emb.device)
     yh = (emb[a_t].double() - emb[b_t].double()).norm(dim=1).cpu().numpy()
+    return fit_offset(yh, y, cap)
+
+
+def fit_offset(yh, y, cap: float = 1024.0):
+    """Least-squares line y ~ a + b * yh through (predicted, true) normalized
+    distances; the ranking offset is a / b clipped to [0, cap], and cap when
+    b <= 0 (no ranking signal: the estimate falls back to the length prior).
+    Returns (offset, a, b, correlation)."""
+    yh = np.asarray(yh, np.float64)
+    y = np.asarray(y, np.float64)
+    if len(yh) < 2 or float(np.ptp(yh)) == 0.0:
+        return cap, float(y.mean()) if len(y) else 0.0, 0.0, 0.0
     b, a = np.polyfit(yh, y, 1)
     corr = float(np.corrcoef(yh, y)[0, 1])
     off = cap if b <= 0 else float(min(max(a / b, 0.0), cap))

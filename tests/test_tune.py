@@ -96,3 +96,25 @@ def test_save_and_load(tmp_path):
     assert M.tune_load(path)
     assert M.tune_get(M.MSA_TUNE_NW, 4, 2) == 64
     assert not M.tune_load(str(tmp_path / "missing.json"))
+
+
+def test_calibration_fit_offset():
+    """The ranking offset of the pruned median is a host-side fit (its value
+    is a parameter of tree_build_pruned): intercept over slope of the line
+    through (predicted, true) distances, clipped; the length prior (cap)
+    when the predictor carries no signal."""
+    import numpy as np
+    from paper_2601_15458_amd.learned import fit_offset
+    yh = np.linspace(0.1, 2.0, 50)
+    off, a, b, r = fit_offset(yh, 0.3 + 0.5 * yh)
+    assert abs(a - 0.3) < 1e-12 and abs(b - 0.5) < 1e-12 and abs(off - 0.6) < 1e-12
+    assert abs(r - 1.0) < 1e-12
+    # noise around the same line keeps the offset near a / b
+    rng = np.random.default_rng(3)
+    off, _, _, r = fit_offset(yh, 0.3 + 0.5 * yh + rng.normal(0, 0.01, 50))
+    assert abs(off - 0.6) < 0.05 and r > 0.99
+    # negative slope, a constant predictor, a negative intercept, the cap
+    assert fit_offset(yh, 1.0 - 0.2 * yh, cap=7.0)[0] == 7.0
+    assert fit_offset(np.ones(10), np.arange(10.0), cap=5.0)[0] == 5.0
+    assert fit_offset(yh, -1.0 + yh)[0] == 0.0
+    assert fit_offset(yh, 100.0 + 0.01 * yh, cap=64.0)[0] == 64.0

@@ -22,7 +22,9 @@
  *     string is smallest (M < D < I).
  *   - Alg. 1 (Partition) with the full geometric median (Sec. 2.1), and
  *     the same with the median taken over candidates that a learned
- *     embedding ranks first (a surrogate of this project, not the paper's).
+ *     embedding ranks first (a surrogate of this project, not the paper's)
+ *     or that their summed distance to a few hashed members ranks first
+ *     (the median over a smaller subset that Sec. 2.1 allows).
  *   - Insertion of new sequences into an existing tree (Sec. 5 names it
  *     as future work; the routing and re-partition rules are this
  *     project's reading, stated at orc_tree_insert).
@@ -352,24 +354,39 @@ static int64_t *dist_row(const uint8_t *codes, const int64_t *off, const int32_t
     return row;
 }
 
+/* The pivot order of the sampled median: MurmurHash3's 32-bit finalizer
+ * (Appleby), a bijection, of the input index; the pivots of a cluster are
+ * its members with the least values. */
+static uint32_t pivot_hash(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
 /* The choice Alg. 1 makes for one cluster C (ascending input indices, k
  * members): out[0] = c, out[1] = l = argmax f(c, x), out[2] = r = argmax
  * f(l, x) (lowest index on ties; l = r = -1 when k = 1 or the radius
- * f(c, l) is 0).  emb == NULL: c is the full geometric median of C
- * (Sec. 2.1).  Otherwise c is the surrogate-pruned median: if C has more
- * than exact_below members, every member x gets the estimate E(x) = sum
- * over C (x itself included) of emb_estimate and the topk members with the least
- * (E, input index) are the candidates, else every member is one; c is the
- * candidate with the least exact sum of f over C (lowest input index on
- * ties). */
+ * f(c, l) is 0).  emb == NULL and pivots == 0: c is the full geometric
+ * median of C (Sec. 2.1).  Otherwise c is a pruned median: if C has more
+ * than exact_below members, every member x gets an estimate E(x) and the
+ * topk members with the least (E, input index) are the candidates, else
+ * every member is one; c is the candidate with the least exact sum of f
+ * over C (lowest input index on ties).  The estimate is either the sum over
+ * C (x itself included) of emb_estimate (ecode != NULL), or, with pivots > 0,
+ * the sum of f(x, p) over the min(pivots, k) members p of least pivot_hash
+ * (the median over a smaller subset that Sec. 2.1 allows, with the subset
+ * drawn by the hash). */
 static void select_impl(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
                         const int8_t *ecode, int eshift, uint32_t emb_q0, int32_t topk,
-                        int32_t exact_below, int32_t out[3]) {
+                        int32_t exact_below, int32_t pivots, int32_t out[3]) {
     out[1] = out[2] = -1;
     if (k == 1) { out[0] = C[0]; return; }
     int64_t best = -1;
     int64_t *rowc;
-    if (ecode == NULL) {
+    if (ecode == NULL && pivots <= 0) {
         /* geometric median over the whole cluster */
         int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(k * k));
         #pragma omp parallel for schedule(dynamic, 1)
@@ -392,10 +409,28 @@ static void select_impl(const uint8_t *codes, const int64_t *off, const int32_t 
         free(D);
     } else {
         uint64_t *E = (uint64_t *)calloc((size_t)k, sizeof(uint64_t));
-        #pragma omp parallel for schedule(dynamic, 1)
-        for (int64_t x = 0; x < k; ++x)
-            for (int64_t y = 0; y < k; ++y)
-                E[x] += emb_estimate(off, ecode, eshift, emb_q0, C[x], C[y]);
+        if (ecode != NULL) {
+            #pragma omp parallel for schedule(dynamic, 1)
+            for (int64_t x = 0; x < k; ++x)
+                for (int64_t y = 0; y < k; ++y)
+                    E[x] += emb_estimate(off, ecode, eshift, emb_q0, C[x], C[y]);
+        } else if (k > exact_below && k > topk) {
+            char *piv = (char *)calloc((size_t)k, 1);
+            const int64_t np = pivots < k ? pivots : k;
+            for (int64_t j = 0; j < np; ++j) {
+                int64_t p = -1;   /* least hash not yet taken */
+                for (int64_t x = 0; x < k; ++x)
+                    if (!piv[x] && (p < 0 || pivot_hash((uint32_t)C[x]) <
+                                                 pivot_hash((uint32_t)C[p])))
+                        p = x;
+                if (p < 0) break;
+                piv[p] = 1;
+                int64_t *row = dist_row(codes, off, C, k, p);
+                for (int64_t x = 0; x < k; ++x) E[x] += (uint64_t)row[x];
+                free(row);
+            }
+            free(piv);
+        }
         char *taken = (char *)calloc((size_t)k, 1);
         int64_t best_sum = 0;
         const int64_t nc = k <= exact_below ? k : (k < topk ? k : topk);
@@ -436,14 +471,15 @@ static void select_impl(const uint8_t *codes, const int64_t *off, const int32_t 
  * comes from all of it), or NULL for the full median. */
 void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
                 const float *emb, int64_t n_emb, uint32_t emb_q0, int32_t topk,
-                int32_t exact_below, int32_t out[3]) {
+                int32_t exact_below, int32_t pivots, int32_t out[3]) {
     int8_t *ecode = NULL;
     int eshift = 0;
     if (emb != NULL) {
         ecode = (int8_t *)malloc((size_t)(n_emb * EMB_DIM));
         eshift = orc_emb_quantize(emb, n_emb, ecode);
     }
-    select_impl(codes, off, C, k, ecode, eshift, emb_q0, topk, exact_below, out);
+    select_impl(codes, off, C, k, ecode, eshift, emb_q0, topk, exact_below,
+                emb != NULL ? 0 : pivots, out);
     free(ecode);
 }
 
@@ -451,7 +487,8 @@ void orc_select(const uint8_t *codes, const int64_t *off, const int32_t *C, int6
  * L = {x : f(l, x) <= f(r, x)}, R = the rest, both in ascending order, and
  * breadth-first node numbering (L before R). */
 static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, const float *emb,
-                         uint32_t emb_q0, int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left, int32_t *right,
+                         uint32_t emb_q0, int32_t topk, int32_t exact_below, int32_t pivots,
+                         int32_t *parent, int32_t *left, int32_t *right,
                          int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
                          int64_t *mstart, int64_t *mcount, int32_t *perm) {
     if (n <= 0) return 0;
@@ -474,7 +511,7 @@ static int32_t tree_impl(const uint8_t *codes, const int64_t *off, int32_t n, co
         int32_t *C = members[v];
         left[v] = right[v] = -1;
         int32_t clr[3];
-        select_impl(codes, off, C, k, ecode, eshift, emb_q0, topk, exact_below, clr);
+        select_impl(codes, off, C, k, ecode, eshift, emb_q0, topk, exact_below, pivots, clr);
         center[v] = clr[0];
         lpole[v] = clr[1];
         rpole[v] = clr[2];
@@ -524,8 +561,20 @@ int32_t orc_tree(const uint8_t *codes, const int64_t *off, int32_t n,
                  int32_t *parent, int32_t *left, int32_t *right, int32_t *center,
                  int32_t *lpole, int32_t *rpole, int32_t *depth,
                  int64_t *mstart, int64_t *mcount, int32_t *perm) {
-    return tree_impl(codes, off, n, NULL, 0, 0, 0, parent, left, right, center, lpole, rpole, depth,
-                     mstart, mcount, perm);
+    return tree_impl(codes, off, n, NULL, 0, 0, 0, 0, parent, left, right, center, lpole, rpole,
+                     depth, mstart, mcount, perm);
+}
+
+/* Alg. 1 with the sampled median: in clusters of more than exact_below and
+ * more than topk members, the topk members with the least summed distance
+ * to `pivots` hashed members are the candidates (select_impl). */
+int32_t orc_tree_sampled(const uint8_t *codes, const int64_t *off, int32_t n, int32_t pivots,
+                         int32_t topk, int32_t exact_below, int32_t *parent, int32_t *left,
+                         int32_t *right, int32_t *center, int32_t *lpole, int32_t *rpole,
+                         int32_t *depth, int64_t *mstart, int64_t *mcount, int32_t *perm) {
+    if (pivots < 1 || topk < 1 || exact_below < 0) return -1;
+    return tree_impl(codes, off, n, NULL, 0, topk, exact_below, pivots, parent, left, right,
+                     center, lpole, rpole, depth, mstart, mcount, perm);
 }
 
 /* ------------------------------------------------------- online insertion
@@ -629,7 +678,7 @@ int32_t orc_tree_insert(const uint8_t *codes, const int64_t *off, int32_t n, int
         int32_t *s_par = sp, *s_l = sp + cs, *s_r = sp + 2 * cs, *s_c = sp + 3 * cs;
         int32_t *s_lp = sp + 4 * cs, *s_rp = sp + 5 * cs, *s_d = sp + 6 * cs;
         int64_t *s_ms = sm, *s_mc = sm + cs;
-        const int32_t sn = tree_impl(sc, so, (int32_t)k, NULL, 0, 0, 0, s_par, s_l, s_r, s_c,
+        const int32_t sn = tree_impl(sc, so, (int32_t)k, NULL, 0, 0, 0, 0, s_par, s_l, s_r, s_c,
                                      s_lp, s_rp, s_d, s_ms, s_mc, sperm);
         /* subtree node u > 0 becomes node base + u - 1; its root is v */
         const int64_t base = nn;
@@ -707,7 +756,7 @@ int32_t orc_tree_pruned(const uint8_t *codes, const int64_t *off, int32_t n, con
                         int32_t *center, int32_t *lpole, int32_t *rpole, int32_t *depth,
                         int64_t *mstart, int64_t *mcount, int32_t *perm) {
     if (emb == NULL || topk < 1 || exact_below < 0) return -1;
-    return tree_impl(codes, off, n, emb, emb_q0, topk, exact_below, parent, left, right, center, lpole,
+    return tree_impl(codes, off, n, emb, emb_q0, topk, exact_below, 0, parent, left, right, center, lpole,
                      rpole, depth,
                      mstart, mcount, perm);
 }

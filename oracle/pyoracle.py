@@ -45,7 +45,9 @@ def lib():
         L.orc_tree_pruned.argtypes = [P, P, C.c_int32, P, C.c_uint32, C.c_int32, C.c_int32] + [P] * 10
         L.orc_select.restype = None
         L.orc_select.argtypes = [P, P, P, C.c_int64, P, C.c_int64, C.c_uint32, C.c_int32,
-                                 C.c_int32, P]
+                                 C.c_int32, C.c_int32, P]
+        L.orc_tree_sampled.restype = C.c_int32
+        L.orc_tree_sampled.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32] + [P] * 10
         L.orc_emb_rowsums.restype = None
         L.orc_emb_rowsums.argtypes = [P, P, C.c_int64, C.c_uint32, P, C.c_int64, P]
         L.orc_emb_quantize.restype = C.c_int32
@@ -187,6 +189,25 @@ def tree(codes, offsets):
 
 
 
+
+def tree_sampled(codes, offsets, pivots=8, topk=16, exact_below=0):
+    """Alg. 1 with the sampled median (orc_tree_sampled)."""
+    codes = _u8(codes)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = len(offsets) - 1
+    cap = max(2 * n - 1, 1)
+    arr = {f: np.zeros(cap, dtype=np.int64 if f in ("mstart", "mcount") else np.int32)
+           for f in TREE_FIELDS}
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    k = lib().orc_tree_sampled(_p(codes), _p(offsets), n, int(pivots), int(topk),
+                               int(exact_below), *[_p(arr[f]) for f in TREE_FIELDS], _p(perm))
+    if k < 0:
+        raise ValueError("oracle tree_sampled: bad arguments")
+    out = {f: arr[f][:k].copy() for f in TREE_FIELDS}
+    out["perm"] = perm[:n].copy()
+    out["n_nodes"] = int(k)
+    return out
+
 def tree_insert(codes, offsets, n_old, t):
     """Online insertion (orc_tree_insert): sequences n_old.. of the set are
     routed into the tree ``t`` built on the first n_old, the leaves they
@@ -238,9 +259,11 @@ def tree_pruned(codes, offsets, emb, topk=16, exact_below=0, emb_q0=0):
     return out
 
 
-def select(codes, offsets, members, emb=None, topk=16, exact_below=0, emb_q0=0):
+def select(codes, offsets, members, emb=None, topk=16, exact_below=0, emb_q0=0, pivots=0):
     """(c, l, r) that Alg. 1 picks for the cluster `members` (input indices);
-    emb=None: full geometric median, else the surrogate-pruned one."""
+    emb=None and pivots=0: full geometric median; emb: the surrogate-pruned
+    one; pivots > 0: the sampled one (candidates ranked by their summed
+    distance to `pivots` hashed members)."""
     codes = _u8(codes)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     mem = np.ascontiguousarray(np.sort(np.asarray(members)), dtype=np.int32)
@@ -248,7 +271,7 @@ def select(codes, offsets, members, emb=None, topk=16, exact_below=0, emb_q0=0):
     out = np.zeros(3, dtype=np.int32)
     lib().orc_select(_p(codes), _p(offsets), _p(mem), len(mem), None if e is None else _p(e),
                      0 if e is None else len(e), int(emb_q0), int(topk), int(exact_below),
-                     _p(out))
+                     int(pivots), _p(out))
     return tuple(int(x) for x in out)
 
 

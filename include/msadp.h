@@ -273,6 +273,23 @@ int tree_build_pruned(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                       int32_t use_graph, void *ws, size_t ws_bytes, int32_t *d_status,
                       hipStream_t s);
 
+/* The tree build with the median taken over a smaller subset, which Sec.
+ * 2.1 allows to save time.  In a cluster of k members, k > exact_below and
+ * k > topk, the min(pivots, k) members with the least h(i) are the pivots,
+ * h being MurmurHash3's 32-bit finalizer (Appleby) of the input index i
+ * (h ^= h >> 16; h *= 0x85EBCA6B; h ^= h >> 13; h *= 0xC2B2AE35;
+ * h ^= h >> 16: a bijection, so no two members tie); every member x gets
+ * E(x) = sum over the pivots p of f(x, p), and the topk members with the
+ * least (E, input index) are the candidates.  The candidates get exact row
+ * sums over the cluster and c is the one with the least (lowest input index
+ * on ties); poles and split stay exact.  A pruned cluster costs about
+ * (pivots + topk) k distances instead of the medoid's k (k - 1) / 2.
+ * 1 <= pivots <= 1024, 1 <= topk <= 1024, exact_below >= 0 (MSA_EINVAL
+ * otherwise).  Same outputs, workspace and errors as tree_build. */
+int tree_build_sampled(const msa_seqs *S, int32_t pivots, int32_t topk, int32_t exact_below,
+                       const msa_tree *T, int32_t *n_nodes, int32_t use_graph, void *ws,
+                       size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
 /* Teacher-forced evaluation of the choice of c, l, r (Alg. 1) on the
  * clusters of a given tree: for every node v < n_nodes of T (as filled by
  * tree_build or tree_build_pruned over the same S; only depth, mstart,
@@ -289,6 +306,13 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                       int32_t exact_below, const msa_tree *T, int32_t n_nodes,
                       int32_t *center, int32_t *lpole, int32_t *rpole, void *ws,
                       size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
+/* tree_eval_centers for the median of tree_build_sampled (same pivots,
+ * topk and exact_below rules and errors). */
+int tree_eval_centers_sampled(const msa_seqs *S, int32_t pivots, int32_t topk,
+                              int32_t exact_below, const msa_tree *T, int32_t n_nodes,
+                              int32_t *center, int32_t *lpole, int32_t *rpole, void *ws,
+                              size_t ws_bytes, int32_t *d_status, hipStream_t s);
 
 /* Online insertion of new sequences into a tree (Sec. 5 names online
  * updates of the clusters, guide tree and alignment as future work and

@@ -24,7 +24,8 @@
 
 namespace msadp {
 
-enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 4 };
+enum { kMedoid = 0, kPoleMax = 1, kPoleMaxStore = 2, kPoleStore = 3, kCandSum = 4,
+       kPivotSum = 5 };
 
 // Surrogate-pruned medoid: clusters above exact_below members get exact row
 // sums for their topk best-ranked members only.  The embeddings are
@@ -76,6 +77,7 @@ struct TreeArgs {
     int32_t *embn;           // [n] squared norms of the codes
     uint32_t *emb_max;       // [2]: bits of max |e|, quantization shift s
     uint32_t emb_q0;         // calibration offset added to every surrogate distance
+    int32_t pivots;          // sampled median: pivots per cluster (0: not sampled)
     int32_t topk;
     int32_t exact_below;     // clusters of at most this many members: all are candidates
     int64_t *ncand;          // per cluster candidate count (nq + 1)
@@ -131,33 +133,58 @@ __device__ __forceinline__ uint64_t far_key(int d, int32_t order_y) {
     return ((uint64_t)(uint32_t)d << 32) | (0xFFFFFFFFu - (uint32_t)order_y);
 }
 
+// The median is pruned (a ranking picks its candidates): by the embedding
+// or by sampled pivots.
+__device__ __forceinline__ bool ranked(const TreeArgs &a) {
+    return a.emb != nullptr || a.pivots > 0;
+}
+
+// Pivot order of the sampled median: MurmurHash3's 32-bit finalizer
+// (Appleby), a bijection of the input index, so no two members tie.
+__device__ __forceinline__ uint32_t pivot_hash(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
 // Level start: reset per-node fields, member sums and the medoid work list.
 __global__ void __launch_bounds__(256) k_level_init(TreeArgs a) {
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
+        // at most max(exact_below, topk) members: every member is a
+        // candidate and no ranking is needed
+        const bool pruned = ranked(a) && k > a.exact_below && k > a.topk;
         if (threadIdx.x == 0) {
             a.left[v] = a.right[v] = a.lpole[v] = a.rpole[v] = -1;
             a.key[q] = ~0ull;
             if (a.emb != nullptr) {
-                // at most max(exact_below, topk) members: every member is a
-                // candidate and no ranking is needed
-                const bool pruned = k > a.exact_below && k > a.topk;
                 a.cnt[q] = pruned ? emb_tiles(k) : 0;
                 a.ncand[q] = pruned ? a.topk : k;
+            } else if (a.pivots > 0) {
+                // first the pivots; the candidates' count is set after them
+                a.cnt[q] = 0;
+                a.ncand[q] = pruned ? min<int64_t>(a.pivots, k) : k;
             } else {
                 a.cnt[q] = k >= 2 ? items_upto(k - 1) : 0;
             }
             a.nleft[q] = -1;
             a.split[q] = 0;
         }
-        for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.rowsum[ms + i] = 0;
+        // the sampled median picks its pivots by the least hash: the hash
+        // stands in the estimate slot until the pivot pass
+        const bool hashed = pruned && a.pivots > 0;
+        for (int64_t i = threadIdx.x; i < k; i += blockDim.x)
+            a.rowsum[ms + i] = hashed ? pivot_hash((uint32_t)a.order[a.perm[ms + i]]) : 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.cnt[nq] = 0;
         a.split[nq] = 0;
-        if (a.emb != nullptr) a.ncand[nq] = 0;
+        if (ranked(a)) a.ncand[nq] = 0;
     }
 }
 
@@ -196,8 +223,10 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
     const int lane = lane_id();
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     const int64_t total = a.items[nq];
-    // A level never holds more work than the triangle of all n sequences.
-    if (nq < 1 || nq > a.n || total < 0 || total > items_upto(a.n)) {
+    // A level never holds more work than n patterns against all n members
+    // (the medoid triangle is half of that; a candidate or pivot pass over
+    // every member of a cluster is all of it).
+    if (nq < 1 || nq > a.n || total < 0 || total > (int64_t)a.n * ((a.n + 63) / 64)) {
         if (blockIdx.x == 0 && lane == 0) set_status(a.st, MSA_DS_CAPACITY);
         return;
     }
@@ -225,7 +254,7 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
             prow = a.perm[prow_pos];
             tpos = ms + blk * 64 + lane;
             tend = ms + u;
-        } else if (MODE == kCandSum) {
+        } else if (MODE == kCandSum || MODE == kPivotSum) {
             const int64_t nblk = (k + 63) / 64;
             const int64_t j = local / nblk, blk = local % nblk;
             cslot = a.coff[q] + j;
@@ -264,6 +293,8 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
             atomicMax((unsigned long long *)&a.candkey[cslot],
                       (unsigned long long)(lane == 0 ? m : 0ull));
         }
+        if (MODE == kPivotSum)
+            atomicAdd((unsigned long long *)&a.rowsum[slot], (unsigned long long)(valid ? d : 0));
         if (MODE == kPoleMaxStore) a.dl[slot] = d;
         if (MODE == kPoleStore) a.dr[slot] = d;
     }
@@ -777,7 +808,10 @@ constexpr int kTopkSel = 2048;      // members a selection may collect in LDS
 // than kTopkSel members fall under T, topk rounds of a block-wide minimum
 // over the members above the last pick are taken instead.  Clears the
 // candidates' sums and sets the work of the candidate-sum pass.
-__global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a) {
+// Phase 0 (sampled median) picks the pivots instead, by the hash in the
+// estimate slots, in pruned clusters only; it then clears those slots for
+// the pivot pass and sets the candidates' count for phase 1.
+__global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
     __shared__ uint64_t se[kTopkSel];
     __shared__ uint32_t si[kTopkSel];
     __shared__ uint32_t count;
@@ -785,12 +819,17 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a) {
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
+        const bool small = k <= a.exact_below || k <= a.topk;
+        if (phase == 0 && small) {         // uniform per block
+            if (threadIdx.x == 0) a.cnt[q] = 0;
+            continue;
+        }
         const int64_t nc = a.ncand[q], base = a.coff[q];
         for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) {
             a.candsum[base + j] = 0;
             a.candkey[base + j] = 0;
         }
-        if (k <= a.exact_below || k <= a.topk) {
+        if (small) {
             for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.cand[base + i] = a.perm[ms + i];
         } else {
             bool done = false;
@@ -873,6 +912,11 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a) {
             }
         }
         if (threadIdx.x == 0) a.cnt[q] = k >= 2 ? nc * ((k + 63) / 64) : 0;
+        if (phase == 0) {
+            __syncthreads();               // every hash has been read
+            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.rowsum[ms + i] = 0;
+            if (threadIdx.x == 0) a.ncand[q] = a.topk;
+        }
         __syncthreads();
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
@@ -909,13 +953,24 @@ static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s)
     hipLaunchKernelGGL(k_level_init, cg, cb, 0, s, a);
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-    if (a.emb == nullptr) {
+    const bool exact = a.emb == nullptr && a.pivots == 0;
+    if (exact) {
         hipLaunchKernelGGL((k_tree_lev<WMAX, kMedoid>), lg, tb, 0, s, a);
         hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
     } else {
-        hipLaunchKernelGGL(k_emb_rowsum, dim3(egrid), tb, 0, s, a);
+        if (a.emb != nullptr) {
+            hipLaunchKernelGGL(k_emb_rowsum, dim3(egrid), tb, 0, s, a);
+        } else {
+            // sampled median: pivots by hash, then every member's summed
+            // distance to them is its estimate
+            hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.ncand, a.coff, a.desc);
+            hipLaunchKernelGGL(k_topk, cg, dim3(kTopkThreads), 0, s, a, 0);
+            hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+            hipLaunchKernelGGL((k_tree_lev<WMAX, kPivotSum>), lg, tb, 0, s, a);
+        }
         hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.ncand, a.coff, a.desc);
-        hipLaunchKernelGGL(k_topk, cg, dim3(kTopkThreads), 0, s, a);
+        hipLaunchKernelGGL(k_topk, cg, dim3(kTopkThreads), 0, s, a, 1);
         hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
         hipLaunchKernelGGL((k_tree_lev<WMAX, kCandSum>), lg, tb, 0, s, a);
@@ -925,7 +980,7 @@ static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s)
     // from the candidate pass, and items[] only tells k_pick_pole which
     // clusters have work.
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-    if (a.emb == nullptr) {
+    if (exact) {
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
         hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMax>), lg, tb, 0, s, a);
     }
@@ -1093,7 +1148,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                       int32_t exact_below, const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
                       int32_t *d_status, hipStream_t s, int forced,
-                      const Forest *fr = nullptr);
+                      const Forest *fr = nullptr, int32_t pivots = 0);
 
 extern "C" {
 
@@ -1108,7 +1163,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                       int32_t exact_below, const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
                       int32_t *d_status, hipStream_t s, int forced,
-                      const Forest *fr) {
+                      const Forest *fr, int32_t pivots) {
     int rc;
     if ((rc = check_seqs(S))) return rc;
     if (T == nullptr || n_nodes == nullptr) return MSA_EINVAL;
@@ -1163,6 +1218,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.emb_max = cv.take<uint32_t>(2);
     a.emb = emb;
     a.emb_q0 = emb_q0;
+    a.pivots = pivots;
     a.topk = topk;
     a.exact_below = exact_below;
     a.sigma = S->sigma;
@@ -1287,18 +1343,50 @@ int msa_autotune_tree(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, in
     return msa_tune_set(MSA_TUNE_TREE, S->sigma, words, bc);
 }
 
+int tree_build_sampled(const msa_seqs *S, int32_t pivots, int32_t topk, int32_t exact_below,
+                       const msa_tree *T, int32_t *n_nodes, int32_t use_graph, void *ws,
+                       size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    if (pivots < 1 || pivots > kMaxTopk || topk < 1 || topk > kMaxTopk || exact_below < 0)
+        return MSA_EINVAL;
+    return build_impl(S, nullptr, 0, topk, exact_below, T, n_nodes, use_graph, ws, ws_bytes,
+                      d_status, s, 0, nullptr, pivots);
+}
+
+static int eval_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t pivots,
+                     int32_t topk, int32_t exact_below, const msa_tree *T, int32_t n_nodes,
+                     int32_t *center, int32_t *lpole, int32_t *rpole, void *ws,
+                     size_t ws_bytes, int32_t *d_status, hipStream_t s);
+
 int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t topk,
                       int32_t exact_below, const msa_tree *T,
                       int32_t n_nodes, int32_t *center, int32_t *lpole, int32_t *rpole,
                       void *ws, size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    if (emb != nullptr &&
+        (topk < 1 || topk > kMaxTopk || exact_below < 0 || emb_q0 > kMaxEmbOffset))
+        return MSA_EINVAL;
+    return eval_impl(S, emb, emb_q0, 0, topk, exact_below, T, n_nodes, center, lpole, rpole, ws,
+                     ws_bytes, d_status, s);
+}
+
+int tree_eval_centers_sampled(const msa_seqs *S, int32_t pivots, int32_t topk,
+                              int32_t exact_below, const msa_tree *T, int32_t n_nodes,
+                              int32_t *center, int32_t *lpole, int32_t *rpole, void *ws,
+                              size_t ws_bytes, int32_t *d_status, hipStream_t s) {
+    if (pivots < 1 || pivots > kMaxTopk || topk < 1 || topk > kMaxTopk || exact_below < 0)
+        return MSA_EINVAL;
+    return eval_impl(S, nullptr, 0, pivots, topk, exact_below, T, n_nodes, center, lpole, rpole,
+                     ws, ws_bytes, d_status, s);
+}
+
+static int eval_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32_t pivots,
+                     int32_t topk, int32_t exact_below, const msa_tree *T, int32_t n_nodes,
+                     int32_t *center, int32_t *lpole, int32_t *rpole, void *ws,
+                     size_t ws_bytes, int32_t *d_status, hipStream_t s) {
     int rc;
     if ((rc = check_seqs(S))) return rc;
     if (T == nullptr || center == nullptr || lpole == nullptr || rpole == nullptr ||
         T->mstart == nullptr || T->mcount == nullptr || T->depth == nullptr ||
         T->perm == nullptr || ws == nullptr || n_nodes < 0)
-        return MSA_EINVAL;
-    if (emb != nullptr &&
-        (topk < 1 || topk > kMaxTopk || exact_below < 0 || emb_q0 > kMaxEmbOffset))
         return MSA_EINVAL;
     if (S->n == 0 || n_nodes == 0) return n_nodes == 0 ? MSA_OK : MSA_EINVAL;
     if (S->n >= (1 << 24)) return MSA_ERANGE;
@@ -1380,6 +1468,7 @@ int tree_eval_centers(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.mcount = T->mcount;
     a.emb = emb;
     a.emb_q0 = emb_q0;
+    a.pivots = pivots;
     a.topk = topk;
     a.exact_below = exact_below;
     a.sigma = S->sigma;

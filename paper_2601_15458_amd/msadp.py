@@ -68,6 +68,10 @@ SIGNATURES = {
                                     C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
     "tree_eval_centers": (C.c_int, [SP, P, C.c_uint32, C.c_int32, C.c_int32, P, C.c_int32, P,
                                     P, P, P, C.c_size_t, P, P]),
+    "tree_build_sampled": (C.c_int, [SP, C.c_int32, C.c_int32, C.c_int32, P,
+                                     C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t, P, P]),
+    "tree_eval_centers_sampled": (C.c_int, [SP, C.c_int32, C.c_int32, C.c_int32, P, C.c_int32,
+                                            P, P, P, P, C.c_size_t, P, P]),
     "tree_insert_workspace_bytes": (C.c_size_t, [SP, C.c_int32, C.c_int32]),
     "tree_insert": (C.c_int, [SP, C.c_int32, P, C.c_int32, P, C.POINTER(C.c_int32), P,
                               C.c_size_t, P, P]),
@@ -542,11 +546,16 @@ class TreeBuilder:
     """Reusable Alg. 1 builder for one sequence set.  With emb (device
     float32 [n, 128]) the medoid is pruned to the topk members that the
     embedding ranks first (tree_build_pruned); emb_offset is the calibration
-    offset added to every embedding distance."""
+    offset added to every embedding distance.  With pivots > 0 (and no emb)
+    the topk members closest in sum to `pivots` hashed members are the
+    candidates (tree_build_sampled)."""
 
     def __init__(self, S: Seqs, use_graph=False, emb=None, topk=16, exact_below=0,
-                 emb_offset=0.0):
+                 emb_offset=0.0, pivots=0):
         self.S = S
+        self.pivots = int(pivots)
+        if self.pivots and emb is not None:
+            raise ValueError("pivots and emb select different rankings: give one")
         if emb is not None:
             if (emb.dtype != torch.float32 or emb.device != S.codes.device
                     or tuple(emb.shape) != (S.n, 128) or not emb.is_contiguous()):
@@ -566,7 +575,13 @@ class TreeBuilder:
 
     def __call__(self, stream=None):
         nn = C.c_int32(0)
-        if self.emb is None:
+        if self.pivots:
+            rc = lib().tree_build_sampled(C.byref(self.ss), self.pivots, self.topk,
+                                          self.exact_below, C.byref(self.ts), C.byref(nn),
+                                          int(self.use_graph), _ptr(self.ws), self.wsb,
+                                          _ptr(self.st.t), _stream(stream))
+            _check(rc, "tree_build_sampled")
+        elif self.emb is None:
             rc = lib().tree_build(C.byref(self.ss), C.byref(self.ts), C.byref(nn),
                                   int(self.use_graph), _ptr(self.ws), self.wsb, _ptr(self.st.t),
                                   _stream(stream))
@@ -590,13 +605,13 @@ def emb_offset_q(offset: float) -> int:
 
 
 def tree_build(S: Seqs, use_graph=False, stream=None, emb=None, topk=16, exact_below=0,
-               emb_offset=0.0):
+               emb_offset=0.0, pivots=0):
     """Alg. 1 guide tree of S; returns host numpy arrays like the oracle's.
-    emb/topk/exact_below/emb_offset select the surrogate-pruned medoid (see
-    TreeBuilder)."""
+    emb/topk/exact_below/emb_offset select the surrogate-pruned medoid,
+    pivots/topk/exact_below the sampled one (see TreeBuilder)."""
     if use_graph and stream is None:
         stream = torch.cuda.Stream()
-    tb = TreeBuilder(S, use_graph, emb, topk, exact_below, emb_offset)
+    tb = TreeBuilder(S, use_graph, emb, topk, exact_below, emb_offset, pivots)
     with torch.cuda.stream(stream) if stream is not None else _nullctx():
         t = tb(stream)
     torch.cuda.synchronize()
@@ -630,10 +645,11 @@ def tree_insert(S: Seqs, n_old: int, tree, stream=None) -> Tree:
 
 
 def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, exact_below=0, emb_offset=0.0,
-                      stream=None):
+                      stream=None, pivots=0):
     """(center, lpole, rpole) host arrays that the build picks for each node
     of `tree` (a device Tree) when that node's members are given: the full
-    median (emb None) or the pruned one."""
+    median (emb None, pivots 0), the embedding-pruned one, or the sampled
+    one (pivots > 0)."""
     dev = S.codes.device
     if isinstance(tree, dict):
         tree = Tree.from_host(tree, dev)
@@ -646,11 +662,19 @@ def tree_eval_centers(S: Seqs, tree, emb=None, topk=16, exact_below=0, emb_offse
     wsb = lib().tree_workspace_bytes(C.byref(ss))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
     st = Status(dev)
-    rc = lib().tree_eval_centers(C.byref(ss), _ptr(emb), emb_offset_q(emb_offset), int(topk),
-                                 int(exact_below),
-                                 C.byref(ts), nn,
-                                 *[_ptr(o) for o in out], _ptr(ws), wsb, _ptr(st.t),
-                                 _stream(stream))
+    if pivots:
+        if emb is not None:
+            raise ValueError("pivots and emb select different rankings: give one")
+        rc = lib().tree_eval_centers_sampled(C.byref(ss), int(pivots), int(topk),
+                                             int(exact_below), C.byref(ts), nn,
+                                             *[_ptr(o) for o in out], _ptr(ws), wsb,
+                                             _ptr(st.t), _stream(stream))
+    else:
+        rc = lib().tree_eval_centers(C.byref(ss), _ptr(emb), emb_offset_q(emb_offset), int(topk),
+                                     int(exact_below),
+                                     C.byref(ts), nn,
+                                     *[_ptr(o) for o in out], _ptr(ws), wsb, _ptr(st.t),
+                                     _stream(stream))
     _check(rc, "tree_eval_centers")
     torch.cuda.synchronize()
     st.check("tree_eval_centers")

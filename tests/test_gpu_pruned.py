@@ -264,3 +264,19 @@ def test_learned_workload_full_size_sampled():
         print(f"[pruned] node {v} ({len(mem)} members) against the oracle", flush=True)
         want = orc.select(codes, off, mem, emb, 16, 0, emb_q0=M.emb_offset_q(0.5))
         assert (int(t["center"][v]), int(t["lpole"][v]), int(t["rpole"][v])) == want, v
+
+
+def test_every_member_a_candidate_on_a_large_cluster():
+    """topk covering a 400-member root: the candidate pass then holds every
+    member against every member (more work items than the medoid triangle),
+    and the tree is the exact one."""
+    import torch
+    M = _msadp()
+    d = synth.protein_tree()
+    rng = np.random.default_rng(55)
+    sub = synth.subset(d, rng.choice(d["n"], size=400, replace=False))
+    S = M.to_device(sub["codes"], sub["offsets"], 20)
+    exact = M.tree_build(S)
+    e = torch.from_numpy(_emb(56, 400)).to(S.codes.device)
+    _equal_trees(M.tree_build(S, emb=e, topk=1024), exact)
+    _equal_trees(M.tree_build(S, emb=e, topk=4, exact_below=400), exact)

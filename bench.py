@@ -93,7 +93,8 @@ def parse():
                     help="hybrid point: clusters of at most this many members keep the full median")
     ap.add_argument("--points", default="",
                     help="pruned builds to run instead of the default set, as ranker:topk:"
-                         "exact_below items (rankers cnn, cnn_raw, shortest, random)")
+                         "exact_below items (rankers cnn, cnn_raw, shortest, random, "
+                         "sampled4, sampled8, sampled16)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -782,6 +783,10 @@ def bench_pruned(msadp, synth, torch, args):
     rankers = {"cnn": (emb, off), "cnn_raw": (emb, 0.0),
                "shortest": (learned.control_embeddings(S, "zero"), 1.0),
                "random": (learned.control_embeddings(S, "random", seed=14), 0.0)}
+    # the median over a smaller subset (Sec. 2.1): candidates ranked by their
+    # summed exact distance to P hashed members ("sampledP"); no embedding
+    for p in (4, 8, 16):
+        rankers[f"sampled{p}"] = (None, 0.0)
     # (ranker, topk, exact_below): pure top-k pruning of every cluster, and
     # the hybrid that keeps the full median for clusters it finds cheap
     # the four rankers at top-16; more candidates (64, 96) and the hybrid
@@ -790,7 +795,9 @@ def bench_pruned(msadp, synth, torch, args):
     points = [("cnn", args.topk, 0), ("cnn_raw", args.topk, 0), ("shortest", args.topk, 0),
               ("random", args.topk, 0),
               ("cnn", 64, 0), ("cnn", 96, 0), ("shortest", 96, 0),
-              ("cnn", args.topk, args.exact_below), ("cnn", args.topk, 8 * args.exact_below)]
+              ("cnn", args.topk, args.exact_below), ("cnn", args.topk, 8 * args.exact_below),
+              ("sampled8", args.topk, 0), ("sampled16", args.topk, 0), ("sampled8", 32, 0),
+              ("sampled16", 32, 0)]
     if args.points:
         points = []
         for item in args.points.split(","):
@@ -799,11 +806,13 @@ def bench_pruned(msadp, synth, torch, args):
                 raise ValueError(f"unknown ranker {name!r} (one of {sorted(rankers)})")
             points.append((name, int(topk), int(eb)))
     out["points"] = []
-    quality_points = {("cnn", args.topk, 0), ("cnn", 96, 0), ("shortest", 96, 0)}
+    quality_points = {("cnn", args.topk, 0), ("cnn", 96, 0), ("shortest", 96, 0),
+                      ("sampled16", 32, 0)}
     for name, topk, eb in points:
         e, eo = rankers[name]
+        piv = int(name[len("sampled"):]) if name.startswith("sampled") else 0
         b = msadp.TreeBuilder(S, use_graph=True, emb=e, topk=topk, exact_below=eb,
-                              emb_offset=eo)
+                              emb_offset=eo, pivots=piv)
         times = []
         with torch.cuda.stream(stream):
             b(stream)
@@ -818,12 +827,14 @@ def bench_pruned(msadp, synth, torch, args):
         if (name, topk, eb) in quality_points:
             quality = msa_quality_of(t)
         t = t.host()
-        clr = msadp.tree_eval_centers(S, exact, emb=e, topk=topk, exact_below=eb, emb_offset=eo)
+        clr = msadp.tree_eval_centers(S, exact, emb=e, topk=topk, exact_below=eb, emb_offset=eo,
+                                      pivots=piv)
         agree = learned.agreement(exact, clr, min_size=17, pruned_above=max(topk, eb))
         rep = learned.reproduced_clusters(exact, t)
         nd, ex_mean, ex_max = learned.rowsum_excess(S, exact, clr, max(topk, eb))
         tp = float(np.median(times))
-        out["points"].append({"ranker": name, "offset": round(eo, 4), "topk": topk,
+        out["points"].append({"ranker": name, "offset": round(eo, 4), "pivots": piv,
+                              "topk": topk,
                               "exact_below": eb,
                               "build_s": round(tp, 4), "speedup": round(t_exact / tp, 2),
                               "agreement": agree, "reproduced_clusters": round(rep, 4),

@@ -278,9 +278,12 @@ int tree_build_pruned(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
  * k > topk, the min(pivots, k) members with the least h(i) are the pivots,
  * h being MurmurHash3's 32-bit finalizer (Appleby) of the input index i
  * (h ^= h >> 16; h *= 0x85EBCA6B; h ^= h >> 13; h *= 0xC2B2AE35;
- * h ^= h >> 16: a bijection, so no two members tie); every member x gets
- * E(x) = sum over the pivots p of f(x, p), and the topk members with the
- * least (E, input index) are the candidates.  The candidates get exact row
+ * h ^= h >> 16: a bijection, so no two members tie); with s = min(pivots,
+ * k), every member x gets E(x) = (sum over the pivots p of f(x, p)) times
+ * s if x is a pivot and max(s - 1, 1) otherwise (so that a pivot's missing
+ * self-term does not favour it: the ranking compares mean distances to the
+ * pivots other than x), and the topk members with the least (E, input
+ * index) are the candidates.  The candidates get exact row
  * sums over the cluster and c is the one with the least (lowest input index
  * on ties); poles and split stay exact.  A pruned cluster costs about
  * (pivots + topk) k distances instead of the medoid's k (k - 1) / 2.

@@ -376,9 +376,11 @@ static uint32_t pivot_hash(uint32_t h) {
  * every member is one; c is the candidate with the least exact sum of f
  * over C (lowest input index on ties).  The estimate is either the sum over
  * C (x itself included) of emb_estimate (ecode != NULL), or, with pivots > 0,
- * the sum of f(x, p) over the min(pivots, k) members p of least pivot_hash
- * (the median over a smaller subset that Sec. 2.1 allows, with the subset
- * drawn by the hash). */
+ * the sum of f(x, p) over the s = min(pivots, k) members p of least
+ * pivot_hash (the median over a smaller subset that Sec. 2.1 allows, with
+ * the subset drawn by the hash), times s for a pivot and max(s - 1, 1) for
+ * any other member: a pivot's sum lacks the term of itself, so the ranking
+ * compares each member's mean distance to the pivots other than itself. */
 static void select_impl(const uint8_t *codes, const int64_t *off, const int32_t *C, int64_t k,
                         const int8_t *ecode, int eshift, uint32_t emb_q0, int32_t topk,
                         int32_t exact_below, int32_t pivots, int32_t out[3]) {
@@ -429,6 +431,11 @@ static void select_impl(const uint8_t *codes, const int64_t *off, const int32_t 
                 for (int64_t x = 0; x < k; ++x) E[x] += (uint64_t)row[x];
                 free(row);
             }
+            /* a pivot's sum has one term fewer (its distance to itself is
+             * 0): compare means over the other pivots, scaled to integers,
+             * E(x) * (np if x is a pivot else max(np - 1, 1)) */
+            for (int64_t x = 0; x < k; ++x)
+                E[x] *= (uint64_t)(piv[x] ? np : (np > 1 ? np - 1 : 1));
             free(piv);
         }
         char *taken = (char *)calloc((size_t)k, 1);

@@ -797,6 +797,15 @@ __device__ void block_sort_keys(uint64_t *e, uint32_t *id, int n) {
 constexpr int kTopkThreads = 256;
 constexpr int kTopkSel = 2048;      // members a selection may collect in LDS
 
+constexpr uint64_t kPivotFlag = 1ull << 63;
+
+__device__ __forceinline__ uint64_t estimate(uint64_t v, bool sampled, int64_t ps) {
+    if (!sampled) return v;
+    const bool piv = (v & kPivotFlag) != 0;
+    const uint64_t m = piv ? (uint64_t)ps : (uint64_t)(ps > 1 ? ps - 1 : 1);
+    return (v & ~kPivotFlag) * m;
+}
+
 // Candidates of each cluster, from its first candidate slot on: every member
 // of a cluster of at most max(exact_below, topk) members (one full row sum
 // each, which keeps every work item 64 texts wide); otherwise the topk members
@@ -812,6 +821,10 @@ constexpr int kTopkSel = 2048;      // members a selection may collect in LDS
 // estimate slots, in pruned clusters only; it then clears those slots for
 // the pivot pass and sets the candidates' count for phase 1.
 __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
+    // Phase 1 of the sampled median ranks by the mean distance to the pivots
+    // other than the member itself: sum * s for a pivot, * max(s - 1, 1) for
+    // the others (s = the cluster's pivots).
+    const bool sampled = phase == 1 && a.emb == nullptr && a.pivots > 0;
     __shared__ uint64_t se[kTopkSel];
     __shared__ uint32_t si[kTopkSel];
     __shared__ uint32_t count;
@@ -820,6 +833,7 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
         const bool small = k <= a.exact_below || k <= a.topk;
+        const int64_t ps = min<int64_t>(a.pivots, k);
         if (phase == 0 && small) {         // uniform per block
             if (threadIdx.x == 0) a.cnt[q] = 0;
             continue;
@@ -838,7 +852,7 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
                 uint64_t be = ~0ull;
                 uint32_t bi = ~0u;
                 for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
-                    const uint64_t sv = a.rowsum[ms + i];
+                    const uint64_t sv = estimate(a.rowsum[ms + i], sampled, ps);
                     const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
                     if (key_less(sv, oi, be, bi)) { be = sv; bi = oi; }
                 }
@@ -852,7 +866,7 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
                 __syncthreads();
                 // every member with key <= (te, ti)
                 for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
-                    const uint64_t sv = a.rowsum[ms + i];
+                    const uint64_t sv = estimate(a.rowsum[ms + i], sampled, ps);
                     const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
                     if (!key_less(te, ti, sv, oi)) {
                         const uint32_t slot = atomicAdd(&count, 1u);
@@ -887,7 +901,7 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
                     uint64_t bs = ~0ull;
                     uint32_t bi = ~0u;
                     for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
-                        const uint64_t sv = a.rowsum[ms + i];
+                        const uint64_t sv = estimate(a.rowsum[ms + i], sampled, ps);
                         const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
                         if (have_last && !key_less(last_s, last_i, sv, oi)) continue;
                         if (key_less(sv, oi, bs, bi)) { bs = sv; bi = oi; }
@@ -914,7 +928,13 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
         if (threadIdx.x == 0) a.cnt[q] = k >= 2 ? nc * ((k + 63) / 64) : 0;
         if (phase == 0) {
             __syncthreads();               // every hash has been read
-            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) a.rowsum[ms + i] = 0;
+            // clear the estimates, keeping a pivot flag in the top bit
+            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
+                const int32_t r = a.perm[ms + i];
+                bool piv = false;
+                for (int64_t j = 0; j < nc; ++j) piv |= a.cand[base + j] == r;
+                a.rowsum[ms + i] = piv ? kPivotFlag : 0ull;
+            }
             if (threadIdx.x == 0) a.ncand[q] = a.topk;
         }
         __syncthreads();

@@ -67,8 +67,12 @@ def _choice(seqs, mem, pivots, topk, exact_below):
         return int(mem[0]), -1, -1
     rows = D.sum(1)
     if k > exact_below and k > topk:
-        piv = sorted(range(k), key=lambda i: fmix32(int(mem[i])))[:min(pivots, k)]
-        E = D[:, piv].sum(1)
+        s = min(pivots, k)
+        piv = sorted(range(k), key=lambda i: fmix32(int(mem[i])))[:s]
+        # mean distance to the pivots other than x, as an exact fraction
+        from fractions import Fraction
+        E = [Fraction(int(D[i, piv].sum()), s - 1 if i in piv else s) if s > 1 or i not in piv
+             else Fraction(0) for i in range(k)]
         cand = sorted(range(k), key=lambda i: (E[i], mem[i]))[:topk]
     else:
         cand = list(range(k))
@@ -98,6 +102,24 @@ def test_every_node_by_brute_force(pivots, topk, exact_below):
             l, r = got[1], got[2]
             want = {int(x) for x in mem if orc.lev(seqs[l], seqs[x]) <= orc.lev(seqs[r], seqs[x])}
             assert L == want
+
+
+def test_a_pivot_is_not_favoured_by_its_own_zero_distance():
+    """Three sequences where the pivot's sum over all pivots (its own 0
+    included) would rank it first, but its mean distance to the other
+    pivots does not."""
+    pivot_of = sorted(range(3), key=fmix32)
+    a, b, c = pivot_of          # a has the least hash
+    seqs = [None] * 3
+    seqs[a] = np.array([0] * 10, np.uint8)               # far from both others
+    seqs[b] = np.array([1] * 10, np.uint8)
+    seqs[c] = np.array([1] * 9 + [2], np.uint8)
+    codes, off = synth.to_csr(seqs)
+    # one pivot (a): every estimate is the distance to a, so a itself ranks first
+    assert orc.select(codes, off, [0, 1, 2], topk=1, pivots=1)[0] == a
+    # two pivots (a, b): a's mean to b is 10, b's mean to a is 10, c's mean
+    # to (a, b) is (10 + 1) / 2: c wins though it is no pivot
+    assert orc.select(codes, off, [0, 1, 2], topk=1, pivots=2)[0] == c
 
 
 def test_sampled_families_beat_shortest_first():

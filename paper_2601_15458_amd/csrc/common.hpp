@@ -57,6 +57,45 @@ struct Staged {
 
 inline int64_t staged_stride(int32_t max_len) { return ((int64_t)max_len + 16 + 15) / 16 * 16; }
 
+// Launch order for batches that give each pair a workgroup of its own and
+// hold about one such workgroup per CU: longest first (the largest m * n),
+// so that the long pairs start at once and the short ones fill the CUs that
+// free up (list scheduling, longest processing time first).  order[r] = the
+// pair of rank r; equal sizes keep their index order; pairs with an index
+// out of range count as empty (the fill reports them).  O(P^2) work, used
+// for batches of at most kLptMaxPairs pairs (beyond that many pairs per CU
+// even out and the index order is kept).
+constexpr int64_t kLptMaxPairs = 8192;
+constexpr int kLptTile = 1024;
+
+__device__ __forceinline__ int64_t pair_cells(const Staged &A, const Staged &B,
+                                              const int32_t *ia, const int32_t *ib, int64_t q) {
+    const int32_t x = ia[q], y = ib[q];
+    if (x < 0 || x >= A.n || y < 0 || y >= B.n) return 0;
+    return (int64_t)A.len[x] * B.len[y];
+}
+
+template <int kTile>
+__global__ void __launch_bounds__(256) k_lpt_order(Staged A, Staged B, const int32_t *ia,
+                                                   const int32_t *ib, int64_t P,
+                                                   int32_t *order) {
+    __shared__ int64_t keys[kTile];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t kp = p < P ? pair_cells(A, B, ia, ib, p) : 0;
+    int64_t rank = 0;
+    for (int64_t base = 0; base < P; base += kTile) {
+        const int64_t cnt = P - base < kTile ? P - base : kTile;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < cnt; i += 256) keys[i] = pair_cells(A, B, ia, ib, base + i);
+        __syncthreads();
+        for (int64_t i = 0; i < cnt; ++i) {
+            const int64_t kq = keys[i];
+            rank += (kq > kp || (kq == kp && base + i < p)) ? 1 : 0;
+        }
+    }
+    if (p < P) order[rank] = (int32_t)p;
+}
+
 // ----------------------------------------------------------- host helpers
 // Bump allocator over the caller's workspace (256-byte aligned pieces).
 struct Carve {

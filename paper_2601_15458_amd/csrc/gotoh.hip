@@ -20,7 +20,7 @@
 // steps, which orders each ring write before its read.
 //
 // Codes.  Per cell one byte, four signs u = sign(x) + 1 in {0, 1, 2} as the
-// base-3 digits of u0 + 3 u1 + 9 u2 + 27 u3 (at most 80):
+// 2-bit fields of u0 + 4 u1 + 16 u2 + 64 u3 (at most 170):
 //   u0: hd - max(E, F)      (hd = H[i-1][j-1] + sub: the diagonal)
 //   u1: F - E
 //   u2: (H[i][j-1] - open - ext) - (E[i][j-1] - ext)    (E opens / extends)
@@ -75,9 +75,16 @@ struct GotohArgs {
     uint8_t *tb;
     const int64_t *tb_off;
     int32_t *st;
+    const int32_t *order;    // launch order (longest pair first), or null
 };
 
 constexpr int kGDppWaveShr1 = 0x138;   // DPP: shift the wavefront right by one lane
+
+// Code records are written through a global-address-space pointer: a flat
+// store would count against the LDS wait counter too, and every LDS read of
+// the score table would then wait for the step's store to complete.
+typedef unsigned int gu32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) gu32x4 g_uint4;
 
 // sign(x - y) in {-1, 0, 1}: one subtraction and one v_med3_i32 (written
 // out, so that the compiler does not turn it into two compares and selects)
@@ -85,6 +92,15 @@ __device__ __forceinline__ int32_t sign_of(int32_t x, int32_t y) {
     int32_t d = x - y, s;
     asm volatile("v_med3_i32 %0, %1, -1, 1" : "=v"(s) : "v"(d));
     return s;
+}
+
+// a << sh + b in one instruction (v_lshl_add_u32), exact in wrapping
+// 32-bit arithmetic for signed a and b
+template <int SH>
+__device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(SH), "v"(b));
+    return r;
 }
 
 struct GotohLane {
@@ -98,11 +114,11 @@ struct GotohLane {
 // One round of kGRound steps.  kSteady: every lane's column lies in [0, n)
 // for the whole round (no range checks).
 template <bool kSteady>
-__device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)[kGRows / 2],
+__device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)[kGRows / 4],
                                             const int32_t *sub_lds, uint32_t feedH,
                                             uint32_t feedP, int t0, int shift, int n,
                                             int32_t open, int32_t ext, bool rec_ok,
-                                            uint4 *rec, int64_t rec_step, uint2 *ring_out,
+                                            g_uint4 *rec, int64_t rec_step, uint2 *ring_out,
                                             int lane) {
     const int32_t oe = open + ext;
 #pragma unroll 1
@@ -116,15 +132,21 @@ __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)
         const int jj = t0 + s - shift;
         const bool in = kSteady || (jj >= 0 && jj < n);
         const int32_t sym = (int32_t)(pk & 0xFFu);
+        const int32_t col = sym * kSubStride;
+        // the row symbols are read afresh each step: otherwise the compiler
+        // hoists 16 unpacked offsets out of the loop and spills them
+        uint32_t rs[kGRows / 4] = {roff[0], roff[1], roff[2], roff[3]};
+        asm volatile("" : "+v"(rs[0]), "+v"(rs[1]), "+v"(rs[2]), "+v"(rs[3]));
         int32_t up_h = htop;
         int32_t up_f = htop - (int32_t)(pk >> 8);
         int32_t diag = L.htop;
-        uint32_t code[kGRows / 4] = {0, 0, 0, 0};
+        // each byte gets its +85 (the +1 of every field) from the start value
+        uint32_t code[kGRows / 4] = {0x55555555u, 0x55555555u, 0x55555555u, 0x55555555u};
         // outside [0, n) a lane keeps its state (its first column is still
         // to come, or its last is done)
 #pragma unroll
         for (int r = 0; r < kGRows; ++r) {
-            const int32_t sv = sub_lds[((roff[r >> 1] >> (16 * (r & 1))) & 0xFFFFu) + sym];
+            const int32_t sv = sub_lds[col + ((rs[r >> 2] >> (8 * (r & 3))) & 0xFFu)];
             int32_t hprev = L.H[r], eprev = L.E[r];
             // tie the row's inputs to the row above's result, so that the
             // compiler does not compute every row's E ahead of the chain
@@ -137,10 +159,21 @@ __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)
             const int32_t hd = diag + sv;
             const int32_t mef = max(e, f);
             const int32_t h = max(hd, mef);
-            // four signs as base-3 digits (sign + 1), one byte in [0, 80]
-            const int32_t c = sign_of(hd, mef) + 3 * sign_of(f, e) + 9 * sign_of(e_opn, e_ext) +
-                              27 * sign_of(f_opn, f_ext) + 40;
-            code[r >> 2] |= (uint32_t)c << (8 * (r & 3));
+            // four signs as 2-bit fields (sign + 1): c = s0 + 4 s1 + 16 s2 +
+            // 64 s3 in [-85, 85], added into the code word at the row's byte;
+            // the words start at 85 per byte, so every byte ends in [0, 170]
+            // and the wrapping sum carries nothing between bytes.  Shifts and
+            // adds only: v_mul_lo_u32 issues at a quarter of the rate.
+            const uint32_t c =
+                lshl_add<2>((uint32_t)sign_of(f, e), (uint32_t)sign_of(hd, mef));
+            const uint32_t c2 = lshl_add<4>((uint32_t)sign_of(e_opn, e_ext), c);
+            const uint32_t c3 = lshl_add<6>((uint32_t)sign_of(f_opn, f_ext), c2);
+            switch (r & 3) {   // resolved at compile time (the row loop is unrolled)
+                case 0: code[r >> 2] = lshl_add<0>(c3, code[r >> 2]); break;
+                case 1: code[r >> 2] = lshl_add<8>(c3, code[r >> 2]); break;
+                case 2: code[r >> 2] = lshl_add<16>(c3, code[r >> 2]); break;
+                default: code[r >> 2] = lshl_add<24>(c3, code[r >> 2]); break;
+            }
             // the code is formed here, not sunk into the (conditional) store,
             // which would keep every row's six compared values alive
             asm volatile("" : "+v"(code[r >> 2]));
@@ -156,20 +189,23 @@ __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)
             L.htop = htop;
             L.outH = up_h;
             L.outP = (uint32_t)sym | ((uint32_t)dF << 8);
-            if (rec_ok) *rec = make_uint4(code[0], code[1], code[2], code[3]);
+            if (rec_ok) *rec = gu32x4{code[0], code[1], code[2], code[3]};
             if (lane == 63) ring_out[jj & (kGRing - 1)] = make_uint2((uint32_t)L.outH, L.outP);
         }
-        rec = (uint4 *)((uint8_t *)rec + rec_step);
+        rec = (g_uint4 *)((uintptr_t)rec + (uintptr_t)rec_step);
     }
 }
 
 __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
     __shared__ int32_t sub_lds[kSubStride * kSubStride];
     __shared__ uint2 ring[kGMaxWaves * kGRing];
-    const int64_t p = blockIdx.x;
+    const int64_t p = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int e = threadIdx.x; e < kSubStride * kSubStride; e += blockDim.x) sub_lds[e] = a.sub[e];
+    // transposed: sub_lds[b * kSubStride + a] = sub[a][b], so that a step's
+    // column of scores starts at one offset and each row adds its symbol
+    for (int e = threadIdx.x; e < kSubStride * kSubStride; e += blockDim.x)
+        sub_lds[(e % kSubStride) * kSubStride + e / kSubStride] = a.sub[e];
     __syncthreads();
     const int32_t x = a.ia[p], y = a.ib[p];
     if (x < 0 || x >= a.A.n || y < 0 || y >= a.B.n) {
@@ -197,19 +233,16 @@ __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
     const bool lane_ok = g < G;
     const int32_t open = a.open, ext = a.ext;
 
-    // the lane's pattern symbols as offsets into the score table, two per
-    // register (16-bit halves)
-    uint32_t roff[kGRows / 2];
+    // the lane's 16 pattern symbols, four per register (one byte each):
+    // row r's score at column j is sub_lds[b_j * kSubStride + byte r]
+    uint32_t roff[kGRows / 4];
     {
         uint4 q = make_uint4(0, 0, 0, 0);
         if (lane_ok) q = *(const uint4 *)(a.A.codes + (int64_t)x * a.A.stride + kGRows * g);
-        const uint32_t qs[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int r = 0; r < kGRows; r += 2) {
-            const uint32_t lo = ((qs[r >> 2] >> (8 * (r & 3))) & 0xFFu) * kSubStride;
-            const uint32_t hi = ((qs[r >> 2] >> (8 * ((r + 1) & 3))) & 0xFFu) * kSubStride;
-            roff[r >> 1] = lo | (hi << 16);
-        }
+        roff[0] = q.x;
+        roff[1] = q.y;
+        roff[2] = q.z;
+        roff[3] = q.w;
     }
     GotohLane L;
     const int32_t row0 = kGRows * g;   // the row above the lane
@@ -235,7 +268,7 @@ __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
     // advances by G records a step (unsigned wrap-around keeps the start,
     // which may lie before the region, exact)
     const int64_t rec0 = -(int64_t)(kGLag - 64) * w * G + g;
-    uint4 *rec = (uint4 *)((uintptr_t)tbp + (uintptr_t)(rec0 * (int64_t)sizeof(uint4)));
+    g_uint4 *rec = (g_uint4 *)((uintptr_t)tbp + (uintptr_t)(rec0 * (int64_t)sizeof(uint4)));
     const int64_t rec_step = G * (int64_t)sizeof(uint4);
     for (int rnd = 0; rnd < rounds; ++rnd) {
         const int t0 = rnd * kGRound;
@@ -264,7 +297,7 @@ __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
         else
             gotoh_round<false>(L, roff, sub_lds, feedH, feedP, t0, shift, n, open, ext, lane_ok,
                                rec, rec_step, ring_out, lane);
-        rec = (uint4 *)((uint8_t *)rec + kGRound * rec_step);
+        rec = (g_uint4 *)((uintptr_t)rec + (uintptr_t)(kGRound * rec_step));
     }
     // the lane state stopped at the last column: H[m][n] is row r_last's H
     if (score_lane && a.score) {
@@ -356,10 +389,10 @@ __global__ void __launch_bounds__(64) k_gotoh_traceback(GotohTbArgs a) {
         const uint32_t w0 = dw == 0 ? d0 : dw == 1 ? d1 : dw == 2 ? d2 : d3;
         const uint32_t w1 = dw == 0 ? e0 : dw == 1 ? e1 : dw == 2 ? e2 : e3;
         const uint32_t c = ((q == 0 ? w0 : w1) >> (8 * (r & 3))) & 0xFFu;
-        const uint32_t u0 = c % 3u, u1 = (c / 3u) % 3u;
+        const uint32_t u0 = c & 3u, u1 = (c >> 2) & 3u;
         const bool hM = u0 >= 1u;                // the diagonal reaches H
         const bool hD = u1 >= 1u && u0 <= 1u;    // F reaches H
-        const uint32_t ne = (nextc / 9u) % 3u, nf = nextc / 27u;
+        const uint32_t ne = (nextc >> 4) & 3u, nf = nextc >> 6;
         uint32_t op;
         if (last == 1u) {          // after D: F[i+1][j] opens (nf >= 1) or extends (nf <= 1)
             op = (hM && nf >= 1u) ? 0u : (nf <= 1u ? 1u : 2u);
@@ -410,10 +443,11 @@ static int gotoh_check_costs(const int32_t *sub, int32_t sigma, int32_t open, in
 struct GotohWs {
     Staged SA, SB;
     int32_t *sub;
+    int32_t *order;
 };
 
 template <class Alloc>
-static GotohWs carve_gotoh(Alloc &al, const msa_seqs *A, const msa_seqs *B) {
+static GotohWs carve_gotoh(Alloc &al, const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
     GotohWs w;
     const int64_t sa = staged_stride(A->max_len), sb = staged_stride(B->max_len);
     w.SA = Staged{al.template take<uint8_t>((size_t)A->n * sa),
@@ -421,6 +455,10 @@ static GotohWs carve_gotoh(Alloc &al, const msa_seqs *A, const msa_seqs *B) {
     w.SB = Staged{al.template take<uint8_t>((size_t)B->n * sb),
                   al.template take<int32_t>((size_t)B->n + 1), sb, B->n};
     w.sub = al.template take<int32_t>(kSubStride * kSubStride);
+    // launch order; min(n_pairs, kLptMaxPairs) entries, so that a workspace
+    // sized for a batch also holds any smaller one
+    w.order = al.template take<int32_t>((size_t)std::min<int64_t>(n_pairs, kLptMaxPairs));
+    if (n_pairs > kLptMaxPairs) w.order = nullptr;
     return w;
 }
 
@@ -438,7 +476,7 @@ size_t gotoh_tb_bytes(int32_t m, int32_t n) {
 size_t gotoh_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
     if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
     Sizer sz;
-    carve_gotoh(sz, A, B);
+    carve_gotoh(sz, A, B, n_pairs);
     return sz.total();
 }
 
@@ -456,10 +494,10 @@ int gotoh_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const i
     if (n_pairs > 0x7fffffffLL) return MSA_ERANGE;
     if (A->max_len > kGMaxRows) return MSA_ERANGE;
     Sizer sz;
-    carve_gotoh(sz, A, B);
+    carve_gotoh(sz, A, B, n_pairs);
     if (ws_bytes < sz.total()) return MSA_ENOSPC;
     Carve cv(ws, ws_bytes);
-    const GotohWs w = carve_gotoh(cv, A, B);
+    const GotohWs w = carve_gotoh(cv, A, B, n_pairs);
     // the score table, padded to a row stride of kSubStride
     int32_t table[kSubStride * kSubStride] = {};
     for (int x = 0; x < A->sigma; ++x)
@@ -469,7 +507,10 @@ int gotoh_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const i
     if ((rc = stage_set(A, nullptr, w.SA, d_status, s))) return rc;
     if ((rc = stage_set(B, nullptr, w.SB, d_status, s))) return rc;
     const int waves = (int)std::max<int64_t>(1, (gotoh_lanes(A->max_len) + 63) / 64);
-    GotohArgs ga{w.SA, w.SB, ia, ib, w.sub, open, ext, score, tb, tb_offsets, d_status};
+    if (w.order)
+        hipLaunchKernelGGL(k_lpt_order<kLptTile>, dim3((unsigned)((n_pairs + 255) / 256)),
+                           dim3(256), 0, s, w.SA, w.SB, ia, ib, n_pairs, w.order);
+    GotohArgs ga{w.SA, w.SB, ia, ib, w.sub, open, ext, score, tb, tb_offsets, d_status, w.order};
     hipLaunchKernelGGL(k_gotoh_fill, dim3((unsigned)n_pairs), dim3(64 * waves), 0, s, ga);
     return launch_status();
 }

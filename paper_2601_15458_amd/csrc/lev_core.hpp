@@ -231,12 +231,14 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(3))) u32x4 lds_u128;
 
 // lev_pass for a lane's bit-plane table (first and only pass; see lev_pass).
-// The match mask of symbol t is (P0 ^ m0) & (P1 ^ m1) with mb = all ones
-// where bit b of t is 0.
+// The match mask of symbol t is ~((P0 ^ s0) | (P1 ^ s1)) with sb = all ones
+// where bit b of t is 1 (a sign-extended bit field).  Holding the planes in
+// registers instead of LDS was tried: 148 VGPRs for 8 words, 3 wavefronts
+// per SIMD instead of 5, and slower.
 template <int W>
 __device__ __forceinline__ int lev_pass_planes(lds_u128 *tbl, const uint8_t *text, int n,
                                                int nmax, int b) {
-    constexpr uint8_t kAndXor = MSADP_LUT(A & (B ^ C));
+    constexpr uint8_t kNorXor = MSADP_LUT(~(A | (B ^ C)));
     uint32_t pl[W], ph[W], ml[W], mh[W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
@@ -251,13 +253,18 @@ __device__ __forceinline__ int lev_pass_planes(lds_u128 *tbl, const uint8_t *tex
         if (j0 + 16 < nmax) nxt = tp[(j0 >> 4) + 1];
         uint32_t c0 = cur.x, c1 = cur.y, c2 = cur.z, c3 = cur.w;
         const int steps = (int)uniform((uint32_t)min(16, nmax - j0));
-        for (int jj = 0; jj < steps; ++jj) {
-            const uint32_t t = c0 & 0xFFu;
-            c0 = __builtin_amdgcn_alignbyte(c1, c0, 1);
-            c1 = __builtin_amdgcn_alignbyte(c2, c1, 1);
-            c2 = __builtin_amdgcn_alignbyte(c3, c2, 1);
-            c3 >>= 8;
-            const uint32_t m0 = (t & 1u) - 1u, m1 = ((t >> 1) & 1u) - 1u;
+        for (int j4 = 0; j4 < steps; j4 += 4) {
+            const uint32_t wd = c0;      // symbols j4 .. j4 + 3, one byte each
+            c0 = c1;
+            c1 = c2;
+            c2 = c3;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+            const int jj = j4 + u;
+            if (jj >= steps) break;      // uniform
+            // s0, s1: all ones where bit 0, 1 of the text symbol is set
+            const uint32_t s0 = (uint32_t)((int32_t)(wd << (31 - 8 * u)) >> 31);
+            const uint32_t s1 = (uint32_t)((int32_t)(wd << (30 - 8 * u)) >> 31);
             uint32_t cph = 1u << 31, cmh = 0u;   // top row: +1
             uint32_t dp = 0, dn = 0;
             u32x4 q0 = tbl[0], q1 = {0u, 0u, 0u, 0u};
@@ -269,8 +276,8 @@ __device__ __forceinline__ int lev_pass_planes(lds_u128 *tbl, const uint8_t *tex
                     if (k & 1) q1 = tbl[(k + 2) * kWave];
                     else q0 = tbl[(k + 2) * kWave];
                 }
-                const uint32_t el = bop3<kAndXor>(q.x ^ m0, q.z, m1);
-                const uint32_t eh = bop3<kAndXor>(q.y ^ m0, q.w, m1);
+                const uint32_t el = bop3<kNorXor>(q.x ^ s0, q.z, s1);
+                const uint32_t eh = bop3<kNorXor>(q.y ^ s0, q.w, s1);
                 const uint32_t elm = el | (cmh >> 31);
                 const uint32_t xvl = el | ml[k], xvh = eh | mh[k];
                 unsigned int cy, cy2;
@@ -299,6 +306,7 @@ __device__ __forceinline__ int lev_pass_planes(lds_u128 *tbl, const uint8_t *tex
                              "+v"(mh[k]));
             }
             score += (j0 + jj < n) ? (int)dp - (int)dn : 0;
+            }
         }
         cur = nxt;
     }

@@ -65,6 +65,7 @@ struct FillArgs {
     const int64_t *tb_off;
     int32_t *st;
     int32_t planes;   // bits per symbol code
+    const int32_t *order;   // launch order (longest pair first), or null
 };
 
 // DPP control: shift the whole wavefront right by one lane.
@@ -235,7 +236,7 @@ __device__ void nw_fill_pair(const FillArgs &a, int64_t p, uint32_t *ring) {
 template <int P, int R>
 __global__ void __launch_bounds__(1024) k_nw_fill(FillArgs a) {
     __shared__ uint32_t ring[kMaxFillWaves * Round<R>::kRing];
-    nw_fill_pair<P, R>(a, blockIdx.x, ring);
+    nw_fill_pair<P, R>(a, a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x, ring);
 }
 
 // ------------------------------------------------------------ traceback
@@ -363,11 +364,15 @@ struct NwPlan {
 };
 
 template <class Alloc>
-static void nw_layout(Alloc &al, const msa_seqs *A, const msa_seqs *B, const NwPlan &pl) {
+static void nw_layout(Alloc &al, const msa_seqs *A, const msa_seqs *B, const NwPlan &pl,
+                      int64_t n_pairs) {
     al.template take<uint8_t>((size_t)A->n * pl.strideA);
     al.template take<int32_t>((size_t)A->n + 1);
     al.template take<uint8_t>((size_t)B->n * pl.strideB);
     al.template take<int32_t>((size_t)B->n + 1);
+    // launch order; sized min(n_pairs, kLptMaxPairs) so that a workspace
+    // sized for a batch also holds any smaller one
+    al.template take<int32_t>((size_t)std::min<int64_t>(n_pairs, kLptMaxPairs));
 }
 
 static NwPlan plan_nw(const msa_seqs *A, const msa_seqs *B) {
@@ -406,17 +411,22 @@ static int nw_batch_impl(const msa_seqs *A, const msa_seqs *B, const int32_t *ia
     if ((W + 63) / 64 > kMaxFillWaves) return MSA_ERANGE;   // patterns up to 32768 rows
     const NwPlan pl = plan_nw(A, B);
     Sizer sz;
-    nw_layout(sz, A, B, pl);
+    nw_layout(sz, A, B, pl, n_pairs);
     if (ws_bytes < sz.total()) return MSA_ENOSPC;
     Carve cv(ws, ws_bytes);
     Staged SA{cv.take<uint8_t>((size_t)A->n * pl.strideA), cv.take<int32_t>((size_t)A->n + 1),
               pl.strideA, A->n};
     Staged SB{cv.take<uint8_t>((size_t)B->n * pl.strideB), cv.take<int32_t>((size_t)B->n + 1),
               pl.strideB, B->n};
+    int32_t *order = cv.take<int32_t>((size_t)std::min<int64_t>(n_pairs, kLptMaxPairs));
+    if (n_pairs > kLptMaxPairs) order = nullptr;
     if ((rc = stage_set(A, nullptr, SA, d_status, s))) return rc;
     if ((rc = stage_set(B, nullptr, SB, d_status, s))) return rc;
     const int waves = (int)std::max<int64_t>(1, (W + 63) / 64);
-    FillArgs fa{SA, SB, ia, ib, score, tb, tb_offsets, d_status, bits_for(A->sigma)};
+    if (order)
+        hipLaunchKernelGGL(k_lpt_order<kLptTile>, dim3((unsigned)((n_pairs + 255) / 256)),
+                           dim3(256), 0, s, SA, SB, ia, ib, n_pairs, order);
+    FillArgs fa{SA, SB, ia, ib, score, tb, tb_offsets, d_status, bits_for(A->sigma), order};
     dim3 grid((unsigned)n_pairs), block(64 * waves);
     const int R = forced > 0 ? forced : tuned_value(MSA_TUNE_NW, A->sigma, waves, kDefaultRound);
     switch (R) {
@@ -439,7 +449,7 @@ size_t nw_tb_bytes(int32_t m, int32_t n) { return (size_t)tb_bytes(m, n); }
 size_t nw_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
     if (check_seqs(A) || check_seqs(B) || n_pairs < 0) return 0;
     Sizer sz;
-    nw_layout(sz, A, B, plan_nw(A, B));
+    nw_layout(sz, A, B, plan_nw(A, B), n_pairs);
     return sz.total();
 }
 

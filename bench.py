@@ -481,7 +481,13 @@ def bench_gotoh(msadp, synth, torch, args):
             "cells": cells, "fill_ms": round(f, 3), "traceback_ms": round(t, 3),
             "fill_gcups": round(cells / f / 1e6, 1),
             "gcups_fill_plus_traceback": round(cells / (f + t) / 1e6, 1),
-            "tb_bytes": tb, "fill_hbm_gbs": round(tb / f / 1e6, 1)}
+            "tb_bytes": tb, "fill_hbm_gbs": round(tb / f / 1e6, 1),
+            # one code byte per cell written: the fill's design bound is HBM
+            # writes (the ALU side is discussed with the kernel)
+            "roofline": {"bound": "hbm", "achieved": round(tb / f / 1e6, 1), "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(tb / f / 1e6 / 8000.0, 4),
+                         "traffic": (counted("k_gotoh_fill") or {}).get("hbm_bytes"),
+                         "kernel": "k_gotoh_fill"}}
 
 
 def bench_band(msadp, synth, torch, args):

@@ -236,6 +236,19 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def oracle_beside(args, fn, cells, sample):
+    """The oracle on a bounded sample of a leg's work, on the host's cores,
+    timed beside the device (skipped with --no-cpu)."""
+    if args.no_cpu:
+        return None
+    from oracle import pyoracle as orc
+    t0 = time.perf_counter()
+    fn()
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "sample": sample, "cells": int(cells), "seconds": round(dt, 3),
+            "gcups": round(cells / dt / 1e9, 3) if cells else None, "cores": orc.num_threads()}
+
+
 def _time_calls(torch, fn, stream, reps):
     fn()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -393,8 +406,14 @@ def bench_nw(msadp, synth, torch, args):
     f = float(np.median(fill))
     t = float(np.median(tb))
     tb_bytes = int(sum(msadp.lib().nw_tb_bytes(int(a), int(b)) for a, b in zip(la, lb)))
+    from oracle import pyoracle as orc
+    sel = np.arange(4)
+    cpu = oracle_beside(args, lambda: orc.nw_pairs(d["a_codes"], d["a_offsets"], d["b_codes"],
+                                                   d["b_offsets"], sel, sel),
+                        (la[sel] * lb[sel]).sum(),
+                        "full-matrix NW with traceback on pairs 0-3 of the 512")
     return {"workload": "nw_batch+nw_traceback: 512 DNA pairs, lengths U{5000..10000}, 10% "
-                        "divergence, unit costs, seed 4", "tuning": tuning,
+                        "divergence, unit costs, seed 4", "tuning": tuning, "cpu_oracle": cpu,
             "cells": cells, "fill_ms": round(f, 3), "traceback_ms": round(t, 3),
             "fill_gcups": round(cells / f / 1e6, 1),
             "gcups_fill_plus_traceback": round(cells / (f + t) / 1e6, 1),
@@ -476,8 +495,16 @@ def bench_gotoh(msadp, synth, torch, args):
     f = _time_calls(torch, lambda: g.fill(stream), stream, reps)
     t = _time_calls(torch, lambda: g.traceback(stream), stream, reps)
     tb = int(sum(msadp.lib().gotoh_tb_bytes(int(a), int(b)) for a, b in zip(la, lb)))
+    from oracle import pyoracle as orc
+    sel = np.argsort(la * lb, kind="stable")[:4].astype(np.int32)
+    cpu = oracle_beside(args, lambda: orc.gotoh_pairs(d["a_codes"], d["a_offsets"], d["b_codes"],
+                                                      d["b_offsets"], sel, sel, _dna_scores(),
+                                                      10, 1),
+                        (la[sel] * lb[sel]).sum(),
+                        "Gotoh's three full matrices and the walk on the 4 smallest pairs")
     return {"workload": "gotoh_batch+gotoh_traceback: 512 DNA pairs, lengths U{5000..10000}, "
                         "10% divergence, +5/-4 matrix, open 10, extension 1, seed 4",
+            "cpu_oracle": cpu,
             "cells": cells, "fill_ms": round(f, 3), "traceback_ms": round(t, 3),
             "fill_gcups": round(cells / f / 1e6, 1),
             "gcups_fill_plus_traceback": round(cells / (f + t) / 1e6, 1),
@@ -517,6 +544,12 @@ def bench_band(msadp, synth, torch, args):
     full = _time_calls(torch, lambda: nb.fill(stream), stream, reps)
     out["full_matrix_fill_ms"] = round(full, 3)
     out["full_matrix_gcups"] = round(cells / full / 1e6, 1)
+    from oracle import pyoracle as orc
+    sel = np.arange(32)
+    out["cpu_oracle"] = oracle_beside(
+        args, lambda: orc.lev_pairs(d["a_codes"], d["a_offsets"], d["b_codes"], d["b_offsets"],
+                                    sel, sel),
+        (la[sel] * lb[sel]).sum(), "Wagner-Fischer (all cells) on pairs 0-31 of the 512")
     return out
 
 
@@ -593,6 +626,17 @@ def bench_insert(msadp, synth, torch, args):
         return q
 
     gh, fh = grown.host(), full.host()
+    from oracle import pyoracle as orc
+    cpu = None
+    if not args.no_cpu:
+        small = synth.subset(allset, np.concatenate([np.arange(150),
+                                                     np.arange(n_old, n_old + 20)]))
+        seqs_small = synth.from_csr(small["codes"], small["offsets"])
+        old_small = orc.tree(*synth.to_csr(seqs_small[:150]))
+        cpu = oracle_beside(args, lambda: orc.tree_insert(small["codes"], small["offsets"], 150,
+                                                          old_small),
+                            0, "20 sequences into the oracle's tree of 150 (routing, "
+                               "re-partition, renumbering; cells not counted)")
     out = {"workload": "tree_insert: 1,000 of the 100,000 learned-workload DNA seqs (seed 42) "
                        "into the exact tree of the other 99,000",
            "old_build_s": round(t_old, 3), "insert_s": round(t_ins, 4),
@@ -600,6 +644,7 @@ def bench_insert(msadp, synth, torch, args):
            "nodes_old": int(old.n_nodes), "nodes_inserted": int(gh["n_nodes"]),
            "nodes_rebuilt": int(fh["n_nodes"]),
            "rebuilt_clusters_kept": round(learned.reproduced_clusters(fh, gh), 4),
+           "cpu_oracle": cpu,
            "alignment_quality": {"rows": "the 1,000 new and 9,000 seeded old rows, all pairs",
                                  "inserted": quality(grown), "rebuilt": quality(full)}}
     _log(f"insert: {out}")
@@ -637,11 +682,26 @@ def bench_tree(msadp, synth, torch, args):
     L = np.diff(d["offsets"]).astype(np.int64)
     cells = tree_cells(host, L)
     tg = times[True]
+    # the oracle's Alg. 1 and the device's on the same seeded 150-sequence
+    # subset (the full set would take the oracle hours)
+    from oracle import pyoracle as orc
+    sub = synth.subset(d, np.random.default_rng(39).choice(d["n"], 150, replace=False))
+    Ss = msadp.to_device(sub["codes"], sub["offsets"], d["sigma"])
+    msadp.tree_build(Ss)
+    t0 = time.perf_counter()
+    small = msadp.tree_build(Ss)
+    t_small = time.perf_counter() - t0
+    ls = np.diff(sub["offsets"]).astype(np.int64)
+    cpu = oracle_beside(args, lambda: orc.tree(sub["codes"], sub["offsets"]),
+                        tree_cells(small, ls),
+                        "Alg. 1 (full median) on a seeded 150-sequence subset")
+    if cpu:
+        cpu["device_seconds_same_subset"] = round(t_small, 4)
     return {"workload": "tree_build: 20,000 protein seqs (200 families, lognormal lengths "
                         "median 350 in [50, 2000], 30% divergence), seed 3", "tuning": tuning,
             "n_nodes": int(host["n_nodes"]), "depth": int(host["depth"].max()),
             "build_s_graph": round(tg, 4), "build_s_launches": round(times[False], 4),
-            "cells": cells, "gcups": round(cells / tg / 1e9, 1)}
+            "cells": cells, "gcups": round(cells / tg / 1e9, 1), "cpu_oracle": cpu}
 
 
 def _log(msg):

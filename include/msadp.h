@@ -436,9 +436,21 @@ int cnn_train_step(void *params, const msa_seqs *S, const int32_t *idx, int32_t 
  *     pairs of one pattern).  1 needs patterns of at most 32 / sigma' words
  *     (sigma' = 4, 8, 32 for sigma <= 4, <= 8, <= 32) and is the default when
  *     they fit; an entry of 1 that does not fit is ignored.
+ *   MSA_TUNE_TREE_XL: bin as for MSA_TUNE_TREE; value = which distance
+ *     passes of the tree builds run with one pair per group of lanes (the
+ *     pattern's 64-bit words spread over the group, carries passed lane to
+ *     lane), packing the pairs of several small clusters into one wavefront:
+ *     (WL << 28) | (pole cap << 14) | sum cap, WL = words per lane (1 or 2),
+ *     the group = the least power of two of lanes holding the longest
+ *     pattern (at most 64); clusters of at most `sum cap` members take
+ *     their medoid, pivot and candidate passes that way, clusters of at
+ *     most `pole cap` their pole passes (cap 0: none, 16383: every
+ *     cluster).  Default WL 2, sum cap 128, pole cap 16383; patterns of more
+ *     than 64 WL words use the one-wavefront-per-pattern passes only.
  * Workspace sizes never depend on the table.  Results never depend on it
  * (every variant computes the same exact values). */
-enum { MSA_TUNE_LEV = 0, MSA_TUNE_NW = 1, MSA_TUNE_TREE = 2, MSA_TUNE_PAIRS = 3 };
+enum { MSA_TUNE_LEV = 0, MSA_TUNE_NW = 1, MSA_TUNE_TREE = 2, MSA_TUNE_PAIRS = 3,
+       MSA_TUNE_TREE_XL = 4 };
 
 /* Set one entry (EINVAL for an unknown kind, a key out of range or a value
  * that is not a variant of the kind). */
@@ -488,6 +500,19 @@ int msa_autotune_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
 int msa_autotune_tree(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, int32_t use_graph,
                       void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
                       int32_t *d_status, hipStream_t s);
+
+/* Time the tree build once per across-lanes variant (msa_tune_candidates of
+ * MSA_TUNE_TREE_XL: off, pole passes only, and both kinds of pass up to
+ * cluster caps of 32 .. 256 members or for every cluster, with one or two
+ * words per lane) and store the fastest for (MSA_TUNE_TREE_XL, S->sigma,
+ * ceil(S->max_len / 64)).  pivots > 0 times tree_build_sampled(S, pivots,
+ * topk, 0, ...), pivots = 0 the exact tree_build.  Every variant builds the
+ * same tree (left in T, *n_nodes).  Arguments otherwise as tree_build;
+ * *best = the value stored, *best_ms = its time per build. */
+int msa_autotune_tree_xl(const msa_seqs *S, int32_t pivots, int32_t topk, const msa_tree *T,
+                         int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
+                         int32_t reps, int32_t *best, float *best_ms, int32_t *d_status,
+                         hipStream_t s);
 
 /* ------------------------------------------------------------------ */
 /* Alignment quality (Sec. 2.3: percentage of gaps, p-score, distance

@@ -21,6 +21,7 @@
 // launches can be captured once into a HIP graph and replayed per level;
 // the host reads one 4-byte split count per level to know when to stop.
 #include "lev_core.hpp"
+#include "lev_xl.hpp"
 
 namespace msadp {
 
@@ -59,13 +60,14 @@ struct TreeArgs {
     int32_t *desc;           // [0] level start, [1] level end, [2] splits of last level
     int64_t *cnt;            // per cluster item count of the next pass (nq + 1)
     int64_t *items;          // exclusive prefix of cnt (read by the pass)
+    int64_t *pitems;         // exclusive prefix of the pairs given to k_tree_xl (nq + 1)
     uint64_t *key;           // per cluster min/max key
     int32_t *pat;            // per cluster pattern rank of the current pass
     int32_t *nleft;          // per cluster |L| (or -1 when it stays a leaf)
     int64_t *split;          // per cluster 1 if split -> exclusive prefix
     uint64_t *rowsum;        // per position
     int32_t *dl, *dr;        // per position f(l, x), f(r, x)
-    uint32_t *counter;
+    uint32_t *counter;       // [0] k_tree_lev's work counter, [1] k_tree_xl's
     uint32_t *hbuf;
     int64_t hstride;
     int32_t *st;             // device status
@@ -78,6 +80,9 @@ struct TreeArgs {
     uint32_t *emb_max;       // [2]: bits of max |e|, quantization shift s
     uint32_t emb_q0;         // calibration offset added to every surrogate distance
     int32_t pivots;          // sampled median: pivots per cluster (0: not sampled)
+    // clusters of at most this many members take their medoid / candidate /
+    // pivot passes (xl_sum) and their pole passes (xl_pole) in k_tree_xl
+    int32_t xl_sum, xl_pole;
     int32_t topk;
     int32_t exact_below;     // clusters of at most this many members: all are candidates
     int64_t *ncand;          // per cluster candidate count (nq + 1)
@@ -214,7 +219,69 @@ __global__ void __launch_bounds__(1024) k_scan_level(const int64_t *in, int64_t 
     }
 }
 
-__global__ void k_zero_counter(uint32_t *c) { *c = 0; }
+__global__ void k_zero_counter(uint32_t *c) {
+    c[0] = 0;
+    c[1] = 0;
+}
+
+// Classes of distance passes, for the split of their work between the kernels.
+enum { kClsMedoid = 0, kClsSum = 1, kClsPole = 2 };
+
+// Work of one distance pass, split by cluster size: a cluster of at most the
+// class's cap members (xl_sum or xl_pole) goes to k_tree_xl as pairs, a
+// larger one to k_tree_lev as cnt[q] items (cnt as set by the kernel that
+// chose the pass's patterns; 0 = no work).  Pairs per cluster of k members:
+// the medoid triangle k (k - 1) / 2; a candidate or pivot pass (cnt = count
+// x ceil(k / 64) items) count x k; a pole pass k.  items and pitems get the
+// exclusive prefixes, q = 0 .. nq (one workgroup).
+__global__ void __launch_bounds__(1024) k_scan_work(TreeArgs a, int cls) {
+    __shared__ int64_t part[2][1024];
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    const int64_t n = (int64_t)nq + 1;
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t lo = min<int64_t>(n, t * chunk), hi = min<int64_t>(n, lo + chunk);
+    const int64_t cap = cls == kClsPole ? a.xl_pole : a.xl_sum;
+    auto work = [&](int64_t q, int64_t &it, int64_t &pr) {
+        it = pr = 0;
+        if (q >= nq) return;
+        const int64_t c = a.cnt[q];
+        if (c == 0) return;
+        const int64_t k = a.mcount[lvl + q];
+        if (k > cap) {
+            it = c;
+            return;
+        }
+        pr = cls == kClsMedoid ? k * (k - 1) / 2 : cls == kClsSum ? c / ((k + 63) / 64) * k : k;
+    };
+    int64_t si = 0, sp = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+        int64_t it, pr;
+        work(i, it, pr);
+        si += it;
+        sp += pr;
+    }
+    part[0][t] = si;
+    part[1][t] = sp;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v0 = t >= off ? part[0][t - off] : 0;
+        const int64_t v1 = t >= off ? part[1][t - off] : 0;
+        __syncthreads();
+        part[0][t] += v0;
+        part[1][t] += v1;
+        __syncthreads();
+    }
+    int64_t ri = part[0][t] - si, rp = part[1][t] - sp;
+    for (int64_t i = lo; i < hi; ++i) {
+        int64_t it, pr;
+        work(i, it, pr);
+        a.items[i] = ri;
+        a.pitems[i] = rp;
+        ri += it;
+        rp += pr;
+    }
+}
 
 // The distance passes of a level.
 template <int WMAX, int MODE>
@@ -300,6 +367,94 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
     }
 }
 
+// The same distance passes for the clusters k_scan_work gave to pairs: one
+// pair per group of G lanes (lev_xl.hpp), kWave / G consecutive pairs of the
+// pitems numbering per work item, so one wavefront serves several small
+// clusters at once, and a pair takes about n + G steps instead of the n
+// times pattern-words steps of one lane.  The group's lane 0 adds the
+// pair's distance where the pass keeps it.
+// Workgroups of four independent wavefronts (a quarter of the workgroups to
+// dispatch for the same resident wavefronts).
+constexpr int kXlBlock = 256;
+
+template <int G, int WL, int NB>
+__global__ void __launch_bounds__(kXlBlock) k_tree_xl(TreeArgs a, int mode) {
+    constexpr int kPpw = kWave / G;
+    const int lane = lane_id(), grp = lane / G;
+    const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
+    const int64_t total = a.pitems[nq];
+    // a pair list never exceeds n members times the largest cluster it holds
+    const int64_t cap = max(a.xl_sum, a.xl_pole);
+    if (nq < 1 || nq > a.n || total < 0 || total > (int64_t)a.n * cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.st, MSA_DS_CAPACITY);
+        return;
+    }
+    for (;;) {
+        const uint32_t it = next_item(a.counter + 1);
+        const int64_t p0 = (int64_t)it * kPpw;
+        if (p0 >= total) break;
+        const bool live = p0 + grp < total;
+        const int64_t p = live ? p0 + grp : p0;
+        const int32_t q = find_cluster(a.pitems, nq, p);
+        const int64_t L = p - a.pitems[q];
+        const int32_t v = lvl + q;
+        const int64_t ms = a.mstart[v], k = a.mcount[v];
+        int64_t tpos, ppos = 0, cslot = 0;
+        int32_t prow;
+        if (mode == kMedoid) {
+            // triangle pair L = u (u - 1) / 2 + t, t < u: member u (the
+            // longer one, members being in length order) is the pattern
+            int64_t u = (int64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)L)) * 0.5f);
+            while (u > 1 && u * (u - 1) / 2 > L) --u;
+            while ((u + 1) * u / 2 <= L) ++u;
+            ppos = ms + u;
+            prow = a.perm[ppos];
+            tpos = ms + (L - u * (u - 1) / 2);
+        } else if (mode == kCandSum || mode == kPivotSum) {
+            const int64_t jj = L / k;
+            cslot = a.coff[q] + jj;
+            prow = a.cand[cslot];
+            tpos = ms + (L - jj * k);
+        } else {
+            prow = a.pat[q];
+            tpos = ms + L;
+        }
+        const int32_t trow = a.perm[tpos];
+        const int d = xl_distance<G, WL, NB>(a.S.codes + (int64_t)prow * a.S.stride, a.S.len[prow],
+                                             a.S.codes + (int64_t)trow * a.S.stride, a.S.len[trow],
+                                             a.S.stride - 16, live);
+        // Pairs of one cluster (pole keys), one candidate (candidate sums and
+        // keys) or one pattern member (medoid sums of the longer member) are
+        // consecutive: their values are first combined across the
+        // wavefront's groups, so each run costs one atomic, not one per pair.
+        const bool lead = live && (lane & (G - 1)) == 0;
+        const uint64_t fk = far_key(d, a.order[trow]);
+        bool head = false;
+        if (mode == kMedoid) {
+            const uint64_t sp = xl_segment<G, false>(live ? ppos : -1, (uint64_t)d, head);
+            if (lead) atomicAdd((unsigned long long *)&a.rowsum[tpos], (unsigned long long)d);
+            if (lead && head) atomicAdd((unsigned long long *)&a.rowsum[ppos], (unsigned long long)sp);
+        } else if (mode == kPivotSum) {
+            if (lead) atomicAdd((unsigned long long *)&a.rowsum[tpos], (unsigned long long)d);
+        } else if (mode == kCandSum) {
+            const uint64_t ss = xl_segment<G, false>(live ? cslot : -1, (uint64_t)d, head);
+            const uint64_t sk = xl_segment<G, true>(live ? cslot : -1, fk, head);
+            if (lead && head) {
+                atomicAdd((unsigned long long *)&a.candsum[cslot], (unsigned long long)ss);
+                atomicMax((unsigned long long *)&a.candkey[cslot], (unsigned long long)sk);
+            }
+        } else {
+            if (mode == kPoleMax || mode == kPoleMaxStore) {
+                const uint64_t sk = xl_segment<G, true>(live ? q : -1, fk, head);
+                if (lead && head)
+                    atomicMax((unsigned long long *)&a.key[q], (unsigned long long)sk);
+            }
+            if (lead && mode == kPoleMaxStore) a.dl[tpos] = d;
+            if (lead && mode == kPoleStore) a.dr[tpos] = d;
+        }
+    }
+}
+
 // c = member with the least row sum (lowest input index on ties).
 __global__ void __launch_bounds__(256) k_pick_center(TreeArgs a) {
     __shared__ uint64_t red[256];
@@ -341,10 +496,7 @@ __global__ void k_pick_pole(TreeArgs a, int which) {
     for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const int32_t v = lvl + q;
         const int64_t k = a.mcount[v];
-        if (a.items[q + 1] == a.items[q]) {     // no work in the last pass: a leaf
-            a.cnt[q] = 0;
-            continue;
-        }
+        if (a.cnt[q] == 0) continue;            // no work in the last pass: a leaf
         const uint64_t key = a.key[q];
         const int32_t far = (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
         const uint32_t dmax = (uint32_t)(key >> 32);
@@ -967,58 +1119,94 @@ __global__ void k_pick_center_cand(TreeArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[nq] = 0;
 }
 
-template <int WMAX>
-static void launch_select(const TreeArgs &a, int grid, int egrid, hipStream_t s) {
-    const dim3 cg(kClusterGrid), cb(256), tb(64), lg(grid);
-    hipLaunchKernelGGL(k_level_init, cg, cb, 0, s, a);
-    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
+// Shape of k_tree_xl for a build: G lanes per pair, WL words per lane, NB
+// bit planes; grid = its persistent grid; caps as in TreeArgs (0 and 0: off).
+struct XlShape {
+    int g = 0, wl = 0, nb = 0, grid = 0;
+    int32_t sum_cap = 0, pole_cap = 0;
+    bool on() const { return g > 0 && (sum_cap > 0 || pole_cap > 0); }
+};
+
+template <int WL, int NB>
+static const void *xl_kernel_g(int g) {
+    switch (g) {
+        case 1: return (const void *)&k_tree_xl<1, WL, NB>;
+        case 2: return (const void *)&k_tree_xl<2, WL, NB>;
+        case 4: return (const void *)&k_tree_xl<4, WL, NB>;
+        case 8: return (const void *)&k_tree_xl<8, WL, NB>;
+        case 16: return (const void *)&k_tree_xl<16, WL, NB>;
+        case 32: return (const void *)&k_tree_xl<32, WL, NB>;
+        default: return (const void *)&k_tree_xl<64, WL, NB>;
+    }
+}
+
+static const void *xl_kernel(int g, int wl, int nb) {
+    if (wl == 1) return nb == 2 ? xl_kernel_g<1, 2>(g) : xl_kernel_g<1, 5>(g);
+    return nb == 2 ? xl_kernel_g<2, 2>(g) : xl_kernel_g<2, 5>(g);
+}
+
+// One distance pass: its work split between k_tree_lev (large clusters) and
+// k_tree_xl (small ones).
+template <int WMAX, int MODE>
+static void dist_pass(const TreeArgs &a, int grid, const XlShape &xl, hipStream_t s) {
+    constexpr int cls = MODE == kMedoid ? kClsMedoid
+                        : (MODE == kCandSum || MODE == kPivotSum) ? kClsSum
+                                                                   : kClsPole;
+    const int32_t cap = xl.on() ? (cls == kClsPole ? xl.pole_cap : xl.sum_cap) : 0;
+    hipLaunchKernelGGL(k_scan_work, dim3(1), dim3(1024), 0, s, a, cls);
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
+    // a cap above n sends every cluster across lanes: k_tree_lev would only
+    // find no work
+    if (cap <= a.n) hipLaunchKernelGGL((k_tree_lev<WMAX, MODE>), dim3(grid), dim3(kWave), 0, s, a);
+    if (cap > 0) {
+        TreeArgs aa = a;
+        int mode = MODE;
+        void *args[] = {&aa, &mode};
+        (void)hipLaunchKernel(xl_kernel(xl.g, xl.wl, xl.nb), dim3(xl.grid), dim3(kXlBlock), args,
+                              0, s);
+    }
+}
+
+template <int WMAX>
+static void launch_select(const TreeArgs &a, int grid, const XlShape &xl, int egrid,
+                          hipStream_t s) {
+    const dim3 cg(kClusterGrid), cb(256), tb(64);
+    hipLaunchKernelGGL(k_level_init, cg, cb, 0, s, a);
     const bool exact = a.emb == nullptr && a.pivots == 0;
     if (exact) {
-        hipLaunchKernelGGL((k_tree_lev<WMAX, kMedoid>), lg, tb, 0, s, a);
+        dist_pass<WMAX, kMedoid>(a, grid, xl, s);
         hipLaunchKernelGGL(k_pick_center, cg, cb, 0, s, a);
     } else {
         if (a.emb != nullptr) {
+            hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
             hipLaunchKernelGGL(k_emb_rowsum, dim3(egrid), tb, 0, s, a);
         } else {
             // sampled median: pivots by hash, then every member's summed
             // distance to them is its estimate
             hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.ncand, a.coff, a.desc);
             hipLaunchKernelGGL(k_topk, cg, dim3(kTopkThreads), 0, s, a, 0);
-            hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-            hipLaunchKernelGGL((k_tree_lev<WMAX, kPivotSum>), lg, tb, 0, s, a);
+            dist_pass<WMAX, kPivotSum>(a, grid, xl, s);
         }
         hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.ncand, a.coff, a.desc);
         hipLaunchKernelGGL(k_topk, cg, dim3(kTopkThreads), 0, s, a, 1);
-        hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-        hipLaunchKernelGGL((k_tree_lev<WMAX, kCandSum>), lg, tb, 0, s, a);
+        dist_pass<WMAX, kCandSum>(a, grid, xl, s);
         hipLaunchKernelGGL(k_pick_center_cand, dim3(256), dim3(256), 0, s, a);
     }
     // l = argmax f(c, x).  Pruned mode: c's far key is already in key[q]
-    // from the candidate pass, and items[] only tells k_pick_pole which
-    // clusters have work.
-    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-    if (exact) {
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-        hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMax>), lg, tb, 0, s, a);
-    }
+    // from the candidate pass.
+    if (exact) dist_pass<WMAX, kPoleMax>(a, grid, xl, s);
     hipLaunchKernelGGL(k_pick_pole, dim3(256), dim3(256), 0, s, a, 0);
-    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-    hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleMaxStore>), lg, tb, 0, s, a);
+    dist_pass<WMAX, kPoleMaxStore>(a, grid, xl, s);
     hipLaunchKernelGGL(k_pick_pole, dim3(256), dim3(256), 0, s, a, 1);
 }
 
 // One level of Alg. 1: c, l, r, then f(r, x), the split and the children.
 template <int WMAX>
-static void launch_passes(const TreeArgs &a, int grid, int egrid, hipStream_t s) {
-    const dim3 cg(kClusterGrid), cb(256), tb(64), lg(grid);
-    launch_select<WMAX>(a, grid, egrid, s);
-    hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.cnt, a.items, a.desc);
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
-    hipLaunchKernelGGL((k_tree_lev<WMAX, kPoleStore>), lg, tb, 0, s, a);
+static void launch_passes(const TreeArgs &a, int grid, const XlShape &xl, int egrid,
+                          hipStream_t s) {
+    const dim3 cg(kClusterGrid), cb(256);
+    launch_select<WMAX>(a, grid, xl, egrid, s);
+    dist_pass<WMAX, kPoleStore>(a, grid, xl, s);
     (void)hipMemcpyAsync(a.perm_next, a.perm, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
     hipLaunchKernelGGL(k_split, cg, cb, 0, s, a);
     hipLaunchKernelGGL(k_scan_level, dim3(1), dim3(1024), 0, s, a.split, a.split, a.desc);
@@ -1027,25 +1215,27 @@ static void launch_passes(const TreeArgs &a, int grid, int egrid, hipStream_t s)
     (void)hipMemcpyAsync(a.perm, a.perm_next, sizeof(int32_t) * (size_t)a.n, hipMemcpyDeviceToDevice, s);
 }
 
-static void level_pass(const TreeArgs &a, int wclass, int grid, int egrid, hipStream_t s) {
+static void level_pass(const TreeArgs &a, int wclass, int grid, const XlShape &xl, int egrid,
+                       hipStream_t s) {
     switch (wclass) {
-        case 4: launch_passes<4>(a, grid, egrid, s); break;
-        case 8: launch_passes<8>(a, grid, egrid, s); break;
-        case 16: launch_passes<16>(a, grid, egrid, s); break;
-        case 20: launch_passes<20>(a, grid, egrid, s); break;
-        case 24: launch_passes<24>(a, grid, egrid, s); break;
-        default: launch_passes<32>(a, grid, egrid, s); break;
+        case 4: launch_passes<4>(a, grid, xl, egrid, s); break;
+        case 8: launch_passes<8>(a, grid, xl, egrid, s); break;
+        case 16: launch_passes<16>(a, grid, xl, egrid, s); break;
+        case 20: launch_passes<20>(a, grid, xl, egrid, s); break;
+        case 24: launch_passes<24>(a, grid, xl, egrid, s); break;
+        default: launch_passes<32>(a, grid, xl, egrid, s); break;
     }
 }
 
-static void level_select(const TreeArgs &a, int wclass, int grid, int egrid, hipStream_t s) {
+static void level_select(const TreeArgs &a, int wclass, int grid, const XlShape &xl, int egrid,
+                         hipStream_t s) {
     switch (wclass) {
-        case 4: launch_select<4>(a, grid, egrid, s); break;
-        case 8: launch_select<8>(a, grid, egrid, s); break;
-        case 16: launch_select<16>(a, grid, egrid, s); break;
-        case 20: launch_select<20>(a, grid, egrid, s); break;
-        case 24: launch_select<24>(a, grid, egrid, s); break;
-        default: launch_select<32>(a, grid, egrid, s); break;
+        case 4: launch_select<4>(a, grid, xl, egrid, s); break;
+        case 8: launch_select<8>(a, grid, xl, egrid, s); break;
+        case 16: launch_select<16>(a, grid, xl, egrid, s); break;
+        case 20: launch_select<20>(a, grid, xl, egrid, s); break;
+        case 24: launch_select<24>(a, grid, xl, egrid, s); break;
+        default: launch_select<32>(a, grid, xl, egrid, s); break;
     }
 }
 
@@ -1080,20 +1270,60 @@ static int tree_grid(int wclass) {
     return g;
 }
 
+static int xl_grid(int g, int wl, int nb) {
+    static std::atomic<int> cache[kMaxDevices][7][2][2];
+    int gi = 0;
+    while ((1 << gi) < g) ++gi;
+    std::atomic<int> &slot = cache[current_device()][gi][wl - 1][nb == 2 ? 0 : 1];
+    int v = slot.load(std::memory_order_relaxed);
+    if (v == 0) {
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, xl_kernel(g, wl, nb), kXlBlock,
+                                                         0) != hipSuccess ||
+            blocks < 1)
+            blocks = 1;
+        v = device_cus() * blocks;
+        slot.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
 struct TreePlan {
     int64_t stride, hstride;
     int wclass, grid;
     size_t hbuf_dwords;     // carry buffer: the largest any admissible class needs
+    XlShape xl;
 };
 
 static int64_t tree_hstride(const msa_seqs *S, int wclass) {
     return needs_passes(S->max_len, wclass) ? ((int64_t)S->max_len + 15) / 16 : 0;
 }
 
+// Across-lanes passes of a build: the tuning table's entry for
+// (MSA_TUNE_TREE_XL, sigma, pattern words) if valid, else the default.  G =
+// the least power of two with G WL >= pattern words (at most 64).
+static XlShape plan_xl(const msa_seqs *S, int forced_xl) {
+    XlShape x;
+    const int words = (int)std::max<int64_t>(1, ((int64_t)S->max_len + 63) / 64);
+    int v = forced_xl > 0 ? forced_xl : tuned_value(MSA_TUNE_TREE_XL, S->sigma, words, 0);
+    if (!xl_value_valid(v)) v = xl_default_value();
+    const int wl = xl_value_wl(v);
+    int g = 1;
+    while (g * wl < words) g <<= 1;
+    if (g > kWave) return x;
+    x.g = g;
+    x.wl = wl;
+    x.nb = xl_planes(S->sigma);
+    x.sum_cap = xl_value_sum_cap(v);
+    x.pole_cap = xl_value_pole_cap(v);
+    if (x.on()) x.grid = xl_grid(g, wl, x.nb);
+    return x;
+}
+
 // forced > 0 selects the class (autotuning); else the tuning table's entry
 // for (MSA_TUNE_TREE, sigma, pattern words) if it is an admissible class,
 // else the default.  Admissible: a tree class within class_within_passes.
-static TreePlan plan_tree(const msa_seqs *S, int forced) {
+static TreePlan plan_tree(const msa_seqs *S, int forced, int forced_xl = 0) {
     TreePlan p;
     p.stride = staged_stride(S->max_len);
     const int words = (int)std::max<int64_t>(1, ((int64_t)S->max_len + 63) / 64);
@@ -1110,6 +1340,7 @@ static TreePlan plan_tree(const msa_seqs *S, int forced) {
         p.hbuf_dwords = std::max(p.hbuf_dwords,
                                  (size_t)tree_grid(c) * kWave * (size_t)tree_hstride(S, c));
     }
+    p.xl = plan_xl(S, forced_xl);
     return p;
 }
 
@@ -1133,7 +1364,7 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<uint64_t>(n + 1);          // rowsum (+ spare slot)
     al.template take<int32_t>(n + 1);           // dl
     al.template take<int32_t>(n + 1);           // dr
-    al.template take<uint32_t>(1);              // counter
+    al.template take<uint32_t>(2);              // counters
     if (p.hbuf_dwords) al.template take<uint32_t>(p.hbuf_dwords);
     al.template take<int64_t>(n + 1);           // candidate counts
     al.template take<int64_t>(n + 1);           // candidate offsets
@@ -1145,6 +1376,7 @@ static void tree_layout(Alloc &al, const msa_seqs *S, const TreePlan &p) {
     al.template take<int8_t>(n * kEmbDim);      // embedding codes
     al.template take<int32_t>(n);               // their squared norms
     al.template take<uint32_t>(2);              // max |e|, spare
+    al.template take<int64_t>(n + 1);           // pitems
 }
 
 // Quantize the embeddings once per call (before any level).
@@ -1168,7 +1400,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                       int32_t exact_below, const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
                       int32_t *d_status, hipStream_t s, int forced,
-                      const Forest *fr = nullptr, int32_t pivots = 0);
+                      const Forest *fr = nullptr, int32_t pivots = 0, int forced_xl = 0);
 
 extern "C" {
 
@@ -1183,7 +1415,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
                       int32_t exact_below, const msa_tree *T,
                       int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
                       int32_t *d_status, hipStream_t s, int forced,
-                      const Forest *fr, int32_t pivots) {
+                      const Forest *fr, int32_t pivots, int forced_xl) {
     int rc;
     if ((rc = check_seqs(S))) return rc;
     if (T == nullptr || n_nodes == nullptr) return MSA_EINVAL;
@@ -1193,7 +1425,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     if (!T->parent || !T->left || !T->right || !T->center || !T->lpole || !T->rpole ||
         !T->depth || !T->mstart || !T->mcount || !T->perm || ws == nullptr)
         return MSA_EINVAL;
-    const TreePlan p = plan_tree(S, forced);
+    const TreePlan p = plan_tree(S, forced, forced_xl);
     Sizer sz;
     tree_layout(sz, S, p);
     if (ws_bytes < sz.total()) return MSA_ENOSPC;
@@ -1221,7 +1453,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.rowsum = cv.take<uint64_t>(n + 1);
     a.dl = cv.take<int32_t>(n + 1);
     a.dr = cv.take<int32_t>(n + 1);
-    a.counter = cv.take<uint32_t>(1);
+    a.counter = cv.take<uint32_t>(2);
     a.hbuf = p.hbuf_dwords ? cv.take<uint32_t>(p.hbuf_dwords) : nullptr;
     a.hstride = p.hstride;
     a.ncand = cv.take<int64_t>(n + 1);
@@ -1236,6 +1468,9 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     a.embq = cv.take<int8_t>(n * kEmbDim);
     a.embn = cv.take<int32_t>(n);
     a.emb_max = cv.take<uint32_t>(2);
+    a.pitems = cv.take<int64_t>(n + 1);
+    a.xl_sum = p.xl.on() ? p.xl.sum_cap : 0;
+    a.xl_pole = p.xl.on() ? p.xl.pole_cap : 0;
     a.emb = emb;
     a.emb_q0 = emb_q0;
     a.pivots = pivots;
@@ -1266,7 +1501,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
     if (use_graph) {
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return MSA_EDEVICE;
-        level_pass(a, p.wclass, p.grid, emb_grid(), s);
+        level_pass(a, p.wclass, p.grid, p.xl, emb_grid(), s);
         if (hipStreamEndCapture(s, &graph) != hipSuccess) return MSA_EDEVICE;
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGraphDestroy(graph);
@@ -1279,7 +1514,7 @@ static int build_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int3
         if (use_graph) {
             if (hipGraphLaunch(exec, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
         } else {
-            level_pass(a, p.wclass, p.grid, emb_grid(), s);
+            level_pass(a, p.wclass, p.grid, p.xl, emb_grid(), s);
         }
         if ((rc = launch_status())) break;
         if (hipMemcpyAsync(host_desc, a.desc, sizeof(host_desc), hipMemcpyDeviceToHost, s) !=
@@ -1361,6 +1596,54 @@ int msa_autotune_tree(const msa_seqs *S, const msa_tree *T, int32_t *n_nodes, in
     *best = bc;
     *best_ms = bms;
     return msa_tune_set(MSA_TUNE_TREE, S->sigma, words, bc);
+}
+
+int msa_autotune_tree_xl(const msa_seqs *S, int32_t pivots, int32_t topk, const msa_tree *T,
+                         int32_t *n_nodes, int32_t use_graph, void *ws, size_t ws_bytes,
+                         int32_t reps, int32_t *best, float *best_ms, int32_t *d_status,
+                         hipStream_t s) {
+    int rc;
+    if ((rc = check_seqs(S))) return rc;
+    if (best == nullptr || best_ms == nullptr || reps < 1 || S->n < 2 || pivots < 0 ||
+        pivots > kMaxTopk || (pivots > 0 && (topk < 1 || topk > kMaxTopk)))
+        return MSA_EINVAL;
+    const int words = (int)std::max<int64_t>(1, ((int64_t)S->max_len + 63) / 64);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MSA_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MSA_EDEVICE;
+    }
+    int bv = 0;
+    float bms = 0.0f;
+    rc = MSA_OK;
+    for (const int v : kXlCandidates) {
+        auto run = [&]() {
+            return build_impl(S, nullptr, 0, pivots > 0 ? topk : 0, 0, T, n_nodes, use_graph, ws,
+                              ws_bytes, d_status, s, 0, nullptr, pivots, v);
+        };
+        if ((rc = run())) break;   // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = MSA_EDEVICE; break; }
+        for (int r = 0; r < reps && rc == MSA_OK; ++r) rc = run();
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = MSA_EDEVICE;
+            break;
+        }
+        ms /= (float)reps;
+        if (bv == 0 || ms < bms) {
+            bv = v;
+            bms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = bv;
+    *best_ms = bms;
+    return msa_tune_set(MSA_TUNE_TREE_XL, S->sigma, words, bv);
 }
 
 int tree_build_sampled(const msa_seqs *S, int32_t pivots, int32_t topk, int32_t exact_below,
@@ -1468,7 +1751,7 @@ static int eval_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32
     a.rowsum = cv.take<uint64_t>(n + 1);
     a.dl = cv.take<int32_t>(n + 1);
     a.dr = cv.take<int32_t>(n + 1);
-    a.counter = cv.take<uint32_t>(1);
+    a.counter = cv.take<uint32_t>(2);
     a.hbuf = p.hbuf_dwords ? cv.take<uint32_t>(p.hbuf_dwords) : nullptr;
     a.hstride = p.hstride;
     a.ncand = cv.take<int64_t>(n + 1);
@@ -1481,6 +1764,9 @@ static int eval_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32
     a.embq = cv.take<int8_t>(n * kEmbDim);
     a.embn = cv.take<int32_t>(n);
     a.emb_max = cv.take<uint32_t>(2);
+    a.pitems = cv.take<int64_t>(n + 1);
+    a.xl_sum = p.xl.on() ? p.xl.sum_cap : 0;
+    a.xl_pole = p.xl.on() ? p.xl.pole_cap : 0;
     a.center = center;
     a.lpole = lpole;
     a.rpole = rpole;
@@ -1508,7 +1794,7 @@ static int eval_impl(const msa_seqs *S, const float *emb, uint32_t emb_q0, int32
         size_t hi = lo + 1;
         while (hi < nn && h_depth[hi] == h_depth[lo]) ++hi;
         hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, s, a.desc, (int32_t)lo, (int32_t)hi);
-        level_select(a, p.wclass, p.grid, emb_grid(), s);
+        level_select(a, p.wclass, p.grid, p.xl, emb_grid(), s);
         rc = launch_status();
         lo = hi;
     }

@@ -11,6 +11,8 @@
 //                     value = lanes sharing one pattern table (1 or 64).
 //   MSA_TUNE_TREE (2): bin = pattern words ceil(max_len / 64) of the set;
 //                     value = words per pass of the tree build's kernels.
+//   MSA_TUNE_TREE_XL (4): bin as for MSA_TUNE_TREE; value = words per lane
+//                     and cluster-size caps of the across-lanes passes.
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -20,6 +22,7 @@
 
 #include "common.hpp"
 #include "lev_core.hpp"
+#include "lev_xl.hpp"
 
 namespace msadp {
 
@@ -32,12 +35,13 @@ bool valid_value(int kind, int value) {
     if (kind == MSA_TUNE_NW) return value == 16 || value == 32 || value == 64;
     if (kind == MSA_TUNE_TREE) return is_tree_class(value);
     if (kind == MSA_TUNE_PAIRS) return value == 1 || value == kWave;
+    if (kind == MSA_TUNE_TREE_XL) return xl_value_valid(value);
     return false;
 }
 
 bool valid_key(int kind, int sigma, int bin) {
     return (kind == MSA_TUNE_LEV || kind == MSA_TUNE_NW || kind == MSA_TUNE_TREE ||
-            kind == MSA_TUNE_PAIRS) &&
+            kind == MSA_TUNE_PAIRS || kind == MSA_TUNE_TREE_XL) &&
            sigma >= 2 && sigma <= 33 &&
            bin >= 1 && bin <= (1 << 20);
 }
@@ -108,6 +112,11 @@ int msa_tune_candidates(int32_t kind, int32_t *values, int32_t cap, int32_t *cou
     } else if (kind == MSA_TUNE_PAIRS) {
         for (int r : {1, kWave}) {
             if (n < cap) values[n] = r;
+            ++n;
+        }
+    } else if (kind == MSA_TUNE_TREE_XL) {
+        for (const int v : kXlCandidates) {
+            if (n < cap) values[n] = v;
             ++n;
         }
     } else {

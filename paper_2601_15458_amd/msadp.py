@@ -18,7 +18,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmsadp.so")
 
 MSA_OK, MSA_EINVAL, MSA_ERANGE, MSA_ENOSPC, MSA_EDEVICE = 0, -1, -2, -3, -4
-MSA_TUNE_LEV, MSA_TUNE_NW, MSA_TUNE_TREE, MSA_TUNE_PAIRS = 0, 1, 2, 3
+MSA_TUNE_LEV, MSA_TUNE_NW, MSA_TUNE_TREE, MSA_TUNE_PAIRS, MSA_TUNE_TREE_XL = 0, 1, 2, 3, 4
+XL_CAP_ALL = (1 << 14) - 1     # an across-lanes cap that takes every cluster
+
+
+def xl_value(wl: int, sum_cap: int, pole_cap: int) -> int:
+    """MSA_TUNE_TREE_XL value: words per lane, and the largest clusters whose
+    medoid / pivot / candidate passes (sum_cap) and pole passes (pole_cap)
+    run with one pair per group of lanes (include/msadp.h)."""
+    return (wl << 28) | (pole_cap << 14) | sum_cap
 DS_NAMES = {0: "ok", 1: "symbol code >= sigma", 2: "sequence index out of range",
             3: "length out of range", 4: "output capacity too small",
             5: "non-finite embedding value"}
@@ -93,6 +101,9 @@ SIGNATURES = {
                                      C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
     "msa_autotune_tree": (C.c_int, [SP, P, C.POINTER(C.c_int32), C.c_int32, P, C.c_size_t,
                                     C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
+    "msa_autotune_tree_xl": (C.c_int, [SP, C.c_int32, C.c_int32, P, C.POINTER(C.c_int32),
+                                       C.c_int32, P, C.c_size_t, C.c_int32,
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_float), P, P]),
     "cnn_param_bytes": (C.c_size_t, []),
     "cnn_set_params": (C.c_int, [P, P, P, P]),
     "cnn_get_params": (C.c_int, [P, P, P, P, P, P]),
@@ -907,6 +918,33 @@ def autotune_tree(S: Seqs, reps: int = 1, use_graph=True, stream=None):
     torch.cuda.synchronize()
     tb.st.check("msa_autotune_tree")
     return best.value, ms.value
+
+
+def autotune_tree_xl(S: Seqs, pivots: int = 0, topk: int = 16, reps: int = 1, use_graph=True,
+                     stream=None):
+    """Time the tree build (sampled with `pivots` > 0, else exact) per
+    across-lanes variant and keep the fastest in the table; returns (the
+    MSA_TUNE_TREE_XL value, ms per build)."""
+    if use_graph and stream is None:
+        stream = torch.cuda.Stream()
+    tb = TreeBuilder(S, use_graph)
+    best, ms, nn = C.c_int32(0), C.c_float(0.0), C.c_int32(0)
+    with torch.cuda.stream(stream) if stream is not None else _nullctx():
+        rc = lib().msa_autotune_tree_xl(C.byref(tb.ss), int(pivots), int(topk), C.byref(tb.ts),
+                                        C.byref(nn), int(tb.use_graph), _ptr(tb.ws), tb.wsb,
+                                        int(reps), C.byref(best), C.byref(ms), _ptr(tb.st.t),
+                                        _stream(stream))
+    _check(rc, "msa_autotune_tree_xl")
+    torch.cuda.synchronize()
+    tb.st.check("msa_autotune_tree_xl")
+    return best.value, ms.value
+
+
+def xl_describe(v: int) -> str:
+    """A MSA_TUNE_TREE_XL value as text."""
+    wl, pc, sc = v >> 28, (v >> 14) & XL_CAP_ALL, v & XL_CAP_ALL
+    cap = lambda c: "all" if c == XL_CAP_ALL else str(c)
+    return f"{wl} word(s) per lane, sums up to {cap(sc)}, poles up to {cap(pc)}"
 
 
 # ---------------------------------------------------------------- embedder

@@ -84,13 +84,16 @@ size_t lev_workspace_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs
  * sigma; two descriptions of the same set are staged once).
  * ia, ib: device int32[n_pairs]; dist: device uint16[n_pairs].  Any order
  * of pairs is correct; the pairs are scheduled on the device in one
- * persistent launch, in one of two layouts (MSA_TUNE_PAIRS below):
+ * persistent launch, in one of three layouts (MSA_TUNE_PAIRS below):
  * pairs grouped by ia, 64 pairs of one pattern per wavefront, groups
  * longest pattern first and each group's texts longest first; or, when the
  * patterns are short enough, one pair per lane with the longer sequence as
  * its pattern, binned by pattern words and ordered by text length, longest
- * first (for sparse lists with few pairs per sequence).  A pair with an
- * index out of range sets MSA_DS_INDEX and dist[p] = 0xFFFF. */
+ * first (for sparse lists with few pairs per sequence); or one pair per
+ * group of lanes, the longer sequence's 64-bit words spread over the group
+ * and the carries between words passed lane to lane (patterns of up to
+ * 16,384 rows; lists of at most 8192 pairs run largest m * n first).  A
+ * pair with an index out of range sets MSA_DS_INDEX and dist[p] = 0xFFFF. */
 int lev_batch(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, const int32_t *ib,
               int64_t n_pairs, uint16_t *dist, void *ws, size_t ws_bytes,
               int32_t *d_status, hipStream_t s);
@@ -430,12 +433,17 @@ int cnn_train_step(void *params, const msa_seqs *S, const int32_t *idx, int32_t 
  *     MSA_TUNE_LEV).  An entry that would take more passes than the default
  *     (and more than two) is ignored.
  *   MSA_TUNE_PAIRS: bin = ceil(max(A->max_len, B->max_len) / 64) of a
- *     lev_batch call; value = lanes that share one pattern table: 1 (every
- *     lane holds its own pair and pattern, pairs binned by pattern words and
- *     text length) or 64 (pairs grouped by A sequence, a wavefront takes 64
- *     pairs of one pattern).  1 needs patterns of at most 32 / sigma' words
- *     (sigma' = 4, 8, 32 for sigma <= 4, <= 8, <= 32) and is the default when
- *     they fit; an entry of 1 that does not fit is ignored.
+ *     lev_batch call; value = the layout: 1 (every lane holds its own pair
+ *     and pattern, pairs binned by pattern words and text length), 2 (a
+ *     pair per group of lanes: one 64-bit word per lane in the least power
+ *     of two of at least 8 lanes holding the longest pattern, else 64 lanes
+ *     of 2, 3 or 4 words) or 64 (pairs grouped by A sequence, a wavefront
+ *     takes 64 pairs of one pattern).  1 needs patterns of at most
+ *     32 / sigma' words (sigma' = 4, 8, 32 for sigma <= 4, <= 8, <= 32) and
+ *     is the default when they fit; 2 needs at most 256 words and is the
+ *     default for longer patterns when the list holds fewer than 16 pairs
+ *     per A sequence; else 64.  An entry whose layout does not fit is
+ *     ignored.
  *   MSA_TUNE_TREE_XL: bin as for MSA_TUNE_TREE; value = which distance
  *     passes of the tree builds run with one pair per group of lanes (the
  *     pattern's 64-bit words spread over the group, carries passed lane to

@@ -26,6 +26,7 @@
 #include <algorithm>
 
 #include "lev_core.hpp"
+#include "lev_xl.hpp"
 
 namespace msadp {
 
@@ -195,6 +196,50 @@ __global__ void __launch_bounds__(64) k_lev_lanes(LanesArgs a) {
 
 __device__ __forceinline__ bool pair_ok(int32_t x, int32_t y, int32_t na, int32_t nb) {
     return x >= 0 && x < na && y >= 0 && y < nb;
+}
+
+// Across-lanes layout: a pair per group of G lanes, its pattern (the longer
+// sequence; the distance is symmetric) spread over the group (lev_xl.hpp),
+// 64 / G pairs per wavefront, in `order` (largest m * n first) when given.
+// For long patterns with few partners each, where one pattern per lane does
+// not fit and a shared pattern table would leave most lanes idle.
+struct XlPairArgs {
+    Staged A, B;             // staged with one common stride
+    const int32_t *ia, *ib;
+    const int32_t *order;    // launch order, or nullptr: index order
+    int64_t n_pairs;
+    uint16_t *out;
+    uint32_t *counter;
+    int32_t *st;
+};
+
+constexpr int kXlPairBlock = 256;   // four independent wavefronts per workgroup
+
+template <int G, int WL, int NB>
+__global__ void __launch_bounds__(kXlPairBlock) k_lev_xl(XlPairArgs a) {
+    constexpr int kPpw = kWave / G;
+    const int lane = lane_id(), grp = lane / G;
+    for (;;) {
+        const uint32_t it = next_item(a.counter);
+        const int64_t p0 = (int64_t)it * kPpw;
+        if (p0 >= a.n_pairs) break;
+        const bool in = p0 + grp < a.n_pairs;
+        const int64_t r = in ? p0 + grp : p0;
+        const int64_t pid = a.order != nullptr ? a.order[r] : r;
+        const int32_t x = a.ia[pid], y = a.ib[pid];
+        const bool ok = pair_ok(x, y, a.A.n, a.B.n);
+        const int32_t xs = ok ? x : 0, ys = ok ? y : 0;
+        const uint8_t *sa = a.A.codes + (int64_t)xs * a.A.stride;
+        const uint8_t *sb = a.B.codes + (int64_t)ys * a.B.stride;
+        const int la = a.A.len[xs], lb = a.B.len[ys];
+        const bool swap = lb > la;
+        const int d = xl_distance<G, WL, NB>(swap ? sb : sa, swap ? lb : la, swap ? sa : sb,
+                                             swap ? la : lb, a.A.stride - 16, in && ok);
+        if (in && (lane & (G - 1)) == 0) {
+            if (!ok) set_status(a.st, MSA_DS_INDEX);
+            a.out[pid] = ok ? (uint16_t)d : (uint16_t)0xFFFF;
+        }
+    }
 }
 
 // grouped layout: pairs per A sequence
@@ -581,24 +626,165 @@ static LanesWs carve_lanes(Alloc &al, const msa_seqs *A, const msa_seqs *B, int6
     return w;
 }
 
-// Workspace of a pair list: enough for either layout and, in the grouped one,
-// for the carry buffers of every word class (so that no tuning entry can
-// outgrow it).  untuned: only what the default layout and class need.
+// Group shape of the across-lanes layout for patterns of up to `words`
+// 64-bit words: one word per lane in the least power of two (at least 8)
+// of lanes that holds them, else 64 lanes of 2, 3 or 4 words; false beyond
+// 256 words.
+struct XlPairShape {
+    int g, wl, nb;
+};
+
+static bool xl_pairs_shape(const msa_seqs *A, const msa_seqs *B, XlPairShape *x) {
+    const int words = pair_words_bin(A, B);
+    x->nb = xl_planes(A->sigma);
+    if (words <= 64) {
+        x->wl = 1;
+        x->g = 8;
+        while (x->g < words) x->g <<= 1;
+        return true;
+    }
+    x->g = kWave;
+    x->wl = (words + 63) / 64;
+    return x->wl <= 4;
+}
+
+template <int NB>
+static const void *xl_pair_kernel_nb(int g, int wl) {
+    if (wl == 1) {
+        switch (g) {
+            case 8: return (const void *)&k_lev_xl<8, 1, NB>;
+            case 16: return (const void *)&k_lev_xl<16, 1, NB>;
+            case 32: return (const void *)&k_lev_xl<32, 1, NB>;
+            default: return (const void *)&k_lev_xl<64, 1, NB>;
+        }
+    }
+    switch (wl) {
+        case 2: return (const void *)&k_lev_xl<64, 2, NB>;
+        case 3: return (const void *)&k_lev_xl<64, 3, NB>;
+        default: return (const void *)&k_lev_xl<64, 4, NB>;
+    }
+}
+
+static const void *xl_pair_kernel(const XlPairShape &x) {
+    return x.nb == 2 ? xl_pair_kernel_nb<2>(x.g, x.wl) : xl_pair_kernel_nb<5>(x.g, x.wl);
+}
+
+static int xl_pair_grid(const XlPairShape &x) {
+    static std::atomic<int> cache[kMaxDevices][4][4][2];
+    int gi = 0;
+    while ((8 << gi) < x.g) ++gi;
+    std::atomic<int> &slot = cache[current_device()][gi][x.wl - 1][x.nb == 2 ? 0 : 1];
+    int v = slot.load(std::memory_order_relaxed);
+    if (v == 0) {
+        int blocks = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, xl_pair_kernel(x),
+                                                         kXlPairBlock, 0) != hipSuccess ||
+            blocks < 1)
+            blocks = 1;
+        v = device_cus() * blocks;
+        slot.store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+struct XlPairWs {
+    Staged SA, SB;
+    int32_t *order;
+    uint32_t *counter;
+};
+
+template <class Alloc>
+static XlPairWs carve_xl_pairs(Alloc &al, const msa_seqs *A, const msa_seqs *B,
+                               int64_t n_pairs) {
+    XlPairWs w;
+    const int64_t stride = staged_stride(std::max(A->max_len, B->max_len));
+    w.SA = Staged{al.template take<uint8_t>((size_t)A->n * stride),
+                  al.template take<int32_t>((size_t)A->n + 1), stride, A->n};
+    if (same_set(A, B)) {
+        w.SB = w.SA;
+    } else {
+        w.SB = Staged{al.template take<uint8_t>((size_t)B->n * stride),
+                      al.template take<int32_t>((size_t)B->n + 1), stride, B->n};
+    }
+    w.order = al.template take<int32_t>((size_t)std::min<int64_t>(n_pairs, kLptMaxPairs));
+    w.counter = al.template take<uint32_t>(1);
+    return w;
+}
+
+static int run_xl_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
+                        const int32_t *ib, int64_t n_pairs, uint16_t *dist, void *ws,
+                        size_t ws_bytes, const XlPairShape &x, int32_t *d_status,
+                        hipStream_t s) {
+    int rc;
+    Carve cv(ws, ws_bytes);
+    const XlPairWs w = carve_xl_pairs(cv, A, B, n_pairs);
+    if (!cv.ok()) return MSA_ENOSPC;
+    if (A->n == 0 || B->n == 0) {   // every index is out of range
+        const int64_t pg = std::min<int64_t>((n_pairs + 255) / 256, 8192);
+        hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)pg), dim3(256), 0, s, ia, ib, n_pairs,
+                           A->n, B->n, (int64_t *)nullptr, dist, d_status);
+        return launch_status();
+    }
+    if ((rc = stage_set(A, nullptr, w.SA, d_status, s))) return rc;
+    if (!same_set(A, B) && (rc = stage_set(B, nullptr, w.SB, d_status, s))) return rc;
+    const bool lpt = n_pairs <= kLptMaxPairs;
+    if (lpt)
+        hipLaunchKernelGGL(k_lpt_order<kLptTile>, dim3((unsigned)((n_pairs + 255) / 256)),
+                           dim3(256), 0, s, w.SA, w.SB, ia, ib, n_pairs, w.order);
+    if ((rc = fill_i32((int32_t *)w.counter, 1, 0, s))) return rc;
+    XlPairArgs xa{w.SA, w.SB, ia, ib, lpt ? w.order : nullptr, n_pairs, dist, w.counter,
+                  d_status};
+    void *args[] = {&xa};
+    if (hipLaunchKernel(xl_pair_kernel(x), dim3(xl_pair_grid(x)), dim3(kXlPairBlock), args, 0,
+                        s) != hipSuccess)
+        return MSA_EDEVICE;
+    return launch_status();
+}
+
+// The pair-list layout: forced (1 = lanes, 2 = across lanes, 64 = grouped;
+// autotuning), else (forced == 0) the tuning table, else the default: lanes
+// whenever the patterns fit it; across lanes for longer patterns with fewer
+// than kXlPartners pairs per A sequence on average; else grouped.  A value
+// whose layout does not fit the sets falls back to the default.
+constexpr int kLayoutXl = 2;
+constexpr int64_t kXlPartners = 16;
+
+static int default_layout(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs) {
+    int wmax, sp;
+    XlPairShape x;
+    if (lanes_fit(A, B, &wmax, &sp)) return 1;
+    if (xl_pairs_shape(A, B, &x) && n_pairs < kXlPartners * std::max<int64_t>(1, A->n))
+        return kLayoutXl;
+    return kWave;
+}
+
+// Workspace of a pair list: enough for every layout that fits the sets and,
+// in the grouped one, for the carry buffers of every word class (so that no
+// tuning entry can outgrow it).  untuned: only what the default layout and
+// class need.
 static size_t pairs_ws_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs,
                              bool untuned) {
     int wmax, sp;
+    XlPairShape x;
     const bool fit = lanes_fit(A, B, &wmax, &sp);
+    const bool xl = xl_pairs_shape(A, B, &x);
+    const int dflt = default_layout(A, B, n_pairs);
     size_t total = 0;
-    if (!untuned || !fit) {
+    if (!untuned || dflt == kWave) {
         Sizer sg;
         const LevPlan pl = plan_lev(A, B, true, untuned ? -1 : 0);
         carve_grouped(sg, A, B, n_pairs, pl, !untuned);
         total = sg.total();
     }
-    if (fit) {
+    if (fit && (!untuned || dflt == 1)) {
         Sizer sl;
         carve_lanes(sl, A, B, n_pairs, wmax);
         total = std::max(total, sl.total());
+    }
+    if (xl && (!untuned || dflt == kLayoutXl)) {
+        Sizer sx;
+        carve_xl_pairs(sx, A, B, n_pairs);
+        total = std::max(total, sx.total());
     }
     return total;
 }
@@ -687,16 +873,20 @@ static int run_lanes(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, co
     return launch_status();
 }
 
-// The pair-list layout: forced (1 = lanes, 64 = grouped; autotuning), else
-// (forced == 0) the tuning table, else lanes whenever the patterns fit it.
-static int pairs_layout(const msa_seqs *A, const msa_seqs *B, int forced, int *wmax) {
+// The layout of a lev_batch call (see default_layout).
+static int pairs_layout(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs, int forced,
+                        int *wmax, XlPairShape *x) {
     int sp;
     const bool fit = lanes_fit(A, B, wmax, &sp);
-    const int dflt = fit ? 1 : kWave;
+    const bool xl = xl_pairs_shape(A, B, x);
+    const int dflt = default_layout(A, B, n_pairs);
     const int v = forced > 0    ? forced
                   : forced == 0 ? tuned_value(MSA_TUNE_PAIRS, A->sigma, pair_words_bin(A, B), dflt)
                                 : dflt;
-    return (v == 1 && fit) ? 1 : kWave;
+    if (v == 1 && fit) return 1;
+    if (v == kLayoutXl && xl) return kLayoutXl;
+    if (v == kWave) return kWave;
+    return dflt;
 }
 
 size_t lev_batch_ws_bytes(const msa_seqs *A, const msa_seqs *B, int64_t n_pairs, bool untuned) {
@@ -717,8 +907,12 @@ int lev_batch_impl(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, cons
     const bool untuned = forced < 0;
     if (ws_bytes < pairs_ws_bytes(A, B, n_pairs, untuned)) return MSA_ENOSPC;
     int wmax;
-    if (pairs_layout(A, B, forced, &wmax) == 1)
+    XlPairShape x;
+    const int layout = pairs_layout(A, B, n_pairs, forced, &wmax, &x);
+    if (layout == 1)
         return run_lanes(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, wmax, d_status, s);
+    if (layout == kLayoutXl)
+        return run_xl_pairs(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, x, d_status, s);
     return run_grouped(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, untuned, d_status, s);
 }
 
@@ -746,7 +940,9 @@ int msa_autotune_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
     if ((rc = check_seqs(A)) || (rc = check_seqs(B))) return rc;
     if (best == nullptr || best_ms == nullptr || reps < 1 || n_pairs < 1) return MSA_EINVAL;
     int wmax, sp;
+    XlPairShape x;
     const bool fit = lanes_fit(A, B, &wmax, &sp);
+    const bool xl = xl_pairs_shape(A, B, &x);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return MSA_EDEVICE;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -756,8 +952,8 @@ int msa_autotune_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
     int bv = 0;
     float bms = 0.0f;
     rc = MSA_OK;
-    for (int v : {kWave, 1}) {
-        if (v == 1 && !fit) continue;
+    for (int v : {kWave, 1, kLayoutXl}) {
+        if ((v == 1 && !fit) || (v == kLayoutXl && !xl)) continue;
         if ((rc = lev_batch_impl(A, B, ia, ib, n_pairs, dist, ws, ws_bytes, d_status, s, v)))
             break;   // warm-up
         if (hipEventRecord(e0, s) != hipSuccess) { rc = MSA_EDEVICE; break; }

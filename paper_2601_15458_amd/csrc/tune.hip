@@ -8,7 +8,8 @@
 //   MSA_TUNE_NW  (1): bin = wavefronts per pair ceil(ceil(max_len_A / 32) / 64);
 //                     value = steps between workgroup barriers of the fill.
 //   MSA_TUNE_PAIRS (3): bin = pattern words of the longer set of a pair list;
-//                     value = lanes sharing one pattern table (1 or 64).
+//                     value = layout: 1 (a pair per lane), 2 (a pair per
+//                     group of lanes) or 64 (64 pairs share a pattern).
 //   MSA_TUNE_TREE (2): bin = pattern words ceil(max_len / 64) of the set;
 //                     value = words per pass of the tree build's kernels.
 //   MSA_TUNE_TREE_XL (4): bin as for MSA_TUNE_TREE; value = words per lane
@@ -34,7 +35,7 @@ bool valid_value(int kind, int value) {
     if (kind == MSA_TUNE_LEV) return is_lev_class(value);
     if (kind == MSA_TUNE_NW) return value == 16 || value == 32 || value == 64;
     if (kind == MSA_TUNE_TREE) return is_tree_class(value);
-    if (kind == MSA_TUNE_PAIRS) return value == 1 || value == kWave;
+    if (kind == MSA_TUNE_PAIRS) return value == 1 || value == 2 || value == kWave;
     if (kind == MSA_TUNE_TREE_XL) return xl_value_valid(value);
     return false;
 }
@@ -110,7 +111,7 @@ int msa_tune_candidates(int32_t kind, int32_t *values, int32_t cap, int32_t *cou
             ++n;
         }
     } else if (kind == MSA_TUNE_PAIRS) {
-        for (int r : {1, kWave}) {
+        for (int r : {1, 2, kWave}) {
             if (n < cap) values[n] = r;
             ++n;
         }

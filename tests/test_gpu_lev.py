@@ -24,9 +24,16 @@ def lanes_fit(sigma, max_len):
     return max_len <= 64 * (32 // sp)
 
 
+def xl_fit(max_len):
+    """Whether lev_batch's across-lanes layout holds these patterns (at most
+    64 lanes of 4 words)."""
+    return (max_len + 63) // 64 <= 256
+
+
 def _check_pairs(codes_a, off_a, codes_b, off_b, sigma, ia, ib, packed=False, same=False):
     """lev_batch in every pair layout that fits (64 lanes per pattern table,
-    and one pattern per lane) against the oracle, bit for bit."""
+    one pattern per lane, a pattern across a group of lanes) against the
+    oracle, bit for bit."""
     M = _msadp()
     if packed:
         A = M.to_device(M.pack_2bit_host(codes_a), off_a, sigma, packed_2bit=True)
@@ -35,7 +42,8 @@ def _check_pairs(codes_a, off_a, codes_b, off_b, sigma, ia, ib, packed=False, sa
         A = M.to_device(codes_a, off_a, sigma)
         B = A if same else M.to_device(codes_b, off_b, sigma)
     want = orc.lev_pairs(codes_a, off_a, codes_b, off_b, ia, ib)
-    layouts = [64] + ([1] if lanes_fit(sigma, max(A.max_len, B.max_len)) else [])
+    ml = max(A.max_len, B.max_len)
+    layouts = [64] + ([1] if lanes_fit(sigma, ml) else []) + ([2] if xl_fit(ml) else [])
     try:
         for v in layouts:
             M.tune_set(M.MSA_TUNE_PAIRS, sigma, M.pairs_words_bin(A, B), v)
@@ -114,7 +122,7 @@ def test_lanes_layout_word_boundaries(same):
     codes, off = synth.to_csr(seqs)
     n = len(seqs)
     ia, ib = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-    assert _check_pairs(codes, off, codes, off, 4, ia.ravel(), ib.ravel(), same=same) == [64, 1]
+    assert _check_pairs(codes, off, codes, off, 4, ia.ravel(), ib.ravel(), same=same) == [64, 1, 2]
 
 
 @pytest.mark.parametrize("sigma,hi", [(2, 512), (3, 500), (5, 256), (8, 256), (9, 64), (20, 64),
@@ -127,7 +135,7 @@ def test_lanes_layout_alphabets(sigma, hi):
     rng = np.random.default_rng(sigma)
     ia = rng.integers(0, 120, size=5000)
     ib = rng.integers(0, 90, size=5000)
-    assert _check_pairs(ca, oa, cb, ob, sigma, ia, ib) == [64, 1]
+    assert _check_pairs(ca, oa, cb, ob, sigma, ia, ib) == [64, 1, 2]
 
 
 def test_sparse_pairs_learned_workload_sampled():
@@ -179,7 +187,7 @@ def test_autotune_pairs_picks_a_layout():
     lb = M.LevBatch(A, A, ia, ib)
     try:
         best, ms = M.autotune_pairs(lb, reps=2)
-        assert best in (1, 64) and ms > 0
+        assert best in (1, 2, 64) and ms > 0
         assert M.tune_get(M.MSA_TUNE_PAIRS, 4, M.pairs_words_bin(A, A)) == best
         want = orc.lev_pairs(codes, off, codes, off, ia, ib)
         assert (lb().cpu().numpy().astype(np.int64) == want).all()
@@ -260,8 +268,8 @@ def test_device_detected_errors():
     A = M.to_device(codes, off, 4)
     with pytest.raises(RuntimeError, match="index"):
         M.lev_batch(A, A, [0], [5])
-    # both layouts flag the bad pair and leave 0xFFFF in its slot
-    for v in (64, 1):
+    # every layout flags the bad pair and leaves 0xFFFF in its slot
+    for v in (64, 1, 2):
         M.tune_set(M.MSA_TUNE_PAIRS, 4, 1, v)
         try:
             got = M.lev_batch(A, A, [0, 1, -1], [1, 0, 0], check=False).cpu().numpy()
@@ -269,3 +277,45 @@ def test_device_detected_errors():
             M.tune_clear()
         assert got[2] == 0xFFFF and got[0] == got[1] == orc.lev_pairs(
             codes, off, codes, off, np.array([0]), np.array([1]))[0]
+
+
+@pytest.mark.parametrize("sigma,lens", [
+    (4, (1, 63, 64, 65, 500, 4095, 4096, 4097, 8191, 8192, 12000, 16384)),   # 1-4 words per lane
+    (20, (5, 64, 700, 2049, 5000)),                                          # five bit planes
+])
+def test_across_lanes_layout_long_patterns(sigma, lens):
+    """A pattern across 8-64 lanes of one to four words each (up to the
+    16,384-row limit), related and unrelated texts, few pairs per sequence,
+    against the oracle."""
+    M = _msadp()
+    rng = np.random.default_rng(103 + sigma)
+    seqs = []
+    for L in lens:
+        a = rng.integers(0, sigma, size=L).astype(np.uint8)
+        seqs += [a, synth.mutate(rng, a, sigma, 0.08, 0.02, 0.02)]
+    codes, off = synth.to_csr(seqs)
+    n = len(seqs)
+    ia = np.concatenate([np.arange(0, n, 2), np.arange(n), [0, n - 1]])
+    ib = np.concatenate([np.arange(1, n, 2), rng.permutation(n), [n - 1, n - 1]])
+    A = M.to_device(codes, off, sigma)
+    want = orc.lev_pairs(codes, off, codes, off, ia, ib)
+    M.tune_clear()
+    got = M.lev_batch(A, A, ia, ib).cpu().numpy().astype(np.int64)   # the default: across lanes
+    assert np.array_equal(got, want)
+
+
+def test_across_lanes_layout_long_pair_workload():
+    """The 512 pairs of 5-10 kbp DNA (10 % divergence) through lev_batch's
+    default layout for them (a pair per 64 lanes of 2-3 words): every
+    distance equal to the oracle's."""
+    M = _msadp()
+    d = synth.nw_long()
+    P = d["n_pairs"]
+    A = M.to_device(d["a_codes"], d["a_offsets"], 4)
+    B = M.to_device(d["b_codes"], d["b_offsets"], 4)
+    ia = ib = np.arange(P)
+    print("[lev] long pairs: device", flush=True)
+    got = M.lev_batch(A, B, ia, ib).cpu().numpy().astype(np.int64)
+    print("[lev] long pairs: oracle", flush=True)
+    want = orc.lev_pairs(d["a_codes"], d["a_offsets"], d["b_codes"], d["b_offsets"], ia, ib)
+    assert np.array_equal(got, want)

@@ -459,7 +459,8 @@ def bench_pairs(msadp, synth, torch, args):
         cells = float((L[xa].astype(np.float64) * L[xb]).sum())
         tc = cells / (ms * 1e-3) / 1e12
         out[name] = {"workload": desc, "pairs": int(len(xa)), "cells": cells,
-                     "layout": {1: "one pattern per lane", 64: "shared patterns"}[best],
+                     "layout": {1: "one pattern per lane", 2: "a pattern across lanes",
+                                64: "shared patterns"}[best],
                      "ms": round(ms, 3), "t_cells_per_s": round(tc, 1),
                      "pairs_per_s": round(len(xa) / (ms * 1e-3), 1),
                      "frac_of_157.3": round(tc / LEV_PEAK_TCUPS, 4)}
@@ -544,6 +545,15 @@ def bench_band(msadp, synth, torch, args):
     full = _time_calls(torch, lambda: nb.fill(stream), stream, reps)
     out["full_matrix_fill_ms"] = round(full, 3)
     out["full_matrix_gcups"] = round(cells / full / 1e6, 1)
+    # the full-matrix distance of the same pairs through lev_batch, whose
+    # default layout for long patterns with one partner each is a pair per
+    # group of 64 lanes (2-3 pattern words per lane, carries passed by DPP)
+    xb = msadp.LevBatch(A, B, np.arange(P), np.arange(P))
+    xb(stream)
+    lev_ms = _time_calls(torch, lambda: xb(stream), stream, reps)
+    xb.st.check("lev_batch")
+    out["lev_batch_across_lanes"] = {"ms": round(lev_ms, 3),
+                                     "gcups": round(cells / lev_ms / 1e6, 1)}
     from oracle import pyoracle as orc
     sel = np.arange(32)
     out["cpu_oracle"] = oracle_beside(
@@ -844,6 +854,21 @@ def bench_pruned(msadp, synth, torch, args):
          f"(corr {corr:.3f}) -> offset {off:.3f}")
     out["calibration"] = {"offset": round(off, 4), "intercept": round(ca, 4),
                           "slope": round(cb, 5), "corr": round(corr, 4)}
+    # which distance passes run with a pair per group of lanes (the set's
+    # patterns: 8 words, one or two per lane): timed per variant on the
+    # sampled build (16 pivots, top 32) and kept for every build below
+    words = (S.max_len + 63) // 64
+    if args.no_tune:
+        xl = {"value": msadp.tune_get(msadp.MSA_TUNE_TREE_XL, d["sigma"], words) or None,
+              "tuned": False}
+    else:
+        with torch.cuda.stream(stream):
+            best, ms = msadp.autotune_tree_xl(S, pivots=16, topk=32, stream=stream)
+        xl = {"value": best, "tuned": True, "ms": round(ms, 1)}
+        _log(f"across-lanes passes: {msadp.xl_describe(best)} ({ms:.1f} ms per sampled build)")
+    if xl["value"]:
+        xl["variant"] = msadp.xl_describe(xl["value"])
+    out["across_lanes"] = xl
     # ranker -> (embedding, offset): the calibrated network, the raw network,
     # the length prior (shortest first) and noise
     rankers = {"cnn": (emb, off), "cnn_raw": (emb, 0.0),

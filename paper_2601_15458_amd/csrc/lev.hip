@@ -55,8 +55,7 @@ __global__ void __launch_bounds__(64) k_lev_allpairs(AllPairsArgs a) {
     const int lane = lane_id();
     const int64_t N = a.S.n;
     uint32_t *hb = a.hbuf ? a.hbuf + (int64_t)blockIdx.x * a.hstride * kWave + lane : nullptr;
-    for (;;) {
-        const uint32_t it = next_item(a.counter);
+    for (uint32_t it = first_item();; it = later_item(a.counter)) {
         if ((int64_t)it >= a.n_items) break;
         const int64_t g = (int64_t)it;
         // find u with items_upto(u-1) <= g < items_upto(u)
@@ -124,8 +123,7 @@ __global__ void __launch_bounds__(64) k_lev_grouped(GroupedArgs a) {
     const int lane = lane_id();
     const int64_t total = *a.n_items;
     uint32_t *hb = a.hbuf ? a.hbuf + (int64_t)blockIdx.x * a.hstride * kWave + lane : nullptr;
-    for (;;) {
-        const uint32_t it = next_item(a.counter);
+    for (uint32_t it = first_item();; it = later_item(a.counter)) {
         if ((int64_t)it >= total) break;
         const Item I = a.items[it];
         const bool valid = lane < I.count;
@@ -157,8 +155,7 @@ __global__ void __launch_bounds__(64) k_lev_lanes(LanesArgs a) {
     __shared__ uint64_t tbl[WMAX * SP * kWave];
     const int lane = lane_id();
     const int64_t total = *a.n_items;
-    for (;;) {
-        const uint32_t it = next_item(a.counter);
+    for (uint32_t it = first_item();; it = later_item(a.counter)) {
         if ((int64_t)it >= total) break;
         const Item I = a.items[it];
         const bool valid = lane < I.count;
@@ -219,8 +216,7 @@ template <int G, int WL, int NB>
 __global__ void __launch_bounds__(kXlPairBlock) k_lev_xl(XlPairArgs a) {
     constexpr int kPpw = kWave / G;
     const int lane = lane_id(), grp = lane / G;
-    for (;;) {
-        const uint32_t it = next_item(a.counter);
+    for (uint32_t it = first_item();; it = later_item(a.counter)) {
         const int64_t p0 = (int64_t)it * kPpw;
         if (p0 >= a.n_pairs) break;
         const bool in = p0 + grp < a.n_pairs;

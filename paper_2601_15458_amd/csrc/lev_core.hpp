@@ -375,6 +375,24 @@ __device__ __forceinline__ uint32_t next_item(uint32_t *counter) {
     return uniform(__builtin_amdgcn_readlane(it, 0));
 }
 
+// Work items of a persistent kernel: wavefront w of the grid starts with
+// item w, with no atomic, and takes later items from the counter (offset by
+// the grid's wavefront count).  Every wavefront that finds no work then exits
+// without touching the counter: atomics on one address serialize (about
+// 12 ns each), so a launch whose few items all went to the first wavefronts
+// used to cost 60-100 us in fetches that found nothing.
+//   for (uint32_t it = first_item();; it = later_item(counter)) {
+//       if (it >= total) break;
+//       ...
+//   }
+__device__ __forceinline__ uint32_t first_item() {
+    return uniform(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+}
+
+__device__ __forceinline__ uint32_t later_item(uint32_t *counter) {
+    return gridDim.x * (blockDim.x / kWave) + next_item(counter);
+}
+
 __host__ __device__ inline int64_t items_upto(int64_t U) {
     // sum_{u=1..U} ceil(u/64): work items of a triangle whose rows hold 1..U texts
     const int64_t Q = U >> 6, s = U & 63;

@@ -298,8 +298,7 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
         return;
     }
     uint32_t *hb = a.hbuf ? a.hbuf + (int64_t)blockIdx.x * a.hstride * kWave + lane : nullptr;
-    for (;;) {
-        const uint32_t it = next_item(a.counter);
+    for (uint32_t it = first_item();; it = later_item(a.counter)) {
         if ((int64_t)it >= total) break;
         const int32_t q = find_cluster(a.items, nq, it);
         const int64_t local = (int64_t)it - a.items[q];
@@ -389,8 +388,7 @@ __global__ void __launch_bounds__(kXlBlock) k_tree_xl(TreeArgs a, int mode) {
         if (blockIdx.x == 0 && threadIdx.x == 0) set_status(a.st, MSA_DS_CAPACITY);
         return;
     }
-    for (;;) {
-        const uint32_t it = next_item(a.counter + 1);
+    for (uint32_t it = first_item();; it = later_item(a.counter + 1)) {
         const int64_t p0 = (int64_t)it * kPpw;
         if (p0 >= total) break;
         const bool live = p0 + grp < total;

@@ -219,11 +219,6 @@ __global__ void __launch_bounds__(1024) k_scan_level(const int64_t *in, int64_t 
     }
 }
 
-__global__ void k_zero_counter(uint32_t *c) {
-    c[0] = 0;
-    c[1] = 0;
-}
-
 // Classes of distance passes, for the split of their work between the kernels.
 enum { kClsMedoid = 0, kClsSum = 1, kClsPole = 2 };
 
@@ -233,9 +228,11 @@ enum { kClsMedoid = 0, kClsSum = 1, kClsPole = 2 };
 // chose the pass's patterns; 0 = no work).  Pairs per cluster of k members:
 // the medoid triangle k (k - 1) / 2; a candidate or pivot pass (cnt = count
 // x ceil(k / 64) items) count x k; a pole pass k.  items and pitems get the
-// exclusive prefixes, q = 0 .. nq (one workgroup).
+// exclusive prefixes, q = 0 .. nq (one workgroup).  It also clears both
+// kernels' work counters for the pass.
 __global__ void __launch_bounds__(1024) k_scan_work(TreeArgs a, int cls) {
     __shared__ int64_t part[2][1024];
+    if (threadIdx.x < 2) a.counter[threadIdx.x] = 0;
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     const int64_t n = (int64_t)nq + 1;
     const int t = threadIdx.x;
@@ -511,60 +508,61 @@ __global__ void k_pick_pole(TreeArgs a, int which) {
 }
 
 // Stable split of every cluster that has both poles: L = f(l,x) <= f(r,x).
-__global__ void __launch_bounds__(256) k_split(TreeArgs a) {
-    __shared__ int32_t sc[256];
-    __shared__ int32_t base_l, base_r;
+// One workgroup per cluster: a count of L, then chunks of 256 members whose
+// destinations come from a ballot prefix inside each wavefront and the
+// wavefronts' counts (double-buffered, so one barrier per chunk).
+constexpr int kSplitThreads = 256;
+constexpr int kSplitWaves = kSplitThreads / kWave;
+
+__global__ void __launch_bounds__(kSplitThreads) k_split(TreeArgs a) {
+    __shared__ int32_t sc[kSplitThreads];
+    __shared__ int32_t wsum[2][kSplitWaves];
+    const int t = threadIdx.x, w = t / kWave;
     const int32_t lvl = a.desc[0], nq = level_clusters(a.desc);
     for (int32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int32_t v = lvl + q;
         if (a.rpole[v] < 0) continue;   // uniform per block
         const int64_t ms = a.mstart[v], k = a.mcount[v];
         int32_t cnt = 0;
-        for (int64_t i = threadIdx.x; i < k; i += blockDim.x) cnt += a.dl[ms + i] <= a.dr[ms + i];
-        sc[threadIdx.x] = cnt;
+        for (int64_t i = t; i < k; i += kSplitThreads) cnt += a.dl[ms + i] <= a.dr[ms + i];
+        sc[t] = cnt;
         __syncthreads();
-        for (int o = 128; o >= 1; o >>= 1) {
-            if (threadIdx.x < o) sc[threadIdx.x] += sc[threadIdx.x + o];
+        for (int o = kSplitThreads / 2; o >= 1; o >>= 1) {
+            if (t < o) sc[t] += sc[t + o];
             __syncthreads();
         }
         const int32_t nl = sc[0];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            base_l = 0;
-            base_r = nl;
-        }
-        __syncthreads();
-        for (int64_t c0 = 0; c0 < k; c0 += blockDim.x) {
-            const int64_t i = c0 + threadIdx.x;
-            const int f = (i < k && a.dl[ms + i] <= a.dr[ms + i]) ? 1 : 0;
-            sc[threadIdx.x] = f;
+        int64_t base_l = 0, base_r = nl;   // the same in every thread
+        int buf = 0;
+        for (int64_t c0 = 0; c0 < k; c0 += kSplitThreads) {
+            const int64_t i = c0 + t;
+            const bool f = i < k && a.dl[ms + i] <= a.dr[ms + i];
+            const uint64_t m = __ballot(f);
+            const int before_w = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if ((t & (kWave - 1)) == 0) wsum[buf][w] = __popcll(m);
             __syncthreads();
-            for (int o = 1; o < 256; o <<= 1) {   // inclusive scan of the chunk's flags
-                const int32_t t = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
-                __syncthreads();
-                sc[threadIdx.x] += t;
-                __syncthreads();
+            int32_t before_l = before_w, chunk_l = 0;
+#pragma unroll
+            for (int x = 0; x < kSplitWaves; ++x) {
+                const int32_t c = wsum[buf][x];
+                chunk_l += c;
+                before_l += x < w ? c : 0;
             }
-            const int32_t incl = sc[threadIdx.x];
-            const int32_t chunk_l = sc[255];
             if (i < k) {
-                const int32_t before_l = incl - f;
                 const int64_t dst = f ? ms + base_l + before_l
-                                      : ms + base_r + (threadIdx.x - before_l);
+                                      : ms + base_r + (t - before_l);
                 a.perm_next[dst] = a.perm[ms + i];
             }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                base_l += chunk_l;
-                base_r += (int32_t)min<int64_t>(blockDim.x, k - c0) - chunk_l;
-            }
-            __syncthreads();
+            base_l += chunk_l;
+            base_r += min<int64_t>(kSplitThreads, k - c0) - chunk_l;
+            buf ^= 1;
         }
-        if (threadIdx.x == 0) {
+        if (t == 0) {
             a.nleft[q] = nl;
             a.split[q] = 1;
         }
-        __syncthreads();
+        __syncthreads();   // sc and wsum are reused by the next cluster
     }
 }
 
@@ -946,6 +944,7 @@ __device__ void block_sort_keys(uint64_t *e, uint32_t *id, int n) {
 
 constexpr int kTopkThreads = 256;
 constexpr int kTopkSel = 2048;      // members a selection may collect in LDS
+static_assert(kMaxTopk <= kTopkSel, "the pivots of a cluster are staged in the selection's LDS");
 
 constexpr uint64_t kPivotFlag = 1ull << 63;
 
@@ -954,6 +953,30 @@ __device__ __forceinline__ uint64_t estimate(uint64_t v, bool sampled, int64_t p
     const bool piv = (v & kPivotFlag) != 0;
     const uint64_t m = piv ? (uint64_t)ps : (uint64_t)(ps > 1 ? ps - 1 : 1);
     return (v & ~kPivotFlag) * m;
+}
+
+// Ranking keys (estimate, input index) of members i0 + u blockDim.x, u <
+// kTopkUnroll, of the cluster at ms (k members); members past the cluster
+// get the largest key, which no comparison selects.
+constexpr int kTopkUnroll = 4;
+
+__device__ __forceinline__ void member_keys(const TreeArgs &a, int64_t ms, int64_t k, int64_t i0,
+                                            bool sampled, int64_t ps, uint64_t (&sv)[kTopkUnroll],
+                                            uint32_t (&oi)[kTopkUnroll]) {
+    uint64_t r[kTopkUnroll];
+    int32_t pm[kTopkUnroll];
+#pragma unroll
+    for (int u = 0; u < kTopkUnroll; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        r[u] = i < k ? a.rowsum[ms + i] : 0ull;
+        pm[u] = i < k ? a.perm[ms + i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kTopkUnroll; ++u) {
+        const int64_t i = i0 + (int64_t)u * blockDim.x;
+        oi[u] = i < k ? (uint32_t)a.order[pm[u]] : ~0u;
+        sv[u] = i < k ? estimate(r[u], sampled, ps) : ~0ull;
+    }
 }
 
 // Candidates of each cluster, from its first candidate slot on: every member
@@ -998,13 +1021,17 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
         } else {
             bool done = false;
             if (nc <= kTopkThreads) {
-                // least key of this thread's share
+                // least key of this thread's share (four members a round,
+                // their loads issued together)
                 uint64_t be = ~0ull;
                 uint32_t bi = ~0u;
-                for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
-                    const uint64_t sv = estimate(a.rowsum[ms + i], sampled, ps);
-                    const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
-                    if (key_less(sv, oi, be, bi)) { be = sv; bi = oi; }
+                for (int64_t i0 = threadIdx.x; i0 < k; i0 += kTopkUnroll * blockDim.x) {
+                    uint64_t sv[kTopkUnroll];
+                    uint32_t oi[kTopkUnroll];
+                    member_keys(a, ms, k, i0, sampled, ps, sv, oi);
+#pragma unroll
+                    for (int u = 0; u < kTopkUnroll; ++u)
+                        if (key_less(sv[u], oi[u], be, bi)) { be = sv[u]; bi = oi[u]; }
                 }
                 se[threadIdx.x] = be;
                 si[threadIdx.x] = bi;
@@ -1015,14 +1042,18 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
                 const uint32_t ti = si[nc - 1];
                 __syncthreads();
                 // every member with key <= (te, ti)
-                for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
-                    const uint64_t sv = estimate(a.rowsum[ms + i], sampled, ps);
-                    const uint32_t oi = (uint32_t)a.order[a.perm[ms + i]];
-                    if (!key_less(te, ti, sv, oi)) {
-                        const uint32_t slot = atomicAdd(&count, 1u);
-                        if (slot < (uint32_t)kTopkSel) {
-                            se[slot] = sv;
-                            si[slot] = oi;
+                for (int64_t i0 = threadIdx.x; i0 < k; i0 += kTopkUnroll * blockDim.x) {
+                    uint64_t sv[kTopkUnroll];
+                    uint32_t oi[kTopkUnroll];
+                    member_keys(a, ms, k, i0, sampled, ps, sv, oi);
+#pragma unroll
+                    for (int u = 0; u < kTopkUnroll; ++u) {
+                        if (!key_less(te, ti, sv[u], oi[u])) {
+                            const uint32_t slot = atomicAdd(&count, 1u);
+                            if (slot < (uint32_t)kTopkSel) {
+                                se[slot] = sv[u];
+                                si[slot] = oi[u];
+                            }
                         }
                     }
                 }
@@ -1078,12 +1109,31 @@ __global__ void __launch_bounds__(kTopkThreads) k_topk(TreeArgs a, int phase) {
         if (threadIdx.x == 0) a.cnt[q] = k >= 2 ? nc * ((k + 63) / 64) : 0;
         if (phase == 0) {
             __syncthreads();               // every hash has been read
+            // the pivots' ranks into LDS (nc <= kMaxTopk <= kTopkSel)
+            for (int64_t j = threadIdx.x; j < nc; j += blockDim.x) si[j] = (uint32_t)a.cand[base + j];
+            __syncthreads();
             // clear the estimates, keeping a pivot flag in the top bit
-            for (int64_t i = threadIdx.x; i < k; i += blockDim.x) {
-                const int32_t r = a.perm[ms + i];
-                bool piv = false;
-                for (int64_t j = 0; j < nc; ++j) piv |= a.cand[base + j] == r;
-                a.rowsum[ms + i] = piv ? kPivotFlag : 0ull;
+            // (four members a round: their loads overlap, and each pivot
+            // read from LDS serves all four)
+            for (int64_t i0 = threadIdx.x; i0 < k; i0 += kTopkUnroll * blockDim.x) {
+                uint32_t r[kTopkUnroll];
+                bool piv[kTopkUnroll];
+#pragma unroll
+                for (int u = 0; u < kTopkUnroll; ++u) {
+                    const int64_t i = i0 + (int64_t)u * blockDim.x;
+                    r[u] = i < k ? (uint32_t)a.perm[ms + i] : ~0u;
+                    piv[u] = false;
+                }
+                for (int64_t j = 0; j < nc; ++j) {
+                    const uint32_t c = si[j];
+#pragma unroll
+                    for (int u = 0; u < kTopkUnroll; ++u) piv[u] |= c == r[u];
+                }
+#pragma unroll
+                for (int u = 0; u < kTopkUnroll; ++u) {
+                    const int64_t i = i0 + (int64_t)u * blockDim.x;
+                    if (i < k) a.rowsum[ms + i] = piv[u] ? kPivotFlag : 0ull;
+                }
             }
             if (threadIdx.x == 0) a.ncand[q] = a.topk;
         }
@@ -1152,7 +1202,6 @@ static void dist_pass(const TreeArgs &a, int grid, const XlShape &xl, hipStream_
                                                                    : kClsPole;
     const int32_t cap = xl.on() ? (cls == kClsPole ? xl.pole_cap : xl.sum_cap) : 0;
     hipLaunchKernelGGL(k_scan_work, dim3(1), dim3(1024), 0, s, a, cls);
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.counter);
     // a cap above n sends every cluster across lanes: k_tree_lev would only
     // find no work
     if (cap <= a.n) hipLaunchKernelGGL((k_tree_lev<WMAX, MODE>), dim3(grid), dim3(kWave), 0, s, a);

@@ -227,7 +227,8 @@ enum { kClsMedoid = 0, kClsSum = 1, kClsPole = 2 };
 // larger one to k_tree_lev as cnt[q] items (cnt as set by the kernel that
 // chose the pass's patterns; 0 = no work).  Pairs per cluster of k members:
 // the medoid triangle k (k - 1) / 2; a candidate or pivot pass (cnt = count
-// x ceil(k / 64) items) count x k; a pole pass k.  items and pitems get the
+// x ceil(k / 64) items) count x k, or the triangle when every member is a
+// candidate; a pole pass k.  items and pitems get the
 // exclusive prefixes, q = 0 .. nq (one workgroup).  It also clears both
 // kernels' work counters for the pass.
 __global__ void __launch_bounds__(1024) k_scan_work(TreeArgs a, int cls) {
@@ -249,7 +250,13 @@ __global__ void __launch_bounds__(1024) k_scan_work(TreeArgs a, int cls) {
             it = c;
             return;
         }
-        pr = cls == kClsMedoid ? k * (k - 1) / 2 : cls == kClsSum ? c / ((k + 63) / 64) * k : k;
+        // a candidate pass over a cluster whose every member is a candidate
+        // (at most topk or exact_below members) takes its triangle: each
+        // distance once, credited to both members
+        const bool all_cand = cls == kClsSum && (k <= a.exact_below || k <= a.topk);
+        pr = cls == kClsMedoid || all_cand ? k * (k - 1) / 2
+             : cls == kClsSum              ? c / ((k + 63) / 64) * k
+                                           : k;
     };
     int64_t si = 0, sp = 0;
     for (int64_t i = lo; i < hi; ++i) {
@@ -394,9 +401,13 @@ __global__ void __launch_bounds__(kXlBlock) k_tree_xl(TreeArgs a, int mode) {
         const int64_t L = p - a.pitems[q];
         const int32_t v = lvl + q;
         const int64_t ms = a.mstart[v], k = a.mcount[v];
-        int64_t tpos, ppos = 0, cslot = 0;
+        int64_t tpos, ppos = 0, cslot = 0, tslot = 0;
         int32_t prow;
-        if (mode == kMedoid) {
+        // candidate pass of a cluster whose members are all candidates
+        // (candidate i = member i): its triangle, as the medoid pass
+        const bool tri = mode == kMedoid ||
+                         (mode == kCandSum && (k <= a.exact_below || k <= a.topk));
+        if (tri) {
             // triangle pair L = u (u - 1) / 2 + t, t < u: member u (the
             // longer one, members being in length order) is the pattern
             int64_t u = (int64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)L)) * 0.5f);
@@ -405,6 +416,8 @@ __global__ void __launch_bounds__(kXlBlock) k_tree_xl(TreeArgs a, int mode) {
             ppos = ms + u;
             prow = a.perm[ppos];
             tpos = ms + (L - u * (u - 1) / 2);
+            cslot = a.coff[q] + u;
+            tslot = a.coff[q] + (tpos - ms);
         } else if (mode == kCandSum || mode == kPivotSum) {
             const int64_t jj = L / k;
             cslot = a.coff[q] + jj;
@@ -437,6 +450,11 @@ __global__ void __launch_bounds__(kXlBlock) k_tree_xl(TreeArgs a, int mode) {
             if (lead && head) {
                 atomicAdd((unsigned long long *)&a.candsum[cslot], (unsigned long long)ss);
                 atomicMax((unsigned long long *)&a.candkey[cslot], (unsigned long long)sk);
+            }
+            if (lead && tri) {   // the other member of a triangle pair
+                atomicAdd((unsigned long long *)&a.candsum[tslot], (unsigned long long)d);
+                atomicMax((unsigned long long *)&a.candkey[tslot],
+                          (unsigned long long)far_key(d, a.order[prow]));
             }
         } else {
             if (mode == kPoleMax || mode == kPoleMaxStore) {

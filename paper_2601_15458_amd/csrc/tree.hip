@@ -246,14 +246,14 @@ __global__ void __launch_bounds__(1024) k_scan_work(TreeArgs a, int cls) {
         const int64_t c = a.cnt[q];
         if (c == 0) return;
         const int64_t k = a.mcount[lvl + q];
-        if (k > cap) {
-            it = c;
-            return;
-        }
         // a candidate pass over a cluster whose every member is a candidate
         // (at most topk or exact_below members) takes its triangle: each
         // distance once, credited to both members
         const bool all_cand = cls == kClsSum && (k <= a.exact_below || k <= a.topk);
+        if (k > cap) {
+            it = all_cand ? items_upto(k - 1) : c;
+            return;
+        }
         pr = cls == kClsMedoid || all_cand ? k * (k - 1) / 2
              : cls == kClsSum              ? c / ((k + 63) / 64) * k
                                            : k;
@@ -312,7 +312,12 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
         int32_t prow;
         int64_t cslot = 0;
         int64_t tend = ms + k;                   // texts are positions [.., tend)
-        if (MODE == kMedoid) {
+        // a candidate pass over a cluster whose every member is a candidate
+        // (candidate i = member i) takes the medoid triangle: each distance
+        // once, credited to both members
+        const bool tri = MODE == kMedoid ||
+                         (MODE == kCandSum && (k <= a.exact_below || k <= a.topk));
+        if (tri) {
             // Member u (the longer of each pair: members are in length order)
             // is the pattern of members 0 .. u-1, which cost fewer bit
             // columns than the other way round and round up fewer rows; the
@@ -324,6 +329,7 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
             prow = a.perm[prow_pos];
             tpos = ms + blk * 64 + lane;
             tend = ms + u;
+            cslot = a.coff[q] + u;
         } else if (MODE == kCandSum || MODE == kPivotSum) {
             const int64_t nblk = (k + 63) / 64;
             const int64_t j = local / nblk, blk = local % nblk;
@@ -362,6 +368,13 @@ __global__ void __launch_bounds__(64) k_tree_lev(TreeArgs a) {
             const uint64_t m = wave_max_u64(key);
             atomicMax((unsigned long long *)&a.candkey[cslot],
                       (unsigned long long)(lane == 0 ? m : 0ull));
+            if (tri) {   // uniform: the texts' side of the triangle pairs
+                const int64_t ts = a.coff[q] + ((valid ? tpos : ms) - ms);
+                atomicAdd((unsigned long long *)&a.candsum[ts],
+                          (unsigned long long)(valid ? d : 0));
+                atomicMax((unsigned long long *)&a.candkey[ts],
+                          (unsigned long long)(valid ? far_key(d, a.order[prow]) : 0ull));
+            }
         }
         if (MODE == kPivotSum)
             atomicAdd((unsigned long long *)&a.rowsum[slot], (unsigned long long)(valid ? d : 0));

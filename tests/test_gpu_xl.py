@@ -163,3 +163,19 @@ def test_autotune_tree_xl_stores_a_candidate():
     finally:
         M.tune_clear()
     _equal_trees(got, orc.tree_sampled(codes, off, pivots=8, topk=8))
+
+
+@pytest.mark.parametrize("v", [(1, 0, 0), (2, 128, 16383), (2, 16383, 16383)])
+def test_all_candidate_clusters_take_the_triangle(v):
+    """Clusters of at most exact_below members take every member as a
+    candidate; their candidate pass runs as the medoid triangle in both
+    kernels (clusters of 129-300 members in the one-pattern-per-wavefront
+    kernel under the default caps, every cluster in it with the across-lanes
+    passes off, every cluster across lanes with caps for all)."""
+    M = _msadp()
+    codes, off = synth.random_set(80, 600, 20, 260, 4)
+    S = M.to_device(codes, off, 4)
+    print(f"[xl] all-candidate clusters variant={v}", flush=True)
+    got = _with_xl(4, off, M.xl_value(*v),
+                   lambda: M.tree_build(S, use_graph=True, pivots=8, topk=4, exact_below=300))
+    _equal_trees(got, orc.tree_sampled(codes, off, pivots=8, topk=4, exact_below=300))

@@ -13,13 +13,16 @@
 // Internal nodes keep their center and poles.  The alignment of the grown
 // set is msa_merge along the new tree.
 //
-// Routing runs level-synchronously: one lev_batch call per tree depth on the
-// (pole, x) pairs of the sequences still above a leaf.  The grown leaves are
+// Routing runs level-synchronously: one distance launch per tree depth on the
+// (pole, x) pairs of the sequences still above a leaf, a pair per group of
+// lanes on the set staged once per call (lev_batch for patterns beyond that
+// layout).  The grown leaves are
 // re-partitioned together, as a forest, by the level passes of tree.hip.
 // The splice walks the combined tree breadth-first inside one workgroup
 // (a block scan per chunk of a level), then sums member counts bottom-up and
 // places ranges top-down, level by level.
 #include "common.hpp"
+#include "lev_xl.hpp"
 
 namespace msadp {
 
@@ -365,9 +368,18 @@ struct InsertWs {
     int32_t *fparent, *fleft, *fright, *fcenter, *flpole, *frpole, *fdepth, *fperm;
     int64_t *fmstart, *fmcount;
     int32_t *bfs, *lvl, *total;
+    // routing distances: the set staged once for the across-lanes kernel
+    // (xl), else lev_batch's workspace
+    bool xl;
+    Staged SS;
+    uint32_t *xl_counter;
     void *lev_ws, *tree_ws;
     size_t lev_bytes, tree_bytes;
 };
+
+// Whether the routing rounds can run across lanes: patterns of up to 256
+// 64-bit words (the across-lanes layout's limit).
+static bool insert_xl(const msa_seqs *S) { return ((int64_t)S->max_len + 63) / 64 <= 256; }
 
 template <class Alloc>
 static void insert_layout(Alloc &al, const msa_seqs *S, int32_t n_old, int32_t n_nodes_old,
@@ -399,8 +411,18 @@ static void insert_layout(Alloc &al, const msa_seqs *S, int32_t n_old, int32_t n
     w.bfs = al.template take<int32_t>(cap);
     w.lvl = al.template take<int32_t>(cap + 1);
     w.total = al.template take<int32_t>(1);
-    w.lev_bytes = nn ? lev_batch_ws_bytes(S, S, 2 * (int64_t)nn, false) : 0;
-    w.lev_ws = al.template take<uint8_t>(w.lev_bytes);
+    w.xl = insert_xl(S);
+    if (w.xl) {
+        const int64_t stride = staged_stride(S->max_len);
+        w.SS = Staged{al.template take<uint8_t>(n * (size_t)stride),
+                      al.template take<int32_t>(n + 1), stride, S->n};
+        w.xl_counter = al.template take<uint32_t>(1);
+        w.lev_bytes = 0;
+        w.lev_ws = nullptr;
+    } else {
+        w.lev_bytes = nn ? lev_batch_ws_bytes(S, S, 2 * (int64_t)nn, false) : 0;
+        w.lev_ws = al.template take<uint8_t>(w.lev_bytes);
+    }
     w.tree_bytes = tree_workspace_bytes(S);
     w.tree_ws = al.template take<uint8_t>(w.tree_bytes);
 }
@@ -465,6 +487,9 @@ int tree_insert(const msa_seqs *S, int32_t n_old, const msa_tree *T_old, int32_t
 
     // 1. routing, one tree depth per round
     if (n_new > 0) {
+        // each round's pairs are a few per new sequence: one launch sized to
+        // them on the set staged once, a pair per group of lanes
+        if (w.xl && (rc = stage_set(S, nullptr, w.SS, d_status, s))) return rc;
         hipLaunchKernelGGL(k_route_init, dim3(blocks(n_new)), dim3(256), 0, s, w.cur, n_new);
         for (int32_t round = 0;; ++round) {
             if (round > n_nodes_old) return MSA_EINVAL;   // a child cycle in T_old
@@ -475,9 +500,14 @@ int tree_insert(const msa_seqs *S, int32_t n_old, const msa_tree *T_old, int32_t
             int32_t h = 0;
             if ((rc = read_i32((const int32_t *)w.cnt, &h, s))) return rc;
             if (h == 0) break;
-            if ((rc = lev_batch_impl(S, S, w.ia, w.ib, 2 * (int64_t)h, w.dist, w.lev_ws,
-                                     w.lev_bytes, d_status, s, 0)))
+            if (w.xl) {
+                if ((rc = lev_xl_staged(w.SS, w.SS, S->sigma, S->max_len, w.ia, w.ib,
+                                        2 * (int64_t)h, w.dist, w.xl_counter, d_status, s)))
+                    return rc;
+            } else if ((rc = lev_batch_impl(S, S, w.ia, w.ib, 2 * (int64_t)h, w.dist, w.lev_ws,
+                                            w.lev_bytes, d_status, s, 0))) {
                 return rc;
+            }
             hipLaunchKernelGGL(k_route_step, dim3(blocks(h)), dim3(256), 0, s, ot, w.cur,
                                w.slot_k, w.dist, h);
         }

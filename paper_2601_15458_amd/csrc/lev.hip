@@ -630,9 +630,8 @@ struct XlPairShape {
     int g, wl, nb;
 };
 
-static bool xl_pairs_shape(const msa_seqs *A, const msa_seqs *B, XlPairShape *x) {
-    const int words = pair_words_bin(A, B);
-    x->nb = xl_planes(A->sigma);
+static bool xl_shape_for(int words, int sigma, XlPairShape *x) {
+    x->nb = xl_planes(sigma);
     if (words <= 64) {
         x->wl = 1;
         x->g = 8;
@@ -642,6 +641,10 @@ static bool xl_pairs_shape(const msa_seqs *A, const msa_seqs *B, XlPairShape *x)
     x->g = kWave;
     x->wl = (words + 63) / 64;
     return x->wl <= 4;
+}
+
+static bool xl_pairs_shape(const msa_seqs *A, const msa_seqs *B, XlPairShape *x) {
+    return xl_shape_for(pair_words_bin(A, B), A->sigma, x);
 }
 
 template <int NB>
@@ -732,6 +735,24 @@ static int run_xl_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
                   d_status};
     void *args[] = {&xa};
     if (hipLaunchKernel(xl_pair_kernel(x), dim3(xl_pair_grid(x)), dim3(kXlPairBlock), args, 0,
+                        s) != hipSuccess)
+        return MSA_EDEVICE;
+    return launch_status();
+}
+
+int lev_xl_staged(const Staged &A, const Staged &B, int32_t sigma, int32_t max_len,
+                  const int32_t *ia, const int32_t *ib, int64_t n_pairs, uint16_t *dist,
+                  uint32_t *counter, int32_t *d_status, hipStream_t s) {
+    XlPairShape x;
+    if (!xl_shape_for((int)std::max<int64_t>(1, ((int64_t)max_len + 63) / 64), sigma, &x))
+        return MSA_ERANGE;
+    if (n_pairs <= 0) return MSA_OK;
+    if (A.stride != B.stride) return MSA_EINVAL;
+    const int64_t waves = (n_pairs + kWave / x.g - 1) / (kWave / x.g);
+    const int64_t grid = (waves + kXlPairBlock / kWave - 1) / (kXlPairBlock / kWave);
+    XlPairArgs xa{A, B, ia, ib, nullptr, n_pairs, dist, counter, d_status};
+    void *args[] = {&xa};
+    if (hipLaunchKernel(xl_pair_kernel(x), dim3((unsigned)grid), dim3(kXlPairBlock), args, 0,
                         s) != hipSuccess)
         return MSA_EDEVICE;
     return launch_status();

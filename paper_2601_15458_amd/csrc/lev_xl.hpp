@@ -254,4 +254,13 @@ __device__ __forceinline__ int xl_distance(const uint8_t *pat, int m, const uint
     return n + xl_group_sum<G>(c);
 }
 
+// Distances of pairs (ia[p], ib[p]) of two sets already staged with one
+// common stride, one pair per group of lanes (the across-lanes layout), in
+// one launch of just enough wavefronts for the pairs, each taking its pairs
+// as its first work item (`counter` may hold any value).  MSA_ERANGE when
+// patterns of max_len rows do not fit the layout (lev.hip).
+int lev_xl_staged(const Staged &A, const Staged &B, int32_t sigma, int32_t max_len,
+                  const int32_t *ia, const int32_t *ib, int64_t n_pairs, uint16_t *dist,
+                  uint32_t *counter, int32_t *d_status, hipStream_t s);
+
 }  // namespace msadp

@@ -249,6 +249,19 @@ def oracle_beside(args, fn, cells, sample):
             "gcups": round(cells / dt / 1e9, 3) if cells else None, "cores": orc.num_threads()}
 
 
+def alu_roofline(entry, ms, kernel):
+    """A kernel's VALU issue against the chip's VALU figure: the counted
+    SQ_INSTS_VALU of one dispatch (profiles/counters.json) x 64 lanes over
+    the timed call; None without a current counter entry."""
+    if not entry or not entry.get("valu_insts"):
+        return None
+    peak = VALU_PEAK_LANE_OPS / 1e12
+    a = entry["valu_insts"] * 64 / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(a, 2), "peak": round(peak, 1),
+            "unit": "T lane-ops/s", "frac": round(a / peak, 4), "kernel": kernel,
+            "valu_insts": entry["valu_insts"], "dual_issue_share": entry.get("valu2_share")}
+
+
 def _time_calls(torch, fn, stream, reps):
     fn()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -426,7 +439,11 @@ def bench_nw(msadp, synth, torch, args):
                          "frac": round(tb_bytes / f / 1e6 / HBM_PEAK_GBS, 4),
                          "traffic": (counted("k_nw_fill", tuning["chosen"] if tuning else 32)
                                      or {}).get("hbm_bytes"),
-                         "kernel": "k_nw_fill"}}
+                         "kernel": "k_nw_fill"},
+            # the same fill against the VALU figure (it is latency-bound: see
+            # the kernel's discussion)
+            "roofline_alu": alu_roofline(counted("k_nw_fill", tuning["chosen"] if tuning else 32),
+                                         f, "k_nw_fill")}
 
 
 def bench_pairs(msadp, synth, torch, args):
@@ -511,11 +528,13 @@ def bench_gotoh(msadp, synth, torch, args):
             "gcups_fill_plus_traceback": round(cells / (f + t) / 1e6, 1),
             "tb_bytes": tb, "fill_hbm_gbs": round(tb / f / 1e6, 1),
             # one code byte per cell written: the fill's design bound is HBM
-            # writes (the ALU side is discussed with the kernel)
+            # writes
             "roofline": {"bound": "hbm", "achieved": round(tb / f / 1e6, 1), "peak": 8000.0,
                          "unit": "GB/s", "frac": round(tb / f / 1e6 / 8000.0, 4),
                          "traffic": (counted("k_gotoh_fill") or {}).get("hbm_bytes"),
-                         "kernel": "k_gotoh_fill"}}
+                         "kernel": "k_gotoh_fill"},
+            # what does bound it: VALU issue, counted
+            "roofline_alu": alu_roofline(counted("k_gotoh_fill"), f, "k_gotoh_fill")}
 
 
 def bench_band(msadp, synth, torch, args):

@@ -441,8 +441,14 @@ __global__ void __launch_bounds__(kXlBlock) k_tree_xl(TreeArgs a, int mode) {
             tpos = ms + L;
         }
         const int32_t trow = a.perm[tpos];
-        const int d = xl_distance<G, WL, NB>(a.S.codes + (int64_t)prow * a.S.stride, a.S.len[prow],
-                                             a.S.codes + (int64_t)trow * a.S.stride, a.S.len[trow],
+        // the longer sequence of the pair is the pattern (the distance is
+        // symmetric): the group's lanes hold the set's longest pattern
+        // anyway, and the steps follow the shorter one
+        const int32_t lp = a.S.len[prow], lt = a.S.len[trow];
+        const bool sw = lt > lp;
+        const int32_t xr = sw ? trow : prow, yr = sw ? prow : trow;
+        const int d = xl_distance<G, WL, NB>(a.S.codes + (int64_t)xr * a.S.stride, sw ? lt : lp,
+                                             a.S.codes + (int64_t)yr * a.S.stride, sw ? lp : lt,
                                              a.S.stride - 16, live);
         // Pairs of one cluster (pole keys), one candidate (candidate sums and
         // keys) or one pattern member (medoid sums of the longer member) are

@@ -22,6 +22,10 @@ def test_candidates():
     assert M.tune_candidates(M.MSA_TUNE_LEV) == [4, 8, 16, 20, 24, 28, 32]
     assert M.tune_candidates(M.MSA_TUNE_NW) == [16, 32, 64]
     assert M.tune_candidates(M.MSA_TUNE_TREE) == [4, 8, 16, 20, 24, 32]
+    assert M.tune_candidates(M.MSA_TUNE_PAIRS) == [1, 2, 64]
+    xl = M.tune_candidates(M.MSA_TUNE_TREE_XL)
+    assert M.xl_value(1, 0, 0) in xl and M.xl_value(2, 128, M.XL_CAP_ALL) in xl
+    assert all(v >> 28 in (1, 2) for v in xl)
 
 
 def test_set_get_clear():
@@ -43,7 +47,10 @@ def test_set_get_clear():
     (0, 4, 25, 30),      # not a word class
     (1, 4, 3, 48),       # not a barrier interval
     (2, 4, 3, 28),       # a pair-kernel class the tree build does not have
-    (3, 4, 3, 32),       # unknown kind
+    (3, 4, 3, 32),       # not a pair layout (1, 2 or 64)
+    (5, 4, 3, 1),        # unknown kind
+    (4, 4, 3, 0),        # across-lanes value with no words per lane
+    (4, 4, 3, 3 << 28),  # three words per lane (the tree passes have 1 or 2)
     (0, 1, 3, 32),       # alphabet too small
     (0, 4, 0, 32),       # empty bin
 ])
@@ -60,16 +67,23 @@ def test_export_import_round_trip():
     M.tune_set(M.MSA_TUNE_LEV, 20, 3, 4)
     M.tune_set(M.MSA_TUNE_NW, 4, 5, 16)
     M.tune_set(M.MSA_TUNE_TREE, 20, 32, 24)
+    M.tune_set(M.MSA_TUNE_PAIRS, 4, 160, 2)
+    xv = M.xl_value(2, 256, M.XL_CAP_ALL)
+    M.tune_set(M.MSA_TUNE_TREE_XL, 4, 8, xv)
     text = M.tune_export()
     doc = json.loads(text)
     assert sorted(map(tuple, doc["entries"])) == [(0, 4, 25, 28), (0, 20, 3, 4), (1, 4, 5, 16),
-                                                  (2, 20, 32, 24)]
+                                                  (2, 20, 32, 24), (3, 4, 160, 2),
+                                                  (4, 4, 8, xv)]
     M.tune_clear()
     M.tune_import(text)
     assert M.tune_get(M.MSA_TUNE_LEV, 4, 25) == 28
     assert M.tune_get(M.MSA_TUNE_LEV, 20, 3) == 4
     assert M.tune_get(M.MSA_TUNE_NW, 4, 5) == 16
     assert M.tune_get(M.MSA_TUNE_TREE, 20, 32) == 24
+    assert M.tune_get(M.MSA_TUNE_PAIRS, 4, 160) == 2
+    assert M.tune_get(M.MSA_TUNE_TREE_XL, 4, 8) == xv
+    assert "sums up to 256, poles up to all" in M.xl_describe(xv)
 
 
 def test_import_rejects_other_arch_and_bad_entries():

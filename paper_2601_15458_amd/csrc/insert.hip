@@ -241,25 +241,36 @@ __device__ UView view(const SpliceArgs &a, int32_t w) {
     return x;
 }
 
-// Inclusive block scan of one int32 per thread (1024 threads).
-__device__ __forceinline__ int32_t block_scan(int32_t v, int32_t *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
+// Count of set flags among threads 0 .. t of the 1024-thread block (an
+// inclusive prefix), and the block's total: a ballot prefix inside each
+// wavefront and the 16 wavefronts' counts through LDS.  wsum holds two
+// buffers of 16, used alternately (buf), so that one barrier per call
+// orders every write before its reads and after the previous call's.
+constexpr int kSpliceWaves = 1024 / kWave;
+
+__device__ __forceinline__ int32_t block_count(bool f, int32_t (*wsum)[kSpliceWaves], int &buf,
+                                               int32_t &total) {
+    const int t = threadIdx.x, w = t / kWave;
+    const uint64_t m = __ballot(f);
+    const int32_t below = (int32_t)__builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if ((t & (kWave - 1)) == 0) wsum[buf][w] = __popcll(m);
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int32_t w = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += w;
-        __syncthreads();
+    int32_t before = 0, tot = 0;
+#pragma unroll
+    for (int x = 0; x < kSpliceWaves; ++x) {
+        const int32_t c = wsum[buf][x];
+        tot += c;
+        before += x < w ? c : 0;
     }
-    const int32_t r = sh[t];
-    __syncthreads();
-    return r;
+    buf ^= 1;
+    total = tot;
+    return before + below + (f ? 1 : 0);
 }
 
 __global__ void __launch_bounds__(1024) k_splice(SpliceArgs a) {
-    __shared__ int32_t sh[1024];
-    __shared__ int32_t s_next, s_bad;
+    __shared__ int32_t wsum[2][kSpliceWaves];
+    __shared__ int32_t s_bad;
     const int t = threadIdx.x;
     const int32_t U = a.o.n_nodes + a.nf - a.K;
     if (t == 0) {
@@ -269,24 +280,22 @@ __global__ void __launch_bounds__(1024) k_splice(SpliceArgs a) {
         s_bad = 0;
     }
     __syncthreads();
-    // breadth-first ids, one level at a time
+    // breadth-first ids, one level at a time; `next` (the next free id) is
+    // the same in every thread
     int32_t lo = 0, hi = 1, d = 0;
+    int buf = 0;
     while (lo < hi) {
-        if (t == 0) {
-            a.lvl[d] = lo;
-            s_next = hi;
-        }
-        __syncthreads();
+        if (t == 0) a.lvl[d] = lo;
+        int32_t next = hi;
         for (int32_t base = lo; base < hi; base += 1024) {
             const int32_t j = base + t;
             UView x{};
             const bool in = j < hi;
             if (in) x = view(a, a.bfs[j]);
             const int32_t c = (in && x.l >= 0) ? 2 : 0;
-            const int32_t incl = block_scan(c, sh);
-            const int32_t next = s_next;
-            const int32_t chunk = sh[1023];
-            __syncthreads();
+            int32_t splits;
+            const int32_t incl = 2 * block_count(c != 0, wsum, buf, splits);
+            const int32_t chunk = 2 * splits;
             if (in) {
                 const int32_t at = next + incl - c;
                 const bool fits = at + c <= U && at + c <= a.cap;
@@ -305,14 +314,14 @@ __global__ void __launch_bounds__(1024) k_splice(SpliceArgs a) {
                     a.out.left[j] = a.out.right[j] = -1;
                 }
             }
-            if (t == 0) s_next = next + chunk;
-            __syncthreads();
-            if (s_bad) break;
+            next += chunk;
         }
+        // every thread's writes of the level (bfs, s_bad) before the next
+        // level reads them
         __syncthreads();
         if (s_bad) break;
         lo = hi;
-        hi = min(s_next, min(U, a.cap));
+        hi = min(next, min(U, a.cap));
         ++d;
     }
     if (s_bad || hi != U) {

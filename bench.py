@@ -9,12 +9,15 @@ workload and 8.4 M random pairs of the all-pairs set), the 512-pair NW fill
 + traceback ("nw"), the same pairs under an affine-gap score matrix
 ("gotoh") and by the exact banded distance ("band"), the exact tree build of
 20,000 protein sequences ("tree": autotuned, graph-replayed levels), the
-learned pruning of the tree build on 100,000 sequences ("pruned": embedder
-training, exact vs pruned build time, teacher-forced agreement, control
-rankers, alignment quality of the pruned trees' alignments) and the
-alignment-quality metrics ("quality") and machine rates ("machine").
+online insertion of 1,000 sequences into the exact tree of 99,000
+("insert"), the learned pruning of the tree build on 100,000 sequences
+("pruned": embedder training, exact vs pruned build time, teacher-forced
+agreement, control rankers, alignment quality of the pruned trees'
+alignments) and the alignment-quality metrics ("quality") and machine rates
+("machine").
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+                    [--no-tune] [--legs a,b,...]
 """
 from __future__ import annotations
 

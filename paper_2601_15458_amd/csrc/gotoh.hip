@@ -7,6 +7,12 @@
 //   F[i][j] = max(F[i-1][j] - ext, H[i-1][j] - open - ext)     (ends with D)
 //   H[i][j] = max(H[i-1][j-1] + sub[a_i][b_j], E[i][j], F[i][j])
 // with H[i][0] = F[i][0] = -(open + i ext), H[0][j] = E[0][j] = -(open + j ext).
+// The fill keeps X + (i + j) ext for X in {H, E, F}: then both extension
+// branches compare without a subtraction (E[i][j] + (i+j) ext =
+// max(E[i][j-1] + (i+j-1) ext, H[i][j-1] + (i+j-1) ext - open), likewise F),
+// the diagonal gains 2 ext (folded into the score table), the borders are
+// -open, and every difference the codes compare is unchanged.  The score is
+// the shifted H[m][n] minus (m + n) ext.
 //
 // Fill layout.  One workgroup per pair; global lane g = 64 w + l owns the 16
 // rows 16g+1 .. 16g+16 of a and keeps their H and E of the previous column
@@ -52,7 +58,8 @@ constexpr int kGLag = 64 + kGRound;        // step lag between consecutive wavef
 constexpr int kGRing = 4 * kGRound;        // ring entries per wavefront boundary
 constexpr int kGMaxWaves = 16;
 constexpr int kGMaxRows = kGRows * kWave * kGMaxWaves;   // 16384
-constexpr int kSubStride = 32;             // row stride of the score table
+constexpr int kSubStride = 32;             // row stride of the score table (host copy)
+constexpr int kLdsSubRow = 64;             // entries per b row of the table in LDS
 constexpr int32_t kNegInf = -(1 << 30);
 constexpr int32_t kMaxSub = 2048;          // |sub| and open + ext at most this
 static_assert(kGLag >= 63 + kGRound, "ring handoff needs a barrier in between");
@@ -94,6 +101,14 @@ __device__ __forceinline__ int32_t sign_of(int32_t x, int32_t y) {
     return s;
 }
 
+// LDS byte address of row r's score at a step: byte 0 of the lane's packed
+// row symbols (each already times 4) and byte 1 the column symbol, i.e.
+// b * 256 + 4 a in one v_perm_b32 (selectors 0-3: bytes of `rows`, 4: byte 0
+// of `pk`, 12: zero)
+__device__ __forceinline__ uint32_t sub_addr(uint32_t pk, uint32_t rows, int r) {
+    return __builtin_amdgcn_perm(pk, rows, 0x0C0C0400u | (uint32_t)(r & 3));
+}
+
 // a << sh + b in one instruction (v_lshl_add_u32), exact in wrapping
 // 32-bit arithmetic for signed a and b
 template <int SH>
@@ -104,8 +119,8 @@ __device__ __forceinline__ uint32_t lshl_add(uint32_t a, uint32_t b) {
 }
 
 struct GotohLane {
-    int32_t H[kGRows];      // H[i][j-1] of the lane's rows
-    int32_t E[kGRows];      // E[i][j-1]
+    int32_t H[kGRows];      // H[i][j-1] of the lane's rows (plus (i + j - 1) ext)
+    int32_t E[kGRows];      // E[i][j-1] (plus (i + j - 1) ext)
     int32_t htop;           // H of the row above the lane at the previous column
     int32_t outH;           // H of the lane's bottom row at the current column
     uint32_t outP;          // packet: symbol | min(H - F, open + 1) << 8
@@ -115,13 +130,14 @@ struct GotohLane {
 // for the whole round (no range checks).
 template <bool kSteady>
 __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)[kGRows / 4],
-                                            const int32_t *sub_lds, uint32_t feedH,
+                                            const char *sub_lds, uint32_t feedH,
                                             uint32_t feedP, int t0, int shift, int n,
-                                            int32_t open, int32_t ext, bool rec_ok,
+                                            int32_t open, bool rec_ok,
                                             g_uint4 *rec, int64_t rec_step, uint2 *ring_out,
                                             int lane) {
-    const int32_t oe = open + ext;
-#pragma unroll 1
+    // two steps per loop iteration: a row's new H and E then alternate
+    // between two registers instead of being copied back at every step
+#pragma unroll 2
     for (int s = 0; s < kGRound; ++s) {
         const uint32_t sinH = __builtin_amdgcn_readlane(feedH, s);
         const uint32_t sinP = __builtin_amdgcn_readlane(feedP, s);
@@ -132,11 +148,17 @@ __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)
         const int jj = t0 + s - shift;
         const bool in = kSteady || (jj >= 0 && jj < n);
         const int32_t sym = (int32_t)(pk & 0xFFu);
-        const int32_t col = sym * kSubStride;
         // the row symbols are read afresh each step: otherwise the compiler
         // hoists 16 unpacked offsets out of the loop and spills them
         uint32_t rs[kGRows / 4] = {roff[0], roff[1], roff[2], roff[3]};
         asm volatile("" : "+v"(rs[0]), "+v"(rs[1]), "+v"(rs[2]), "+v"(rs[3]));
+        // the step's 16 scores are read before the row chain starts, so that
+        // one LDS round trip is waited for per step instead of one per row
+        // (the empty asm statements below keep later loads from moving)
+        int32_t svs[kGRows];
+#pragma unroll
+        for (int r = 0; r < kGRows; ++r)
+            svs[r] = *(const int32_t *)(sub_lds + sub_addr(pk, rs[r >> 2], r));
         int32_t up_h = htop;
         int32_t up_f = htop - (int32_t)(pk >> 8);
         int32_t diag = L.htop;
@@ -146,15 +168,15 @@ __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)
         // to come, or its last is done)
 #pragma unroll
         for (int r = 0; r < kGRows; ++r) {
-            const int32_t sv = sub_lds[col + ((rs[r >> 2] >> (8 * (r & 3))) & 0xFFu)];
+            const int32_t sv = svs[r];
             int32_t hprev = L.H[r], eprev = L.E[r];
             // tie the row's inputs to the row above's result, so that the
             // compiler does not compute every row's E ahead of the chain
             // (which would hold ~4 more registers per row)
             asm volatile("" : "+v"(hprev), "+v"(eprev) : "v"(up_h));
-            const int32_t e_ext = eprev - ext, e_opn = hprev - oe;
+            const int32_t e_ext = eprev, e_opn = hprev - open;
             const int32_t e = max(e_ext, e_opn);
-            const int32_t f_ext = up_f - ext, f_opn = up_h - oe;
+            const int32_t f_ext = up_f, f_opn = up_h - open;
             const int32_t f = max(f_ext, f_opn);
             const int32_t hd = diag + sv;
             const int32_t mef = max(e, f);
@@ -197,15 +219,16 @@ __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)
 }
 
 __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
-    __shared__ int32_t sub_lds[kSubStride * kSubStride];
+    __shared__ int32_t sub_lds[kSubStride * kLdsSubRow];
     __shared__ uint2 ring[kGMaxWaves * kGRing];
     const int64_t p = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // transposed: sub_lds[b * kSubStride + a] = sub[a][b], so that a step's
-    // column of scores starts at one offset and each row adds its symbol
+    // transposed, with the diagonal's 2 ext of the shifted recurrences:
+    // sub_lds[b * kLdsSubRow + a] = sub[a][b] + 2 ext, at byte b * 256 + 4 a
+    // (entries a >= kSubStride of a row are never read)
     for (int e = threadIdx.x; e < kSubStride * kSubStride; e += blockDim.x)
-        sub_lds[(e % kSubStride) * kSubStride + e / kSubStride] = a.sub[e];
+        sub_lds[(e % kSubStride) * kLdsSubRow + e / kSubStride] = a.sub[e] + 2 * a.ext;
     __syncthreads();
     const int32_t x = a.ia[p], y = a.ib[p];
     if (x < 0 || x >= a.A.n || y < 0 || y >= a.B.n) {
@@ -233,25 +256,27 @@ __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
     const bool lane_ok = g < G;
     const int32_t open = a.open, ext = a.ext;
 
-    // the lane's 16 pattern symbols, four per register (one byte each):
-    // row r's score at column j is sub_lds[b_j * kSubStride + byte r]
+    // the lane's 16 pattern symbols times 4, four per register (one byte
+    // each; staged symbols are below 32, so the shift carries nothing between
+    // bytes): row r's score at column j is at LDS byte b_j * 256 + byte r
     uint32_t roff[kGRows / 4];
     {
         uint4 q = make_uint4(0, 0, 0, 0);
         if (lane_ok) q = *(const uint4 *)(a.A.codes + (int64_t)x * a.A.stride + kGRows * g);
-        roff[0] = q.x;
-        roff[1] = q.y;
-        roff[2] = q.z;
-        roff[3] = q.w;
+        roff[0] = q.x << 2;
+        roff[1] = q.y << 2;
+        roff[2] = q.z << 2;
+        roff[3] = q.w << 2;
     }
+    // column 0 in the shifted form: H = -open below row 0, H[0][0] = 0
     GotohLane L;
     const int32_t row0 = kGRows * g;   // the row above the lane
 #pragma unroll
     for (int r = 0; r < kGRows; ++r) {
-        L.H[r] = -(open + (row0 + r + 1) * ext);
+        L.H[r] = -open;
         L.E[r] = kNegInf;
     }
-    L.htop = row0 == 0 ? 0 : -(open + row0 * ext);
+    L.htop = row0 == 0 ? 0 : -open;
     L.outH = 0;
     L.outP = 0;
     const int r_last = (m - 1) - kGRows * (int)((m - 1) / kGRows);
@@ -281,7 +306,7 @@ __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
             const int jj = t0 + lane - kGLag * w;
             if (lane < kGRound && jj >= 0 && jj < n) {
                 if (w == 0) {
-                    feedH = (uint32_t)(-(open + (jj + 1) * ext));
+                    feedH = (uint32_t)(-open);   // row 0, shifted
                     feedP = (uint32_t)text[jj] | ((uint32_t)(open + 1) << 8);
                 } else {
                     const uint2 v = ring_in[jj & (kGRing - 1)];
@@ -292,19 +317,20 @@ __global__ void __launch_bounds__(1024) k_gotoh_fill(GotohArgs a) {
         }
         const bool steady = t0 - kGLag * w - 63 >= 0 && t0 + kGRound - 1 - kGLag * w < n;
         if (steady)
-            gotoh_round<true>(L, roff, sub_lds, feedH, feedP, t0, shift, n, open, ext, lane_ok,
-                              rec, rec_step, ring_out, lane);
+            gotoh_round<true>(L, roff, (const char *)sub_lds, feedH, feedP, t0, shift, n, open,
+                              lane_ok, rec, rec_step, ring_out, lane);
         else
-            gotoh_round<false>(L, roff, sub_lds, feedH, feedP, t0, shift, n, open, ext, lane_ok,
-                               rec, rec_step, ring_out, lane);
+            gotoh_round<false>(L, roff, (const char *)sub_lds, feedH, feedP, t0, shift, n, open,
+                               lane_ok, rec, rec_step, ring_out, lane);
         rec = (g_uint4 *)((uintptr_t)rec + (uintptr_t)(kGRound * rec_step));
     }
-    // the lane state stopped at the last column: H[m][n] is row r_last's H
+    // the lane state stopped at the last column: H[m][n] is row r_last's H,
+    // less the (m + n) ext of the shifted form
     if (score_lane && a.score) {
         int32_t sc = 0;
 #pragma unroll
         for (int r = 0; r < kGRows; ++r) sc = r == r_last ? L.H[r] : sc;
-        a.score[p] = sc;
+        a.score[p] = sc - (m + n) * ext;
     }
 }
 

@@ -83,6 +83,32 @@ def test_block_and_wavefront_boundaries(kind):
     _check(ca, oa, cb, ob, sigma, np.arange(P), np.arange(P), sub, 10, 1)
 
 
+def test_extreme_costs_and_alphabet():
+    """Costs at the admitted limits (|sub| up to 2048, open + ext = 2048, a
+    zero open or extension), the largest alphabet (symbol 31 on both sides),
+    patterns over several wavefronts and a 65,535-symbol text: the fill's
+    values (offset by (i + j) ext) reach their widest range here."""
+    rng = np.random.default_rng(11)
+    sigma = 32
+    sub = rng.integers(-2048, 2049, size=(sigma, sigma)).astype(np.int32)
+    sub[sigma - 1, sigma - 1] = 2048
+    seqs_a, seqs_b = [], []
+    for L in (1, 17, 1025, 2100, 3100):
+        a = rng.integers(0, sigma, size=L).astype(np.uint8)
+        a[-1] = sigma - 1
+        seqs_a.append(a)
+        seqs_b.append(synth.mutate(rng, a, sigma, 0.1, 0.03, 0.03))
+        seqs_a.append(a)
+        seqs_b.append(rng.integers(0, sigma, size=int(rng.integers(1, 700))).astype(np.uint8))
+    seqs_a.append(rng.integers(0, sigma, size=40).astype(np.uint8))
+    seqs_b.append(rng.integers(0, sigma, size=65535).astype(np.uint8))
+    ca, oa = synth.to_csr(seqs_a)
+    cb, ob = synth.to_csr(seqs_b)
+    P = len(seqs_a)
+    for open_, ext in [(0, 2048), (2048, 0), (48, 2000), (1000, 1000)]:
+        _check(ca, oa, cb, ob, sigma, np.arange(P), np.arange(P), sub, open_, ext)
+
+
 def test_longest_patterns_sixteen_wavefronts():
     """16,384-row patterns (16 wavefronts of one workgroup) against short and
     related texts; one row more is refused on the host."""

@@ -946,10 +946,14 @@ def bench_pruned(msadp, synth, torch, args):
         rep = learned.reproduced_clusters(exact, t)
         nd, ex_mean, ex_max = learned.rowsum_excess(S, exact, clr, max(topk, eb))
         tp = float(np.median(times))
+        # the network's rankings need the embedding pass (once per set);
+        # the other rankers need none
+        t_emb = t_embed if name.startswith("cnn") else 0.0
         out["points"].append({"ranker": name, "offset": round(eo, 4), "pivots": piv,
                               "topk": topk,
                               "exact_below": eb,
                               "build_s": round(tp, 4), "speedup": round(t_exact / tp, 2),
+                              "speedup_with_embedding": round(t_exact / (tp + t_emb), 2),
                               "agreement": agree, "reproduced_clusters": round(rep, 4),
                               "center_differs": nd, "rowsum_excess_mean": round(ex_mean, 6),
                               "rowsum_excess_max": round(ex_max, 6),

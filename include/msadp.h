@@ -493,10 +493,10 @@ int msa_autotune_nw(const msa_seqs *A, const msa_seqs *B, const int32_t *ia, con
                     void *ws, size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,
                     int32_t *d_status, hipStream_t s);
 /* The same for the pair-list layout of lev_batch (same arguments as
- * lev_batch; dist holds the last run's exact distances): both layouts when
- * the patterns fit the per-lane one, fastest stored for (MSA_TUNE_PAIRS,
- * A->sigma, ceil(max(A->max_len, B->max_len) / 64)); *best = 1 or 64.
- * n_pairs >= 1. */
+ * lev_batch; dist holds the last run's exact distances): every layout the
+ * patterns fit (64 always, 1 and 2 under the limits of MSA_TUNE_PAIRS),
+ * fastest stored for (MSA_TUNE_PAIRS, A->sigma, ceil(max(A->max_len,
+ * B->max_len) / 64)); *best = 1, 2 or 64.  n_pairs >= 1. */
 int msa_autotune_pairs(const msa_seqs *A, const msa_seqs *B, const int32_t *ia,
                        const int32_t *ib, int64_t n_pairs, uint16_t *dist, void *ws,
                        size_t ws_bytes, int32_t reps, int32_t *best, float *best_ms,

@@ -878,7 +878,8 @@ def autotune_lev(S: Seqs, reps: int = 2, stream=None):
 
 def autotune_pairs(lb: "LevBatch", reps: int = 2, stream=None):
     """Time the lev_batch pair layouts on a prepared LevBatch and keep the
-    fastest; returns (lanes per pattern table: 1 or 64, ms per call)."""
+    fastest; returns (the layout: 1 one pair per lane, 2 a pair per group
+    of lanes, 64 pairs grouped by pattern; ms per call)."""
     best, ms = C.c_int32(0), C.c_float(0.0)
     rc = lib().msa_autotune_pairs(*lb.args(), int(reps), C.byref(best), C.byref(ms),
                                   _ptr(lb.st.t), _stream(stream))

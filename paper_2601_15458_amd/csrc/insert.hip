@@ -91,32 +91,6 @@ __global__ void __launch_bounds__(256) k_leaf_count(const int32_t *cur, int32_t 
     if (k < n_new && cur[k] >= 0) atomicAdd(&arrivals[cur[k]], 1);
 }
 
-// Exclusive scan of n int32 flags into int32 (one workgroup; in == out
-// allowed); out[n] = the total.
-__global__ void __launch_bounds__(1024) k_scan_flags(const int32_t *in, int32_t *out, int32_t n) {
-    __shared__ int32_t part[1024];
-    const int t = threadIdx.x;
-    const int32_t chunk = (n + 1023) / 1024;
-    const int32_t lo = min(n, t * chunk), hi = min(n, lo + chunk);
-    int32_t sum = 0;
-    for (int32_t i = lo; i < hi; ++i) sum += in[i] > 0;
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int32_t v = t >= off ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int32_t run = part[t] - sum;
-    for (int32_t i = lo; i < hi; ++i) {
-        const int32_t v = in[i] > 0;
-        out[i] = run;
-        run += v;
-    }
-    if (t == 1023) out[n] = part[1023];
-}
-
 // Exclusive scan of n int64 in place (one workgroup); a[n] = the total.
 __global__ void __launch_bounds__(1024) k_scan_i64(int64_t *a, int32_t n) {
     __shared__ int64_t part[1024];
@@ -266,6 +240,38 @@ __device__ __forceinline__ int32_t block_count(bool f, int32_t (*wsum)[kSpliceWa
     buf ^= 1;
     total = tot;
     return before + below + (f ? 1 : 0);
+}
+
+// Exclusive scan of n int32 flags (an entry counts when it is > 0) into
+// out, one workgroup of 1024 threads; in == out allowed (every entry is read
+// and written by the same thread); out[n] = the total.  Entries go in tiles
+// of 1024, thread t taking entry t of each (coalesced), the loads of
+// kScanTiles tiles issued together; block_count gives each entry its offset
+// within its tile and a running total carries from tile to tile.
+constexpr int kScanTiles = 8;
+
+__global__ void __launch_bounds__(1024) k_scan_flags(const int32_t *in, int32_t *out, int32_t n) {
+    __shared__ int32_t wsum[2][kSpliceWaves];
+    const int t = threadIdx.x;
+    int buf = 0;
+    int32_t run = 0;   // flags before the current tile (the same in every thread)
+    for (int64_t base = 0; base < n; base += 1024 * kScanTiles) {
+        bool f[kScanTiles];
+#pragma unroll
+        for (int k = 0; k < kScanTiles; ++k) {
+            const int64_t i = base + 1024 * k + t;
+            f[k] = i < n && in[i] > 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kScanTiles; ++k) {
+            const int64_t i = base + 1024 * k + t;
+            int32_t tile_total;
+            const int32_t incl = block_count(f[k], wsum, buf, tile_total);
+            if (i < n) out[i] = run + incl - (f[k] ? 1 : 0);
+            run += tile_total;
+        }
+    }
+    if (t == 0) out[n] = run;
 }
 
 __global__ void __launch_bounds__(1024) k_splice(SpliceArgs a) {

@@ -40,6 +40,21 @@ def test_exhaustive_tiny_pairs_random_costs(sym):
         assert list(ops) == want_ops, (t, a, b, sub.tolist(), open_, ext)
 
 
+def test_exhaustive_tiny_pairs_extreme_costs():
+    """The same enumeration at the largest admitted magnitudes (|sub| up to
+    2048, open + ext = 2048, either one zero) and the largest alphabet."""
+    rng = np.random.default_rng(35)
+    for t, (open_, ext) in enumerate([(0, 2048), (2048, 0), (48, 2000), (1000, 1000)] * 60):
+        sigma = 32 if t % 2 else int(rng.integers(2, 5))
+        sub = _rand_sub(rng, sigma, lo=-2048, hi=2048, sym=bool(t % 3))
+        a = [int(x) for x in rng.integers(0, sigma, size=int(rng.integers(0, 6)))]
+        b = [int(x) for x in rng.integers(0, sigma, size=int(rng.integers(0, 6)))]
+        want_s, want_ops = best_affine_alignment(a, b, sub, open_, ext)
+        s, ops = orc.gotoh(a, b, sub, open_, ext)
+        assert s == want_s, (t, a, b, open_, ext)
+        assert list(ops) == want_ops, (t, a, b, open_, ext)
+
+
 def test_all_short_binary_pairs_tie_heavy_costs():
     """Costs chosen to make many alignments tie: match 0, mismatch -1,
     open 1, extension 1, every pair of binary strings up to length 4."""

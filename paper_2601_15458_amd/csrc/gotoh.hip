@@ -148,8 +148,9 @@ __device__ __forceinline__ void gotoh_round(GotohLane &L, const uint32_t (&roff)
         const int jj = t0 + s - shift;
         const bool in = kSteady || (jj >= 0 && jj < n);
         const int32_t sym = (int32_t)(pk & 0xFFu);
-        // the row symbols are read afresh each step: otherwise the compiler
-        // hoists 16 unpacked offsets out of the loop and spills them
+        // the packed row symbols go through an empty asm each step, so that
+        // nothing derived from them is hoisted out of the step loop into
+        // registers that would spill
         uint32_t rs[kGRows / 4] = {roff[0], roff[1], roff[2], roff[3]};
         asm volatile("" : "+v"(rs[0]), "+v"(rs[1]), "+v"(rs[2]), "+v"(rs[3]));
         // the step's 16 scores are read before the row chain starts, so that
